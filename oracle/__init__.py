@@ -1,0 +1,205 @@
+"""CPU FP64 oracle for the QQMC charge integrand (arXiv:2002.12372).
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the ``cpu_baseline`` leg of ``bench.py``; the product package never
+imports it.  The arithmetic lives in ``qqmc_oracle.c`` (plain C, one LU per
+determinant, all 2^n Keldysh index vectors enumerated); this module only
+marshals numpy arrays through ctypes.
+
+Every entry point mirrors a function of ``qqmc_oracle.h``; see that header for
+the passages of the paper each one writes out.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(verbose=False):
+    """Compile ``liboracle.so`` with gcc (C11, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wextra",
+           os.path.join(_HERE, "qqmc_oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    d, i, i64, u64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    P = ctypes.POINTER(ctypes.c_double)
+    PI = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_tables.argtypes = [d, d, d, d, i, d, P, P, P]
+    lib.oracle_tables.restype = i
+    lib.oracle_n_sigma.argtypes = [d, d, d, d]
+    lib.oracle_n_sigma.restype = d
+    lib.oracle_gf_direct.argtypes = [d, d, d, d, d, P]
+    lib.oracle_interp.argtypes = [P, i, d, d, P]
+    lib.oracle_det.argtypes = [i, P, P]
+    lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, i, P, PI, P]
+    lib.oracle_keldysh_sum.argtypes = [P, P, i, d, d, d, i, P, P, P]
+    lib.oracle_lattice_point.argtypes = [u64, i, i, u64, P, P]
+    lib.oracle_warp.argtypes = [i, P, d, d, P, P]
+    lib.oracle_warp.restype = i
+    lib.oracle_eval_sums.argtypes = [P, P, i, d, d, d, i, i, u64, i, P, d, i,
+                                     i64, i64, i, P]
+    lib.oracle_eval_sums.restype = i
+    lib.oracle_max_threads.restype = i
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Tables:
+    """g^<, g^> on the uniform grid plus the exact n_sigma (App. E)."""
+
+    def __init__(self, eps_d, gamma, beta, bias_v, n_grid=8192, t_half=10.0):
+        lib = _load()
+        self.eps_d, self.gamma, self.beta, self.bias_v = eps_d, gamma, beta, bias_v
+        self.n_grid, self.t_half = int(n_grid), float(t_half)
+        self.gl = np.zeros(2 * self.n_grid)
+        self.gg = np.zeros(2 * self.n_grid)
+        ns = ctypes.c_double()
+        rc = lib.oracle_tables(eps_d, gamma, beta, bias_v, self.n_grid,
+                               self.t_half, _p(self.gl), _p(self.gg),
+                               ctypes.byref(ns))
+        if rc != 0:
+            raise ValueError("oracle_tables: bad arguments")
+        self.n_sigma = ns.value
+
+    @property
+    def grid(self):
+        h = 2.0 * self.t_half / (self.n_grid - 1)
+        return -self.t_half + np.arange(self.n_grid) * h
+
+    def gl_c(self):
+        return self.gl[0::2] + 1j * self.gl[1::2]
+
+    def gg_c(self):
+        return self.gg[0::2] + 1j * self.gg[1::2]
+
+    def interp(self, which, tau):
+        tab = self.gl if which == "<" else self.gg
+        out = np.zeros(2)
+        _load().oracle_interp(_p(tab), self.n_grid, self.t_half, float(tau), _p(out))
+        return out[0] + 1j * out[1]
+
+    def _args(self):
+        return (_p(self.gl), _p(self.gg), self.n_grid, self.t_half, self.n_sigma)
+
+
+def n_sigma(eps_d, gamma, beta, bias_v):
+    return _load().oracle_n_sigma(eps_d, gamma, beta, bias_v)
+
+
+def gf_direct(eps_d, gamma, beta, bias_v, tau):
+    out = np.zeros(4)
+    _load().oracle_gf_direct(eps_d, gamma, beta, bias_v, float(tau), _p(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def det(mat):
+    mat = np.asarray(mat, dtype=np.complex128)
+    m = mat.shape[0]
+    a = _f64(np.stack([mat.real, mat.imag], axis=-1).reshape(-1))
+    out = np.zeros(2)
+    _load().oracle_det(m, _p(a), _p(out))
+    return out[0] + 1j * out[1]
+
+
+def wick_matrix(tables, t_meas, u, a):
+    u = _f64(u)
+    n = u.shape[0]
+    av = np.ascontiguousarray(a, dtype=np.int32)
+    out = np.zeros(2 * (n + 1) ** 2)
+    _load().oracle_wick_matrix(*tables._args(), t_meas, n, _p(u),
+                               av.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                               _p(out))
+    c = out[0::2] + 1j * out[1::2]
+    return c.reshape(n + 1, n + 1)
+
+
+def keldysh_sum(tables, t_meas, u):
+    """S(u) and the term mass M(u) for one point u = (u_1..u_n)."""
+    u = _f64(u)
+    S = np.zeros(2)
+    M = ctypes.c_double()
+    _load().oracle_keldysh_sum(*tables._args(), t_meas, u.shape[0], _p(u),
+                               _p(S), ctypes.byref(M))
+    return S[0] + 1j * S[1], M.value
+
+
+def integrand(tables, t_meas, u):
+    """f_n(u) = -2 i^{n+1} S(u): integrand of Q_n over the ordered simplex."""
+    S, M = keldysh_sum(tables, t_meas, u)
+    n = len(u)
+    return -2.0 * (1j ** (n + 1)) * S, 2.0 * M
+
+
+def lattice_point(i, n, log2_n, lattice_a, shift):
+    x = np.zeros(n)
+    sh = _f64(shift)
+    _load().oracle_lattice_point(int(i), n, log2_n, int(lattice_a), _p(sh), _p(x))
+    return x
+
+
+def warp(x, model_tau, t_meas):
+    x = _f64(x)
+    u = np.zeros(x.shape[0])
+    W = ctypes.c_double()
+    inside = _load().oracle_warp(x.shape[0], _p(x), model_tau, t_meas, _p(u),
+                                 ctypes.byref(W))
+    return u, W.value, bool(inside)
+
+
+def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
+              i_begin=0, i_end=None, n_threads=0):
+    """Per-shift sums of fbar over lattice indices [i_begin, i_end)."""
+    shifts = _f64(shifts)
+    K = shifts.shape[0]
+    assert shifts.shape == (K, n)
+    if i_end is None:
+        i_end = 1 << log2_n
+    sums = np.zeros(2 * K)
+    rc = _load().oracle_eval_sums(*tables._args(), t_meas, n, log2_n,
+                                  int(lattice_a), K, _p(shifts), model_tau,
+                                  mode, int(i_begin), int(i_end), n_threads,
+                                  _p(sums))
+    if rc != 0:
+        raise ValueError("oracle_eval_sums: bad arguments")
+    return sums[0::2] + 1j * sums[1::2]
+
+
+def eval_order(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
+               n_threads=0):
+    """Q^{(s)} for every shift, their mean and standard error (App. G)."""
+    N = 1 << log2_n
+    q = eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau,
+                  mode, 0, N, n_threads) / N
+    K = q.shape[0]
+    mean = q.mean()
+    stderr = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
+    return q, mean, stderr
+
+
+def max_threads():
+    return _load().oracle_max_threads()

@@ -1,0 +1,508 @@
+/*
+ * qqmc_oracle.c -- CPU FP64 oracle for the QQMC charge integrand of
+ * arXiv:2002.12372.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product library.  It is
+ * written for a reader holding the paper: plain loops, no blocking, no
+ * fusion, one LU factorisation per determinant, every one of the 2^n Keldysh
+ * index vectors enumerated.
+ *
+ * Conventions (readings of the paper, all listed in the design notes):
+ *  - Keldysh Green's functions use the standard sign, g^< = +i <c^dag c>,
+ *    so g^<(0) = i n_sigma.  The frequency-domain formulas printed in App. E
+ *    carry an extra factor -2 relative to this; Q_0 = 1 at eps_d = 0 (main
+ *    text, "Benchmark") fixes the standard normalisation.
+ *  - Every equal-time (diagonal) Wick entry is g^<(0), whatever the Keldysh
+ *    index; off-diagonal entries follow the 2x2 Keldysh rule of App. E with a
+ *    strict inequality d > 0 for the time ordering.
+ *  - Q_n = -2 i^{n+1} * integral over 0 < u_n < ... < u_1 < t of S(u): the
+ *    factor 2 is the spin sum of Q, the 1/n! of Eq. (integral_gf) is absorbed
+ *    by restricting to the time-ordered simplex (S is symmetric).
+ *  - The estimator is (C/N) sum_{i=0}^{N-1} f/p (Eq. (warped_int2) with the
+ *    sum ending at N-1; App. B drops C, which is restored here).
+ */
+#define _GNU_SOURCE 1
+#include "qqmc_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Non-interacting Green's functions (App. E, "Model" and
+ * "Expressions for the integrands"): wide band, Delta(omega) = -i Gamma, so
+ * the dot spectral function is the Lorentzian
+ *     A(omega) = 2 Gamma / ((omega - eps_d)^2 + Gamma^2),
+ * the symmetric bias V gives the mean occupation of the two leads
+ *     fbar(omega) = [n_F(omega - V/2) + n_F(omega + V/2)] / 2,
+ * and
+ *     g^<(tau) =  i Int domega/2pi A fbar      e^{-i omega tau},
+ *     g^>(tau) = -i Int domega/2pi A (1-fbar)  e^{-i omega tau}.
+ * ------------------------------------------------------------------------ */
+
+/* Fermi function of a complex argument, 1/(e^{beta z} + 1), written so that
+ * the exponential never overflows. */
+static cplx fermi_c(double beta, cplx z)
+{
+    cplx bz = beta * z;
+    if (creal(bz) > 0.0) {
+        cplx e = cexp(-bz);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (cexp(bz) + 1.0);
+}
+
+static double fermi_r(double beta, double x)
+{
+    double bx = beta * x;
+    if (bx > 0.0) {
+        double e = exp(-bx);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (exp(bx) + 1.0);
+}
+
+static cplx lorentz_c(double eps_d, double gamma, cplx z)
+{
+    cplx d = z - eps_d;
+    return 2.0 * gamma / (d * d + gamma * gamma);
+}
+
+/* Matsubara part shared by both half-plane closures:
+ *   sum_{k>=0} A(mu - i nu_k) e^{-nu_k tau},  nu_k = (2k+1) pi / beta,
+ * for tau > 0.  Terms are added from the smallest (largest k) upwards. */
+static cplx matsubara_sum(double eps_d, double gamma, double beta, double mu,
+                          double tau)
+{
+    /* stop where e^{-nu_k tau} < e^{-45}; the terms also fall as 1/nu_k^2 */
+    double nu_max = 45.0 / tau;
+    long kmax = (long)ceil((nu_max * beta / M_PI - 1.0) / 2.0) + 1;
+    if (kmax < 1) kmax = 1;
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0; /* Kahan, per component */
+    for (long k = kmax; k >= 0; --k) {
+        double nu = (2.0 * k + 1.0) * M_PI / beta;
+        cplx term = lorentz_c(eps_d, gamma, mu - I * nu) * exp(-nu * tau);
+        double y = creal(term) - cr, s = sr + y;
+        cr = (s - sr) - y; sr = s;
+        y = cimag(term) - ci; s = si + y;
+        ci = (s - si) - y; si = s;
+    }
+    return sr + I * si;
+}
+
+/* For tau > 0 close the omega contour in the lower half plane.  Poles there:
+ * the Lorentzian pole omega = eps_d - i Gamma (residue of A: i) and the Fermi
+ * poles omega = mu - i nu_k (residue of n_F(omega - mu): -1/beta; residue of
+ * 1 - n_F(omega - mu) = n_F(mu - omega): +1/beta).  This gives
+ *   Int domega/2pi A n_F(omega-mu) e^{-i omega tau}
+ *     = n_F(eps_d - mu - i Gamma) e^{-i eps_d tau - Gamma tau}
+ *       + (i/beta) e^{-i mu tau} sum_k A(mu - i nu_k) e^{-nu_k tau},
+ *   Int domega/2pi A (1 - n_F(omega-mu)) e^{-i omega tau}
+ *     = n_F(mu - eps_d + i Gamma) e^{-i eps_d tau - Gamma tau}
+ *       - (i/beta) e^{-i mu tau} sum_k A(mu - i nu_k) e^{-nu_k tau}. */
+static void gf_positive_tau(double eps_d, double gamma, double beta,
+                            double bias_v, double tau, cplx *glt, cplx *ggt)
+{
+    cplx lor = cexp(-I * eps_d * tau - gamma * tau);
+    cplx sum_l = 0.0, sum_g = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        double mu = side == 0 ? 0.5 * bias_v : -0.5 * bias_v;
+        cplx ms = matsubara_sum(eps_d, gamma, beta, mu, tau);
+        cplx ph = cexp(-I * mu * tau);
+        sum_l += fermi_c(beta, eps_d - mu - I * gamma) * lor + (I / beta) * ph * ms;
+        sum_g += fermi_c(beta, mu - eps_d + I * gamma) * lor - (I / beta) * ph * ms;
+    }
+    *glt = I * 0.5 * sum_l;
+    *ggt = -I * 0.5 * sum_g;
+}
+
+/* Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_m. */
+static void gauss_legendre(int m, double *x, double *w)
+{
+    for (int i = 0; i < m; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= m; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            dp = m * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* n(mu) = Int domega/2pi A(omega) n_F(omega - mu), written as the exact
+ * zero-temperature part plus an exponentially convergent remainder:
+ *   n(mu) = 1/2 + atan((mu - eps_d)/Gamma)/pi
+ *           + (1/2pi) Int_0^inf [A(mu + x) - A(mu - x)] n_F(x) dx. */
+static double occupation_one_lead(double eps_d, double gamma, double beta,
+                                  double mu)
+{
+    enum { M = 20 };
+    double gx[M], gw[M];
+    gauss_legendre(M, gx, gw);
+    double xmax = 45.0 / beta;
+    double feature = gamma < 1.0 / beta ? gamma : 1.0 / beta;
+    long panels = (long)ceil(xmax / (0.25 * feature));
+    if (panels < 8) panels = 8;
+    double width = xmax / panels, acc = 0.0;
+    for (long p = 0; p < panels; ++p) {
+        double a = p * width, part = 0.0;
+        for (int q = 0; q < M; ++q) {
+            double x = a + 0.5 * width * (gx[q] + 1.0);
+            double ap = 2.0 * gamma / ((mu + x - eps_d) * (mu + x - eps_d) + gamma * gamma);
+            double am = 2.0 * gamma / ((mu - x - eps_d) * (mu - x - eps_d) + gamma * gamma);
+            part += gw[q] * (ap - am) * fermi_r(beta, x);
+        }
+        acc += 0.5 * width * part;
+    }
+    return 0.5 + atan((mu - eps_d) / gamma) / M_PI + acc / (2.0 * M_PI);
+}
+
+double oracle_n_sigma(double eps_d, double gamma, double beta, double bias_v)
+{
+    return 0.5 * (occupation_one_lead(eps_d, gamma, beta, 0.5 * bias_v) +
+                  occupation_one_lead(eps_d, gamma, beta, -0.5 * bias_v));
+}
+
+void oracle_gf_direct(double eps_d, double gamma, double beta, double bias_v,
+                      double tau, double *out)
+{
+    cplx l, g;
+    if (tau > 0.0) {
+        gf_positive_tau(eps_d, gamma, beta, bias_v, tau, &l, &g);
+    } else if (tau < 0.0) {
+        /* g(-tau) = -conj(g(tau)): the Fourier integral of i * (real
+         * spectral weight) is hermitian in this sense. */
+        gf_positive_tau(eps_d, gamma, beta, bias_v, -tau, &l, &g);
+        l = -conj(l);
+        g = -conj(g);
+    } else {
+        double ns = oracle_n_sigma(eps_d, gamma, beta, bias_v);
+        l = I * ns;
+        g = I * (ns - 1.0);
+    }
+    out[0] = creal(l); out[1] = cimag(l);
+    out[2] = creal(g); out[3] = cimag(g);
+}
+
+int oracle_tables(double eps_d, double gamma, double beta, double bias_v,
+                  int n_grid, double t_half,
+                  double *gl, double *gg, double *n_sigma)
+{
+    if (n_grid < 2 || !(t_half > 0.0) || !(gamma > 0.0) || !(beta > 0.0))
+        return -1;
+    double h = 2.0 * t_half / (n_grid - 1);
+    double ns = oracle_n_sigma(eps_d, gamma, beta, bias_v);
+    #pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < n_grid; ++j) {
+        double tau = -t_half + j * h;
+        double v[4];
+        if (tau == 0.0) {
+            v[0] = 0.0; v[1] = ns; v[2] = 0.0; v[3] = ns - 1.0;
+        } else {
+            oracle_gf_direct(eps_d, gamma, beta, bias_v, tau, v);
+        }
+        gl[2 * j] = v[0]; gl[2 * j + 1] = v[1];
+        gg[2 * j] = v[2]; gg[2 * j + 1] = v[3];
+    }
+    *n_sigma = ns;
+    return 0;
+}
+
+/* Linear interpolation on the uniform grid; outside the grid the end value is
+ * held (the index and the fraction are both clamped). */
+static cplx interp_c(const double *tab, int n_grid, double t_half, double tau)
+{
+    double h = 2.0 * t_half / (n_grid - 1);
+    double s = (tau + t_half) / h;
+    double fl = floor(s);
+    long j = (long)fl;
+    if (j < 0) j = 0;
+    if (j > n_grid - 2) j = n_grid - 2;
+    double phi = s - (double)j;
+    if (phi < 0.0) phi = 0.0;
+    if (phi > 1.0) phi = 1.0;
+    cplx a = tab[2 * j] + I * tab[2 * j + 1];
+    cplx b = tab[2 * j + 2] + I * tab[2 * j + 3];
+    return (1.0 - phi) * a + phi * b;
+}
+
+void oracle_interp(const double *tab, int n_grid, double t_half, double tau,
+                   double *out)
+{
+    cplx v = interp_c(tab, n_grid, t_half, tau);
+    out[0] = creal(v); out[1] = cimag(v);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Determinants (textbook LU with partial pivoting).                        */
+/* ------------------------------------------------------------------------ */
+static cplx det_lu(int m, cplx *a /* m*m, destroyed */)
+{
+    cplx det = 1.0;
+    for (int k = 0; k < m; ++k) {
+        int piv = k;
+        double best = cabs(a[k * m + k]);
+        for (int r = k + 1; r < m; ++r) {
+            double v = cabs(a[r * m + k]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return 0.0;
+        if (piv != k) {
+            for (int c = 0; c < m; ++c) {
+                cplx t = a[k * m + c];
+                a[k * m + c] = a[piv * m + c];
+                a[piv * m + c] = t;
+            }
+            det = -det;
+        }
+        cplx p = a[k * m + k];
+        det *= p;
+        for (int r = k + 1; r < m; ++r) {
+            cplx f = a[r * m + k] / p;
+            for (int c = k + 1; c < m; ++c) a[r * m + c] -= f * a[k * m + c];
+        }
+    }
+    return det;
+}
+
+void oracle_det(int m, const double *a, double *out)
+{
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)(m > 0 ? m * m : 1));
+    for (int i = 0; i < m * m; ++i) w[i] = a[2 * i] + I * a[2 * i + 1];
+    cplx d = m > 0 ? det_lu(m, w) : 1.0;
+    free(w);
+    out[0] = creal(d); out[1] = cimag(d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wick matrices of Eq. (integral_gf) with the Keldysh 2x2 rule of App. E:  */
+/*   g[(u,a),(u',a')] = [[g^T, g^<], [g^>, g^Tbar]]_{a a'} at d = u - u',    */
+/*   g^T(d) = d > 0 ? g^>(d) : g^<(d),  g^Tbar(d) = d > 0 ? g^<(d) : g^>(d). */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;            /* number of vertices                                 */
+    cplx g0;          /* exact equal-time value g^<(0) = i n_sigma           */
+    const cplx *gl_d; /* (n+1)^2: g^<(tau_r - tau_c), point 0 = measurement  */
+    const cplx *gg_d; /* (n+1)^2: g^>(tau_r - tau_c)                         */
+    const double *tm; /* (n+1): times, tm[0] = t, tm[k] = u_k                */
+} wick_ctx;
+
+static cplx keldysh_entry(const wick_ctx *w, int r, int alpha, int c, int beta_)
+{
+    int np1 = w->n + 1;
+    double d = w->tm[r] - w->tm[c];
+    cplx gl = w->gl_d[r * np1 + c], gg = w->gg_d[r * np1 + c];
+    if (alpha == 0 && beta_ == 0) return d > 0.0 ? gg : gl;
+    if (alpha == 0 && beta_ == 1) return gl;
+    if (alpha == 1 && beta_ == 0) return gg;
+    return d > 0.0 ? gl : gg;
+}
+
+/* Spin-up matrix: rows (0,t,0), U_1..U_n; columns (0,t,1), U_1..U_n. */
+static void build_up(const wick_ctx *w, const int *a, cplx *m)
+{
+    int np1 = w->n + 1;
+    for (int r = 0; r < np1; ++r) {
+        for (int c = 0; c < np1; ++c) {
+            if (r == c) { m[r * np1 + c] = w->g0; continue; }
+            int ar = r == 0 ? 0 : a[r - 1];
+            int ac = c == 0 ? 1 : a[c - 1];
+            m[r * np1 + c] = keldysh_entry(w, r, ar, c, ac);
+        }
+    }
+}
+
+static void fill_pair_values(const double *gl, const double *gg, int n_grid,
+                             double t_half, int n, const double *tm,
+                             cplx *gl_d, cplx *gg_d)
+{
+    int np1 = n + 1;
+    for (int r = 0; r < np1; ++r)
+        for (int c = 0; c < np1; ++c) {
+            double d = tm[r] - tm[c];
+            gl_d[r * np1 + c] = interp_c(gl, n_grid, t_half, d);
+            gg_d[r * np1 + c] = interp_c(gg, n_grid, t_half, d);
+        }
+}
+
+void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
+                        double t_half, double n_sigma, double t_meas,
+                        int n, const double *u, const int *a, double *out)
+{
+    int np1 = n + 1;
+    double *tm = (double *)malloc(sizeof(double) * np1);
+    cplx *gl_d = (cplx *)malloc(sizeof(cplx) * np1 * np1);
+    cplx *gg_d = (cplx *)malloc(sizeof(cplx) * np1 * np1);
+    cplx *m = (cplx *)malloc(sizeof(cplx) * np1 * np1);
+    tm[0] = t_meas;
+    for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
+    fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
+    wick_ctx w = { n, I * n_sigma, gl_d, gg_d, tm };
+    build_up(&w, a, m);
+    for (int i = 0; i < np1 * np1; ++i) {
+        out[2 * i] = creal(m[i]);
+        out[2 * i + 1] = cimag(m[i]);
+    }
+    free(tm); free(gl_d); free(gg_d); free(m);
+}
+
+/* S(u) of Eq. (integral_gf): sum over a in {0,1}^n, natural binary order
+ * (bit k-1 of the counter is a_k), of (-1)^{sum a} det_up(a) det_dn(a),
+ * where det_dn is the vertex block (rows/columns 1..n) of the up matrix. */
+void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
+                        double t_half, double n_sigma, double t_meas,
+                        int n, const double *u, double *S_out, double *M_out)
+{
+    int np1 = n + 1;
+    double tm[32];
+    cplx gl_d[32 * 32], gg_d[32 * 32], up[32 * 32], dn[32 * 32];
+    int a[32];
+    tm[0] = t_meas;
+    for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
+    fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
+    wick_ctx w = { n, I * n_sigma, gl_d, gg_d, tm };
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0, mass = 0.0;
+    for (long mask = 0; mask < (1L << n); ++mask) {
+        int parity = 0;
+        for (int k = 0; k < n; ++k) {
+            a[k] = (int)((mask >> k) & 1L);
+            parity ^= a[k];
+        }
+        build_up(&w, a, up);
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) dn[r * n + c] = up[(r + 1) * np1 + (c + 1)];
+        cplx d_up = det_lu(np1, up);
+        cplx d_dn = det_lu(n, dn);
+        cplx term = d_up * d_dn;
+        if (parity) term = -term;
+        mass += cabs(term);
+        double y = creal(term) - cr, s = sr + y;
+        cr = (s - sr) - y; sr = s;
+        y = cimag(term) - ci; s = si + y;
+        ci = (s - si) - y; si = s;
+    }
+    S_out[0] = sr; S_out[1] = si;
+    *M_out = mass;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Points: randomly shifted rank-1 lattice (randomised QMC, App. G) and the  */
+/* product-model warping (Eqs. (warper1d), (x_of_v_simple), (hi_expo)).     */
+/* ------------------------------------------------------------------------ */
+void oracle_lattice_point(uint64_t i, int n, int log2_n, uint64_t lattice_a,
+                          const double *shift, double *x)
+{
+    uint64_t N = (uint64_t)1 << log2_n, z = 1 % N;
+    for (int j = 0; j < n; ++j) {
+        uint64_t m = (i * z) % N;
+        double y = (double)m / (double)N + shift[j];
+        if (y >= 1.0) y -= 1.0;
+        x[j] = y;
+        z = (z * lattice_a) % N;
+    }
+}
+
+/* x_m(v_m) = Int_0^{v_m} h / Int_0^inf h = 1 - e^{-v_m/tau} for
+ * h(v) = e^{-v/tau}, so v_m = -tau log(1 - x_m); u_0 = t, u_m = u_{m-1} - v_m;
+ * p_n(u) = prod_m h(u_{m-1} - u_m); C = Int_{[0,inf)^n} p_n dv = tau^n;
+ * the Jacobian |du/dx| = C/p_n(u) (App. D). */
+int oracle_warp(int n, const double *x, double model_tau, double t_meas,
+                double *u, double *W)
+{
+    double prev = t_meas, p = 1.0, c = 1.0;
+    for (int m = 0; m < n; ++m) {
+        double v = -model_tau * log1p(-x[m]);
+        u[m] = prev - v;
+        p *= exp(-(prev - u[m]) / model_tau);
+        prev = u[m];
+        c *= model_tau;
+    }
+    *W = c / p;
+    return u[n - 1] > 0.0 ? 1 : 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
+                     double t_half, double n_sigma, double t_meas,
+                     int n, int log2_n, uint64_t lattice_a,
+                     int n_shifts, const double *shifts, double model_tau,
+                     int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                     double *sums)
+{
+    if (n < 1 || n > 24 || log2_n < 1 || log2_n > 40 || i_end < i_begin ||
+        i_begin < 0 || n_shifts < 1 || mode < 0 || mode > 2)
+        return -1;
+    int64_t cnt = i_end - i_begin;
+    double *vals = (double *)malloc(sizeof(double) * 2 * (size_t)(cnt > 0 ? cnt : 1));
+    if (!vals) return -1;
+    int nt = n_threads > 0 ? n_threads : oracle_max_threads();
+    /* i^{n+1} */
+    cplx ipow = 1.0;
+    for (int k = 0; k < n + 1; ++k) ipow *= I;
+    for (int s = 0; s < n_shifts; ++s) {
+        const double *sh = shifts + (size_t)s * n;
+        #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+        for (int64_t q = 0; q < cnt; ++q) {
+            double x[32], u[32], W, S[2], M;
+            oracle_lattice_point((uint64_t)(i_begin + q), n, log2_n, lattice_a, sh, x);
+            int inside = oracle_warp(n, x, model_tau, t_meas, u, &W);
+            cplx f = 0.0;
+            if (mode == 1) {
+                /* f := p_n on the whole v-domain: f/p * C = C */
+                double p = 1.0, prev = t_meas;
+                for (int m = 0; m < n; ++m) {
+                    p *= exp(-(prev - u[m]) / model_tau);
+                    prev = u[m];
+                }
+                f = p * W;
+            } else if (inside) {
+                if (mode == 2) {
+                    f = W;
+                } else {
+                    oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, t_meas,
+                                       n, u, S, &M);
+                    f = -2.0 * ipow * (S[0] + I * S[1]) * W;
+                }
+            }
+            vals[2 * q] = creal(f);
+            vals[2 * q + 1] = cimag(f);
+        }
+        double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;
+        for (int64_t q = 0; q < cnt; ++q) {
+            double y = vals[2 * q] - cr, t = sr + y;
+            cr = (t - sr) - y; sr = t;
+            y = vals[2 * q + 1] - ci; t = si + y;
+            ci = (t - si) - y; si = t;
+        }
+        sums[2 * s] = sr;
+        sums[2 * s + 1] = si;
+    }
+    free(vals);
+    return 0;
+}

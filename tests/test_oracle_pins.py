@@ -1,0 +1,373 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: every expected value is a
+closed form, a value printed in the paper (tests/golden/), an independent
+library routine (scipy's QAWF Fourier quadrature, mpmath's digamma), or a
+brute-force evaluation (Leibniz determinant expansion, plain Monte Carlo).
+"""
+import itertools
+import math
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+from qqmc_inputs import Dot, order_job
+
+DOTS = [
+    Dot(0.0, 1.0, 20.0, 0.0),
+    Dot(0.7, 0.5, 20.0, 1.0),
+    Dot(-2.5, 2.0, 20.0, 0.5),
+    Dot(-0.5, 1.0, 20.0, 0.2),
+]
+
+
+def _tables(oracle_mod, d, n_grid=8192, t_half=10.0):
+    return oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, n_grid, t_half)
+
+
+# --------------------------------------------------------------------------
+# Green's function tables (App. E)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d", DOTS)
+def test_greater_minus_lesser_is_fourier_of_lorentzian(oracle_mod, d):
+    """g^>(tau) - g^<(tau) = -i Int A e^{-i w tau} dw/2pi
+    = -i exp(-i eps_d tau - Gamma |tau|), for any bias and temperature."""
+    tb = _tables(oracle_mod, d)
+    tau = tb.grid
+    exact = -1j * np.exp(-1j * d.eps_d * tau - d.gamma * np.abs(tau))
+    assert np.max(np.abs(tb.gg_c() - tb.gl_c() - exact)) < 1e-13
+
+
+@pytest.mark.parametrize("d", DOTS)
+def test_tables_hermitian(oracle_mod, d):
+    """g(-tau) = -conj(g(tau)) on the symmetric grid."""
+    tb = _tables(oracle_mod, d)
+    for g in (tb.gl_c(), tb.gg_c()):
+        assert np.max(np.abs(g[::-1] + np.conj(g))) < 1e-14
+
+
+def test_symmetric_point_real_part(oracle_mod):
+    """At eps_d = 0, V = 0: Re[g^<(tau)/i] = Int A (n_F(w)+n_F(-w))/2 cos/2pi
+    = exp(-Gamma |tau|)/2 exactly."""
+    d = Dot(0.0, 1.3, 20.0, 0.0)
+    tb = _tables(oracle_mod, d)
+    ref = 0.5 * np.exp(-d.gamma * np.abs(tb.grid))
+    assert np.max(np.abs((tb.gl_c() / 1j).real - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("d", DOTS + [Dot(2.9, 0.6, 35.0, 0.9)])
+def test_n_sigma_digamma(oracle_mod, d):
+    """n_sigma = (1/2) sum_{mu=+-V/2} [1/2 - Im psi(1/2 + beta(Gamma +
+    i(eps_d - mu))/2pi)/pi] (Lorentzian times Fermi, summed over Matsubara
+    poles), evaluated with mpmath."""
+    mpmath.mp.dps = 30
+    ref = 0.0
+    for mu in (0.5 * d.bias_v, -0.5 * d.bias_v):
+        z = 0.5 + d.beta * (d.gamma + 1j * (d.eps_d - mu)) / (2 * math.pi)
+        ref += 0.5 * (0.5 - float(mpmath.im(mpmath.digamma(z))) / math.pi)
+    assert abs(oracle_mod.n_sigma(d.eps_d, d.gamma, d.beta, d.bias_v) - ref) < 1e-14
+
+
+def test_q0_is_one_at_symmetric_point(oracle_mod):
+    """Q_0 = -2 i g^<(0) = 2 n_sigma = 1 at eps_d = 0 (main text,
+    "Benchmark")."""
+    for beta in (5.0, 20.0, 100.0):
+        assert abs(2.0 * oracle_mod.n_sigma(0.0, 1.0, beta, 0.0) - 1.0) < 1e-14
+
+
+def _qawf_gf(d, tau):
+    """g^<(tau), g^>(tau) by scipy's QAWF Fourier-integral quadrature of the
+    defining integrals, split at omega = 0."""
+    def A(w):
+        return 2 * d.gamma / ((w - d.eps_d) ** 2 + d.gamma ** 2)
+
+    def nf(x):
+        return 0.5 * (1 - math.tanh(0.5 * d.beta * x))
+
+    def fbar(w):
+        return 0.5 * (nf(w - 0.5 * d.bias_v) + nf(w + 0.5 * d.bias_v))
+
+    out = []
+    for occ in (fbar, lambda w: 1.0 - fbar(w)):
+        def fpos(w):
+            return A(w) * occ(w)
+
+        def fneg(x):
+            return A(-x) * occ(-x)
+        kw = dict(weight="cos", wvar=tau, limlst=200, limit=400, epsabs=1e-13)
+        c = integrate.quad(fpos, 0, np.inf, **kw)[0] + integrate.quad(fneg, 0, np.inf, **kw)[0]
+        kw["weight"] = "sin"
+        s = integrate.quad(fpos, 0, np.inf, **kw)[0] - integrate.quad(fneg, 0, np.inf, **kw)[0]
+        out.append((c - 1j * s) / (2 * math.pi))
+    return 1j * out[0], -1j * out[1]
+
+
+@pytest.mark.parametrize("d", DOTS)
+@pytest.mark.parametrize("tau", [0.37, 1.5, 4.2, 9.9, -2.7])
+def test_gf_against_fourier_quadrature(oracle_mod, d, tau):
+    gl_ref, gg_ref = _qawf_gf(d, tau)
+    gl, gg = oracle_mod.gf_direct(d.eps_d, d.gamma, d.beta, d.bias_v, tau)
+    assert abs(gl - gl_ref) < 2e-9
+    assert abs(gg - gg_ref) < 2e-9
+
+
+def test_interpolation_is_linear_between_nodes(oracle_mod, tiny_tables):
+    tb = tiny_tables
+    g = tb.gl_c()
+    tau = tb.grid
+    for j in (0, 17, 4095, 4096, 8190):
+        for phi in (0.0, 0.25, 0.5, 1.0):
+            x = tau[j] + phi * (tau[j + 1] - tau[j])
+            exp = (1 - phi) * g[j] + phi * g[j + 1]
+            assert abs(tb.interp("<", x) - exp) < 1e-13
+    # outside the grid the end values are held
+    assert abs(tb.interp("<", 11.0) - g[-1]) == 0.0
+    assert abs(tb.interp("<", -11.0) - g[0]) == 0.0
+
+
+# --------------------------------------------------------------------------
+# Determinants
+# --------------------------------------------------------------------------
+def _leibniz(m):
+    n = m.shape[0]
+    tot = 0j
+    for perm in itertools.permutations(range(n)):
+        sgn = 1
+        p = list(perm)
+        for i in range(n):
+            while p[i] != i:
+                j = p[i]
+                p[i], p[j] = p[j], p[i]
+                sgn = -sgn
+        prod = 1 + 0j
+        for i in range(n):
+            prod *= m[i, perm[i]]
+        tot += sgn * prod
+    return tot
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_det_matches_leibniz(oracle_mod, m):
+    rng = np.random.default_rng(100 + m)
+    for _ in range(5):
+        a = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+        ref = _leibniz(a)
+        assert abs(oracle_mod.det(a) - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_det_singular_and_pivoting(oracle_mod):
+    a = np.array([[0, 1j], [2, 0]], dtype=complex)      # needs a row swap
+    assert abs(oracle_mod.det(a) - (-2j)) < 1e-15
+    b = np.array([[1, 2], [2, 4]], dtype=complex)
+    assert oracle_mod.det(b) == 0
+
+
+def test_wick_matrices_leibniz(oracle_mod, tiny_tables):
+    """det_up and det_dn of the actual Wick matrices against Leibniz."""
+    u = np.array([9.1, 6.0, 3.3, 0.4])
+    for a in itertools.product((0, 1), repeat=4):
+        m = oracle_mod.wick_matrix(tiny_tables, 10.0, u, a)
+        assert abs(oracle_mod.det(m) - _leibniz(m)) < 1e-14
+        assert abs(oracle_mod.det(m[1:, 1:]) - _leibniz(m[1:, 1:])) < 1e-14
+
+
+def test_wick_matrix_keldysh_rule(oracle_mod, tiny_tables):
+    """Spot entries of the 2x2 Keldysh rule of App. E: rows (0,t,0), U_k;
+    columns (0,t,1), U_k; g^T = g^> for a later first argument."""
+    tb = tiny_tables
+    t = 10.0
+    u = np.array([7.0, 2.0])
+    m = oracle_mod.wick_matrix(tb, t, u, (0, 1))
+    g0 = 1j * tb.n_sigma
+    assert m[0, 0] == g0 and m[1, 1] == g0 and m[2, 2] == g0
+    # (t,0) vs (u1,0): time ordered, t later -> g^>(t - u1)
+    assert m[0, 1] == tb.interp(">", t - 7.0)
+    # (t,0) vs (u2,1): lesser
+    assert m[0, 2] == tb.interp("<", t - 2.0)
+    # (u1,0) vs (t,1): lesser at u1 - t
+    assert m[1, 0] == tb.interp("<", 7.0 - t)
+    # (u2,1) vs (t,1): anti-time-ordered, t later -> g^>(u2 - t)
+    assert m[2, 0] == tb.interp(">", 2.0 - t)
+    # (u1,0) vs (u2,1): lesser at u1 - u2
+    assert m[1, 2] == tb.interp("<", 5.0)
+    # (u2,1) vs (u1,0): greater at u2 - u1
+    assert m[2, 1] == tb.interp(">", -5.0)
+
+
+# --------------------------------------------------------------------------
+# Integrand invariants
+# --------------------------------------------------------------------------
+def test_order_one_closed_form(oracle_mod, tiny_tables):
+    """n = 1: S = g^<(0) [g^<(tau) g^>(-tau) - g^>(tau) g^<(-tau)],
+    tau = t - u, written out from the two 2x2 determinants by hand."""
+    tb = tiny_tables
+    g0 = 1j * tb.n_sigma
+    for u in (0.3, 4.4, 9.7):
+        tau = 10.0 - u
+        ref = g0 * (tb.interp("<", tau) * tb.interp(">", -tau)
+                    - tb.interp(">", tau) * tb.interp("<", -tau))
+        S, M = oracle_mod.keldysh_sum(tb, 10.0, [u])
+        assert abs(S - ref) < 1e-15
+
+
+def _random_points(rng, n, t, count):
+    out = []
+    while len(out) < count:
+        v = -np.log1p(-rng.random(n))
+        u = t - np.cumsum(v)
+        if u[-1] > 0:
+            out.append(u)
+    return out
+
+
+@pytest.mark.parametrize("d", DOTS[:3])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_causality(oracle_mod, d, n):
+    """A vertex after the measurement time makes S vanish (the Keldysh sum
+    over that latest vertex's index cancels term by term)."""
+    tb = _tables(oracle_mod, d)
+    rng = np.random.default_rng(7 * n)
+    t = 8.0
+    for _ in range(4):
+        u = rng.uniform(0.0, 9.5, size=n)
+        u[rng.integers(n)] = rng.uniform(8.05, 9.9)
+        S, M = oracle_mod.keldysh_sum(tb, t, u)
+        assert abs(S) <= 1e-14 * M
+
+
+@pytest.mark.parametrize("d", DOTS)
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_reality_and_permutation(oracle_mod, d, n):
+    """f_n = -2 i^{n+1} S is real (g(A,B)* = -g(Bbar, Abar) pairs every
+    Wick matrix with its conjugate), and S is symmetric in the vertices."""
+    tb = _tables(oracle_mod, d)
+    rng = np.random.default_rng(11 * n)
+    for u in _random_points(rng, n, 10.0, 3):
+        f, M2 = oracle_mod.integrand(tb, 10.0, u)
+        assert abs(f.imag) <= 1e-14 * M2
+        perm = rng.permutation(n)
+        f2, _ = oracle_mod.integrand(tb, 10.0, u[perm])
+        assert abs(f2 - f) <= 1e-14 * M2
+
+
+# --------------------------------------------------------------------------
+# Points, warping and estimator
+# --------------------------------------------------------------------------
+def test_lattice_points_brute_force(oracle_mod):
+    log2_n, n = 10, 4
+    N = 1 << log2_n
+    a = 0x1F5
+    shift = np.array([0.0, 0.25, 0.5, 0.875])
+    z = [pow(a, j, N) for j in range(n)]
+    pts = set()
+    for i in range(N):
+        x = oracle_mod.lattice_point(i, n, log2_n, a, shift)
+        exp = [((i * z[j]) % N) / N + shift[j] for j in range(n)]
+        exp = [e - 1 if e >= 1 else e for e in exp]
+        assert list(x) == exp
+        pts.add(tuple(x))
+    assert len(pts) == N  # z_0 = 1: the points are distinct
+
+
+def test_warp_closed_form(oracle_mod):
+    x = np.array([0.1, 0.5, 0.3])
+    u, W, inside = oracle_mod.warp(x, 0.95, 10.0)
+    v = -0.95 * np.log1p(-x)
+    assert np.allclose(u, 10.0 - np.cumsum(v), rtol=0, atol=1e-14)
+    assert abs(W - 0.95 ** 3 * np.exp(np.sum(v) / 0.95)) < 1e-12
+    assert inside
+    _, _, inside = oracle_mod.warp(np.array([0.999999, 0.99]), 1.0, 10.0)
+    assert not inside
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.95, 1.5])
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_model_function_mode_is_exact(oracle_mod, tiny_tables, tau, n):
+    """f := p_n makes every warped sample equal C = tau^n (App. D)."""
+    job = order_job(5, n, 10, 4, model_tau=tau, mode=1)
+    q, mean, _ = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n,
+                                       job.lattice_a, job.shifts, tau, mode=1)
+    assert np.max(np.abs(q - tau ** n)) <= 1e-13 * tau ** n
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_constant_integrand_gives_simplex_volume(oracle_mod, tiny_tables, n):
+    """f := 1 on 0 < u_n < ... < u_1 < t integrates to t^n/n!."""
+    job = order_job(6, n, 14, 16, mode=2)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n,
+                                        job.lattice_a, job.shifts, 1.0, mode=2)
+    exact = 10.0 ** n / math.factorial(n)
+    assert abs(mean.real - exact) < 5 * se + 1e-9 * exact
+
+
+# --------------------------------------------------------------------------
+# Physics pins of the whole charge coefficient
+# --------------------------------------------------------------------------
+def test_q1_closed_form(oracle_mod, tiny_tables):
+    """Q_1 = 2 n_sigma dn/deps_d (Hartree shift of the level); for the
+    Lorentzian at eps_d = 0, V = 0 and t -> infinity this is
+    -(beta/2 pi^2) psi'(1/2 + beta Gamma/2 pi).  At t = 10 the transient
+    and the grid interpolation leave a few 1e-6."""
+    beta, gam = 20.0, 1.0
+    mpmath.mp.dps = 30
+    closed = -beta / (2 * math.pi ** 2) * float(mpmath.psi(1, 0.5 + beta * gam / (2 * math.pi)))
+
+    def f1(u):
+        f, _ = oracle_mod.integrand(tiny_tables, 10.0, [u])
+        return f.real
+    quad = integrate.quad(f1, 0, 10.0, limit=200, epsabs=1e-12, epsrel=1e-12)[0]
+    assert abs(quad - closed) < 2e-5
+    # the QMC estimate (n = 1, N = 2^14, 16 shifts) agrees with the quadrature
+    job = order_job(1, 1, 14, 16)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, 1, job.log2_n,
+                                        job.lattice_a, job.shifts, 1.0)
+    assert abs(mean.real - quad) < 5 * se + 1e-9
+    assert abs(mean.imag) < 1e-12
+
+
+def test_q2_two_dimensional_quadrature(oracle_mod, tiny_tables):
+    """Q_2 by nested adaptive quadrature over the ordered simplex agrees with
+    the warped lattice estimate within its randomised-QMC error bar."""
+    def inner(u1):
+        return integrate.quad(lambda u2: oracle_mod.integrand(tiny_tables, 10.0, [u1, u2])[0].real,
+                              0, u1, epsabs=1e-11, epsrel=1e-10, limit=200)[0]
+    quad = integrate.quad(inner, 0, 10.0, epsabs=1e-10, epsrel=1e-9, limit=200)[0]
+    job = order_job(1, 2, 14, 16)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, 2, job.log2_n,
+                                        job.lattice_a, job.shifts, 1.0)
+    assert abs(mean.real - quad) < 5 * se + 1e-8
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_plain_monte_carlo(oracle_mod, tiny_tables, n):
+    """Plain Monte Carlo with numpy's MT19937, uniform on the simplex
+    (sorted uniforms), against the warped lattice estimate."""
+    rs = np.random.RandomState(1234 + n)
+    M = 6000
+    vals = np.empty(M)
+    for k in range(M):
+        u = np.sort(rs.uniform(0, 10.0, size=n))[::-1]
+        vals[k] = oracle_mod.integrand(tiny_tables, 10.0, u)[0].real
+    vol = 10.0 ** n / math.factorial(n)
+    mc, mc_se = vol * vals.mean(), vol * vals.std(ddof=1) / math.sqrt(M)
+    job = order_job(1, n, 14, 16)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n,
+                                        job.lattice_a, job.shifts, 1.0)
+    assert abs(mean.real - mc) < 4 * math.hypot(mc_se, se)
+
+
+def test_bethe_orders_close_at_low_temperature(oracle_mod, tiny_tables):
+    """The printed Bethe-ansatz Q_1..Q_3 hold at T = 0, t -> infinity; at
+    beta = 20, t = 10 the finite-temperature and transient shifts are a few
+    percent, far below any sign or factor error."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "bethe_qn.txt")
+    bethe = {int(l.split()[0]): float(l.split()[1]) for l in open(path)
+             if l.strip() and not l.startswith("#")}
+    for n, tol in ((1, 0.02), (2, 0.03), (3, 0.08)):
+        job = order_job(1, n, 14, 16)
+        q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n,
+                                            job.lattice_a, job.shifts, 1.0)
+        assert abs(mean.real / bethe[n] - 1.0) < tol, (n, mean, bethe[n])

@@ -1,0 +1,225 @@
+/*
+ * qqmc.h -- C ABI of the MI355X quantum quasi-Monte Carlo (QQMC) library.
+ *
+ * The library estimates the order-n coefficient Q_n of the charge
+ * Q(U) = sum_n Q_n U^n of a wide-band Anderson quantum dot (arXiv:2002.12372,
+ * Macek et al.): a randomly shifted rank-1 lattice is warped through the
+ * product-of-exponentials model function into time-ordered interaction
+ * vertices, and at every point the Keldysh sum of products of spin-up and
+ * spin-down Wick determinants is evaluated on the GPU.
+ *
+ * General conventions
+ *  - All arithmetic is IEEE binary64; complex numbers are (re, im) pairs of
+ *    doubles.
+ *  - Pointers marked "host" are ordinary host memory; pointers marked
+ *    "device" are HIP device allocations (for example torch tensors'
+ *    data_ptr()).  The caller owns every buffer it passes; the library owns
+ *    the memory behind the opaque handles it returns.
+ *  - Streams are hipStream_t values passed as void*; NULL is the null stream.
+ *    Calls that return host results synchronise the stream before returning.
+ *  - Functions return a qqmc_status; on failure qqmc_last_error() gives a
+ *    message (per thread).  No call throws across the ABI.
+ *  - Time and energy units: Gamma sets the scale only through the caller's
+ *    choice; nothing is normalised inside.
+ */
+#ifndef QQMC_H
+#define QQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QQMC_OK = 0,
+    QQMC_PENDING = 1,      /* qqmc_poll: the request has not finished      */
+    QQMC_EINVAL = -1,      /* an argument is outside its documented range  */
+    QQMC_ENOMEM = -2,      /* a host or device allocation failed           */
+    QQMC_EDEVICE = -3,     /* a HIP runtime call failed                    */
+    QQMC_EADMIT = -4,      /* qqmc_submit: the request can never fit       */
+    QQMC_ENOTICKET = -5    /* qqmc_poll: unknown or already collected      */
+} qqmc_status;
+
+/* Highest perturbation order the kernels are built for. */
+#define QQMC_MAX_ORDER 14
+
+/* Wide-band Anderson dot (App. E "Model", hybridisation Delta = -i Gamma,
+ * quadratic shift alpha = 0).  The Green's functions are tabulated on the
+ * uniform grid tau_j = -t_half + j*h, h = 2 t_half/(n_grid-1). */
+typedef struct {
+    double eps_d;    /* dot level                                           */
+    double gamma;    /* tunnelling rate Gamma > 0                           */
+    double beta;     /* inverse temperature > 0                             */
+    double bias_v;   /* symmetric bias V between the two leads              */
+    double t_half;   /* half-range of the table grid (>= measurement time)  */
+    int32_t n_grid;  /* number of grid points, 2 .. 2^24                    */
+} qqmc_dot;
+
+typedef struct qqmc_tables_s *qqmc_tables;
+
+/* Integrand modes of qqmc_eval_order. */
+enum {
+    QQMC_MODE_CHARGE = 0,   /* -2 i^{n+1} S(u) W: the charge coefficient      */
+    QQMC_MODE_MODEL = 1,    /* f := p_n over the whole v-domain: every sample
+                               equals C = tau^n (warp/estimator self-test)    */
+    QQMC_MODE_CONSTANT = 2  /* f := 1 on the ordered simplex: t^n/n!          */
+};
+
+/* One order-n integral (Eq. (warped_int2)): N = 2^log2_n points of the rank-1
+ * lattice with generating vector (1, a, a^2, ...) mod N, each shifted by the
+ * n_shifts rows of `shifts`, warped with h(v) = exp(-v/model_tau)
+ * (Eq. (hi_expo)) towards the measurement time t_meas. */
+typedef struct {
+    int32_t order;          /* n, 1 .. QQMC_MAX_ORDER                         */
+    int32_t log2_n;         /* 6 .. 24                                        */
+    uint64_t lattice_a;     /* odd Korobov multiplier, 1 < a < N              */
+    int32_t n_shifts;       /* K >= 1                                         */
+    const double *shifts;   /* host, K x order row-major, each in [0, 1);
+                               copied during the call                          */
+    double model_tau;       /* tau > 0                                        */
+    double t_meas;          /* measurement time t, 0 < t <= table t_half      */
+    int32_t mode;           /* QQMC_MODE_*                                    */
+} qqmc_order;
+
+/* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
+ * standard Keldysh normalisation g^< = i A fbar, g^> = -i A (1 - fbar)) --- */
+
+/* Builds g^<(tau_j), g^>(tau_j) and n_sigma = -i g^<(0) on the host (exact
+ * residue series over the Matsubara poles), uploads them to the current
+ * device on `stream`, and returns a handle.  EINVAL for gamma <= 0,
+ * beta <= 0, t_half <= 0 or n_grid outside 2..2^24. */
+qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream,
+                             qqmc_tables *out);
+
+/* Wraps caller-supplied tables (host arrays of 2*n_grid doubles each, same
+ * grid convention) so that any Green's function can be integrated.  The data
+ * are copied; the caller may free them on return. */
+qqmc_status qqmc_tables_from_host(const double *gl, const double *gg,
+                                  int32_t n_grid, double t_half,
+                                  double n_sigma, void *stream,
+                                  qqmc_tables *out);
+
+/* Copies the tables back: gl, gg host arrays of 2*n_grid doubles (either may
+ * be NULL), n_sigma host scalar (may be NULL). */
+qqmc_status qqmc_tables_export(qqmc_tables t, double *gl, double *gg,
+                               double *n_sigma);
+
+/* Grid size and half-range of a table handle (either pointer may be NULL). */
+qqmc_status qqmc_tables_info(qqmc_tables t, int32_t *n_grid, double *t_half);
+
+/* Releases the handle and its device memory.  NULL is ignored. */
+void qqmc_free_tables(qqmc_tables t);
+
+/* ---- The hot path -------------------------------------------------------
+ * qqmc_eval_order: estimates Q_n (Eq. (warped_int2), randomised over shifts
+ * as in App. G).  Launches the integrand kernel over all N x K points on
+ * `stream`, reduces on the device, copies K complex per-shift estimates
+ * back and synchronises the stream.
+ *   q_shift  host, 2*n_shifts doubles: Q^{(s)} = (1/N) sum_i fbar_{i,s}
+ *   q_mean   host, 2 doubles: mean over shifts (may be NULL)
+ *   q_stderr host, 1 double: sample standard deviation of Re Q^{(s)} over
+ *            shifts / sqrt(K); NaN for K = 1 (may be NULL)
+ * EINVAL on any out-of-range field, an even or out-of-range lattice_a, a
+ * shift outside [0, 1) or t_meas > t_half.  Q_n is real; the imaginary part
+ * is a rounding diagnostic. */
+qqmc_status qqmc_eval_order(qqmc_tables t, const qqmc_order *ord,
+                            void *stream, double *q_shift, double *q_mean,
+                            double *q_stderr);
+
+/* Asynchronous form of qqmc_eval_order for callers that keep results on the
+ * device: launches on `stream` and returns without synchronising.
+ *   tile_len   lattice indices per work tile (a multiple of 64 dividing N),
+ *              or 0 for the library's choice
+ *   tile_sums  device, 2*n_tiles doubles or NULL: per-tile sums of fbar,
+ *              tile k covering shift k / (N/tile_len) and lattice indices
+ *              [(k % (N/tile_len)) * tile_len, ... + tile_len)
+ *   shift_sums device, 2*n_shifts doubles: sum_i fbar_{i,s} (not divided
+ *              by N)
+ * n_tiles_out (host, may be NULL) receives the number of tiles.  The buffers
+ * must stay valid until the stream reaches the end of the launch. */
+qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
+                                  int32_t tile_len, void *stream,
+                                  double *tile_sums, double *shift_sums,
+                                  int64_t *n_tiles_out);
+
+/* Per-point integrand f_n(u) = -2 i^{n+1} S(u) of Eq. (integral_gf) (the
+ * integrand of Q_n over the ordered simplex, without warping weight).
+ *   u       device, n_points x order row-major, vertex times (u_1..u_n)
+ *   f       device, 2*n_points doubles (re, im)
+ *   method  QQMC_METHOD_TREE: the production kernel; requires
+ *           t_meas >= u_1 >= u_2 >= ... >= u_n >= 0 per row and writes NaN
+ *           for rows that violate it;
+ *           QQMC_METHOD_DIRECT: enumerates all 2^n Keldysh index vectors with
+ *           one partially pivoted LU per determinant; any vertex times
+ *           (within the table range).
+ * Asynchronous on `stream`. */
+enum { QQMC_METHOD_TREE = 0, QQMC_METHOD_DIRECT = 1 };
+qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
+                             const double *u, int64_t n_points,
+                             int32_t method, double *f, void *stream);
+
+/* ---- Batched form -------------------------------------------------------
+ * Many (parameter point, order) integrals in one persistent launch.  Each
+ * item is estimated exactly as qqmc_eval_order would (the same tile
+ * decomposition, hence the same per-shift sums bit for bit).  The plan owns
+ * device buffers and a captured HIP graph; qqmc_plan_run replays it. */
+typedef struct {
+    qqmc_tables tables;
+    qqmc_order order;      /* shifts are copied at plan creation */
+} qqmc_batch_item;
+
+typedef struct qqmc_plan_s *qqmc_plan;
+
+/* tile_len: lattice indices per tile (0 = autotuned); grid_blocks:
+ * persistent workgroups (0 = autotuned). */
+qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items,
+                             int32_t tile_len, int32_t grid_blocks,
+                             void *stream, qqmc_plan *out);
+/* Replays the launch on `stream` (asynchronous). */
+qqmc_status qqmc_plan_run(qqmc_plan p, void *stream);
+/* Synchronises `stream` and copies results: q_shift host, concatenated
+ * 2*n_shifts(item) doubles per item in item order (divided by N). */
+qqmc_status qqmc_plan_results(qqmc_plan p, void *stream, double *q_shift);
+/* Number of tiles and of lattice points (all items, all shifts). */
+qqmc_status qqmc_plan_info(qqmc_plan p, int64_t *n_tiles, int64_t *n_points,
+                           int32_t *tile_len, int32_t *grid_blocks);
+void qqmc_plan_destroy(qqmc_plan p);
+
+/* ---- Serving ------------------------------------------------------------
+ * A background scheduler admits requests while their device footprint fits
+ * in hbm_budget_bytes and a slot is free, keeps tables and partial sums on
+ * the device, and launches batches that mix the pending tiles of every
+ * admitted request (continuous batching: requests that arrive while others
+ * run join the next batch).  Each request's result is the same, bit for bit,
+ * as qqmc_eval_order on the same input. */
+typedef struct qqmc_server_s *qqmc_server;
+
+/* max_slots: requests resident at once; batch_tiles: tiles per launch
+ * (0 = default).  Uses the current device and a stream of its own. */
+qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots,
+                               int32_t batch_tiles, qqmc_server *out);
+/* Queues a request; never blocks on the GPU.  EADMIT if its footprint alone
+ * exceeds hbm_budget_bytes; EINVAL as for qqmc_eval_order. */
+qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot,
+                        const qqmc_order *ord, uint64_t *ticket);
+/* QQMC_PENDING until done; then fills the outputs (as qqmc_eval_order, each
+ * may be NULL), t_submit_s / t_done_s on the server's monotonic clock, and
+ * forgets the ticket (a second poll gives ENOTICKET). */
+qqmc_status qqmc_poll(qqmc_server s, uint64_t ticket, double *q_shift,
+                      double *q_mean, double *q_stderr, double *t_submit_s,
+                      double *t_done_s);
+/* Seconds on the server's clock (the clock of t_submit_s / t_done_s). */
+double qqmc_server_now(qqmc_server s);
+/* Blocks until every submitted request has finished. */
+qqmc_status qqmc_server_drain(qqmc_server s);
+void qqmc_server_destroy(qqmc_server s);
+
+/* Message describing the last failure on the calling thread. */
+const char *qqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QQMC_H */

@@ -1,0 +1,92 @@
+/*
+ * qqmc_internal.h -- structures shared by the host API and the kernels.
+ */
+#ifndef QQMC_INTERNAL_H
+#define QQMC_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qqmc.h"
+
+namespace qqmc {
+
+/* Device-side description of one order-n integral. */
+struct ItemDesc {
+    const double *tab;       /* device: (g^<, g^>) per grid node, 4 doubles */
+    const double *shifts;    /* device: n_shifts x order                    */
+    double t_half, h;        /* grid half-range and spacing                 */
+    double g0x, g0y;         /* g^<(0) = i n_sigma                          */
+    double t_meas, tau, tau_n, inv_n;
+    uint32_t z[QQMC_MAX_ORDER]; /* Korobov generating vector a^j mod N     */
+    uint32_t mask;           /* N - 1                                       */
+    int32_t n_grid, order, mode, n_shifts;
+    int32_t tile_len, tiles_per_shift;
+    int64_t n_tiles;
+    double *tile_sums;       /* device, 2 per tile, or null                 */
+};
+
+/* Entry of the batched tile list: which item, which tile of it. */
+struct TileRef {
+    int32_t item;
+    int32_t pad;
+    int64_t tile;
+};
+
+/* Launchers (defined in qqmc_kernels.hip).  All return hipSuccess or the
+ * first launch error. */
+hipError_t launch_order(const ItemDesc &it, hipStream_t s);
+hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
+                               const int64_t *shift_base_dev,
+                               double *shift_sums, int32_t total_shifts,
+                               hipStream_t s);
+hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half,
+                              double h, double g0y, int32_t order,
+                              double t_meas, const double *u, int64_t n_points,
+                              double *f, hipStream_t s);
+hipError_t launch_points_direct(const double *tab, int32_t n_grid,
+                                double t_half, double h, double g0y,
+                                int32_t order, double t_meas, const double *u,
+                                int64_t n_points, double *f, hipStream_t s);
+hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev,
+                        int64_t n_tiles, int32_t *counter_dev,
+                        int32_t grid_blocks, int32_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+int32_t lds_bytes_for_order(int32_t order);
+int32_t batch_lds_bytes(int32_t max_order);
+int32_t batch_blocks_per_cu(int32_t lds_bytes);
+int32_t default_tile_len(const ItemDesc &d, int64_t N);
+qqmc_status check_tables(qqmc_tables t);
+void fill_item_tables(ItemDesc &d, const qqmc_tables_s *t);
+
+/* Host table builder (qqmc_tables.cpp). */
+double occupation_per_spin(double eps_d, double gamma, double beta,
+                           double bias_v);
+void build_tables_host(double eps_d, double gamma, double beta, double bias_v,
+                       int32_t n_grid, double t_half, double n_sigma,
+                       double *tab /* 4*n_grid, interleaved */);
+
+/* Error reporting (qqmc_api.cpp). */
+qqmc_status set_error(qqmc_status st, const std::string &msg);
+qqmc_status hip_error(hipError_t e, const char *what);
+
+struct Validated {
+    ItemDesc desc;             /* pointers not yet set */
+    std::vector<double> shifts;
+};
+qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid,
+                           double t_half, Validated *out);
+
+} // namespace qqmc
+
+struct qqmc_tables_s {
+    double *d_tab = nullptr;   /* 4*n_grid doubles: (g<re, g<im, g>re, g>im) */
+    int32_t n_grid = 0;
+    double t_half = 0.0, h = 0.0, n_sigma = 0.0;
+    int device = 0;
+};
+
+#endif

@@ -1,0 +1,645 @@
+/*
+ * qqmc_kernels.hip -- gfx950 kernels of the QQMC hot path (arXiv:2002.12372).
+ *
+ * Work decomposition.  One workgroup is one 64-lane wavefront.  A work tile
+ * is (shift s, 64*c consecutive lattice indices).  For every 64 indices the
+ * wave
+ *   1. generates the shifted Korobov lattice point and warps it through the
+ *      inverse CDF of the product model h(v) = exp(-v/tau) (one lane per
+ *      index: Eqs. (warper1d), (x_of_v_simple), (hi_expo)),
+ *   2. compacts the points inside the domain 0 < u_n (App. I: points outside
+ *      contribute exactly zero) with a ballot,
+ *   3. for every compacted point builds the pair table of interpolated
+ *      g^<(tau), g^>(tau) in LDS (lanes of the point's group share the work),
+ *   4. evaluates the Keldysh sum with the elimination tree of qqmc_tree.h,
+ *      G = 2^T lanes per point (or per top-level prefix for n > 8),
+ *   5. folds -2 i^{n+1} S(u) W into a per-lane compensated accumulator.
+ * The tile's sum goes to one slot of a partials array; a second kernel sums
+ * the slots of each shift in a fixed order.  No floating-point atomics are
+ * used anywhere, so results are bitwise reproducible.
+ */
+#include "qqmc_internal.h"
+#include "qqmc_tree.h"
+
+namespace qqmc {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+template <int N> struct Lds {
+    using Gm = Geo<N>;
+    static constexpr int times = 0;                                    /* 64*N doubles   */
+    static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
+    static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
+    static constexpr int pairs = S + 64 * 16;                          /* PPW*NP pairv   */
+    static constexpr int res = pairs + Gm::PPW * Gm::NP * 32;          /* PPW cplx       */
+    static constexpr int row = res + Gm::PPW * 16;                     /* PPW*(N+1) cplx */
+    static constexpr int c0 = row + (Gm::OFF > 0 ? Gm::PPW * (N + 1) * 16 : 0);
+    static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+};
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m)
+{
+    return __shfl_xor(v, m, WAVE);
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+/* -2 i^{n+1} S: the charge prefactor (spin sum 2, i^n of the expansion, the
+ * extra -i of <n> = -i g^<). */
+template <int N> __device__ __forceinline__ cplx charge_prefactor(cplx s)
+{
+    constexpr int q = (N + 1) & 3;
+    if constexpr (q == 0) return cmk(-2.0 * s.x, -2.0 * s.y);
+    else if constexpr (q == 1) return cmk(2.0 * s.y, -2.0 * s.x);
+    else if constexpr (q == 2) return cmk(2.0 * s.x, 2.0 * s.y);
+    else return cmk(-2.0 * s.y, 2.0 * s.x);
+}
+
+struct Kahan {
+    double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
+    __device__ __forceinline__ void add(cplx v)
+    {
+        double y = v.x - cx, t = sx + y;
+        cx = (t - sx) - y; sx = t;
+        y = v.y - cy; t = sy + y;
+        cy = (t - sy) - y; sy = t;
+    }
+    __device__ __forceinline__ cplx value() const { return cmk(sx - cx, sy - cy); }
+};
+
+/* Fixed-order butterfly over the whole wave; every lane ends with the same
+ * bits (IEEE addition is commutative). */
+__device__ __forceinline__ cplx wave_sum(cplx v)
+{
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+        v.x += shfl_xor_d(v.x, m);
+        v.y += shfl_xor_d(v.y, m);
+    }
+    return v;
+}
+
+/* Environment of the points being evaluated (one parameter point). */
+struct Env {
+    const double *tab;
+    double t_half, h, t_meas;
+    cplx g0;
+    int n_grid;
+};
+
+/* The first OFF = n - 8 eliminations of a work item (n > 8), done by the 16
+ * lanes of the item's group with one matrix row per lane (right-looking, no
+ * pivoting, index prefix `top`).  Leaves the 9 x 9 trailing correction block
+ * in s_c0 and returns the product of the OFF pivots. */
+template <int N>
+__device__ cplx top_block(const pairv *pr, int top, int r, cplx g0, cplx *s_row,
+                          cplx *s_c0)
+{
+    using Gm = Geo<N>;
+    constexpr int OFF = Gm::OFF, K = Gm::K;
+    cplx crow[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) crow[j] = cmk(0.0, 0.0);
+    cplx prod = cmk(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < OFF; ++k) {
+        const int b = (top >> (OFF - 1 - k)) & 1;
+        if (r == k) {
+            s_row[k] = csub(g0, crow[k]);
+#pragma unroll
+            for (int j = k + 1; j <= N; ++j) s_row[j] = csub(wick_entry(pr, k, j, b), crow[j]);
+        }
+        __syncthreads();
+        const cplx p = s_row[k];
+        if (r > k && r <= N) {
+            const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[k]), crecip(p));
+#pragma unroll
+            for (int j = k + 1; j <= N; ++j) crow[j] = cfma(ch, s_row[j], crow[j]);
+        }
+        prod = cmul(prod, p);
+        __syncthreads();
+    }
+    if (r >= OFF && r <= N) {
+#pragma unroll
+        for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[j];
+    }
+    __syncthreads();
+    return prod;
+}
+
+/* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
+ * earliest first) sit in s_times; writes S to s_S[0..cnt). */
+template <int N>
+__device__ void keldysh_points(int cnt, const Env &env, char *lds)
+{
+    using Gm = Geo<N>;
+    using L = Lds<N>;
+    const double *s_times = reinterpret_cast<const double *>(lds + L::times);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
+    cplx *s_res = reinterpret_cast<cplx *>(lds + L::res);
+    const int lane = threadIdx.x;
+    const int grp = lane / Gm::G, sub = lane % Gm::G;
+    const int n_items = cnt * Gm::IPP;
+    for (int base = 0; base < n_items; base += Gm::PPW) {
+        const int item = base + grp;
+        const bool active = item < n_items;
+        const int pt = active ? item / Gm::IPP : 0;
+        const int top = active ? item % Gm::IPP : 0;
+        pairv *prg = s_pairs + grp * Gm::NP;
+        const double *tm = s_times + pt * N;
+        for (int q = sub; q < Gm::NP; q += Gm::G) {
+            int j = 1;
+            while ((j + 1) * j / 2 <= q) ++j;
+            const int i = q - j * (j - 1) / 2;
+            const double tj = j == N ? env.t_meas : tm[j];
+            prg[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+        }
+        __syncthreads();
+        cplx prod = cmk(1.0, 0.0);
+        int sgn = 0;
+        BlockSrc<N> src;
+        src.c = nullptr;
+        if constexpr (Gm::OFF > 0) {
+            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * (N + 1);
+            cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
+            prod = top_block<N>(prg, top, sub, env.g0, s_row, s_c0);
+            sgn = __popc((unsigned)top) & 1;
+            src.c = s_c0;
+        }
+        cplx s = lane_sum<N>(prg, src, sub, prod, sgn, env.g0);
+#pragma unroll
+        for (int m = 1; m < Gm::G; m <<= 1) {
+            s.x += shfl_xor_d(s.x, m);
+            s.y += shfl_xor_d(s.y, m);
+        }
+        if constexpr (Gm::IPP == 1) {
+            if (sub == 0 && active) s_S[pt] = s;
+        } else {
+            if (sub == 0) s_res[grp] = s;
+            __syncthreads();
+            if (lane == 0) {
+                for (int g = 0; g < Gm::PPW; ++g) {
+                    const int it = base + g;
+                    if (it < n_items) s_S[it / Gm::IPP] = cadd(s_S[it / Gm::IPP], s_res[g]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+/* One work tile of one order-n integral: sum of fbar over 64*c lattice
+ * indices of one shift.  Returns the wave's sum (same bits in every lane). */
+template <int N>
+__device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
+{
+    using L = Lds<N>;
+    double *s_times = reinterpret_cast<double *>(lds + L::times);
+    double *s_w = reinterpret_cast<double *>(lds + L::w);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    const int lane = threadIdx.x;
+    const int s = (int)(tile / it.tiles_per_shift);
+    const uint32_t i0 = (uint32_t)(tile % it.tiles_per_shift) * (uint32_t)it.tile_len;
+    const double *sh = it.shifts + (int64_t)s * N;
+    double shift[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) shift[j] = sh[j];
+    Env env;
+    env.tab = it.tab; env.t_half = it.t_half; env.h = it.h; env.t_meas = it.t_meas;
+    env.g0 = cmk(it.g0x, it.g0y); env.n_grid = it.n_grid;
+    Kahan acc;
+    for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
+        const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
+        /* rank-1 lattice point, then u_m = u_{m-1} - v_m, v_m = -tau log(1-x_m) */
+        double u[N];
+        double prev = it.t_meas, p = 1.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const uint32_t m = (idx * it.z[j]) & it.mask;
+            double y = (double)m * it.inv_n + shift[j];
+            if (y >= 1.0) y -= 1.0;
+            const double v = -it.tau * log1p(-y);
+            u[j] = prev - v;
+            p *= exp(-(prev - u[j]) / it.tau);
+            prev = u[j];
+        }
+        const double W = it.tau_n / p;
+        const bool inside = u[N - 1] > 0.0;
+        if (it.mode != QQMC_MODE_CHARGE) {
+            if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * W, 0.0));
+            else if (inside) acc.add(cmk(W, 0.0));
+            continue;
+        }
+        const uint64_t mask = __ballot(inside);
+        const int cnt = __popcll(mask);
+        if (inside) {
+            const int rk = lane_rank(mask);
+#pragma unroll
+            for (int k = 0; k < N; ++k) s_times[rk * N + k] = u[N - 1 - k];
+            s_w[rk] = W;
+            s_S[rk] = cmk(0.0, 0.0);
+        }
+        __syncthreads();
+        keldysh_points<N>(cnt, env, lds);
+        if (lane < cnt) {
+            const cplx f = charge_prefactor<N>(s_S[lane]);
+            const double w = s_w[lane];
+            acc.add(cmk(f.x * w, f.y * w));
+        }
+        __syncthreads();
+    }
+    return wave_sum(acc.value());
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) order_kernel(ItemDesc it)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
+        const cplx v = order_tile<N>(it, tile, lds);
+        if (threadIdx.x == 0) {
+            it.tile_sums[2 * tile] = v.x;
+            it.tile_sums[2 * tile + 1] = v.y;
+        }
+    }
+}
+
+/* Per-shift sums of the tile partials, fixed order: thread j adds tiles
+ * j, j+256, ... (compensated), then a fixed tree over the 256 threads. */
+__global__ void __launch_bounds__(256) shift_reduce_kernel(const ItemDesc *items,
+                                                           const int64_t *shift_base,
+                                                           double *shift_sums)
+{
+    __shared__ double sx[256], sy[256];
+    const int item = blockIdx.y;
+    const ItemDesc &it = items[item];
+    const int s = blockIdx.x;
+    if (s >= it.n_shifts) return;
+    Kahan acc;
+    const int64_t t0 = (int64_t)s * it.tiles_per_shift;
+    for (int64_t t = threadIdx.x; t < it.tiles_per_shift; t += 256)
+        acc.add(cmk(it.tile_sums[2 * (t0 + t)], it.tile_sums[2 * (t0 + t) + 1]));
+    const cplx v = acc.value();
+    sx[threadIdx.x] = v.x;
+    sy[threadIdx.x] = v.y;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sx[threadIdx.x] += sx[threadIdx.x + w];
+            sy[threadIdx.x] += sy[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t o = shift_base[item] + s;
+        shift_sums[2 * o] = sx[0];
+        shift_sums[2 * o + 1] = sy[0];
+    }
+}
+
+/* Production-kernel evaluation at caller-given vertex times (tree method). */
+template <int N>
+__global__ void __launch_bounds__(64) points_tree_kernel(Env env, const double *u,
+                                                        int64_t n_points, double *f)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    using L = Lds<N>;
+    double *s_times = reinterpret_cast<double *>(lds + L::times);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    const int lane = threadIdx.x;
+    for (int64_t c0 = (int64_t)blockIdx.x * WAVE; c0 < n_points; c0 += (int64_t)gridDim.x * WAVE) {
+        const int64_t row = c0 + lane;
+        double ur[N];
+        bool ok = row < n_points;
+        if (ok) {
+            double prev = env.t_meas;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                ur[j] = u[row * N + j];
+                ok = ok && (ur[j] <= prev);
+                prev = ur[j];
+            }
+            ok = ok && ur[N - 1] >= 0.0;
+        }
+        const uint64_t mask = __ballot(ok);
+        const int cnt = __popcll(mask);
+        const int rk = lane_rank(mask);
+        if (ok) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) s_times[rk * N + k] = ur[N - 1 - k];
+            s_S[rk] = cmk(0.0, 0.0);
+        }
+        __syncthreads();
+        keldysh_points<N>(cnt, env, lds);
+        if (row < n_points) {
+            cplx v = cmk(__builtin_nan(""), __builtin_nan(""));
+            if (ok) v = charge_prefactor<N>(s_S[rk]);
+            f[2 * row] = v.x;
+            f[2 * row + 1] = v.y;
+        }
+        __syncthreads();
+    }
+}
+
+/* Direct enumeration (no shared elimination): for every index vector a,
+ * build the (n+1) x (n+1) Wick matrix in the paper's order (measurement
+ * first) from the 2x2 Keldysh rule with the actual time differences, and
+ * factorise it and its vertex block with partial pivoting.  One workgroup
+ * per point, index vectors spread over the 64 lanes. */
+template <int M>
+__device__ cplx det_pivoted(cplx (&a)[M][M], int m)
+{
+    cplx det = cmk(1.0, 0.0);
+    for (int k = 0; k < m; ++k) {
+        int piv = k;
+        double best = hypot(a[k][k].x, a[k][k].y);
+        for (int r = k + 1; r < m; ++r) {
+            const double v = hypot(a[r][k].x, a[r][k].y);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return cmk(0.0, 0.0);
+        if (piv != k) {
+            for (int c = 0; c < m; ++c) {
+                const cplx t = a[k][c];
+                a[k][c] = a[piv][c];
+                a[piv][c] = t;
+            }
+            det = cmk(-det.x, -det.y);
+        }
+        const cplx p = a[k][k];
+        det = cmul(det, p);
+        const cplx rp = crecip(p);
+        for (int r = k + 1; r < m; ++r) {
+            const cplx fct = cmul(a[r][k], rp);
+            for (int c = k + 1; c < m; ++c) a[r][c] = cfms(fct, a[k][c], a[r][c]);
+        }
+    }
+    return det;
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double *u,
+                                                          int64_t n_points, double *f)
+{
+    constexpr int NP1 = N + 1;
+    __shared__ pairv s_g[NP1 * NP1];
+    __shared__ double s_tm[NP1];
+    __shared__ double sx[WAVE], sy[WAVE];
+    const int lane = threadIdx.x;
+    for (int64_t pt = blockIdx.x; pt < n_points; pt += gridDim.x) {
+        if (lane == 0) s_tm[0] = env.t_meas;
+        if (lane < N) s_tm[lane + 1] = u[pt * N + lane];
+        __syncthreads();
+        for (int q = lane; q < NP1 * NP1; q += WAVE) {
+            const int r = q / NP1, c = q % NP1;
+            s_g[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, s_tm[r] - s_tm[c]);
+        }
+        __syncthreads();
+        Kahan acc;
+        for (int a = lane; a < (1 << N); a += WAVE) {
+            cplx up[NP1][NP1], dn[NP1][NP1];
+            for (int r = 0; r < NP1; ++r) {
+                for (int c = 0; c < NP1; ++c) {
+                    cplx v;
+                    if (r == c) {
+                        v = env.g0;
+                    } else {
+                        const int al = r == 0 ? 0 : (a >> (r - 1)) & 1;
+                        const int be = c == 0 ? 1 : (a >> (c - 1)) & 1;
+                        const double d = s_tm[r] - s_tm[c];
+                        const pairv g = s_g[r * NP1 + c];
+                        if (al == 0 && be == 0) v = d > 0.0 ? g.gg : g.gl;
+                        else if (al == 0) v = g.gl;
+                        else if (be == 0) v = g.gg;
+                        else v = d > 0.0 ? g.gl : g.gg;
+                    }
+                    up[r][c] = v;
+                    if (r > 0 && c > 0) dn[r - 1][c - 1] = v;
+                }
+            }
+            const cplx du = det_pivoted<NP1>(up, NP1);
+            const cplx dd = det_pivoted<NP1>(dn, N);
+            cplx term = cmul(du, dd);
+            if (__popc((unsigned)a) & 1) term = cmk(-term.x, -term.y);
+            acc.add(term);
+        }
+        const cplx v = acc.value();
+        sx[lane] = v.x;
+        sy[lane] = v.y;
+        __syncthreads();
+        for (int w = WAVE / 2; w > 0; w >>= 1) {
+            if (lane < w) {
+                sx[lane] += sx[lane + w];
+                sy[lane] += sy[lane + w];
+            }
+            __syncthreads();
+        }
+        if (lane == 0) {
+            const cplx out = charge_prefactor<N>(cmk(sx[0], sy[0]));
+            f[2 * pt] = out.x;
+            f[2 * pt + 1] = out.y;
+        }
+        __syncthreads();
+    }
+}
+
+/* Persistent batched kernel: workgroups take tiles from a shared list (most
+ * expensive first) through an atomic counter; each tile runs the same
+ * order_tile code as the single-order kernel, so per-tile sums are the same
+ * bits.  Every workgroup leaves the loop once the counter passes the end. */
+__global__ void __launch_bounds__(64) batch_kernel(const ItemDesc *items,
+                                                   const TileRef *tiles,
+                                                   int64_t n_tiles, int32_t *counter)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ int64_t s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t t = s_next;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const TileRef ref = tiles[t];
+        const ItemDesc &it = items[ref.item];
+        cplx v;
+        switch (it.order) {
+#define QQMC_CASE(NN) case NN: v = order_tile<NN>(it, ref.tile, lds); break;
+            QQMC_CASE(1) QQMC_CASE(2) QQMC_CASE(3) QQMC_CASE(4) QQMC_CASE(5)
+            QQMC_CASE(6) QQMC_CASE(7) QQMC_CASE(8) QQMC_CASE(9) QQMC_CASE(10)
+            QQMC_CASE(11) QQMC_CASE(12) QQMC_CASE(13) QQMC_CASE(14)
+#undef QQMC_CASE
+        default: v = cmk(0.0, 0.0); break;
+        }
+        if (threadIdx.x == 0) {
+            it.tile_sums[2 * ref.tile] = v.x;
+            it.tile_sums[2 * ref.tile + 1] = v.y;
+        }
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <template <int> class F, typename... A>
+hipError_t dispatch(int order, A... args)
+{
+    switch (order) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 9: return F<9>::run(args...);
+    case 10: return F<10>::run(args...);
+    case 11: return F<11>::run(args...);
+    case 12: return F<12>::run(args...);
+    case 13: return F<13>::run(args...);
+    case 14: return F<14>::run(args...);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N> struct OrderLaunch {
+    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    {
+        const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
+        hipLaunchKernelGGL(order_kernel<N>, dim3((unsigned)blocks), dim3(64),
+                           Lds<N>::bytes, s, it);
+        return hipGetLastError();
+    }
+};
+
+template <int N> struct LdsSize {
+    static hipError_t run(int32_t *out)
+    {
+        *out = Lds<N>::bytes;
+        return hipSuccess;
+    }
+};
+
+template <int N> struct TreePointsLaunch {
+    static hipError_t run(Env env, const double *u, int64_t n_points, double *f,
+                          hipStream_t s)
+    {
+        int64_t blocks = (n_points + WAVE - 1) / WAVE;
+        if (blocks > 65536) blocks = 65536;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(points_tree_kernel<N>, dim3((unsigned)blocks), dim3(64),
+                           Lds<N>::bytes, s, env, u, n_points, f);
+        return hipGetLastError();
+    }
+};
+
+template <int N> struct DirectPointsLaunch {
+    static hipError_t run(Env env, const double *u, int64_t n_points, double *f,
+                          hipStream_t s)
+    {
+        int64_t blocks = n_points < 65536 ? n_points : 65536;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(points_direct_kernel<N>, dim3((unsigned)blocks), dim3(64), 0, s,
+                           env, u, n_points, f);
+        return hipGetLastError();
+    }
+};
+
+Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double g0y,
+             double t_meas)
+{
+    Env e;
+    e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.h = h; e.t_meas = t_meas;
+    e.g0 = cmk(0.0, g0y);
+    return e;
+}
+
+} // namespace
+
+int32_t batch_blocks_per_cu(int32_t lds_bytes)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel, 64, (size_t)lds_bytes) !=
+        hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+int32_t lds_bytes_for_order(int32_t order)
+{
+    int32_t b = 0;
+    if (dispatch<LdsSize>(order, &b) != hipSuccess) return -1;
+    return b;
+}
+
+int32_t batch_lds_bytes(int32_t max_order)
+{
+    int32_t m = 0;
+    for (int n = 1; n <= max_order; ++n) {
+        const int32_t b = lds_bytes_for_order(n);
+        if (b > m) m = b;
+    }
+    return m;
+}
+
+hipError_t launch_order(const ItemDesc &it, hipStream_t s)
+{
+    return dispatch<OrderLaunch>(it.order, it, s);
+}
+
+hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
+                               const int64_t *shift_base_dev, double *shift_sums,
+                               int32_t max_shifts, hipStream_t s)
+{
+    hipLaunchKernelGGL(shift_reduce_kernel, dim3((unsigned)max_shifts, (unsigned)n_items),
+                       dim3(256), 0, s, items_dev, shift_base_dev, shift_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half, double h,
+                              double g0y, int32_t order, double t_meas, const double *u,
+                              int64_t n_points, double *f, hipStream_t s)
+{
+    if (n_points <= 0) return hipSuccess;
+    return dispatch<TreePointsLaunch>(order, make_env(tab, n_grid, t_half, h, g0y, t_meas),
+                                      u, n_points, f, s);
+}
+
+hipError_t launch_points_direct(const double *tab, int32_t n_grid, double t_half,
+                                double h, double g0y, int32_t order, double t_meas,
+                                const double *u, int64_t n_points, double *f,
+                                hipStream_t s)
+{
+    if (n_points <= 0) return hipSuccess;
+    return dispatch<DirectPointsLaunch>(order, make_env(tab, n_grid, t_half, h, g0y, t_meas),
+                                        u, n_points, f, s);
+}
+
+hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
+                        int32_t *counter_dev, int32_t grid_blocks, int32_t lds_bytes,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid_blocks), dim3(64),
+                       (unsigned)lds_bytes, s, items_dev, tiles_dev, n_tiles, counter_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256),
+                       0, s, p, v, n);
+    return hipGetLastError();
+}
+
+} // namespace qqmc

@@ -1,0 +1,358 @@
+/*
+ * qqmc_plan.cpp -- batched form: many (parameter point, order) integrals in
+ * one persistent launch, captured in a HIP graph.
+ *
+ * Every item is cut into the same tiles qqmc_eval_order would use for the
+ * same tile length, so each tile sum, and therefore each per-shift sum, is
+ * bitwise the one the single-order launch produces.  The tiles of all items
+ * are listed most expensive first (cost model below) and handed out to a
+ * fixed set of resident workgroups through an atomic counter, which balances
+ * the very uneven per-item work (2^n index vectors per point, 2^16..2^22
+ * points per item).
+ *
+ * The tile length and the number of resident workgroups are chosen by a
+ * small autotuner when the caller passes 0: each candidate is timed on a
+ * subsample of the tile list (every k-th tile) and the fastest per point is
+ * kept.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "qqmc_internal.h"
+
+namespace qqmc {
+
+namespace {
+
+/* Probability that the warped point lies in the domain: sum of n
+ * exponential(1/tau) spacings below t, i.e. the regularised lower incomplete
+ * gamma function P(n, t/tau) (series). */
+double inside_fraction(int n, double t_over_tau)
+{
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 400; ++k) {
+        term *= t_over_tau / (n + k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    double lg = std::lgamma((double)n + 1.0);
+    return std::exp(n * std::log(t_over_tau) - t_over_tau - lg) * sum;
+}
+
+/* Relative cost of one tile: warp for every point, the Keldysh sum (about
+ * 12 complex multiply-adds per index vector plus O(n^2) setup) for the
+ * points inside the domain. */
+double tile_cost(const ItemDesc &d)
+{
+    const double frac = d.mode == QQMC_MODE_CHARGE ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;
+    const double per_point = 8.0 * d.order + frac * (48.0 * std::ldexp(1.0, d.order) + 30.0 * d.order * d.order);
+    return per_point * d.tile_len;
+}
+
+struct Buffers {
+    double *shifts = nullptr, *tile_sums = nullptr, *shift_sums = nullptr;
+    ItemDesc *items = nullptr;
+    int64_t *base = nullptr;
+    TileRef *tiles = nullptr;
+    int32_t *counter = nullptr;
+    void release()
+    {
+        if (shifts) hipFree(shifts);
+        if (tile_sums) hipFree(tile_sums);
+        if (shift_sums) hipFree(shift_sums);
+        if (items) hipFree(items);
+        if (base) hipFree(base);
+        if (tiles) hipFree(tiles);
+        if (counter) hipFree(counter);
+        *this = Buffers();
+    }
+};
+
+} // namespace
+
+} // namespace qqmc
+
+struct qqmc_plan_s {
+    std::vector<qqmc::ItemDesc> items;   /* device pointers filled in */
+    std::vector<std::vector<double>> shifts;
+    std::vector<int64_t> shift_base;
+    std::vector<double> inv_n;
+    std::vector<qqmc::TileRef> tiles;
+    qqmc::Buffers buf;
+    int64_t n_tiles = 0, n_points = 0, total_shifts = 0;
+    int32_t tile_len = 0, grid_blocks = 0, lds_bytes = 0, max_shifts = 0, max_order = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+
+    void drop_graph()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~qqmc_plan_s()
+    {
+        drop_graph();
+        buf.release();
+        if (cap) hipStreamDestroy(cap);
+    }
+};
+
+namespace qqmc {
+namespace {
+
+/* Lays out tiles for tile length `tl` and (re)allocates the device buffers. */
+qqmc_status layout(qqmc_plan_s *p, int32_t tl)
+{
+    p->buf.release();
+    p->tile_len = tl;
+    p->tiles.clear();
+    int64_t tile_off = 0;
+    std::vector<std::pair<double, TileRef>> order;
+    for (size_t i = 0; i < p->items.size(); ++i) {
+        ItemDesc &d = p->items[i];
+        const int64_t N = (int64_t)d.mask + 1;
+        d.tile_len = tl < N ? tl : (int32_t)N;
+        d.tiles_per_shift = (int32_t)(N / d.tile_len);
+        d.n_tiles = (int64_t)d.tiles_per_shift * d.n_shifts;
+        const double c = tile_cost(d);
+        for (int64_t t = 0; t < d.n_tiles; ++t) {
+            TileRef r;
+            r.item = (int32_t)i;
+            r.pad = 0;
+            r.tile = t;
+            order.push_back({c, r});
+        }
+        tile_off += d.n_tiles;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto &a, const auto &b) { return a.first > b.first; });
+    for (auto &o : order) p->tiles.push_back(o.second);
+    p->n_tiles = (int64_t)p->tiles.size();
+
+    size_t n_shift_vals = 0;
+    for (auto &s : p->shifts) n_shift_vals += s.size();
+    hipError_t e = hipMalloc(&p->buf.shifts, sizeof(double) * (n_shift_vals ? n_shift_vals : 1));
+    if (e == hipSuccess) e = hipMalloc(&p->buf.tile_sums, sizeof(double) * 2 * (tile_off ? tile_off : 1));
+    if (e == hipSuccess) e = hipMalloc(&p->buf.shift_sums, sizeof(double) * 2 * p->total_shifts);
+    if (e == hipSuccess) e = hipMalloc(&p->buf.items, sizeof(ItemDesc) * p->items.size());
+    if (e == hipSuccess) e = hipMalloc(&p->buf.base, sizeof(int64_t) * p->items.size());
+    if (e == hipSuccess) e = hipMalloc(&p->buf.tiles, sizeof(TileRef) * (p->n_tiles ? p->n_tiles : 1));
+    if (e == hipSuccess) e = hipMalloc(&p->buf.counter, sizeof(int32_t));
+    if (e != hipSuccess) {
+        p->buf.release();
+        return hip_error(e, "plan buffers");
+    }
+    size_t so = 0;
+    int64_t to = 0;
+    for (size_t i = 0; i < p->items.size(); ++i) {
+        ItemDesc &d = p->items[i];
+        e = hipMemcpy(p->buf.shifts + so, p->shifts[i].data(), sizeof(double) * p->shifts[i].size(),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_error(e, "plan upload");
+        d.shifts = p->buf.shifts + so;
+        d.tile_sums = p->buf.tile_sums + 2 * to;
+        so += p->shifts[i].size();
+        to += d.n_tiles;
+    }
+    e = hipMemcpy(p->buf.items, p->items.data(), sizeof(ItemDesc) * p->items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->buf.base, p->shift_base.data(), sizeof(int64_t) * p->items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->n_tiles)
+        e = hipMemcpy(p->buf.tiles, p->tiles.data(), sizeof(TileRef) * p->n_tiles, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "plan upload");
+    return QQMC_OK;
+}
+
+hipError_t enqueue(qqmc_plan_s *p, const TileRef *tiles, int64_t n_tiles, int32_t grid, hipStream_t s)
+{
+    hipError_t e = launch_fill_i32(p->buf.counter, 0, 1, s);
+    if (e == hipSuccess) e = launch_batch(p->buf.items, tiles, n_tiles, p->buf.counter, grid, p->lds_bytes, s);
+    if (e == hipSuccess)
+        e = launch_shift_reduce(p->buf.items, (int32_t)p->items.size(), p->buf.base, p->buf.shift_sums,
+                                p->max_shifts, s);
+    return e;
+}
+
+qqmc_status capture(qqmc_plan_s *p)
+{
+    p->drop_graph();
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    hipError_t le = enqueue(p, p->buf.tiles, p->n_tiles, p->grid_blocks, p->cap);
+    e = hipStreamEndCapture(p->cap, &p->graph);
+    if (le != hipSuccess) return hip_error(le, "plan capture launch");
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
+    return QQMC_OK;
+}
+
+/* Times the plan on every k-th tile with `grid` workgroups; seconds per
+ * lattice point of the subsample. */
+double probe(qqmc_plan_s *p, int32_t grid)
+{
+    const int64_t want = 4096;
+    const int64_t step = p->n_tiles > want ? p->n_tiles / want : 1;
+    std::vector<TileRef> sub;
+    double pts = 0.0;
+    for (int64_t t = 0; t < p->n_tiles; t += step) {
+        sub.push_back(p->tiles[t]);
+        pts += p->items[p->tiles[t].item].tile_len;
+    }
+    TileRef *d_sub = nullptr;
+    if (hipMalloc(&d_sub, sizeof(TileRef) * sub.size()) != hipSuccess) return 1e30;
+    hipMemcpy(d_sub, sub.data(), sizeof(TileRef) * sub.size(), hipMemcpyHostToDevice);
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    double best = 1e30;
+    for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(a, p->cap);
+        hipError_t e = enqueue(p, d_sub, (int64_t)sub.size(), grid, p->cap);
+        hipEventRecord(b, p->cap);
+        hipStreamSynchronize(p->cap);
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && rep > 0) best = std::min(best, (double)ms * 1e-3 / pts);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipFree(d_sub);
+    return best;
+}
+
+} // namespace
+} // namespace qqmc
+
+using namespace qqmc;
+
+extern "C" {
+
+qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int32_t tile_len,
+                             int32_t grid_blocks, void *stream, qqmc_plan *out)
+{
+    (void)stream;
+    if (!items || n_items < 1 || !out) return set_error(QQMC_EINVAL, "no items");
+    if (tile_len != 0 && (tile_len < 64 || tile_len % 64 != 0 || (tile_len & (tile_len - 1)) != 0))
+        return set_error(QQMC_EINVAL, "tile_len must be 0 or a power of two >= 64");
+    if (grid_blocks < 0) return set_error(QQMC_EINVAL, "grid_blocks < 0");
+    auto *p = new (std::nothrow) qqmc_plan_s();
+    if (!p) return set_error(QQMC_ENOMEM, "host allocation failed");
+    hipGetDevice(&p->device);
+    int64_t sb = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        if (qqmc_status st = check_tables(items[i].tables)) {
+            delete p;
+            return st;
+        }
+        Validated v;
+        if (qqmc_status st = validate_order(&items[i].order, items[i].tables->n_grid,
+                                            items[i].tables->t_half, &v)) {
+            delete p;
+            return set_error(st, "item " + std::to_string(i) + ": " + qqmc_last_error());
+        }
+        fill_item_tables(v.desc, items[i].tables);
+        p->items.push_back(v.desc);
+        p->shifts.push_back(v.shifts);
+        p->shift_base.push_back(sb);
+        p->inv_n.push_back(v.desc.inv_n);
+        sb += v.desc.n_shifts;
+        p->max_shifts = std::max(p->max_shifts, v.desc.n_shifts);
+        p->max_order = std::max(p->max_order, v.desc.order);
+        p->n_points += (int64_t)(v.desc.mask + 1) * v.desc.n_shifts;
+    }
+    p->total_shifts = sb;
+    p->lds_bytes = batch_lds_bytes(p->max_order);
+    hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_error(e, "hipStreamCreate");
+    }
+    hipDeviceProp_t prop;
+    hipGetDeviceProperties(&prop, p->device);
+    const int32_t occ = batch_blocks_per_cu(p->lds_bytes);
+    const int32_t full = prop.multiProcessorCount * occ;
+
+    std::vector<int32_t> tls = tile_len ? std::vector<int32_t>{tile_len}
+                                        : std::vector<int32_t>{256, 512, 1024, 2048};
+    std::vector<int32_t> grids = grid_blocks ? std::vector<int32_t>{grid_blocks}
+                                             : std::vector<int32_t>{full, full / 2 > 0 ? full / 2 : 1};
+    int32_t best_tl = tls[0], best_grid = grids[0];
+    if (tls.size() * grids.size() > 1) {
+        double best = 1e30;
+        for (int32_t tl : tls) {
+            if (qqmc_status st = layout(p, tl)) {
+                delete p;
+                return st;
+            }
+            for (int32_t g : grids) {
+                const double v = probe(p, g);
+                if (v < best) {
+                    best = v;
+                    best_tl = tl;
+                    best_grid = g;
+                }
+            }
+        }
+    }
+    p->grid_blocks = best_grid;
+    if (qqmc_status st = layout(p, best_tl)) {
+        delete p;
+        return st;
+    }
+    if (qqmc_status st = capture(p)) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_plan_run(qqmc_plan p, void *stream)
+{
+    if (!p || !p->exec) return set_error(QQMC_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_plan_results(qqmc_plan p, void *stream, double *q_shift)
+{
+    if (!p || !q_shift) return set_error(QQMC_EINVAL, "NULL argument");
+    std::vector<double> sums(2 * (size_t)p->total_shifts);
+    hipError_t e = hipMemcpyAsync(sums.data(), p->buf.shift_sums, sizeof(double) * sums.size(),
+                                  hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "plan results");
+    for (size_t i = 0; i < p->items.size(); ++i) {
+        const int64_t b = p->shift_base[i];
+        for (int32_t s = 0; s < p->items[i].n_shifts; ++s) {
+            q_shift[2 * (b + s)] = sums[2 * (b + s)] * p->inv_n[i];
+            q_shift[2 * (b + s) + 1] = sums[2 * (b + s) + 1] * p->inv_n[i];
+        }
+    }
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_plan_info(qqmc_plan p, int64_t *n_tiles, int64_t *n_points, int32_t *tile_len,
+                           int32_t *grid_blocks)
+{
+    if (!p) return set_error(QQMC_EINVAL, "plan is NULL");
+    if (n_tiles) *n_tiles = p->n_tiles;
+    if (n_points) *n_points = p->n_points;
+    if (tile_len) *tile_len = p->tile_len;
+    if (grid_blocks) *grid_blocks = p->grid_blocks;
+    return QQMC_OK;
+}
+
+void qqmc_plan_destroy(qqmc_plan p) { delete p; }
+
+} // extern "C"

@@ -1,0 +1,257 @@
+/*
+ * qqmc_tree.h -- per-lane arithmetic of the Keldysh sum (Eq. (integral_gf)).
+ *
+ * The sum S(u) = sum_a (-1)^{|a|} det_up(a) det_dn(a) runs over the 2^n
+ * Keldysh index vectors a.  With the vertices ordered by time, earliest first,
+ * and the measurement point last, the 2x2 Keldysh rule of App. E makes every
+ * off-diagonal Wick entry depend only on the index of the EARLIER of its two
+ * points (for u_k > u_l the first argument is later and
+ * [[g^T, g^<],[g^>, g^Tbar]] collapses to g^> for a_l = 0 and g^< for
+ * a_l = 1, whatever a_k).  Hence
+ *   - eliminating the points in time order without pivoting, the pivot of
+ *     step k and every Schur-complement correction carried past step k depend
+ *     only on a_0..a_k, so the 2^n determinants share their elimination
+ *     prefixes: a depth-first walk over a binary tree whose level-k node
+ *     holds the trailing Schur complement after k steps does the work of all
+ *     2^n factorisations with one rank-1 update per tree edge (about twelve
+ *     complex multiply-adds per index vector instead of ~n^3);
+ *   - the n x n spin-down block is the leading block of the (n+1) x (n+1)
+ *     spin-up matrix, so det_dn is the product of the first n pivots and
+ *     det_up = det_dn * (last pivot);
+ *   - the last vertex's two indices differ only in the measurement pivot,
+ *     which gives the pair of leaves in closed form (no reciprocal).
+ * Off-diagonal entries: for points i earlier than j with tau = t_j - t_i > 0,
+ *     entry (i, j) = a_i ? g^>(-tau) : g^<(-tau) = -conj(a_i ? g^> : g^<)(tau)
+ *     entry (j, i) = a_i ? g^<(tau)  : g^>(tau);
+ * diagonal entries are g^<(0) = i n_sigma.  The measurement point is the
+ * latest point, so its own indices (0 as a row, 1 as a column) never enter.
+ *
+ * Work split across the lanes of one work item (G = 2^T lanes):
+ *   block  K x K trailing block the lanes start from (K = min(n, 8) + 1,
+ *          with the first n + 1 - K eliminations done cooperatively before);
+ *   path   T levels eliminated per lane, left-looking, for the lane's own
+ *          index prefix (lane number within the item);
+ *   tree   the remaining B = K - 1 - T <= 4 levels walked depth first with
+ *          the Schur complements held in registers.
+ * Everything here is straight-line code for a compile-time order n.
+ */
+#ifndef QQMC_TREE_H
+#define QQMC_TREE_H
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define QQMC_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>
+#define QQMC_HD inline
+#endif
+
+namespace qqmc {
+
+struct cplx {
+    double x, y;
+};
+
+QQMC_HD cplx cmk(double x, double y) { cplx r; r.x = x; r.y = y; return r; }
+QQMC_HD cplx cadd(cplx a, cplx b) { return cmk(a.x + b.x, a.y + b.y); }
+QQMC_HD cplx csub(cplx a, cplx b) { return cmk(a.x - b.x, a.y - b.y); }
+QQMC_HD cplx cmul(cplx a, cplx b)
+{
+    return cmk(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+/* c + a*b */
+QQMC_HD cplx cfma(cplx a, cplx b, cplx c)
+{
+    return cmk(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+/* c - a*b */
+QQMC_HD cplx cfms(cplx a, cplx b, cplx c)
+{
+    return cmk(fma(-a.x, b.x, fma(a.y, b.y, c.x)), fma(-a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+/* -conj(a) */
+QQMC_HD cplx cnc(cplx a) { return cmk(-a.x, a.y); }
+QQMC_HD cplx crecip(cplx a)
+{
+    double d = 1.0 / fma(a.x, a.x, a.y * a.y);
+    return cmk(a.x * d, -a.y * d);
+}
+QQMC_HD cplx csel(int b, cplx one, cplx zero) { return b ? one : zero; }
+
+/* g^<(tau), g^>(tau) for a pair of points, tau = later - earlier > 0 */
+struct pairv {
+    cplx gl, gg;
+};
+
+/* index of the pair (i, j), i < j, in the triangular pair table */
+QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
+
+/* distance, in pairs, from pair (i, i+1) to pair (i, i+d) */
+template <int I> QQMC_HD constexpr int pidx_step(int d) { return pidx(I, I + d) - pidx(I, I + 1); }
+
+template <int N> struct Geo {
+    static constexpr int K = (N < 8 ? N : 8) + 1;      /* block size          */
+    static constexpr int OFF = N + 1 - K;              /* cooperative levels  */
+    static constexpr int T = (K - 1 > 4) ? K - 5 : 0;  /* per-lane path       */
+    static constexpr int G = 1 << T;                   /* lanes per item      */
+    static constexpr int PPW = 64 / G;                 /* items per wave      */
+    static constexpr int IPP = 1 << OFF;               /* items per point     */
+    static constexpr int NP = N * (N + 1) / 2;         /* pair-table length   */
+};
+
+template <int M> struct Blk {
+    cplx v[M][M];
+};
+
+/* Depth-first walk below block level L (block indices L..K-1 remain).  C is
+ * the accumulated Schur correction of the trailing block, so the current
+ * trailing matrix is (Wick entries) - C.  prod = product of the pivots
+ * eliminated so far, sgn = parity of the indices fixed so far. */
+template <int N, int L>
+QQMC_HD void subtree(const Blk<Geo<N>::K - L> &C, cplx prod, int sgn,
+                     const pairv *pr, cplx g0, cplx &acc)
+{
+    constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
+    const cplx p = csub(g0, C.v[0][0]);
+    if constexpr (M == 2) {
+        /* latest vertex and the measurement: the two leaves differ only in
+         * the last pivot g0 - C11 - col_b row_b / p, so
+         * sum_b (-1)^b dn_b up_b = prod^2 p (col_1 row_1 - col_0 row_0). */
+        const pairv P = pr[pidx(OFF + L, N)];
+        const cplx col0 = csub(P.gg, C.v[1][0]), row0 = csub(cnc(P.gl), C.v[0][1]);
+        const cplx col1 = csub(P.gl, C.v[1][0]), row1 = csub(cnc(P.gg), C.v[0][1]);
+        const cplx d = cfms(col0, row0, cmul(col1, row1));
+        const cplx term = cmul(cmul(cmul(prod, prod), p), d);
+        acc = sgn ? csub(acc, term) : cadd(acc, term);
+    } else {
+        const cplx r = crecip(p);
+        const cplx np = cmul(prod, p);
+        /* pair (L, L+i) holds (g^<, g^>) as two consecutive cplx: the column
+         * entry for index b is element 1-b, the row entry -conj(element b) */
+        const cplx *base = &pr[pidx(OFF + L, OFF + L + 1)].gl;
+#pragma unroll 1
+        for (int b = 0; b < 2; ++b) {
+            Blk<M - 1> D;
+            cplx rowv[M - 1];
+#pragma unroll
+            for (int j = 1; j < M; ++j)
+                rowv[j - 1] = csub(cnc(base[2 * pidx_step<OFF + L>(j) + b]), C.v[0][j]);
+#pragma unroll
+            for (int i = 1; i < M; ++i) {
+                const cplx ch = cmul(csub(base[2 * pidx_step<OFF + L>(i) + 1 - b], C.v[i][0]), r);
+#pragma unroll
+                for (int j = 1; j < M; ++j) D.v[i - 1][j - 1] = cfma(ch, rowv[j - 1], C.v[i][j]);
+            }
+            subtree<N, L + 1>(D, np, sgn ^ b, pr, g0, acc);
+        }
+    }
+}
+
+/* Block correction accessor: zero when the lanes start from the full matrix
+ * (n <= 8), otherwise the cooperative block in local memory. */
+template <int N> struct BlockSrc {
+    const cplx *c; /* K*K row-major, or unused */
+    QQMC_HD cplx at(int i, int j) const
+    {
+        if constexpr (Geo<N>::OFF == 0) {
+            (void)i; (void)j;
+            return cmk(0.0, 0.0);
+        } else {
+            return c[i * Geo<N>::K + j];
+        }
+    }
+};
+
+/* One lane's share of an item: index prefix `pre` (T bits, most significant
+ * bit = earliest block level), starting block correction C0, product of the
+ * pivots eliminated before the block, parity of the indices fixed before.
+ * Returns the signed sum over the lane's 2^B index vectors. */
+template <int N>
+QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
+                      int sgn, cplx g0)
+{
+    constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, T = Geo<N>::T;
+    cplx acc = cmk(0.0, 0.0);
+    if constexpr (T == 0) {
+        (void)pre;
+        Blk<K> C;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
+        subtree<N, 0>(C, prod, sgn, pr, g0, acc);
+    } else {
+        cplx chat[T][K], rowv[T][K];
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            const int b = (pre >> (T - 1 - k)) & 1;
+            sgn ^= b;
+            cplx pk = csub(g0, C0.at(k, k));
+#pragma unroll
+            for (int l = 0; l < k; ++l) pk = cfms(chat[l][k], rowv[l][k], pk);
+            const cplx r = crecip(pk);
+#pragma unroll
+            for (int i = k + 1; i < K; ++i) {
+                const pairv P = pr[pidx(OFF + k, OFF + i)];
+                cplx col = csub(csel(b, P.gl, P.gg), C0.at(i, k));
+                cplx row = csub(cnc(csel(b, P.gg, P.gl)), C0.at(k, i));
+#pragma unroll
+                for (int l = 0; l < k; ++l) {
+                    col = cfms(chat[l][i], rowv[l][k], col);
+                    row = cfms(chat[l][k], rowv[l][i], row);
+                }
+                chat[k][i] = cmul(col, r);
+                rowv[k][i] = row;
+            }
+            prod = cmul(prod, pk);
+        }
+        Blk<K - T> C;
+#pragma unroll
+        for (int i = T; i < K; ++i)
+#pragma unroll
+            for (int j = T; j < K; ++j) {
+                cplx c = C0.at(i, j);
+#pragma unroll
+                for (int l = 0; l < T; ++l) c = cfma(chat[l][i], rowv[l][j], c);
+                C.v[i - T][j - T] = c;
+            }
+        subtree<N, T>(C, prod, sgn, pr, g0, acc);
+    }
+    return acc;
+}
+
+/* Wick entry (i, j), i != j, of global elimination indices for index b of
+ * the earlier point min(i, j). */
+QQMC_HD cplx wick_entry(const pairv *pr, int i, int j, int b)
+{
+    if (i < j) {
+        const pairv P = pr[pidx(i, j)];
+        return cnc(csel(b, P.gg, P.gl));
+    }
+    const pairv P = pr[pidx(j, i)];
+    return csel(b, P.gl, P.gg);
+}
+
+/* Linear interpolation on the uniform grid tau_j = -t_half + j h (index and
+ * fraction clamped, so values outside the grid hold the end values).  The
+ * table stores (g^<, g^>) per node as four doubles. */
+QQMC_HD pairv interp_pair(const double *tab, int n_grid, double t_half, double h,
+                          double tau)
+{
+    const double s = (tau + t_half) / h;
+    long j = (long)floor(s);
+    if (j < 0) j = 0;
+    if (j > n_grid - 2) j = n_grid - 2;
+    double phi = s - (double)j;
+    if (phi < 0.0) phi = 0.0;
+    if (phi > 1.0) phi = 1.0;
+    const double q = 1.0 - phi;
+    const double *a = tab + 4 * j;
+    pairv r;
+    r.gl = cmk(q * a[0] + phi * a[4], q * a[1] + phi * a[5]);
+    r.gg = cmk(q * a[2] + phi * a[6], q * a[3] + phi * a[7]);
+    return r;
+}
+
+} // namespace qqmc
+#endif

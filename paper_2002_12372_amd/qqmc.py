@@ -1,0 +1,303 @@
+"""Python binding of libqqmc (argument marshalling only).
+
+Every function wraps the C entry point of the same name in ``include/qqmc.h``;
+all arithmetic runs in the library's HIP kernels.  PyTorch supplies device
+buffers (``tensor.data_ptr()``) and streams (``torch.cuda.current_stream()``)
+and nothing else.  Importing this module does not build anything: if
+``libqqmc.so`` is missing the first call raises, it never falls back to
+other code.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqqmc.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, EDEVICE, EADMIT, ENOTICKET = -1, -2, -3, -4, -5
+MODE_CHARGE, MODE_MODEL, MODE_CONSTANT = 0, 1, 2
+METHOD_TREE, METHOD_DIRECT = 0, 1
+MAX_ORDER = 14
+
+
+class QQMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("qqmc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class qqmc_dot(ctypes.Structure):
+    _fields_ = [("eps_d", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("beta", ctypes.c_double), ("bias_v", ctypes.c_double),
+                ("t_half", ctypes.c_double), ("n_grid", ctypes.c_int32)]
+
+
+class qqmc_order(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("log2_n", ctypes.c_int32),
+                ("lattice_a", ctypes.c_uint64), ("n_shifts", ctypes.c_int32),
+                ("shifts", ctypes.POINTER(ctypes.c_double)),
+                ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
+                ("mode", ctypes.c_int32)]
+
+
+class qqmc_batch_item(ctypes.Structure):
+    _fields_ = [("tables", ctypes.c_void_p), ("order", qqmc_order)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported symbol of include/qqmc.h
+_P = ctypes.POINTER
+_d, _i32, _i64, _u64, _vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.c_uint64, ctypes.c_void_p)
+_PD = _P(ctypes.c_double)
+SIGNATURES = [
+    ("qqmc_make_tables", _i32, [_P(qqmc_dot), _vp, _P(_vp)]),
+    ("qqmc_tables_from_host", _i32, [_PD, _PD, _i32, _d, _d, _vp, _P(_vp)]),
+    ("qqmc_tables_export", _i32, [_vp, _PD, _PD, _PD]),
+    ("qqmc_tables_info", _i32, [_vp, _P(_i32), _PD]),
+    ("qqmc_free_tables", None, [_vp]),
+    ("qqmc_eval_order", _i32, [_vp, _P(qqmc_order), _vp, _PD, _PD, _PD]),
+    ("qqmc_eval_order_async", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _vp, _P(_i64)]),
+    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _vp, _i64, _i32, _vp, _vp]),
+    ("qqmc_plan_create", _i32, [_P(qqmc_batch_item), _i32, _i32, _i32, _vp, _P(_vp)]),
+    ("qqmc_plan_run", _i32, [_vp, _vp]),
+    ("qqmc_plan_results", _i32, [_vp, _vp, _PD]),
+    ("qqmc_plan_info", _i32, [_vp, _P(_i64), _P(_i64), _P(_i32), _P(_i32)]),
+    ("qqmc_plan_destroy", None, [_vp]),
+    ("qqmc_server_create", _i32, [ctypes.c_size_t, _i32, _i32, _P(_vp)]),
+    ("qqmc_submit", _i32, [_vp, _P(qqmc_dot), _P(qqmc_order), _P(_u64)]),
+    ("qqmc_poll", _i32, [_vp, _u64, _PD, _PD, _PD, _PD, _PD]),
+    ("qqmc_server_now", _d, [_vp]),
+    ("qqmc_server_drain", _i32, [_vp]),
+    ("qqmc_server_destroy", None, [_vp]),
+    ("qqmc_last_error", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libqqmc.so is not built (run __graft_entry__.build())")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def last_error():
+    return lib().qqmc_last_error().decode()
+
+
+def _check(st):
+    if st < 0:
+        raise QQMCError(st, last_error())
+    return st
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _pd(a):
+    return a.ctypes.data_as(_PD)
+
+
+class Tables:
+    """Owning wrapper of a qqmc_tables handle."""
+
+    def __init__(self, handle, n_grid, t_half):
+        self.handle = ctypes.c_void_p(handle)
+        self.n_grid, self.t_half = n_grid, t_half
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.qqmc_free_tables(self.handle)
+            self.handle = None
+
+
+def make_dot(d):
+    return qqmc_dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_half, d.n_grid)
+
+
+def make_tables(dot, stream=None):
+    """dot: qqmc_inputs.Dot (or anything with the same fields)."""
+    h = ctypes.c_void_p()
+    cd = make_dot(dot)
+    _check(lib().qqmc_make_tables(ctypes.byref(cd), _stream(stream), ctypes.byref(h)))
+    return Tables(h.value, dot.n_grid, dot.t_half)
+
+
+def tables_from_host(gl, gg, n_grid, t_half, n_sigma, stream=None):
+    gl = np.ascontiguousarray(gl, dtype=np.float64)
+    gg = np.ascontiguousarray(gg, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().qqmc_tables_from_host(_pd(gl), _pd(gg), int(n_grid), float(t_half),
+                                       float(n_sigma), _stream(stream), ctypes.byref(h)))
+    return Tables(h.value, n_grid, t_half)
+
+
+def tables_export(tables):
+    gl = np.zeros(2 * tables.n_grid)
+    gg = np.zeros(2 * tables.n_grid)
+    ns = ctypes.c_double()
+    _check(lib().qqmc_tables_export(tables.handle, _pd(gl), _pd(gg), ctypes.byref(ns)))
+    return gl, gg, ns.value
+
+
+def make_order(job, t_meas):
+    """job: qqmc_inputs.OrderJob.  The returned struct keeps the shift array
+    alive through the attribute ``_keep``."""
+    sh = np.ascontiguousarray(job.shifts, dtype=np.float64)
+    o = qqmc_order(job.order, job.log2_n, job.lattice_a, sh.shape[0], _pd(sh),
+                   job.model_tau, t_meas, job.mode)
+    o._keep = sh
+    return o
+
+
+def eval_order(tables, job, t_meas, stream=None):
+    """(q_shift complex[K], q_mean complex, q_stderr float)."""
+    o = make_order(job, t_meas)
+    K = o.n_shifts
+    q = np.zeros(2 * K)
+    m = np.zeros(2)
+    se = ctypes.c_double()
+    _check(lib().qqmc_eval_order(tables.handle, ctypes.byref(o), _stream(stream), _pd(q),
+                                 _pd(m), ctypes.byref(se)))
+    return q[0::2] + 1j * q[1::2], m[0] + 1j * m[1], se.value
+
+
+def eval_order_async(tables, job, t_meas, shift_sums, tile_sums=None, tile_len=0, stream=None):
+    """shift_sums / tile_sums: float64 CUDA tensors (2*K, 2*n_tiles)."""
+    o = make_order(job, t_meas)
+    nt = ctypes.c_int64()
+    _check(lib().qqmc_eval_order_async(
+        tables.handle, ctypes.byref(o), int(tile_len), _stream(stream),
+        ctypes.c_void_p(tile_sums.data_ptr() if tile_sums is not None else 0),
+        ctypes.c_void_p(shift_sums.data_ptr()), ctypes.byref(nt)))
+    return nt.value
+
+
+def n_tiles(job, tile_len):
+    return job.shifts.shape[0] * ((1 << job.log2_n) // tile_len)
+
+
+def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None):
+    """u: (P, order) float64 CUDA tensor; f: (P, 2) float64 CUDA tensor."""
+    P = u.shape[0]
+    assert u.dtype.is_floating_point and u.is_contiguous() and f.is_contiguous()
+    assert f.numel() >= 2 * P and u.numel() == P * order
+    _check(lib().qqmc_eval_points(tables.handle, int(order), float(t_meas),
+                                  ctypes.c_void_p(u.data_ptr()), P, int(method),
+                                  ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+
+
+class Plan:
+    def __init__(self, handle, items, n_shifts):
+        self.handle = ctypes.c_void_p(handle)
+        self._items = items
+        self.n_shifts = n_shifts
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.qqmc_plan_destroy(self.handle)
+            self.handle = None
+
+
+def plan_create(entries, t_meas, tile_len=0, grid_blocks=0, stream=None):
+    """entries: list of (Tables, OrderJob)."""
+    arr = (qqmc_batch_item * len(entries))()
+    keep = []
+    for k, (tb, job) in enumerate(entries):
+        o = make_order(job, t_meas)
+        keep.append((tb, o))
+        arr[k].tables = tb.handle
+        arr[k].order = o
+    h = ctypes.c_void_p()
+    _check(lib().qqmc_plan_create(arr, len(entries), int(tile_len), int(grid_blocks),
+                                  _stream(stream), ctypes.byref(h)))
+    return Plan(h.value, keep, [job.shifts.shape[0] for _, job in entries])
+
+
+def plan_run(plan, stream=None):
+    _check(lib().qqmc_plan_run(plan.handle, _stream(stream)))
+
+
+def plan_results(plan, stream=None):
+    tot = sum(plan.n_shifts)
+    q = np.zeros(2 * tot)
+    _check(lib().qqmc_plan_results(plan.handle, _stream(stream), _pd(q)))
+    qc = q[0::2] + 1j * q[1::2]
+    out, b = [], 0
+    for k in plan.n_shifts:
+        out.append(qc[b:b + k])
+        b += k
+    return out
+
+
+def plan_info(plan):
+    nt, npnt, tl, gb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().qqmc_plan_info(plan.handle, ctypes.byref(nt), ctypes.byref(npnt),
+                                ctypes.byref(tl), ctypes.byref(gb)))
+    return dict(n_tiles=nt.value, n_points=npnt.value, tile_len=tl.value, grid_blocks=gb.value)
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, max_slots, batch_tiles=0):
+        h = ctypes.c_void_p()
+        _check(lib().qqmc_server_create(int(hbm_budget_bytes), int(max_slots), int(batch_tiles),
+                                        ctypes.byref(h)))
+        self.handle = h
+        self._n_shifts = {}
+
+    def submit(self, dot, job, t_meas):
+        cd = make_dot(dot)
+        o = make_order(job, t_meas)
+        t = ctypes.c_uint64()
+        _check(lib().qqmc_submit(self.handle, ctypes.byref(cd), ctypes.byref(o), ctypes.byref(t)))
+        self._n_shifts[t.value] = o.n_shifts
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending; else dict(q_shift, q_mean, q_stderr, t_submit, t_done)."""
+        K = self._n_shifts.get(ticket, 1)
+        q = np.zeros(2 * K)
+        m = np.zeros(2)
+        se, ts, td = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = lib().qqmc_poll(self.handle, ctypes.c_uint64(ticket), _pd(q), _pd(m),
+                             ctypes.byref(se), ctypes.byref(ts), ctypes.byref(td))
+        if st == PENDING:
+            return None
+        _check(st)
+        self._n_shifts.pop(ticket, None)
+        return dict(q_shift=q[0::2] + 1j * q[1::2], q_mean=m[0] + 1j * m[1],
+                    q_stderr=se.value, t_submit=ts.value, t_done=td.value)
+
+    def now(self):
+        return lib().qqmc_server_now(self.handle)
+
+    def drain(self):
+        _check(lib().qqmc_server_drain(self.handle))
+
+    def close(self):
+        if self.handle and self.handle.value:
+            lib().qqmc_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

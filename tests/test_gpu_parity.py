@@ -1,0 +1,229 @@
+"""GPU path against the CPU oracle, element by element, through the C ABI.
+
+Tolerances (floating point, complex128 throughout):
+  per integrand value: |f_gpu - f_oracle| <= 1e-10 |f_oracle|, or, where the
+      Keldysh sum cancels so much that the value sits near rounding level of
+      its own terms, <= 1e-13 * sum_a |term_a| (the term mass);
+  per estimate Q^{(s)} and per tile sum: relative 1e-9 (absolute floor
+      1e-13 times the sum of |f|, approximated by the mass of the sum).
+Both sides use the same Green's-function tables (the oracle's, uploaded with
+qqmc_tables_from_host) except in the table test itself.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from qqmc_inputs import Dot, order_job, TINY_DOT, STRESS_DOT
+
+pytestmark = pytest.mark.gpu
+
+DOTS = [TINY_DOT, STRESS_DOT, Dot(2.5, 0.5, 20.0, 1.0), Dot(-2.2, 2.0, 20.0, 0.5)]
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_12372_amd import qqmc
+    qqmc.lib()
+    return qqmc
+
+
+def _upload(q, tb):
+    return q.tables_from_host(tb.gl, tb.gg, tb.n_grid, tb.t_half, tb.n_sigma)
+
+
+def _points(rng, n, t, count, inside=True):
+    out = []
+    while len(out) < count:
+        v = -np.log1p(-rng.random(n))
+        u = t - np.cumsum(v)
+        if (u[-1] > 0) == inside:
+            out.append(u)
+    return np.array(out)
+
+
+def _check_values(f_gpu, f_or, mass, label):
+    err = np.abs(f_gpu - f_or)
+    ok = (err <= 1e-10 * np.abs(f_or)) | (err <= 1e-13 * mass)
+    bad = np.flatnonzero(~ok)
+    assert bad.size == 0, "%s: %d/%d values off, worst err/mass %.3e" % (
+        label, bad.size, ok.size, np.max(err / mass))
+    return float(np.mean(err <= 1e-10 * np.abs(f_or)))
+
+
+@pytest.mark.parametrize("d", DOTS)
+def test_tables_match_oracle(q, oracle_mod, d):
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    gt = q.make_tables(d)
+    gl, gg, ns = q.tables_export(gt)
+    assert abs(ns - tb.n_sigma) < 1e-14
+    assert np.max(np.abs(gl - tb.gl)) < 1e-13
+    assert np.max(np.abs(gg - tb.gg)) < 1e-13
+
+
+def _eval_points(q, gt, n, u, method):
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    f = torch.zeros((u.shape[0], 2), dtype=torch.float64, device="cuda")
+    q.eval_points(gt, n, 10.0, ut, f, method=method)
+    torch.cuda.synchronize()
+    fh = f.cpu().numpy()
+    return fh[:, 0] + 1j * fh[:, 1]
+
+
+@pytest.mark.parametrize("d", DOTS[:3])
+@pytest.mark.parametrize("n", list(range(1, 15)))
+def test_points_tree_vs_oracle(q, oracle_mod, d, n):
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    gt = _upload(q, tb)
+    rng = np.random.default_rng(1000 + n)
+    count = 130 if n <= 8 else (24 if n <= 11 else 6)
+    u = _points(rng, n, 10.0, count)
+    f_gpu = _eval_points(q, gt, n, u, q.METHOD_TREE)
+    ref = [oracle_mod.integrand(tb, 10.0, row) for row in u]
+    f_or = np.array([r[0] for r in ref])
+    mass = np.array([r[1] for r in ref])
+    frac = _check_values(f_gpu, f_or, mass, "tree n=%d" % n)
+    print("n=%d pure-relative pass fraction %.3f" % (n, frac))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 10])
+def test_points_direct_vs_oracle_and_causality(q, oracle_mod, tiny_tables, n):
+    gt = _upload(q, tiny_tables)
+    rng = np.random.default_rng(2000 + n)
+    count = 40 if n <= 8 else 6
+    u = _points(rng, n, 10.0, count)
+    # a vertex after the measurement time (t = 8 below the table range 10)
+    late = rng.uniform(0.0, 9.5, size=(count // 2, n))
+    late[np.arange(count // 2), rng.integers(n, size=count // 2)] = rng.uniform(8.05, 9.9, size=count // 2)
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    f = torch.zeros((u.shape[0], 2), dtype=torch.float64, device="cuda")
+    q.eval_points(gt, n, 10.0, ut, f, method=q.METHOD_DIRECT)
+    lt = torch.tensor(late, dtype=torch.float64, device="cuda")
+    fl = torch.zeros((late.shape[0], 2), dtype=torch.float64, device="cuda")
+    q.eval_points(gt, n, 8.0, lt, fl, method=q.METHOD_DIRECT)
+    torch.cuda.synchronize()
+    fh = f.cpu().numpy()
+    ref = [oracle_mod.integrand(tiny_tables, 10.0, row) for row in u]
+    _check_values(fh[:, 0] + 1j * fh[:, 1], np.array([r[0] for r in ref]),
+                  np.array([r[1] for r in ref]), "direct n=%d" % n)
+    flh = fl.cpu().numpy()
+    for k, row in enumerate(late):
+        _, M2 = oracle_mod.integrand(tiny_tables, 8.0, row)
+        assert abs(flh[k, 0] + 1j * flh[k, 1]) <= 1e-13 * M2
+
+
+def test_points_tree_rejects_unordered_rows(q, tiny_tables):
+    gt = _upload(q, tiny_tables)
+    u = np.array([[9.0, 5.0, 1.0], [5.0, 9.0, 1.0], [11.0, 5.0, 1.0], [9.0, 5.0, -0.1]])
+    f = _eval_points(q, gt, 3, u, q.METHOD_TREE)
+    assert np.isfinite(f[0])
+    assert np.all(np.isnan(f[1:]))
+
+
+def _compare_q(q_gpu, q_or, label, rel=1e-9):
+    for s in range(len(q_or)):
+        scale = max(abs(q_or[s]), 1e-300)
+        assert abs(q_gpu[s] - q_or[s]) <= rel * scale + 1e-15, \
+            "%s shift %d: %r vs %r" % (label, s, q_gpu[s], q_or[s])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_eval_order_tiny_workload(q, oracle_mod, tiny_tables, n):
+    """Orders 1..3, N = 2^14, 16 shifts: every Q^{(s)} and the mean."""
+    gt = _upload(q, tiny_tables)
+    job = order_job(1, n, 14, 16)
+    qs, mean, se = q.eval_order(gt, job, 10.0)
+    qo, mo, seo = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                        job.shifts, job.model_tau)
+    _compare_q(qs, qo, "n=%d" % n)
+    assert abs(mean - mo) <= 1e-9 * abs(mo)
+    assert abs(se - seo) <= 1e-6 * seo
+
+
+@pytest.mark.parametrize("n,log2_n,K", [(4, 12, 4), (5, 12, 4), (6, 11, 4), (7, 11, 3), (8, 11, 3),
+                                        (9, 9, 2), (10, 9, 2), (11, 8, 2), (12, 8, 1),
+                                        (13, 7, 1), (14, 7, 1)])
+def test_eval_order_vs_oracle(q, oracle_mod, n, log2_n, K):
+    d = STRESS_DOT if n >= 11 else TINY_DOT
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    gt = _upload(q, tb)
+    job = order_job(3, n, log2_n, K)
+    qs, mean, se = q.eval_order(gt, job, 10.0)
+    qo, mo, _ = oracle_mod.eval_order(tb, 10.0, n, job.log2_n, job.lattice_a, job.shifts,
+                                      job.model_tau)
+    _compare_q(qs, qo, "n=%d" % n)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.95])
+def test_model_mode_full_size(q, tiny_tables, tau):
+    """f := p_n at N = 2^20, 32 shifts, n = 8: every sample is tau^8."""
+    gt = _upload(q, tiny_tables)
+    job = order_job(1, 8, 20, 32, model_tau=tau, mode=q.MODE_MODEL)
+    qs, mean, se = q.eval_order(gt, job, 10.0)
+    assert np.max(np.abs(qs - tau ** 8)) <= 1e-12 * tau ** 8
+
+
+def test_constant_mode_full_size(q, tiny_tables):
+    gt = _upload(q, tiny_tables)
+    job = order_job(1, 8, 20, 32, mode=q.MODE_CONSTANT)
+    qs, mean, se = q.eval_order(gt, job, 10.0)
+    exact = 10.0 ** 8 / math.factorial(8)
+    assert abs(mean.real - exact) < 5 * se
+
+
+def test_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
+    """n = 8, N = 2^20, 32 shifts, the launch configuration of the benchmark:
+    sampled tile sums against the oracle over the same index ranges, and the
+    tile sums of each shift add up to its shift sum."""
+    gt = _upload(q, tiny_tables)
+    job = order_job(1, 8, 20, 32)
+    tile_len = 1024
+    nt = q.n_tiles(job, tile_len)
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    sums = torch.zeros(2 * 32, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    sh = sums.cpu().numpy()
+    sc = sh[0::2] + 1j * sh[1::2]
+    per = (1 << 20) // tile_len
+    for s in range(32):
+        part = tc[s * per:(s + 1) * per]
+        assert abs(part.sum() - sc[s]) <= 1e-12 * np.sum(np.abs(part))
+    rng = np.random.default_rng(99)
+    for k in rng.choice(nt, size=3, replace=False):
+        s, i0 = divmod(int(k), per)
+        ref = oracle_mod.eval_sums(tiny_tables, 10.0, 8, 20, job.lattice_a, job.shifts[s:s + 1],
+                                   1.0, 0, i0 * tile_len, (i0 + 1) * tile_len)[0]
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13
+
+
+def test_eval_order_is_deterministic(q, tiny_tables):
+    gt = _upload(q, tiny_tables)
+    job = order_job(7, 6, 14, 8)
+    a = q.eval_order(gt, job, 10.0)[0]
+    b = q.eval_order(gt, job, 10.0)[0]
+    assert np.array_equal(a, b)
+
+
+def test_eval_order_rejects_bad_input(q, tiny_tables):
+    gt = _upload(q, tiny_tables)
+    job = order_job(1, 3, 10, 2)
+    job.lattice_a = 4
+    with pytest.raises(q.QQMCError):
+        q.eval_order(gt, job, 10.0)
+    job = order_job(1, 3, 10, 2)
+    job.shifts[0, 0] = 1.0
+    with pytest.raises(q.QQMCError):
+        q.eval_order(gt, job, 10.0)
+    job = order_job(1, 15, 10, 2)
+    with pytest.raises(q.QQMCError):
+        q.eval_order(gt, job, 10.0)
+    job = order_job(1, 3, 10, 2)
+    with pytest.raises(q.QQMCError):
+        q.eval_order(gt, job, 10.5)

@@ -55,6 +55,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=1 << 15)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run one plain device copy of this many bytes first (a reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -72,6 +75,12 @@ def main():
     job = order_job(1, n, args.log2n, args.shifts)
     N = 1 << args.log2n
     points = N * args.shifts
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tables = qqmc.make_tables(d)
     sums = torch.zeros(2 * args.shifts, dtype=torch.float64, device="cuda")
 

@@ -93,6 +93,11 @@ typedef struct {
 qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream,
                              qqmc_tables *out);
 
+/* Host-only form of the same computation: fills caller arrays (2*n_grid
+ * doubles each, (re, im) per node) and n_sigma without touching the GPU. */
+qqmc_status qqmc_tables_compute_host(const qqmc_dot *dot, double *gl,
+                                     double *gg, double *n_sigma);
+
 /* Wraps caller-supplied tables (host arrays of 2*n_grid doubles each, same
  * grid convention) so that any Green's function can be integrated.  The data
  * are copied; the caller may free them on return. */

@@ -146,15 +146,40 @@ extern "C" {
 
 const char *qqmc_last_error(void) { return g_last_error.c_str(); }
 
-qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out)
+static qqmc_status check_dot(const qqmc_dot *dot)
 {
-    if (!dot || !out) return set_error(QQMC_EINVAL, "NULL argument");
+    if (!dot) return set_error(QQMC_EINVAL, "NULL argument");
     if (!(dot->gamma > 0.0) || !(dot->beta > 0.0) || !(dot->t_half > 0.0) ||
         !std::isfinite(dot->eps_d) || !std::isfinite(dot->bias_v) ||
-        !std::isfinite(dot->beta) || !std::isfinite(dot->gamma))
+        !std::isfinite(dot->beta) || !std::isfinite(dot->gamma) || !std::isfinite(dot->t_half))
         return set_error(QQMC_EINVAL, "gamma, beta and t_half must be positive and finite");
     if (dot->n_grid < 2 || dot->n_grid > (1 << 24))
         return set_error(QQMC_EINVAL, "n_grid must be in 2..2^24");
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_tables_compute_host(const qqmc_dot *dot, double *gl, double *gg, double *n_sigma)
+{
+    if (qqmc_status st = check_dot(dot)) return st;
+    if (!gl || !gg) return set_error(QQMC_EINVAL, "NULL output");
+    const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
+    std::vector<double> tab(4 * (size_t)dot->n_grid);
+    build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,
+                      dot->t_half, ns, tab.data());
+    for (int32_t j = 0; j < dot->n_grid; ++j) {
+        gl[2 * j] = tab[4 * j];
+        gl[2 * j + 1] = tab[4 * j + 1];
+        gg[2 * j] = tab[4 * j + 2];
+        gg[2 * j + 1] = tab[4 * j + 3];
+    }
+    if (n_sigma) *n_sigma = ns;
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out)
+{
+    if (qqmc_status st = check_dot(dot)) return st;
+    if (!out) return set_error(QQMC_EINVAL, "NULL argument");
     const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
     std::vector<double> tab(4 * (size_t)dot->n_grid);
     build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,

@@ -55,6 +55,7 @@ _d, _i32, _i64, _u64, _vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
 _PD = _P(ctypes.c_double)
 SIGNATURES = [
     ("qqmc_make_tables", _i32, [_P(qqmc_dot), _vp, _P(_vp)]),
+    ("qqmc_tables_compute_host", _i32, [_P(qqmc_dot), _PD, _PD, _PD]),
     ("qqmc_tables_from_host", _i32, [_PD, _PD, _i32, _d, _d, _vp, _P(_vp)]),
     ("qqmc_tables_export", _i32, [_vp, _PD, _PD, _PD]),
     ("qqmc_tables_info", _i32, [_vp, _P(_i32), _PD]),
@@ -138,6 +139,16 @@ def make_tables(dot, stream=None):
     cd = make_dot(dot)
     _check(lib().qqmc_make_tables(ctypes.byref(cd), _stream(stream), ctypes.byref(h)))
     return Tables(h.value, dot.n_grid, dot.t_half)
+
+
+def tables_compute_host(dot):
+    """(gl, gg, n_sigma) computed on the host, no GPU involved."""
+    gl = np.zeros(2 * dot.n_grid)
+    gg = np.zeros(2 * dot.n_grid)
+    ns = ctypes.c_double()
+    cd = make_dot(dot)
+    _check(lib().qqmc_tables_compute_host(ctypes.byref(cd), _pd(gl), _pd(gg), ctypes.byref(ns)))
+    return gl, gg, ns.value
 
 
 def tables_from_host(gl, gg, n_grid, t_half, n_sigma, stream=None):

@@ -1,0 +1,132 @@
+"""Batched persistent launch (HIP graph) and the continuous-batching server.
+
+Each batched item and each served request must give exactly the bits of the
+single-order launch with the same tile length (the tiles are identical and
+every reduction runs in a fixed order), hence the same result alone and in
+the mix.  The single-order launch itself is checked against the oracle in
+test_gpu_parity.py; here one batched item is also checked against the
+oracle directly.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from qqmc_inputs import Dot, order_job, serving_trace
+
+pytestmark = pytest.mark.gpu
+
+T_MEAS = 10.0
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_12372_amd import qqmc
+    qqmc.lib()
+    return qqmc
+
+
+def _solo(q, tables, job, tile_len):
+    K = job.shifts.shape[0]
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    q.eval_order_async(tables, job, T_MEAS, sums, None, tile_len=min(tile_len, 1 << job.log2_n))
+    torch.cuda.synchronize()
+    s = sums.cpu().numpy()
+    return (s[0::2] + 1j * s[1::2]) / (1 << job.log2_n)
+
+
+def _entries(q):
+    dots = [Dot(0.0, 1.0, 20.0, 0.0), Dot(-1.7, 0.5, 20.0, 1.0), Dot(2.2, 1.0, 20.0, 0.5)]
+    tabs = [q.make_tables(d) for d in dots]
+    entries = []
+    for p, tb in enumerate(tabs):
+        for n in (1, 3, 5, 8, 9):
+            entries.append((tb, order_job(50 + p, n, 10 + (n % 3), 4)))
+    return dots, tabs, entries
+
+
+def test_plan_matches_single_launches_bitwise(q, oracle_mod):
+    dots, tabs, entries = _entries(q)
+    plan = q.plan_create(entries, T_MEAS, tile_len=256)
+    info = q.plan_info(plan)
+    assert info["tile_len"] == 256
+    for rep in range(3):          # graph replays, with eager work in between
+        q.plan_run(plan)
+        res = q.plan_results(plan)
+        for (tb, job), got in zip(entries, res):
+            assert np.array_equal(got, _solo(q, tb, job, 256)), (job.order, rep)
+    # one item straight against the oracle
+    d = dots[1]
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    job = entries[8][1]
+    qo = oracle_mod.eval_sums(tb, T_MEAS, job.order, job.log2_n, job.lattice_a, job.shifts,
+                              1.0) / (1 << job.log2_n)
+    assert np.max(np.abs(res[8] - qo) / np.abs(qo)) < 1e-9
+
+
+def test_plan_autotuned(q):
+    dots, tabs, entries = _entries(q)
+    plan = q.plan_create(entries, T_MEAS)
+    info = q.plan_info(plan)
+    assert info["tile_len"] in (256, 512, 1024, 2048) and info["grid_blocks"] > 0
+    q.plan_run(plan)
+    res = q.plan_results(plan)
+    for (tb, job), got in zip(entries, res):
+        ref = _solo(q, tb, job, info["tile_len"])
+        assert np.array_equal(got, ref)
+
+
+def test_server_results_equal_solo_runs(q):
+    trace = serving_trace(seed=11, n_requests=12, k_min=10, k_max=12, n_min=2, n_max=9)
+    srv = q.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    tickets = [srv.submit(r.dot, r.job, T_MEAS) for r in trace]
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.005)
+    assert len(out) == len(tickets)
+    for t, r in zip(tickets, trace):
+        tb = q.make_tables(r.dot)
+        ref = _solo(q, tb, r.job, 1024)
+        assert np.array_equal(out[t]["q_shift"], ref)
+        assert out[t]["t_done"] >= out[t]["t_submit"]
+    with pytest.raises(q.QQMCError):
+        srv.poll(tickets[0])          # already collected
+    srv.close()
+
+
+def test_server_admission_and_alone_vs_mix(q):
+    trace = serving_trace(seed=12, n_requests=6, k_min=10, k_max=11, n_min=3, n_max=7)
+    # alone: a fresh server per request
+    alone = []
+    for r in trace:
+        srv = q.Server(hbm_budget_bytes=1 << 28, max_slots=1)
+        t = srv.submit(r.dot, r.job, T_MEAS)
+        srv.drain()
+        alone.append(srv.poll(t)["q_shift"])
+        srv.close()
+    # in the mix: all at once on one server
+    srv = q.Server(hbm_budget_bytes=1 << 28, max_slots=3)
+    ts = [srv.submit(r.dot, r.job, T_MEAS) for r in trace]
+    srv.drain()
+    for t, a in zip(ts, alone):
+        assert np.array_equal(srv.poll(t)["q_shift"], a)
+    # a budget smaller than one request's footprint is refused at submission
+    tiny = q.Server(hbm_budget_bytes=4096, max_slots=2)
+    with pytest.raises(q.QQMCError) as e:
+        tiny.submit(trace[0].dot, trace[0].job, T_MEAS)
+    assert e.value.status == q.EADMIT
+    with pytest.raises(q.QQMCError) as e:
+        tiny.poll(12345)
+    assert e.value.status == q.ENOTICKET
+    tiny.close()
+    srv.close()

@@ -1,0 +1,92 @@
+"""CPU-side checks of the product: the C ABI exports, the host table
+builder against the oracle, the seeded input recipes, the flop model."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from qqmc_inputs import (Dot, SplitMix64, batched_jobs, batched_log2_n, order_job,
+                         serving_trace, shifts, lattice_multiplier)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "qqmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qqmc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libq():
+    from paper_2002_12372_amd import qqmc
+    if not os.path.exists(qqmc.LIB_PATH):
+        pytest.skip("libqqmc.so not built")
+    return qqmc
+
+
+def test_library_exports_every_declared_symbol(libq):
+    names = _declared()
+    assert len(names) >= 20
+    raw = ctypes.CDLL(libq.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    bound = {s[0] for s in libq.SIGNATURES}
+    assert set(names) == bound
+
+
+@pytest.mark.parametrize("d", [Dot(0.0, 1.0, 20.0, 0.0), Dot(-0.5, 1.0, 20.0, 0.2),
+                               Dot(2.7, 0.6, 20.0, 0.9), Dot(-1.3, 1.7, 35.0, 0.3)])
+def test_host_tables_match_oracle(libq, oracle_mod, d):
+    gl, gg, ns = libq.tables_compute_host(d)
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    assert abs(ns - tb.n_sigma) < 1e-14
+    assert np.max(np.abs(gl - tb.gl)) < 1e-13
+    assert np.max(np.abs(gg - tb.gg)) < 1e-13
+
+
+def test_host_tables_reject_bad_dot(libq):
+    with pytest.raises(libq.QQMCError):
+        libq.tables_compute_host(Dot(0.0, -1.0, 20.0, 0.0))
+    with pytest.raises(libq.QQMCError):
+        libq.tables_compute_host(Dot(0.0, 1.0, 20.0, 0.0, n_grid=1))
+
+
+def test_splitmix_is_deterministic_and_uniform():
+    a, b = SplitMix64(42), SplitMix64(42)
+    xs = [a.uniform() for _ in range(20000)]
+    assert xs[:100] == [b.uniform() for _ in range(100)]
+    xs = np.array(xs)
+    assert xs.min() >= 0.0 and xs.max() < 1.0
+    assert abs(xs.mean() - 0.5) < 0.01
+
+
+def test_lattice_multiplier_and_shifts():
+    r = SplitMix64(3)
+    for k in (6, 14, 20, 24):
+        a = lattice_multiplier(r, k)
+        assert a % 2 == 1 and 1 < a < (1 << k)
+    sh = shifts(r, 16, 5)
+    assert sh.shape == (16, 5) and np.all((sh >= 0) & (sh < 1))
+    j1, j2 = order_job(1, 8, 20, 32), order_job(1, 8, 20, 32)
+    assert j1.lattice_a == j2.lattice_a and np.array_equal(j1.shifts, j2.shifts)
+
+
+def test_workload_recipes():
+    assert [batched_log2_n(n) for n in range(1, 11)] == [16, 16, 17, 18, 18, 19, 20, 20, 21, 22]
+    jobs = batched_jobs()
+    assert len(jobs) == 640
+    tr = serving_trace(n_requests=64)
+    t = np.array([r.arrival_s for r in tr])
+    assert np.all(np.diff(t) > 0)
+    assert all(2 <= r.job.order <= 12 and 14 <= r.job.log2_n <= 22 for r in tr)
+
+
+def test_flop_model():
+    from paper_2002_12372_amd.flops import tree_flops, lane_flops
+    for n in range(1, 15):
+        assert tree_flops(n) <= lane_flops(n)
+        # per index vector the tree costs O(1): between 30 and 150 operations
+        assert 30 < tree_flops(n) / 2 ** n < 150

@@ -52,9 +52,8 @@ hipError_t launch_points_direct(const double *tab, int32_t n_grid,
                                 int32_t order, double t_meas, const double *u,
                                 int64_t n_points, double *f, hipStream_t s);
 hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev,
-                        int64_t n_tiles, int32_t *counter_dev,
-                        int32_t grid_blocks, int32_t lds_bytes, hipStream_t s);
-hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+                        int64_t n_tiles, int32_t grid_blocks, int32_t lds_bytes,
+                        hipStream_t s);
 int32_t lds_bytes_for_order(int32_t order);
 int32_t batch_lds_bytes(int32_t max_order);
 int32_t batch_blocks_per_cu(int32_t lds_bytes);

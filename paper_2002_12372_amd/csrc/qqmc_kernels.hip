@@ -450,22 +450,20 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
     }
 }
 
-/* Persistent batched kernel: workgroups take tiles from a shared list (most
- * expensive first) through an atomic counter; each tile runs the same
- * order_tile code as the single-order kernel, so per-tile sums are the same
- * bits.  Every workgroup leaves the loop once the counter passes the end. */
+/* Persistent batched kernel: resident workgroups walk a tile list that the
+ * host sorted by decreasing cost, workgroup b taking entries b, b + G,
+ * b + 2G, ... (G = grid size).  The loop index comes from blockIdx, so the
+ * loop is wave-uniform; every tile runs the same order_tile code as the
+ * single-order kernel, so per-tile sums are the same bits.  (A work queue
+ * fed by a lane-0 atomic was tried first: the compiler threaded the lane-0
+ * branches at the top and bottom of the loop into an inner cycle for lanes
+ * 1..63 that never reached the next atomic.) */
 __global__ void __launch_bounds__(64) batch_kernel(const ItemDesc *items,
                                                    const TileRef *tiles,
-                                                   int64_t n_tiles, int32_t *counter)
+                                                   int64_t n_tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    __shared__ int64_t s_next;
-    for (;;) {
-        if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int64_t t = s_next;
-        __syncthreads();
-        if (t >= n_tiles) break;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
         const ItemDesc &it = items[ref.item];
         cplx v;
@@ -482,12 +480,6 @@ __global__ void __launch_bounds__(64) batch_kernel(const ItemDesc *items,
             it.tile_sums[2 * ref.tile + 1] = v.y;
         }
     }
-}
-
-__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
 }
 
 template <template <int> class F, typename... A>
@@ -626,19 +618,12 @@ hipError_t launch_points_direct(const double *tab, int32_t n_grid, double t_half
 }
 
 hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
-                        int32_t *counter_dev, int32_t grid_blocks, int32_t lds_bytes,
-                        hipStream_t s)
+                        int32_t grid_blocks, int32_t lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid_blocks), dim3(64),
-                       (unsigned)lds_bytes, s, items_dev, tiles_dev, n_tiles, counter_dev);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
-{
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256),
-                       0, s, p, v, n);
+    if (n_tiles <= 0) return hipSuccess;
+    const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)g), dim3(64), (unsigned)lds_bytes, s,
+                       items_dev, tiles_dev, n_tiles);
     return hipGetLastError();
 }
 

@@ -5,8 +5,9 @@
  * Every item is cut into the same tiles qqmc_eval_order would use for the
  * same tile length, so each tile sum, and therefore each per-shift sum, is
  * bitwise the one the single-order launch produces.  The tiles of all items
- * are listed most expensive first (cost model below) and handed out to a
- * fixed set of resident workgroups through an atomic counter, which balances
+ * are listed most expensive first (cost model below) and dealt round robin
+ * to a fixed set of resident workgroups (workgroup b takes list entries
+ * b, b + G, ...), which balances
  * the very uneven per-item work (2^n index vectors per point, 2^16..2^22
  * points per item).
  *
@@ -57,7 +58,6 @@ struct Buffers {
     ItemDesc *items = nullptr;
     int64_t *base = nullptr;
     TileRef *tiles = nullptr;
-    int32_t *counter = nullptr;
     void release()
     {
         if (shifts) hipFree(shifts);
@@ -66,7 +66,6 @@ struct Buffers {
         if (items) hipFree(items);
         if (base) hipFree(base);
         if (tiles) hipFree(tiles);
-        if (counter) hipFree(counter);
         *this = Buffers();
     }
 };
@@ -144,7 +143,6 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
     if (e == hipSuccess) e = hipMalloc(&p->buf.items, sizeof(ItemDesc) * p->items.size());
     if (e == hipSuccess) e = hipMalloc(&p->buf.base, sizeof(int64_t) * p->items.size());
     if (e == hipSuccess) e = hipMalloc(&p->buf.tiles, sizeof(TileRef) * (p->n_tiles ? p->n_tiles : 1));
-    if (e == hipSuccess) e = hipMalloc(&p->buf.counter, sizeof(int32_t));
     if (e != hipSuccess) {
         p->buf.release();
         return hip_error(e, "plan buffers");
@@ -173,8 +171,7 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
 
 hipError_t enqueue(qqmc_plan_s *p, const TileRef *tiles, int64_t n_tiles, int32_t grid, hipStream_t s)
 {
-    hipError_t e = launch_fill_i32(p->buf.counter, 0, 1, s);
-    if (e == hipSuccess) e = launch_batch(p->buf.items, tiles, n_tiles, p->buf.counter, grid, p->lds_bytes, s);
+    hipError_t e = launch_batch(p->buf.items, tiles, n_tiles, grid, p->lds_bytes, s);
     if (e == hipSuccess)
         e = launch_shift_reduce(p->buf.items, (int32_t)p->items.size(), p->buf.base, p->buf.shift_sums,
                                 p->max_shifts, s);

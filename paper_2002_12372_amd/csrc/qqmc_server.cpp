@@ -71,7 +71,6 @@ struct Launch {
     hipEvent_t done = nullptr;
     ItemDesc *d_items = nullptr;
     TileRef *d_tiles = nullptr;
-    int32_t *d_counter = nullptr;
     size_t cap_items = 0, cap_tiles = 0;
     std::vector<std::pair<std::shared_ptr<Request>, int64_t>> issued; /* request, #tiles */
     bool busy = false;
@@ -301,16 +300,14 @@ hipError_t submit_launch(qqmc_server_s *s, Launch &L, const std::vector<ItemDesc
         L.cap_tiles = std::max<size_t>(tiles.size(), 2 * L.cap_tiles);
         e = hipMalloc(&L.d_tiles, sizeof(TileRef) * L.cap_tiles);
     }
-    if (e == hipSuccess && !L.d_counter) e = hipMalloc(&L.d_counter, sizeof(int32_t));
     if (e == hipSuccess)
         e = hipMemcpyAsync(L.d_items, items.data(), sizeof(ItemDesc) * items.size(), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L.d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_fill_i32(L.d_counter, 0, 1, s->stream);
     if (e == hipSuccess) {
         int32_t grid = s->grid;
         if ((int64_t)grid > (int64_t)tiles.size()) grid = (int32_t)tiles.size();
-        e = launch_batch(L.d_items, L.d_tiles, (int64_t)tiles.size(), L.d_counter, grid, s->lds, s->stream);
+        e = launch_batch(L.d_items, L.d_tiles, (int64_t)tiles.size(), grid, s->lds, s->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(L.done, s->stream);
     return e;
@@ -496,7 +493,6 @@ void qqmc_server_destroy(qqmc_server s)
         if (L.done) hipEventDestroy(L.done);
         if (L.d_items) hipFree(L.d_items);
         if (L.d_tiles) hipFree(L.d_tiles);
-        if (L.d_counter) hipFree(L.d_counter);
     }
     for (auto &kv : s->all) {
         auto &r = kv.second;

@@ -25,6 +25,32 @@ METRIC = "Keldysh-summed integrand points/s at n=8 FP64, % FP64 peak; p99 sweep 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 
+KERNEL_SOURCES = ["paper_2002_12372_amd/csrc/qqmc_kernels.hip",
+                  "paper_2002_12372_amd/csrc/qqmc_tree.h"]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(order):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, only
+    if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_order%d.json" % order)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def inside_fraction(n, t_over_tau):
     from scipy.special import gammainc
     return float(gammainc(n, t_over_tau))
@@ -130,7 +156,7 @@ def main():
                    "inside_points_per_s": value * frac_in},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(n),
                      "flops_per_inside_point": tree_flops(n),
                      "avg_launch_ms": avg_launch_s * 1e3},
     }

@@ -70,32 +70,29 @@ def cpu_baseline(order, log2_n, lattice_a, shifts, count):
                       "%d OpenMP threads, %.1f s" % (count - 1, order, threads, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--order", type=int, default=8)
-    ap.add_argument("--log2n", type=int, default=20)
-    ap.add_argument("--shifts", type=int, default=32)
-    ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-bytes", type=int, default=0,
-                    help="run one plain device copy of this many bytes first (a reference "
-                         "for hardware byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def timed_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
 
+
+def run_plain(args):
     import torch
     from paper_2002_12372_amd import qqmc
     from paper_2002_12372_amd.flops import tree_flops, warp_flops
     from qqmc_inputs import TINY_DOT as d, order_job
 
-    torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     n = args.order
     job = order_job(1, n, args.log2n, args.shifts)
@@ -113,23 +110,9 @@ def main():
     def step():
         qqmc.eval_order_async(tables, job, d.t_meas, sums, None, tile_len=args.tile, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    wall, launch_ms = timed_steps(step, args.steps, args.warmup, stream)
     ms_per_step = wall * 1e3 / args.steps
     value = points * args.steps / wall
-
     frac_in = inside_fraction(n, d.t_meas / job.model_tau)
     alg_flops = points * (frac_in * tree_flops(n) + warp_flops(n))
     avg_launch_s = sum(launch_ms) / len(launch_ms) * 1e-3
@@ -164,6 +147,220 @@ def main():
         out["cpu_baseline"] = cpu_baseline(n, args.log2n, job.lattice_a, job.shifts,
                                            args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """64 dots x orders 1..10 x 16 shifts, lattice sizes 2^(16+floor(2(n-1)/3)-shrink):
+    one autotuned persistent launch (HIP graph) against one launch per item."""
+    import numpy as np
+    import torch
+    from paper_2002_12372_amd import qqmc
+    from paper_2002_12372_amd.flops import tree_flops
+    from qqmc_inputs import batched_dots, batched_jobs
+
+    stream = torch.cuda.current_stream()
+    dots = batched_dots(count=args.params)
+    tables = [qqmc.make_tables(d) for d in dots]
+    jobs = batched_jobs(count=args.params, log2_offset=args.shrink)
+    entries = [(tables[p], job) for p, job in jobs]
+    t0 = time.perf_counter()
+    plan = qqmc.plan_create(entries, 10.0)
+    t_plan = time.perf_counter() - t0
+    info = qqmc.plan_info(plan)
+    points = info["n_points"]
+    print("batched: %d items, %d points, %d tiles, tile_len %d, grid %d, plan %.2f s"
+          % (len(entries), points, info["n_tiles"], info["tile_len"], info["grid_blocks"], t_plan),
+          file=sys.stderr, flush=True)
+    wall_b, ms_b = timed_steps(lambda: qqmc.plan_run(plan, stream), args.steps, args.warmup, stream)
+    res_b = qqmc.plan_results(plan)
+    sums = [torch.zeros(2 * job.shifts.shape[0], dtype=torch.float64, device="cuda")
+            for _, job in entries]
+
+    def per_item():
+        for (tb, job), buf in zip(entries, sums):
+            qqmc.eval_order_async(tb, job, 10.0, buf, None,
+                                  tile_len=min(info["tile_len"], 1 << job.log2_n), stream=stream)
+
+    wall_p, ms_p = timed_steps(per_item, args.steps, args.warmup, stream)
+    same = all(np.array_equal(rb, (lambda h: (h[0::2] + 1j * h[1::2]) / (1 << job.log2_n))(
+        buf.cpu().numpy())) for rb, buf, (_, job) in zip(res_b, sums, entries))
+    flops = 0.0
+    for _, job in entries:
+        flops += (1 << job.log2_n) * job.shifts.shape[0] * inside_fraction(job.order, 10.0) * \
+            tree_flops(job.order)
+    tb_s = sum(ms_b) / len(ms_b) * 1e-3
+    tp_s = sum(ms_p) / len(ms_p) * 1e-3
+    print(json.dumps({
+        "metric": "batched Keldysh-summed integrand points/s (64 parameter points x orders 1..10)",
+        "value": points / tb_s, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": tb_s * 1e3, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "64 wide-band dots (eps_d~U[-3,3], V in {0,.5,1}, Gamma in {.5,1}, "
+                               "beta=20) x orders 1..10 x 16 shifts, N_n = 2^(16+floor(2(n-1)/3)-%d)"
+                               % args.shrink,
+                   "items": len(entries), "points": points, "tile_len": info["tile_len"],
+                   "grid_blocks": info["grid_blocks"], "plan_create_s": t_plan},
+        "per_order_launches": {"value": points / tp_s, "unit": "points/s",
+                               "ms_per_step": tp_s * 1e3},
+        "speedup_vs_per_order": tp_s / tb_s,
+        "bitwise_equal_to_per_order": bool(same),
+        "roofline": {"bound": "alu", "achieved": flops / tb_s / 1e12,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / tb_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
+    }), flush=True)
+
+
+def run_serving(args):
+    """Poisson sweep requests through the continuous-batching server, then the
+    same trace through one plain launch per request in arrival order."""
+    import numpy as np
+    import torch
+    from paper_2002_12372_amd import qqmc
+    from qqmc_inputs import serving_trace
+
+    trace = serving_trace(seed=3, n_requests=args.requests, rate_hz=args.rate)
+    pts = [(1 << r.job.log2_n) * r.job.shifts.shape[0] for r in trace]
+
+    def serve(rate_scale):
+        srv = qqmc.Server(hbm_budget_bytes=args.budget_gb << 30, max_slots=args.slots)
+        t0 = srv.now()
+        pending, done = {}, {}
+        k = 0
+        while k < len(trace) or pending:
+            now = srv.now() - t0
+            while k < len(trace) and trace[k].arrival_s / rate_scale <= now:
+                pending[srv.submit(trace[k].dot, trace[k].job, 10.0)] = k
+                k += 1
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    done[pending.pop(tk)] = r
+            time.sleep(0.0005)
+        lat = np.array([done[i]["t_done"] - (t0 + trace[i].arrival_s / rate_scale)
+                        for i in range(len(trace))])
+        span = max(done[i]["t_done"] for i in done) - t0
+        srv.close()
+        return lat, span, done
+
+    lat_s, span_s, done = serve(1.0)
+    print("served %d requests in %.2f s" % (len(trace), span_s), file=sys.stderr, flush=True)
+    # plain: one launch per request, first come first served
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    lat_p = []
+    same = True
+    busy = 0.0
+    for i, r in enumerate(trace):
+        now = time.perf_counter() - t0
+        if now < r.arrival_s:
+            time.sleep(r.arrival_s - now)
+        ts = time.perf_counter()
+        tb = qqmc.make_tables(r.dot)
+        K = r.job.shifts.shape[0]
+        buf = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+        qqmc.eval_order_async(tb, r.job, 10.0, buf, None,
+                              tile_len=min(1024, 1 << r.job.log2_n), stream=stream)
+        h = buf.cpu().numpy()
+        q = (h[0::2] + 1j * h[1::2]) / (1 << r.job.log2_n)
+        te = time.perf_counter()
+        busy += te - ts
+        lat_p.append(te - t0 - r.arrival_s)
+        same = same and np.array_equal(q, done[i]["q_shift"])
+    span_p = time.perf_counter() - t0
+    lat_p = np.array(lat_p)
+    capacity = len(trace) / busy
+    out = {
+        "metric": "p99 sweep latency (served), s",
+        "value": float(np.percentile(lat_s, 99)), "unit": "s", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Poisson %.0f req/s, %d requests: eps_d~U[-3,3], Gamma~U[.5,2], "
+                               "V~U[0,1], n~U{2..12}, N=2^k k~U{14..22}, 16 shifts, beta=20, t=10"
+                               % (args.rate, args.requests),
+                   "slots": args.slots, "budget_gb": args.budget_gb},
+        "served": {"p50_s": float(np.percentile(lat_s, 50)), "p99_s": float(np.percentile(lat_s, 99)),
+                   "makespan_s": span_s, "points_per_s": sum(pts) / span_s},
+        "plain_per_request": {"p50_s": float(np.percentile(lat_p, 50)),
+                              "p99_s": float(np.percentile(lat_p, 99)),
+                              "makespan_s": span_p, "points_per_s": sum(pts) / span_p,
+                              "busy_s": busy},
+        "capacity_req_per_s_estimate": capacity,
+        "results_bitwise_equal_served_vs_plain": bool(same),
+    }
+    if args.serve_at_fraction > 0:
+        scale = capacity * args.serve_at_fraction / args.rate
+        lat_f, span_f, _ = serve(scale)
+        out["served_at_fraction_of_capacity"] = {
+            "fraction": args.serve_at_fraction, "rate_req_per_s": args.rate * scale,
+            "p50_s": float(np.percentile(lat_f, 50)), "p99_s": float(np.percentile(lat_f, 99)),
+            "makespan_s": span_f}
+    print(json.dumps(out), flush=True)
+
+
+def run_stress(args):
+    """Orders 11..14 (eps_d=-0.5, V=0.2), N = 2^18 x 16 shifts, with the
+    model-function exactness check on device."""
+    import numpy as np
+    import torch
+    from paper_2002_12372_amd import qqmc
+    from paper_2002_12372_amd.flops import tree_flops
+    from qqmc_inputs import STRESS_DOT as d, order_job
+
+    stream = torch.cuda.current_stream()
+    tables = qqmc.make_tables(d)
+    rows = []
+    for n in range(11, 15):
+        job = order_job(4, n, args.stress_log2n, 16)
+        t0 = time.perf_counter()
+        q, mean, se = qqmc.eval_order(tables, job, 10.0)
+        dt = time.perf_counter() - t0
+        jm = order_job(4, n, args.stress_log2n, 16, mode=qqmc.MODE_MODEL)
+        qm, _, _ = qqmc.eval_order(tables, jm, 10.0)
+        pts = (1 << job.log2_n) * 16
+        fl = pts * inside_fraction(n, 10.0) * tree_flops(n)
+        rows.append({"order": n, "Q": mean.real, "stderr": se, "seconds": dt,
+                     "points_per_s": pts / dt, "tflops": fl / dt / 1e12,
+                     "model_mode_max_dev": float(np.max(np.abs(qm - 1.0)))})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "stress orders 11..14", "rows": rows,
+                      "config": {"workload": "eps_d=-0.5, V=0.2, Gamma=1, beta=20, t=10, "
+                                             "N=2^%d x 16 shifts" % args.stress_log2n}}),
+          flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["plain", "batched", "serving", "stress"],
+                    default="plain")
+    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--shifts", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run one plain device copy of this many bytes first (a reference "
+                         "for hardware byte counters)")
+    ap.add_argument("--params", type=int, default=64)
+    ap.add_argument("--shrink", type=int, default=10,
+                    help="batched: lattice sizes divided by 2^shrink")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=int, default=16)
+    ap.add_argument("--serve-at-fraction", type=float, default=0.0)
+    ap.add_argument("--stress-log2n", type=int, default=18)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    {"plain": run_plain, "batched": run_batched, "serving": run_serving,
+     "stress": run_stress}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -86,10 +86,11 @@ typedef struct {
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
  * standard Keldysh normalisation g^< = i A fbar, g^> = -i A (1 - fbar)) --- */
 
-/* Builds g^<(tau_j), g^>(tau_j) and n_sigma = -i g^<(0) on the host (exact
- * residue series over the Matsubara poles), uploads them to the current
- * device on `stream`, and returns a handle.  EINVAL for gamma <= 0,
- * beta <= 0, t_half <= 0 or n_grid outside 2..2^24. */
+/* Builds g^<(tau_j), g^>(tau_j) on the current device (exact residue series
+ * over the Matsubara poles, one workgroup per grid node, launched on
+ * `stream`; the handle is usable by later work on the same stream) and
+ * n_sigma = -i g^<(0) on the host (digamma closed form).  EINVAL for
+ * gamma <= 0, beta <= 0, t_half <= 0 or n_grid outside 2..2^24. */
 qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream,
                              qqmc_tables *out);
 

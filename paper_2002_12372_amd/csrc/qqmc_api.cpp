@@ -181,10 +181,25 @@ qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out
     if (qqmc_status st = check_dot(dot)) return st;
     if (!out) return set_error(QQMC_EINVAL, "NULL argument");
     const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
-    std::vector<double> tab(4 * (size_t)dot->n_grid);
-    build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,
-                      dot->t_half, ns, tab.data());
-    return upload_tables(tab.data(), dot->n_grid, dot->t_half, ns, (hipStream_t)stream, out);
+    auto *t = new (std::nothrow) qqmc_tables_s();
+    if (!t) return set_error(QQMC_ENOMEM, "host allocation failed");
+    hipGetDevice(&t->device);
+    t->n_grid = dot->n_grid;
+    t->t_half = dot->t_half;
+    t->h = 2.0 * dot->t_half / (dot->n_grid - 1);
+    t->n_sigma = ns;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&t->d_tab, sizeof(double) * 4 * (size_t)dot->n_grid);
+    if (e == hipSuccess)
+        e = launch_tables(t->d_tab, dot->n_grid, dot->t_half, dot->eps_d, dot->gamma, dot->beta,
+                          dot->bias_v, ns, s);
+    if (e != hipSuccess) {
+        if (t->d_tab) hipFree(t->d_tab);
+        delete t;
+        return hip_error(e, "device table build");
+    }
+    *out = t;
+    return QQMC_OK;
 }
 
 qqmc_status qqmc_tables_from_host(const double *gl, const double *gg, int32_t n_grid,
@@ -210,8 +225,10 @@ qqmc_status qqmc_tables_export(qqmc_tables t, double *gl, double *gg, double *n_
     if (n_sigma) *n_sigma = t->n_sigma;
     if (!gl && !gg) return QQMC_OK;
     std::vector<double> tab(4 * (size_t)t->n_grid);
-    hipError_t e = hipMemcpy(tab.data(), t->d_tab, sizeof(double) * tab.size(),
-                             hipMemcpyDeviceToHost);
+    /* the table may still be being built on the stream given at creation */
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(tab.data(), t->d_tab, sizeof(double) * tab.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_error(e, "hipMemcpy(tables)");
     for (int32_t j = 0; j < t->n_grid; ++j) {
         if (gl) { gl[2 * j] = tab[4 * j]; gl[2 * j + 1] = tab[4 * j + 1]; }

@@ -51,12 +51,16 @@ hipError_t launch_points_direct(const double *tab, int32_t n_grid,
                                 double t_half, double h, double g0y,
                                 int32_t order, double t_meas, const double *u,
                                 int64_t n_points, double *f, hipStream_t s);
-hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev,
-                        int64_t n_tiles, int32_t grid_blocks, int32_t lds_bytes,
-                        hipStream_t s);
-int32_t lds_bytes_for_order(int32_t order);
-int32_t batch_lds_bytes(int32_t max_order);
-int32_t batch_blocks_per_cu(int32_t lds_bytes);
+/* One persistent launch over a tile list whose tiles all have this order. */
+hipError_t launch_batch(int32_t order, const ItemDesc *items_dev,
+                        const TileRef *tiles_dev, int64_t n_tiles,
+                        int32_t grid_blocks, hipStream_t s);
+hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_d,
+                         double gamma, double beta, double bias_v, double n_sigma,
+                         hipStream_t s);
+int32_t batch_blocks_per_cu(int32_t order);
+/* Relative cost of one tile of an item (qqmc_plan.cpp). */
+double tile_cost(const ItemDesc &d);
 int32_t default_tile_len(const ItemDesc &d, int64_t N);
 qqmc_status check_tables(qqmc_tables t);
 void fill_item_tables(ItemDesc &d, const qqmc_tables_s *t);

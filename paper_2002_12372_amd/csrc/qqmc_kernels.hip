@@ -14,10 +14,14 @@
  *   4. evaluates the Keldysh sum with the elimination tree of qqmc_tree.h,
  *      G = 2^T lanes per point (or per top-level prefix for n > 8),
  *   5. folds -2 i^{n+1} S(u) W into a per-lane compensated accumulator.
+ * The tree kernels are compiled for two waves per SIMD (256 registers per
+ * lane; the few values that do not fit go to scratch), which measured
+ * faster than one wave per SIMD with no spills.
  * The tile's sum goes to one slot of a partials array; a second kernel sums
  * the slots of each shift in a fixed order.  No floating-point atomics are
  * used anywhere, so results are bitwise reproducible.
  */
+#include "qqmc_gf.h"
 #include "qqmc_internal.h"
 #include "qqmc_tree.h"
 
@@ -259,7 +263,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 }
 
 template <int N>
-__global__ void __launch_bounds__(64) order_kernel(ItemDesc it)
+__global__ void __launch_bounds__(64, 2) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
@@ -306,7 +310,7 @@ __global__ void __launch_bounds__(256) shift_reduce_kernel(const ItemDesc *items
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
 template <int N>
-__global__ void __launch_bounds__(64) points_tree_kernel(Env env, const double *u,
+__global__ void __launch_bounds__(64, 2) points_tree_kernel(Env env, const double *u,
                                                         int64_t n_points, double *f)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -450,35 +454,80 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
     }
 }
 
-/* Persistent batched kernel: resident workgroups walk a tile list that the
- * host sorted by decreasing cost, workgroup b taking entries b, b + G,
- * b + 2G, ... (G = grid size).  The loop index comes from blockIdx, so the
- * loop is wave-uniform; every tile runs the same order_tile code as the
- * single-order kernel, so per-tile sums are the same bits.  (A work queue
- * fed by a lane-0 atomic was tried first: the compiler threaded the lane-0
- * branches at the top and bottom of the loop into an inner cycle for lanes
- * 1..63 that never reached the next atomic.) */
-__global__ void __launch_bounds__(64) batch_kernel(const ItemDesc *items,
-                                                   const TileRef *tiles,
+/* Persistent batched kernel for one order: resident workgroups walk a tile
+ * list (tiles of many items, all of order N) that the host sorted by
+ * decreasing cost, workgroup b taking entries b, b + G, b + 2G, ... (G =
+ * grid size).  The loop index comes from blockIdx, so the loop is
+ * wave-uniform, and every tile runs the same order_tile code as the
+ * single-order kernel, so per-tile sums are the same bits.  Work of several
+ * orders runs as concurrent launches of this kernel (graph branches).
+ * (A work queue fed by a lane-0 atomic was tried first: the compiler
+ * threaded the lane-0 branches at the top and bottom of the loop into an
+ * inner cycle for lanes 1..63 that never reached the next atomic.) */
+template <int N>
+__global__ void __launch_bounds__(64, 2) batch_kernel(const ItemDesc *items, const TileRef *tiles,
                                                    int64_t n_tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
         const ItemDesc &it = items[ref.item];
-        cplx v;
-        switch (it.order) {
-#define QQMC_CASE(NN) case NN: v = order_tile<NN>(it, ref.tile, lds); break;
-            QQMC_CASE(1) QQMC_CASE(2) QQMC_CASE(3) QQMC_CASE(4) QQMC_CASE(5)
-            QQMC_CASE(6) QQMC_CASE(7) QQMC_CASE(8) QQMC_CASE(9) QQMC_CASE(10)
-            QQMC_CASE(11) QQMC_CASE(12) QQMC_CASE(13) QQMC_CASE(14)
-#undef QQMC_CASE
-        default: v = cmk(0.0, 0.0); break;
-        }
+        const cplx v = order_tile<N>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;
             it.tile_sums[2 * ref.tile + 1] = v.y;
         }
+    }
+}
+
+/* Device build of the Green's-function grid: one workgroup per node; the
+ * 256 threads split the Matsubara terms of g^<(|tau|) (thread j takes
+ * k = kmax - j, kmax - j - 256, ..., compensated), a fixed tree combines
+ * them, and thread 0 assembles the node (qqmc_gf.h). */
+__global__ void __launch_bounds__(256) tables_kernel(double *tab, int32_t n_grid, double t_half,
+                                                     double h, double eps_d, double gamma,
+                                                     double beta, double bias_v, double n_sigma)
+{
+    __shared__ double red[4][256];
+    const int j = blockIdx.x;
+    const double tau = -t_half + j * h;
+    const double at = fabs(tau);
+    const int tid = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, comp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tau != 0.0) {
+        const long kmax = matsubara_kmax(beta, at);
+        for (long k = kmax - tid; k >= 0; k -= 256) {
+            const cplx tp = matsubara_term(eps_d, gamma, beta, 0.5 * bias_v, at, k);
+            const cplx tm = matsubara_term(eps_d, gamma, beta, -0.5 * bias_v, at, k);
+            const double v[4] = {tp.x, tp.y, tm.x, tm.y};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double y = v[c] - comp[c], t = acc[c] + y;
+                comp[c] = (t - acc[c]) - y;
+                acc[c] = t;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][tid] = acc[c] - comp[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][tid] += red[c][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        cplx gl_abs = cmk(0.0, 0.0);
+        if (tau != 0.0)
+            gl_abs = lesser_from_sums(eps_d, gamma, beta, bias_v, at, cmk(red[0][0], red[1][0]),
+                                      cmk(red[2][0], red[3][0]));
+        const pairv v = node_values(eps_d, gamma, tau, gl_abs, n_sigma);
+        tab[4 * j + 0] = v.gl.x;
+        tab[4 * j + 1] = v.gl.y;
+        tab[4 * j + 2] = v.gg.x;
+        tab[4 * j + 3] = v.gg.y;
     }
 }
 
@@ -511,14 +560,6 @@ template <int N> struct OrderLaunch {
         hipLaunchKernelGGL(order_kernel<N>, dim3((unsigned)blocks), dim3(64),
                            Lds<N>::bytes, s, it);
         return hipGetLastError();
-    }
-};
-
-template <int N> struct LdsSize {
-    static hipError_t run(int32_t *out)
-    {
-        *out = Lds<N>::bytes;
-        return hipSuccess;
     }
 };
 
@@ -558,30 +599,13 @@ Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double 
 
 } // namespace
 
-int32_t batch_blocks_per_cu(int32_t lds_bytes)
+hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_d, double gamma,
+                         double beta, double bias_v, double n_sigma, hipStream_t s)
 {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel, 64, (size_t)lds_bytes) !=
-        hipSuccess)
-        return 1;
-    return blocks > 0 ? blocks : 1;
-}
-
-int32_t lds_bytes_for_order(int32_t order)
-{
-    int32_t b = 0;
-    if (dispatch<LdsSize>(order, &b) != hipSuccess) return -1;
-    return b;
-}
-
-int32_t batch_lds_bytes(int32_t max_order)
-{
-    int32_t m = 0;
-    for (int n = 1; n <= max_order; ++n) {
-        const int32_t b = lds_bytes_for_order(n);
-        if (b > m) m = b;
-    }
-    return m;
+    const double h = 2.0 * t_half / (n_grid - 1);
+    hipLaunchKernelGGL(tables_kernel, dim3((unsigned)n_grid), dim3(256), 0, s, tab, n_grid, t_half,
+                       h, eps_d, gamma, beta, bias_v, n_sigma);
+    return hipGetLastError();
 }
 
 hipError_t launch_order(const ItemDesc &it, hipStream_t s)
@@ -617,14 +641,41 @@ hipError_t launch_points_direct(const double *tab, int32_t n_grid, double t_half
                                         u, n_points, f, s);
 }
 
-hipError_t launch_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
-                        int32_t grid_blocks, int32_t lds_bytes, hipStream_t s)
+namespace {
+template <int N> struct BatchLaunch {
+    static hipError_t run(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
+                          int32_t grid_blocks, hipStream_t s)
+    {
+        const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
+        hipLaunchKernelGGL(batch_kernel<N>, dim3((unsigned)g), dim3(64), Lds<N>::bytes, s,
+                           items_dev, tiles_dev, n_tiles);
+        return hipGetLastError();
+    }
+};
+template <int N> struct BatchOcc {
+    static hipError_t run(int32_t *out)
+    {
+        int blocks = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<N>, 64,
+                                                                    (size_t)Lds<N>::bytes);
+        *out = (e == hipSuccess && blocks > 0) ? blocks : 1;
+        return hipSuccess;
+    }
+};
+} // namespace
+
+hipError_t launch_batch(int32_t order, const ItemDesc *items_dev, const TileRef *tiles_dev,
+                        int64_t n_tiles, int32_t grid_blocks, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)g), dim3(64), (unsigned)lds_bytes, s,
-                       items_dev, tiles_dev, n_tiles);
-    return hipGetLastError();
+    return dispatch<BatchLaunch>(order, items_dev, tiles_dev, n_tiles, grid_blocks, s);
+}
+
+int32_t batch_blocks_per_cu(int32_t order)
+{
+    int32_t b = 1;
+    if (dispatch<BatchOcc>(order, &b) != hipSuccess) return 1;
+    return b;
 }
 
 } // namespace qqmc

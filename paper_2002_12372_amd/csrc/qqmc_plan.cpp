@@ -1,20 +1,23 @@
 /*
  * qqmc_plan.cpp -- batched form: many (parameter point, order) integrals in
- * one persistent launch, captured in a HIP graph.
+ * one HIP-graph launch.
  *
- * Every item is cut into the same tiles qqmc_eval_order would use for the
+ * Every item is cut into the same tiles qqmc_eval_order_async uses for the
  * same tile length, so each tile sum, and therefore each per-shift sum, is
- * bitwise the one the single-order launch produces.  The tiles of all items
- * are listed most expensive first (cost model below) and dealt round robin
- * to a fixed set of resident workgroups (workgroup b takes list entries
- * b, b + G, ...), which balances
+ * bitwise the one the single-order launch produces.  Tiles are grouped by
+ * order; inside a group they are sorted by decreasing cost (cost model
+ * below) and dealt round robin to the resident workgroups of one persistent
+ * launch of that order's kernel (workgroup b takes entries b, b + G, ...).
+ * The groups run as concurrent branches of the graph (at most four branch
+ * streams, groups assigned greedily to the least loaded branch, most
+ * expensive first), joined before the per-shift reduction.  This balances
  * the very uneven per-item work (2^n index vectors per point, 2^16..2^22
- * points per item).
+ * points per item) while every kernel keeps the register allocation of its
+ * own order.
  *
- * The tile length and the number of resident workgroups are chosen by a
- * small autotuner when the caller passes 0: each candidate is timed on a
- * subsample of the tile list (every k-th tile) and the fastest per point is
- * kept.
+ * The tile length and the share of resident workgroups are chosen by a small
+ * autotuner when the caller passes 0: each candidate is timed on a subsample
+ * of every group (every k-th tile) and the fastest per point is kept.
  */
 #include <algorithm>
 #include <cmath>
@@ -28,9 +31,11 @@ namespace qqmc {
 
 namespace {
 
-/* Probability that the warped point lies in the domain: sum of n
- * exponential(1/tau) spacings below t, i.e. the regularised lower incomplete
- * gamma function P(n, t/tau) (series). */
+constexpr int kBranches = 4;
+
+/* Probability that the warped point lies in the domain: the sum of n
+ * exponential(tau) spacings stays below t, i.e. the regularised lower
+ * incomplete gamma function P(n, t/tau) (series). */
 double inside_fraction(int n, double t_over_tau)
 {
     double term = 1.0, sum = 1.0;
@@ -41,16 +46,6 @@ double inside_fraction(int n, double t_over_tau)
     }
     double lg = std::lgamma((double)n + 1.0);
     return std::exp(n * std::log(t_over_tau) - t_over_tau - lg) * sum;
-}
-
-/* Relative cost of one tile: warp for every point, the Keldysh sum (about
- * 12 complex multiply-adds per index vector plus O(n^2) setup) for the
- * points inside the domain. */
-double tile_cost(const ItemDesc &d)
-{
-    const double frac = d.mode == QQMC_MODE_CHARGE ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;
-    const double per_point = 8.0 * d.order + frac * (48.0 * std::ldexp(1.0, d.order) + 30.0 * d.order * d.order);
-    return per_point * d.tile_len;
 }
 
 struct Buffers {
@@ -70,7 +65,23 @@ struct Buffers {
     }
 };
 
+struct Group {
+    int32_t order = 0, branch = 0, grid = 0;
+    int64_t offset = 0, count = 0;
+    double cost = 0.0;
+};
+
 } // namespace
+
+/* Relative cost of one tile: warp for every point, the Keldysh sum (about
+ * 140 FP64 operations per index vector plus O(n^2) setup) for the points
+ * inside the domain. */
+double tile_cost(const ItemDesc &d)
+{
+    const double frac = d.mode == QQMC_MODE_CHARGE ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;
+    const double per_point = 8.0 * d.order + frac * (140.0 * std::ldexp(1.0, d.order) + 30.0 * d.order * d.order);
+    return per_point * d.tile_len;
+}
 
 } // namespace qqmc
 
@@ -79,11 +90,15 @@ struct qqmc_plan_s {
     std::vector<std::vector<double>> shifts;
     std::vector<int64_t> shift_base;
     std::vector<double> inv_n;
-    std::vector<qqmc::TileRef> tiles;
+    std::vector<qqmc::TileRef> tiles;    /* grouped by order */
+    std::vector<qqmc::Group> groups;
     qqmc::Buffers buf;
     int64_t n_tiles = 0, n_points = 0, total_shifts = 0;
-    int32_t tile_len = 0, grid_blocks = 0, lds_bytes = 0, max_shifts = 0, max_order = 0;
+    int32_t tile_len = 0, grid_blocks = 0, max_shifts = 0, n_cu = 1;
+    double grid_share = 1.0;
     hipStream_t cap = nullptr;
+    hipStream_t branch[qqmc::kBranches] = {};
+    hipEvent_t fork = nullptr, join[qqmc::kBranches] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
@@ -99,6 +114,11 @@ struct qqmc_plan_s {
     {
         drop_graph();
         buf.release();
+        if (fork) hipEventDestroy(fork);
+        for (auto &e : join)
+            if (e) hipEventDestroy(e);
+        for (auto &s : branch)
+            if (s) hipStreamDestroy(s);
         if (cap) hipStreamDestroy(cap);
     }
 };
@@ -106,14 +126,49 @@ struct qqmc_plan_s {
 namespace qqmc {
 namespace {
 
+/* Groups of a tile list by order, sorted within a group by decreasing
+ * cost, groups assigned to branches (longest processing time first). */
+void make_groups(qqmc_plan_s *p, const std::vector<std::pair<double, TileRef>> &all,
+                 std::vector<TileRef> &tiles, std::vector<Group> &groups)
+{
+    std::vector<std::vector<std::pair<double, TileRef>>> by(QQMC_MAX_ORDER + 1);
+    for (auto &c : all) by[p->items[c.second.item].order].push_back(c);
+    tiles.clear();
+    groups.clear();
+    for (int n = 1; n <= QQMC_MAX_ORDER; ++n) {
+        auto &v = by[n];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        Group g;
+        g.order = n;
+        g.offset = (int64_t)tiles.size();
+        g.count = (int64_t)v.size();
+        for (auto &c : v) {
+            g.cost += c.first;
+            tiles.push_back(c.second);
+        }
+        groups.push_back(g);
+    }
+    std::vector<size_t> idx(groups.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return groups[a].cost > groups[b].cost; });
+    double load[kBranches] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i : idx) {
+        int best = 0;
+        for (int b = 1; b < kBranches; ++b)
+            if (load[b] < load[best]) best = b;
+        groups[i].branch = best;
+        load[best] += groups[i].cost;
+    }
+}
+
 /* Lays out tiles for tile length `tl` and (re)allocates the device buffers. */
 qqmc_status layout(qqmc_plan_s *p, int32_t tl)
 {
     p->buf.release();
     p->tile_len = tl;
-    p->tiles.clear();
     int64_t tile_off = 0;
-    std::vector<std::pair<double, TileRef>> order;
+    std::vector<std::pair<double, TileRef>> all;
     for (size_t i = 0; i < p->items.size(); ++i) {
         ItemDesc &d = p->items[i];
         const int64_t N = (int64_t)d.mask + 1;
@@ -126,13 +181,11 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
             r.item = (int32_t)i;
             r.pad = 0;
             r.tile = t;
-            order.push_back({c, r});
+            all.push_back({c, r});
         }
         tile_off += d.n_tiles;
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const auto &a, const auto &b) { return a.first > b.first; });
-    for (auto &o : order) p->tiles.push_back(o.second);
+    make_groups(p, all, p->tiles, p->groups);
     p->n_tiles = (int64_t)p->tiles.size();
 
     size_t n_shift_vals = 0;
@@ -169,9 +222,28 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
     return QQMC_OK;
 }
 
-hipError_t enqueue(qqmc_plan_s *p, const TileRef *tiles, int64_t n_tiles, int32_t grid, hipStream_t s)
+/* Fork to the branch streams, one persistent launch per order group, join,
+ * then the per-shift reduction, all ordered after the work already on s. */
+hipError_t enqueue(qqmc_plan_s *p, const std::vector<Group> &groups, const TileRef *d_tiles,
+                   double share, hipStream_t s)
 {
-    hipError_t e = launch_batch(p->buf.items, tiles, n_tiles, grid, p->lds_bytes, s);
+    hipError_t e = hipEventRecord(p->fork, s);
+    bool used[kBranches] = {false, false, false, false};
+    for (const Group &g : groups) {
+        if (e != hipSuccess) break;
+        hipStream_t b = p->branch[g.branch];
+        if (!used[g.branch]) {
+            e = hipStreamWaitEvent(b, p->fork, 0);
+            used[g.branch] = true;
+        }
+        int32_t grid = (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.order));
+        if (e == hipSuccess) e = launch_batch(g.order, p->buf.items, d_tiles + g.offset, g.count, grid, b);
+    }
+    for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
+        if (!used[b]) continue;
+        e = hipEventRecord(p->join[b], p->branch[b]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[b], 0);
+    }
     if (e == hipSuccess)
         e = launch_shift_reduce(p->buf.items, (int32_t)p->items.size(), p->buf.base, p->buf.shift_sums,
                                 p->max_shifts, s);
@@ -183,7 +255,7 @@ qqmc_status capture(qqmc_plan_s *p)
     p->drop_graph();
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    hipError_t le = enqueue(p, p->buf.tiles, p->n_tiles, p->grid_blocks, p->cap);
+    hipError_t le = enqueue(p, p->groups, p->buf.tiles, p->grid_share, p->cap);
     e = hipStreamEndCapture(p->cap, &p->graph);
     if (le != hipSuccess) return hip_error(le, "plan capture launch");
     if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
@@ -192,20 +264,28 @@ qqmc_status capture(qqmc_plan_s *p)
     return QQMC_OK;
 }
 
-/* Times the plan on every k-th tile with `grid` workgroups; seconds per
- * lattice point of the subsample. */
-double probe(qqmc_plan_s *p, int32_t grid)
+/* Times the plan on a subsample (every k-th tile of each group) with the
+ * given workgroup share; seconds per lattice point. */
+double probe(qqmc_plan_s *p, double share)
 {
     const int64_t want = 4096;
     const int64_t step = p->n_tiles > want ? p->n_tiles / want : 1;
     std::vector<TileRef> sub;
+    std::vector<Group> groups;
     double pts = 0.0;
-    for (int64_t t = 0; t < p->n_tiles; t += step) {
-        sub.push_back(p->tiles[t]);
-        pts += p->items[p->tiles[t].item].tile_len;
+    for (const Group &g : p->groups) {
+        Group h = g;
+        h.offset = (int64_t)sub.size();
+        for (int64_t t = 0; t < g.count; t += step) {
+            const TileRef r = p->tiles[g.offset + t];
+            sub.push_back(r);
+            pts += p->items[r.item].tile_len;
+        }
+        h.count = (int64_t)sub.size() - h.offset;
+        if (h.count) groups.push_back(h);
     }
     TileRef *d_sub = nullptr;
-    if (hipMalloc(&d_sub, sizeof(TileRef) * sub.size()) != hipSuccess) return 1e30;
+    if (sub.empty() || hipMalloc(&d_sub, sizeof(TileRef) * sub.size()) != hipSuccess) return 1e30;
     hipMemcpy(d_sub, sub.data(), sizeof(TileRef) * sub.size(), hipMemcpyHostToDevice);
     hipEvent_t a, b;
     hipEventCreate(&a);
@@ -213,7 +293,7 @@ double probe(qqmc_plan_s *p, int32_t grid)
     double best = 1e30;
     for (int rep = 0; rep < 2; ++rep) {
         hipEventRecord(a, p->cap);
-        hipError_t e = enqueue(p, d_sub, (int64_t)sub.size(), grid, p->cap);
+        hipError_t e = enqueue(p, groups, d_sub, share, p->cap);
         hipEventRecord(b, p->cap);
         hipStreamSynchronize(p->cap);
         float ms = 0.0f;
@@ -238,7 +318,7 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
 {
     (void)stream;
     if (!items || n_items < 1 || !out) return set_error(QQMC_EINVAL, "no items");
-    if (tile_len != 0 && (tile_len < 64 || tile_len % 64 != 0 || (tile_len & (tile_len - 1)) != 0))
+    if (tile_len != 0 && (tile_len < 64 || (tile_len & (tile_len - 1)) != 0))
         return set_error(QQMC_EINVAL, "tile_len must be 0 or a power of two >= 64");
     if (grid_blocks < 0) return set_error(QQMC_EINVAL, "grid_blocks < 0");
     auto *p = new (std::nothrow) qqmc_plan_s();
@@ -263,44 +343,50 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
         p->inv_n.push_back(v.desc.inv_n);
         sb += v.desc.n_shifts;
         p->max_shifts = std::max(p->max_shifts, v.desc.n_shifts);
-        p->max_order = std::max(p->max_order, v.desc.order);
         p->n_points += (int64_t)(v.desc.mask + 1) * v.desc.n_shifts;
     }
     p->total_shifts = sb;
-    p->lds_bytes = batch_lds_bytes(p->max_order);
     hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
+        e = hipStreamCreateWithFlags(&p->branch[b], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete p;
-        return hip_error(e, "hipStreamCreate");
+        return hip_error(e, "plan streams");
     }
     hipDeviceProp_t prop;
     hipGetDeviceProperties(&prop, p->device);
-    const int32_t occ = batch_blocks_per_cu(p->lds_bytes);
-    const int32_t full = prop.multiProcessorCount * occ;
+    p->n_cu = prop.multiProcessorCount;
 
+    /* grid_blocks given: it caps the workgroups of every order's launch,
+     * expressed as a share of that order's full residency */
     std::vector<int32_t> tls = tile_len ? std::vector<int32_t>{tile_len}
                                         : std::vector<int32_t>{256, 512, 1024, 2048};
-    std::vector<int32_t> grids = grid_blocks ? std::vector<int32_t>{grid_blocks}
-                                             : std::vector<int32_t>{full, full / 2 > 0 ? full / 2 : 1};
-    int32_t best_tl = tls[0], best_grid = grids[0];
-    if (tls.size() * grids.size() > 1) {
+    std::vector<double> shares = {1.0, 0.5};
+    if (grid_blocks) shares = {std::min(1.0, (double)grid_blocks / (p->n_cu * batch_blocks_per_cu(8)))};
+    int32_t best_tl = tls[0];
+    double best_share = shares[0];
+    if (tls.size() * shares.size() > 1) {
         double best = 1e30;
         for (int32_t tl : tls) {
             if (qqmc_status st = layout(p, tl)) {
                 delete p;
                 return st;
             }
-            for (int32_t g : grids) {
-                const double v = probe(p, g);
+            for (double sh : shares) {
+                const double v = probe(p, sh);
                 if (v < best) {
                     best = v;
                     best_tl = tl;
-                    best_grid = g;
+                    best_share = sh;
                 }
             }
         }
     }
-    p->grid_blocks = best_grid;
+    p->grid_share = best_share;
+    p->grid_blocks = (int32_t)std::max(1.0, best_share * p->n_cu * batch_blocks_per_cu(8));
     if (qqmc_status st = layout(p, best_tl)) {
         delete p;
         return st;

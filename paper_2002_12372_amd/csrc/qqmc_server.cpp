@@ -5,20 +5,27 @@
  * A scheduler thread owns the device work:
  *   admission   requests queue in arrival order; the head is admitted while
  *               a slot is free and its device footprint (tables unless
- *               cached, shifts, tile sums) fits in the HBM budget;
+ *               cached, shifts, tile sums) fits in the HBM budget.  Tables
+ *               are built on the device by a kernel on the server stream;
+ *               per-request buffers come from the stream-ordered allocator,
+ *               so admission never waits for the GPU;
  *   batching    every launch takes tiles from all admitted requests in turn
  *               (round robin, up to a per-launch cost budget), so requests
- *               that arrive while others run share the next launches;
- *   pipelining  two launches are in flight on the server's stream, so the
- *               host prepares launch k+1 while launch k runs;
- *   completion  when all tiles of a request are done its per-shift sums are
- *               reduced on the device and copied back, and its device
- *               buffers are released.
+ *               that arrive while others run share the next launches.  The
+ *               tiles of a launch are grouped by order and run as concurrent
+ *               persistent launches of each order's kernel on branch
+ *               streams, joined on the server stream;
+ *   completion  a request whose last tile is in a launch gets its per-shift
+ *               reduction and the copy of its K sums into pinned host memory
+ *               appended to that launch, so its result is on the host when
+ *               the launch's event fires;
+ *   pipelining  two launches are in flight, so the host prepares launch k+1
+ *               while launch k runs.
  * Green's-function tables stay on the device, shared by requests with the
  * same dot parameters (reference counted; unused ones are evicted first when
  * memory runs short).  Tiles are the same as qqmc_eval_order_async's for the
  * server's tile length, so every result equals the solo evaluation bit for
- * bit.
+ * bit, alone or in the mix.
  */
 #include <algorithm>
 #include <chrono>
@@ -26,7 +33,6 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -39,7 +45,7 @@
 namespace qqmc {
 namespace {
 
-using Clock = std::chrono::steady_clock;
+constexpr int kBranches = 4;
 
 struct TableEntry {
     qqmc_tables t = nullptr;
@@ -56,9 +62,8 @@ struct Request {
     ItemDesc desc{};
     std::vector<double> shifts;
     TableKey key;
-    size_t footprint = 0;
-    double *d_shifts = nullptr, *d_tiles = nullptr, *d_sums = nullptr;
-    int64_t next_tile = 0, done_tiles = 0;
+    double *d_shifts = nullptr, *d_tiles = nullptr;
+    int64_t next_tile = 0;
     double t_submit = 0.0, t_done = 0.0;
     bool finished = false;
     qqmc_status status = QQMC_OK;
@@ -67,14 +72,34 @@ struct Request {
     double q_stderr = 0.0;
 };
 
+/* Pinned host staging and device buffers of one launch slot. */
 struct Launch {
-    hipEvent_t done = nullptr;
-    ItemDesc *d_items = nullptr;
-    TileRef *d_tiles = nullptr;
-    size_t cap_items = 0, cap_tiles = 0;
-    std::vector<std::pair<std::shared_ptr<Request>, int64_t>> issued; /* request, #tiles */
+    hipEvent_t done = nullptr, fork = nullptr, join[kBranches] = {};
+    ItemDesc *h_items = nullptr, *d_items = nullptr; /* batch items, then completing items */
+    TileRef *h_tiles = nullptr, *d_tiles = nullptr;
+    int64_t *h_base = nullptr, *d_base = nullptr;
+    double *h_sums = nullptr, *d_sums = nullptr;
+    size_t cap_items = 0, cap_tiles = 0, cap_base = 0, cap_sums = 0;
+    std::vector<std::shared_ptr<Request>> completing;
+    std::vector<int64_t> completing_base;
     bool busy = false;
+    uint64_t seq = 0;
 };
+
+/* Grows a pinned host / device buffer pair to at least `need` elements. */
+template <typename T> hipError_t grow_pair(T **h, T **d, size_t *cap, size_t need)
+{
+    if (need <= *cap) return hipSuccess;
+    const size_t n = std::max<size_t>(need, 2 * *cap);
+    if (*h) hipHostFree(*h);
+    if (*d) hipFree(*d);
+    *h = nullptr;
+    *d = nullptr;
+    hipError_t e = hipHostMalloc((void **)h, sizeof(T) * n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)d, sizeof(T) * n);
+    *cap = e == hipSuccess ? n : 0;
+    return e;
+}
 
 } // namespace
 } // namespace qqmc
@@ -83,23 +108,21 @@ struct qqmc_server_s {
     size_t budget = 0, used = 0;
     int32_t max_slots = 1, tile_len = 1024;
     double launch_cost = 0.0;
-    int device = 0;
+    int device = 0, n_cu = 1;
     hipStream_t stream = nullptr;
-    int32_t grid = 0, lds = 0;
+    hipStream_t branch[qqmc::kBranches] = {};
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
-    uint64_t next_ticket = 1, use_clock = 0;
+    uint64_t next_ticket = 1, use_clock = 0, next_seq = 1;
     std::deque<std::shared_ptr<qqmc::Request>> waiting;
     std::vector<std::shared_ptr<qqmc::Request>> active;
     std::map<uint64_t, std::shared_ptr<qqmc::Request>> all;
     std::map<qqmc::TableKey, qqmc::TableEntry> tables;
     qqmc::Launch launches[2];
-    int next_launch = 0;
     std::thread worker;
-    std::string fatal;
 
     double now() const
     {
@@ -115,7 +138,15 @@ size_t table_bytes(const qqmc_dot &d) { return sizeof(double) * 4 * (size_t)d.n_
 size_t request_bytes(const Request &r, bool need_table)
 {
     return (need_table ? table_bytes(r.dot) : 0) + sizeof(double) * r.shifts.size() +
-           sizeof(double) * 2 * (size_t)r.desc.n_tiles + sizeof(double) * 2 * (size_t)r.desc.n_shifts;
+           sizeof(double) * 2 * (size_t)r.desc.n_tiles;
+}
+
+void fail(qqmc_server_s *s, const std::shared_ptr<Request> &r, qqmc_status st)
+{
+    r->status = st;
+    r->finished = true;
+    r->t_done = s->now();
+    s->cv_done.notify_all();
 }
 
 /* Frees unused cached tables (oldest first) until `need` more bytes fit. */
@@ -124,16 +155,18 @@ void evict_tables(qqmc_server_s *s, size_t need)
     while (s->used + need > s->budget) {
         auto victim = s->tables.end();
         for (auto it = s->tables.begin(); it != s->tables.end(); ++it)
-            if (it->second.refs == 0 && (victim == s->tables.end() || it->second.last_use < victim->second.last_use))
+            if (it->second.refs == 0 &&
+                (victim == s->tables.end() || it->second.last_use < victim->second.last_use))
                 victim = it;
         if (victim == s->tables.end()) return;
         s->used -= victim->second.bytes;
+        hipStreamSynchronize(s->stream); /* no launch may still read it */
         qqmc_free_tables(victim->second.t);
         s->tables.erase(victim);
     }
 }
 
-/* Admits waiting requests in arrival order (called with the lock held). */
+/* Admits waiting requests in arrival order (lock held). */
 void admit(qqmc_server_s *s)
 {
     while (!s->waiting.empty() && (int32_t)s->active.size() < s->max_slots) {
@@ -148,10 +181,7 @@ void admit(qqmc_server_s *s)
             qqmc_tables t = nullptr;
             qqmc_status st = qqmc_make_tables(&r->dot, s->stream, &t);
             if (st != QQMC_OK) {
-                r->status = st;
-                r->finished = true;
-                r->t_done = s->now();
-                s->cv_done.notify_all();
+                fail(s, r, st);
                 continue;
             }
             TableEntry e;
@@ -164,18 +194,15 @@ void admit(qqmc_server_s *s)
         it->second.refs += 1;
         it->second.last_use = ++s->use_clock;
         fill_item_tables(r->desc, it->second.t);
-        hipError_t e = hipMalloc(&r->d_shifts, sizeof(double) * r->shifts.size());
-        if (e == hipSuccess) e = hipMalloc(&r->d_tiles, sizeof(double) * 2 * r->desc.n_tiles);
-        if (e == hipSuccess) e = hipMalloc(&r->d_sums, sizeof(double) * 2 * r->desc.n_shifts);
+        hipError_t e = hipMallocAsync((void **)&r->d_shifts, sizeof(double) * r->shifts.size(), s->stream);
+        if (e == hipSuccess)
+            e = hipMallocAsync((void **)&r->d_tiles, sizeof(double) * 2 * r->desc.n_tiles, s->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->d_shifts, r->shifts.data(), sizeof(double) * r->shifts.size(),
                                hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) {
-            r->status = hip_error(e, "server admission");
-            r->finished = true;
-            r->t_done = s->now();
             it->second.refs -= 1;
-            s->cv_done.notify_all();
+            fail(s, r, hip_error(e, "server admission"));
             continue;
         }
         r->desc.shifts = r->d_shifts;
@@ -185,73 +212,17 @@ void admit(qqmc_server_s *s)
     }
 }
 
-void finish(qqmc_server_s *s, const std::shared_ptr<Request> &r)
+/* Fills and submits launch slot L with tiles of the active requests (lock
+ * held).  Returns false if there was nothing to issue. */
+bool issue(qqmc_server_s *s, Launch &L)
 {
-    /* device reduction of the tile sums, then the host epilogue */
-    ItemDesc *d_item = nullptr;
-    int64_t *d_base = nullptr;
-    const int64_t zero = 0;
-    hipError_t e = hipMalloc(&d_item, sizeof(ItemDesc));
-    if (e == hipSuccess) e = hipMalloc(&d_base, sizeof(int64_t));
-    if (e == hipSuccess) e = hipMemcpyAsync(d_item, &r->desc, sizeof(ItemDesc), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_base, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_shift_reduce(d_item, 1, d_base, r->d_sums, r->desc.n_shifts, s->stream);
-    std::vector<double> sums(2 * (size_t)r->desc.n_shifts);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sums.data(), r->d_sums, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (d_item) hipFree(d_item);
-    if (d_base) hipFree(d_base);
-    if (e != hipSuccess) {
-        r->status = hip_error(e, "server completion");
-    } else {
-        const int K = r->desc.n_shifts;
-        const double N = (double)r->desc.mask + 1.0;
-        r->q_shift.resize(2 * (size_t)K);
-        double mr = 0.0, mi = 0.0;
-        for (int k = 0; k < K; ++k) {
-            r->q_shift[2 * k] = sums[2 * k] / N;
-            r->q_shift[2 * k + 1] = sums[2 * k + 1] / N;
-            mr += r->q_shift[2 * k];
-            mi += r->q_shift[2 * k + 1];
-        }
-        mr /= K;
-        mi /= K;
-        r->q_mean[0] = mr;
-        r->q_mean[1] = mi;
-        double ss = 0.0;
-        for (int k = 0; k < K; ++k) ss += (r->q_shift[2 * k] - mr) * (r->q_shift[2 * k] - mr);
-        r->q_stderr = K > 1 ? std::sqrt(ss / (K - 1)) / std::sqrt((double)K) : std::nan("");
-    }
-    hipFree(r->d_shifts);
-    hipFree(r->d_tiles);
-    hipFree(r->d_sums);
-    r->d_shifts = r->d_tiles = r->d_sums = nullptr;
-    s->used -= request_bytes(*r, false);
-    auto it = s->tables.find(r->key);
-    if (it != s->tables.end()) it->second.refs -= 1;
-    r->t_done = s->now();
-    r->finished = true;
-}
-
-/* Fills launch slot L with tiles of the active requests (lock held).
- * Returns false if there was nothing to issue. */
-bool build_launch(qqmc_server_s *s, Launch &L, std::vector<ItemDesc> &items, std::vector<TileRef> &tiles)
-{
-    items.clear();
-    tiles.clear();
-    L.issued.clear();
     std::vector<std::shared_ptr<Request>> open;
     for (auto &r : s->active)
         if (r->next_tile < r->desc.n_tiles) open.push_back(r);
     if (open.empty()) return false;
     std::vector<double> cost(open.size());
     std::vector<int64_t> take(open.size(), 0);
-    for (size_t i = 0; i < open.size(); ++i) {
-        const ItemDesc &d = open[i]->desc;
-        const double frac = 0.5;
-        cost[i] = d.tile_len * (8.0 * d.order + frac * (48.0 * std::ldexp(1.0, d.order) + 30.0 * d.order * d.order));
-    }
+    for (size_t i = 0; i < open.size(); ++i) cost[i] = tile_cost(open[i]->desc);
     /* round robin, one tile per request per pass, until the cost budget */
     double spent = 0.0;
     bool progress = true;
@@ -265,6 +236,12 @@ bool build_launch(qqmc_server_s *s, Launch &L, std::vector<ItemDesc> &items, std
             }
         }
     }
+    /* items of the launch, tiles grouped by order */
+    std::vector<ItemDesc> items;
+    std::vector<std::vector<TileRef>> by(QQMC_MAX_ORDER + 1);
+    L.completing.clear();
+    L.completing_base.clear();
+    int64_t sums = 0;
     for (size_t i = 0; i < open.size(); ++i) {
         if (!take[i]) continue;
         const int32_t idx = (int32_t)items.size();
@@ -274,60 +251,132 @@ bool build_launch(qqmc_server_s *s, Launch &L, std::vector<ItemDesc> &items, std
             t.item = idx;
             t.pad = 0;
             t.tile = open[i]->next_tile + k;
-            tiles.push_back(t);
+            by[open[i]->desc.order].push_back(t);
         }
         open[i]->next_tile += take[i];
-        L.issued.push_back({open[i], take[i]});
+        if (open[i]->next_tile == open[i]->desc.n_tiles) {
+            L.completing.push_back(open[i]);
+            L.completing_base.push_back(sums);
+            sums += open[i]->desc.n_shifts;
+        }
     }
-    /* most expensive tiles first inside the launch */
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const TileRef &a, const TileRef &b) {
-        return items[a.item].order > items[b.item].order;
-    });
+    std::vector<TileRef> tiles;
+    struct G {
+        int32_t order;
+        int64_t off, cnt;
+    };
+    std::vector<G> groups;
+    for (int n = QQMC_MAX_ORDER; n >= 1; --n) {
+        if (by[n].empty()) continue;
+        groups.push_back({n, (int64_t)tiles.size(), (int64_t)by[n].size()});
+        tiles.insert(tiles.end(), by[n].begin(), by[n].end());
+    }
+    const size_t n_items = items.size() + L.completing.size();
+    hipError_t e = grow_pair(&L.h_items, &L.d_items, &L.cap_items, n_items);
+    if (e == hipSuccess) e = grow_pair(&L.h_tiles, &L.d_tiles, &L.cap_tiles, tiles.size());
+    if (e == hipSuccess) e = grow_pair(&L.h_base, &L.d_base, &L.cap_base, L.completing.size() + 1);
+    if (e == hipSuccess) e = grow_pair(&L.h_sums, &L.d_sums, &L.cap_sums, 2 * (size_t)(sums + 1));
+    if (e == hipSuccess) {
+        std::memcpy(L.h_items, items.data(), sizeof(ItemDesc) * items.size());
+        for (size_t c = 0; c < L.completing.size(); ++c) {
+            L.h_items[items.size() + c] = L.completing[c]->desc;
+            L.h_base[c] = L.completing_base[c];
+        }
+        std::memcpy(L.h_tiles, tiles.data(), sizeof(TileRef) * tiles.size());
+        e = hipMemcpyAsync(L.d_items, L.h_items, sizeof(ItemDesc) * n_items, hipMemcpyHostToDevice, s->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L.d_tiles, L.h_tiles, sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess && !L.completing.empty())
+        e = hipMemcpyAsync(L.d_base, L.h_base, sizeof(int64_t) * L.completing.size(),
+                           hipMemcpyHostToDevice, s->stream);
+    /* fork: one persistent launch per order on the branch streams */
+    if (e == hipSuccess) e = hipEventRecord(L.fork, s->stream);
+    bool used[kBranches] = {false, false, false, false};
+    for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
+        const int b = (int)(g % kBranches);
+        if (!used[b]) {
+            e = hipStreamWaitEvent(s->branch[b], L.fork, 0);
+            used[b] = true;
+        }
+        const int32_t grid = s->n_cu * batch_blocks_per_cu(groups[g].order);
+        if (e == hipSuccess)
+            e = launch_batch(groups[g].order, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
+                             s->branch[b]);
+    }
+    for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
+        if (!used[b]) continue;
+        e = hipEventRecord(L.join[b], s->branch[b]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, L.join[b], 0);
+    }
+    /* completions: per-shift reduction and copy of the sums to the host */
+    if (e == hipSuccess && !L.completing.empty()) {
+        int32_t kmax = 1;
+        for (auto &r : L.completing) kmax = std::max(kmax, r->desc.n_shifts);
+        e = launch_shift_reduce(L.d_items + items.size(), (int32_t)L.completing.size(), L.d_base,
+                                L.d_sums, kmax, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L.h_sums, L.d_sums, sizeof(double) * 2 * sums, hipMemcpyDeviceToHost,
+                               s->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(L.done, s->stream);
+    if (e != hipSuccess) {
+        const qqmc_status st = hip_error(e, "server launch");
+        for (auto &r : L.completing) r->status = st;
+        hipEventRecord(L.done, s->stream);
+    }
+    L.busy = true;
+    L.seq = s->next_seq++;
     return true;
 }
 
-hipError_t submit_launch(qqmc_server_s *s, Launch &L, const std::vector<ItemDesc> &items,
-                         const std::vector<TileRef> &tiles)
-{
-    hipError_t e = hipSuccess;
-    if (items.size() > L.cap_items) {
-        if (L.d_items) hipFree(L.d_items);
-        L.cap_items = std::max<size_t>(items.size(), 2 * L.cap_items);
-        e = hipMalloc(&L.d_items, sizeof(ItemDesc) * L.cap_items);
-    }
-    if (e == hipSuccess && tiles.size() > L.cap_tiles) {
-        if (L.d_tiles) hipFree(L.d_tiles);
-        L.cap_tiles = std::max<size_t>(tiles.size(), 2 * L.cap_tiles);
-        e = hipMalloc(&L.d_tiles, sizeof(TileRef) * L.cap_tiles);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(L.d_items, items.data(), sizeof(ItemDesc) * items.size(), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(L.d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) {
-        int32_t grid = s->grid;
-        if ((int64_t)grid > (int64_t)tiles.size()) grid = (int32_t)tiles.size();
-        e = launch_batch(L.d_items, L.d_tiles, (int64_t)tiles.size(), grid, s->lds, s->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(L.done, s->stream);
-    return e;
-}
-
+/* Waits for launch L (lock released meanwhile) and finishes the requests it
+ * completed. */
 void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
 {
     lk.unlock();
     hipEventSynchronize(L.done);
     lk.lock();
     L.busy = false;
-    for (auto &pr : L.issued) pr.first->done_tiles += pr.second;
-    L.issued.clear();
-    std::vector<std::shared_ptr<Request>> still;
-    for (auto &r : s->active) {
-        if (r->done_tiles == r->desc.n_tiles) finish(s, r);
-        else still.push_back(r);
+    const double now = s->now();
+    for (size_t c = 0; c < L.completing.size(); ++c) {
+        auto &r = L.completing[c];
+        if (r->status == QQMC_OK) {
+            const int K = r->desc.n_shifts;
+            const double N = (double)r->desc.mask + 1.0;
+            const double *sums = L.h_sums + 2 * L.completing_base[c];
+            r->q_shift.resize(2 * (size_t)K);
+            double mr = 0.0, mi = 0.0;
+            for (int k = 0; k < K; ++k) {
+                r->q_shift[2 * k] = sums[2 * k] / N;
+                r->q_shift[2 * k + 1] = sums[2 * k + 1] / N;
+                mr += r->q_shift[2 * k];
+                mi += r->q_shift[2 * k + 1];
+            }
+            mr /= K;
+            mi /= K;
+            r->q_mean[0] = mr;
+            r->q_mean[1] = mi;
+            double ss = 0.0;
+            for (int k = 0; k < K; ++k) ss += (r->q_shift[2 * k] - mr) * (r->q_shift[2 * k] - mr);
+            r->q_stderr = K > 1 ? std::sqrt(ss / (K - 1)) / std::sqrt((double)K) : std::nan("");
+        }
+        hipFreeAsync(r->d_shifts, s->stream);
+        hipFreeAsync(r->d_tiles, s->stream);
+        r->d_shifts = r->d_tiles = nullptr;
+        s->used -= request_bytes(*r, false);
+        auto it = s->tables.find(r->key);
+        if (it != s->tables.end()) it->second.refs -= 1;
+        r->t_done = now;
+        r->finished = true;
     }
-    if (still.size() != s->active.size()) {
+    if (!L.completing.empty()) {
+        std::vector<std::shared_ptr<Request>> still;
+        for (auto &r : s->active)
+            if (!r->finished) still.push_back(r);
         s->active.swap(still);
+        L.completing.clear();
         s->cv_done.notify_all();
     }
 }
@@ -335,44 +384,31 @@ void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
 void worker_loop(qqmc_server_s *s)
 {
     hipSetDevice(s->device);
-    std::vector<ItemDesc> items;
-    std::vector<TileRef> tiles;
-    uint64_t seq[2] = {0, 0}, next_seq = 1;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         admit(s);
         int slot = -1;
         for (int i = 0; i < 2; ++i)
-            if (!s->launches[i].busy) { slot = i; break; }
-        if (slot >= 0 && build_launch(s, s->launches[slot], items, tiles)) {
-            Launch &L = s->launches[slot];
-            hipError_t e = submit_launch(s, L, items, tiles);
-            if (e != hipSuccess) {
-                s->fatal = std::string("server launch: ") + hipGetErrorString(e);
-                for (auto &pr : L.issued) pr.first->status = QQMC_EDEVICE;
-                hipEventRecord(L.done, s->stream);
+            if (!s->launches[i].busy) {
+                slot = i;
+                break;
             }
-            L.busy = true;
-            seq[slot] = next_seq++;
-            continue;
-        }
+        if (slot >= 0 && issue(s, s->launches[slot])) continue;
         /* nothing to issue now: retire the oldest launch in flight */
         int oldest = -1;
         for (int i = 0; i < 2; ++i)
-            if (s->launches[i].busy && (oldest < 0 || seq[i] < seq[oldest])) oldest = i;
+            if (s->launches[i].busy && (oldest < 0 || s->launches[i].seq < s->launches[oldest].seq))
+                oldest = i;
         if (oldest >= 0) {
             retire(s, s->launches[oldest], lk);
             continue;
         }
         if (s->stop && s->waiting.empty() && s->active.empty()) break;
         if (!s->waiting.empty() && s->active.empty()) {
-            /* the head does not fit although nothing runs: fail it */
+            /* the head does not fit although nothing runs: refuse it */
             auto r = s->waiting.front();
             s->waiting.pop_front();
-            r->status = set_error(QQMC_EADMIT, "request cannot be admitted");
-            r->finished = true;
-            r->t_done = s->now();
-            s->cv_done.notify_all();
+            fail(s, r, set_error(QQMC_EADMIT, "request cannot be admitted"));
             continue;
         }
         s->cv_work.wait(lk, [&] { return s->stop || !s->waiting.empty(); });
@@ -398,21 +434,34 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     s->tile_len = 1024;
     hipGetDevice(&s->device);
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&s->launches[i].done, hipEventDisableTiming);
+    for (int b = 0; b < kBranches && e == hipSuccess; ++b)
+        e = hipStreamCreateWithFlags(&s->branch[b], hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        Launch &L = s->launches[i];
+        e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming);
+        for (int b = 0; b < kBranches && e == hipSuccess; ++b)
+            e = hipEventCreateWithFlags(&L.join[b], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         delete s;
-        return hip_error(e, "server stream");
+        return hip_error(e, "server streams");
     }
     hipDeviceProp_t prop;
     hipGetDeviceProperties(&prop, s->device);
-    s->lds = batch_lds_bytes(QQMC_MAX_ORDER);
-    s->grid = prop.multiProcessorCount * batch_blocks_per_cu(s->lds);
-    /* cost budget of one launch: enough tiles to keep every resident
-     * workgroup busy for a few tiles of order 8 (or batch_tiles tiles) */
-    const double c8 = 1024.0 * (64.0 + 0.5 * (48.0 * 256.0 + 30.0 * 64.0));
-    const int32_t bt = batch_tiles ? batch_tiles : 4 * s->grid;
-    s->launch_cost = c8 * bt;
-    s->t0 = Clock::now();
+    s->n_cu = prop.multiProcessorCount;
+    /* cost budget of one launch: enough order-8 tiles (or batch_tiles tiles)
+     * to give every resident workgroup about four */
+    ItemDesc ref;
+    std::memset(&ref, 0, sizeof(ref));
+    ref.order = 8;
+    ref.mode = QQMC_MODE_CHARGE;
+    ref.tile_len = 1024;
+    ref.t_meas = 10.0;
+    ref.tau = 1.0;
+    const int32_t bt = batch_tiles ? batch_tiles : 4 * s->n_cu * batch_blocks_per_cu(8);
+    s->launch_cost = tile_cost(ref) * bt;
+    s->t0 = std::chrono::steady_clock::now();
     s->worker = std::thread(worker_loop, s);
     *out = s;
     return QQMC_OK;
@@ -459,7 +508,10 @@ qqmc_status qqmc_poll(qqmc_server s, uint64_t ticket, double *q_shift, double *q
     s->all.erase(it);
     if (r->status != QQMC_OK) return set_error(r->status, "request failed");
     if (q_shift) std::memcpy(q_shift, r->q_shift.data(), sizeof(double) * r->q_shift.size());
-    if (q_mean) { q_mean[0] = r->q_mean[0]; q_mean[1] = r->q_mean[1]; }
+    if (q_mean) {
+        q_mean[0] = r->q_mean[0];
+        q_mean[1] = r->q_mean[1];
+    }
     if (q_stderr) *q_stderr = r->q_stderr;
     if (t_submit_s) *t_submit_s = r->t_submit;
     if (t_done_s) *t_done_s = r->t_done;
@@ -472,10 +524,7 @@ qqmc_status qqmc_server_drain(qqmc_server s)
 {
     if (!s) return set_error(QQMC_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] {
-        if (!s->waiting.empty() || !s->active.empty()) return false;
-        return true;
-    });
+    s->cv_done.wait(lk, [&] { return s->waiting.empty() && s->active.empty(); });
     return QQMC_OK;
 }
 
@@ -491,16 +540,26 @@ void qqmc_server_destroy(qqmc_server s)
     hipStreamSynchronize(s->stream);
     for (auto &L : s->launches) {
         if (L.done) hipEventDestroy(L.done);
+        if (L.fork) hipEventDestroy(L.fork);
+        for (auto &j : L.join)
+            if (j) hipEventDestroy(j);
+        if (L.h_items) hipHostFree(L.h_items);
         if (L.d_items) hipFree(L.d_items);
+        if (L.h_tiles) hipHostFree(L.h_tiles);
         if (L.d_tiles) hipFree(L.d_tiles);
+        if (L.h_base) hipHostFree(L.h_base);
+        if (L.d_base) hipFree(L.d_base);
+        if (L.h_sums) hipHostFree(L.h_sums);
+        if (L.d_sums) hipFree(L.d_sums);
     }
     for (auto &kv : s->all) {
         auto &r = kv.second;
         if (r->d_shifts) hipFree(r->d_shifts);
         if (r->d_tiles) hipFree(r->d_tiles);
-        if (r->d_sums) hipFree(r->d_sums);
     }
     for (auto &kv : s->tables) qqmc_free_tables(kv.second.t);
+    for (auto &b : s->branch)
+        if (b) hipStreamDestroy(b);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
 }

@@ -86,9 +86,6 @@ struct pairv {
 /* index of the pair (i, j), i < j, in the triangular pair table */
 QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
 
-/* distance, in pairs, from pair (i, i+1) to pair (i, i+d) */
-template <int I> QQMC_HD constexpr int pidx_step(int d) { return pidx(I, I + d) - pidx(I, I + 1); }
-
 template <int N> struct Geo {
     static constexpr int K = (N < 8 ? N : 8) + 1;      /* block size          */
     static constexpr int OFF = N + 1 - K;              /* cooperative levels  */
@@ -106,7 +103,10 @@ template <int M> struct Blk {
 /* Depth-first walk below block level L (block indices L..K-1 remain).  C is
  * the accumulated Schur correction of the trailing block, so the current
  * trailing matrix is (Wick entries) - C.  prod = product of the pivots
- * eliminated so far, sgn = parity of the indices fixed so far. */
+ * eliminated so far, sgn = parity of the indices fixed so far.  A node
+ * builds the correction blocks of BOTH children (indices 0 and 1 of the
+ * level's point) before descending, so while the first child's subtree runs
+ * only the second child's (m-1) x (m-1) block is held, not the m x m parent. */
 template <int N, int L>
 QQMC_HD void subtree(const Blk<Geo<N>::K - L> &C, cplx prod, int sgn,
                      const pairv *pr, cplx g0, cplx &acc)
@@ -126,24 +126,31 @@ QQMC_HD void subtree(const Blk<Geo<N>::K - L> &C, cplx prod, int sgn,
     } else {
         const cplx r = crecip(p);
         const cplx np = cmul(prod, p);
-        /* pair (L, L+i) holds (g^<, g^>) as two consecutive cplx: the column
-         * entry for index b is element 1-b, the row entry -conj(element b) */
-        const cplx *base = &pr[pidx(OFF + L, OFF + L + 1)].gl;
-#pragma unroll 1
-        for (int b = 0; b < 2; ++b) {
-            Blk<M - 1> D;
-            cplx rowv[M - 1];
+        Blk<M - 1> D0, D1;
+        {
+            /* pair (L, L+i) holds (g^<, g^>): index 0 takes column g^> and row
+             * -conj(g^<), index 1 column g^< and row -conj(g^>) */
+            cplx row0[M - 1], row1[M - 1];
 #pragma unroll
-            for (int j = 1; j < M; ++j)
-                rowv[j - 1] = csub(cnc(base[2 * pidx_step<OFF + L>(j) + b]), C.v[0][j]);
+            for (int j = 1; j < M; ++j) {
+                const pairv P = pr[pidx(OFF + L, OFF + L + j)];
+                row0[j - 1] = csub(cnc(P.gl), C.v[0][j]);
+                row1[j - 1] = csub(cnc(P.gg), C.v[0][j]);
+            }
 #pragma unroll
             for (int i = 1; i < M; ++i) {
-                const cplx ch = cmul(csub(base[2 * pidx_step<OFF + L>(i) + 1 - b], C.v[i][0]), r);
+                const pairv P = pr[pidx(OFF + L, OFF + L + i)];
+                const cplx c0 = cmul(csub(P.gg, C.v[i][0]), r);
+                const cplx c1 = cmul(csub(P.gl, C.v[i][0]), r);
 #pragma unroll
-                for (int j = 1; j < M; ++j) D.v[i - 1][j - 1] = cfma(ch, rowv[j - 1], C.v[i][j]);
+                for (int j = 1; j < M; ++j) {
+                    D0.v[i - 1][j - 1] = cfma(c0, row0[j - 1], C.v[i][j]);
+                    D1.v[i - 1][j - 1] = cfma(c1, row1[j - 1], C.v[i][j]);
+                }
             }
-            subtree<N, L + 1>(D, np, sgn ^ b, pr, g0, acc);
         }
+        subtree<N, L + 1>(D0, np, sgn, pr, g0, acc);
+        subtree<N, L + 1>(D1, np, sgn ^ 1, pr, g0, acc);
     }
 }
 

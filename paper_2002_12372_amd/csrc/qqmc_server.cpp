@@ -6,21 +6,20 @@
  *   admission   requests queue in arrival order; the head is admitted while
  *               a slot is free and its device footprint (tables unless
  *               cached, shifts, tile sums) fits in the HBM budget.  Tables
- *               are built on the device by a kernel on the server stream;
- *               per-request buffers come from the stream-ordered allocator,
- *               so admission never waits for the GPU;
+ *               are built on the device by a kernel, per-request buffers
+ *               come from the stream-ordered allocator, all on an admission
+ *               stream, so admission never waits for the GPU;
  *   batching    every launch takes tiles from all admitted requests in turn
  *               (round robin, up to a per-launch cost budget), so requests
  *               that arrive while others run share the next launches.  The
- *               tiles of a launch are grouped by order and run as concurrent
- *               persistent launches of each order's kernel on branch
- *               streams, joined on the server stream;
- *   completion  a request whose last tile is in a launch gets its per-shift
- *               reduction and the copy of its K sums into pinned host memory
- *               appended to that launch, so its result is on the host when
- *               the launch's event fires;
- *   pipelining  two launches are in flight, so the host prepares launch k+1
- *               while launch k runs.
+ *               tiles of a launch are grouped by order, one persistent launch
+ *               of that order's kernel per group;
+ *   overlap     three launches are in flight on three streams, so the tail of
+ *               one launch overlaps the next and the host prepares launches
+ *               while the GPU runs;
+ *   completion  when every tile of a request is done, its per-shift sums are
+ *               reduced on a completion stream, copied to pinned host memory
+ *               and its device buffers are returned to the pool.
  * Green's-function tables stay on the device, shared by requests with the
  * same dot parameters (reference counted; unused ones are evicted first when
  * memory runs short).  Tiles are the same as qqmc_eval_order_async's for the
@@ -45,7 +44,7 @@
 namespace qqmc {
 namespace {
 
-constexpr int kBranches = 4;
+constexpr int kSlots = 3;
 
 struct TableEntry {
     qqmc_tables t = nullptr;
@@ -63,7 +62,7 @@ struct Request {
     std::vector<double> shifts;
     TableKey key;
     double *d_shifts = nullptr, *d_tiles = nullptr;
-    int64_t next_tile = 0;
+    int64_t next_tile = 0, done_tiles = 0;
     double t_submit = 0.0, t_done = 0.0;
     bool finished = false;
     qqmc_status status = QQMC_OK;
@@ -72,18 +71,25 @@ struct Request {
     double q_stderr = 0.0;
 };
 
-/* Pinned host staging and device buffers of one launch slot. */
+/* Pinned host staging and device buffers of one launch slot (own stream). */
 struct Launch {
-    hipEvent_t done = nullptr, fork = nullptr, join[kBranches] = {};
-    ItemDesc *h_items = nullptr, *d_items = nullptr; /* batch items, then completing items */
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    ItemDesc *h_items = nullptr, *d_items = nullptr;
     TileRef *h_tiles = nullptr, *d_tiles = nullptr;
-    int64_t *h_base = nullptr, *d_base = nullptr;
-    double *h_sums = nullptr, *d_sums = nullptr;
-    size_t cap_items = 0, cap_tiles = 0, cap_base = 0, cap_sums = 0;
-    std::vector<std::shared_ptr<Request>> completing;
-    std::vector<int64_t> completing_base;
+    size_t cap_items = 0, cap_tiles = 0;
+    std::vector<std::pair<std::shared_ptr<Request>, int64_t>> issued; /* request, #tiles */
     bool busy = false;
     uint64_t seq = 0;
+};
+
+/* Per-shift reduction of finished requests. */
+struct Completion {
+    hipStream_t stream = nullptr;
+    ItemDesc *h_items = nullptr, *d_items = nullptr;
+    int64_t *h_base = nullptr, *d_base = nullptr;
+    double *h_sums = nullptr, *d_sums = nullptr;
+    size_t cap_items = 0, cap_base = 0, cap_sums = 0;
 };
 
 /* Grows a pinned host / device buffer pair to at least `need` elements. */
@@ -109,8 +115,9 @@ struct qqmc_server_s {
     int32_t max_slots = 1, tile_len = 1024;
     double launch_cost = 0.0;
     int device = 0, n_cu = 1;
-    hipStream_t stream = nullptr;
-    hipStream_t branch[qqmc::kBranches] = {};
+    hipStream_t admit_stream = nullptr;
+    hipEvent_t admitted = nullptr;   /* last admission work on admit_stream */
+    bool admitted_pending = false;
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -121,7 +128,8 @@ struct qqmc_server_s {
     std::vector<std::shared_ptr<qqmc::Request>> active;
     std::map<uint64_t, std::shared_ptr<qqmc::Request>> all;
     std::map<qqmc::TableKey, qqmc::TableEntry> tables;
-    qqmc::Launch launches[2];
+    qqmc::Launch launches[qqmc::kSlots];
+    qqmc::Completion comp;
     std::thread worker;
 
     double now() const
@@ -160,7 +168,9 @@ void evict_tables(qqmc_server_s *s, size_t need)
                 victim = it;
         if (victim == s->tables.end()) return;
         s->used -= victim->second.bytes;
-        hipStreamSynchronize(s->stream); /* no launch may still read it */
+        /* no launch may still read it */
+        for (auto &L : s->launches) hipStreamSynchronize(L.stream);
+        hipStreamSynchronize(s->admit_stream);
         qqmc_free_tables(victim->second.t);
         s->tables.erase(victim);
     }
@@ -179,7 +189,7 @@ void admit(qqmc_server_s *s)
         s->waiting.pop_front();
         if (need_table) {
             qqmc_tables t = nullptr;
-            qqmc_status st = qqmc_make_tables(&r->dot, s->stream, &t);
+            qqmc_status st = qqmc_make_tables(&r->dot, s->admit_stream, &t);
             if (st != QQMC_OK) {
                 fail(s, r, st);
                 continue;
@@ -194,12 +204,15 @@ void admit(qqmc_server_s *s)
         it->second.refs += 1;
         it->second.last_use = ++s->use_clock;
         fill_item_tables(r->desc, it->second.t);
-        hipError_t e = hipMallocAsync((void **)&r->d_shifts, sizeof(double) * r->shifts.size(), s->stream);
+        hipError_t e = hipMallocAsync((void **)&r->d_shifts, sizeof(double) * r->shifts.size(),
+                                      s->admit_stream);
         if (e == hipSuccess)
-            e = hipMallocAsync((void **)&r->d_tiles, sizeof(double) * 2 * r->desc.n_tiles, s->stream);
+            e = hipMallocAsync((void **)&r->d_tiles, sizeof(double) * 2 * r->desc.n_tiles, s->admit_stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->d_shifts, r->shifts.data(), sizeof(double) * r->shifts.size(),
-                               hipMemcpyHostToDevice, s->stream);
+                               hipMemcpyHostToDevice, s->admit_stream);
+        if (e == hipSuccess) e = hipEventRecord(s->admitted, s->admit_stream);
+        if (e == hipSuccess) s->admitted_pending = true;
         if (e != hipSuccess) {
             it->second.refs -= 1;
             fail(s, r, hip_error(e, "server admission"));
@@ -239,9 +252,7 @@ bool issue(qqmc_server_s *s, Launch &L)
     /* items of the launch, tiles grouped by order */
     std::vector<ItemDesc> items;
     std::vector<std::vector<TileRef>> by(QQMC_MAX_ORDER + 1);
-    L.completing.clear();
-    L.completing_base.clear();
-    int64_t sums = 0;
+    L.issued.clear();
     for (size_t i = 0; i < open.size(); ++i) {
         if (!take[i]) continue;
         const int32_t idx = (int32_t)items.size();
@@ -254,11 +265,7 @@ bool issue(qqmc_server_s *s, Launch &L)
             by[open[i]->desc.order].push_back(t);
         }
         open[i]->next_tile += take[i];
-        if (open[i]->next_tile == open[i]->desc.n_tiles) {
-            L.completing.push_back(open[i]);
-            L.completing_base.push_back(sums);
-            sums += open[i]->desc.n_shifts;
-        }
+        L.issued.push_back({open[i], take[i]});
     }
     std::vector<TileRef> tiles;
     struct G {
@@ -271,86 +278,81 @@ bool issue(qqmc_server_s *s, Launch &L)
         groups.push_back({n, (int64_t)tiles.size(), (int64_t)by[n].size()});
         tiles.insert(tiles.end(), by[n].begin(), by[n].end());
     }
-    const size_t n_items = items.size() + L.completing.size();
-    hipError_t e = grow_pair(&L.h_items, &L.d_items, &L.cap_items, n_items);
+    hipError_t e = grow_pair(&L.h_items, &L.d_items, &L.cap_items, items.size());
     if (e == hipSuccess) e = grow_pair(&L.h_tiles, &L.d_tiles, &L.cap_tiles, tiles.size());
-    if (e == hipSuccess) e = grow_pair(&L.h_base, &L.d_base, &L.cap_base, L.completing.size() + 1);
-    if (e == hipSuccess) e = grow_pair(&L.h_sums, &L.d_sums, &L.cap_sums, 2 * (size_t)(sums + 1));
+    /* launches must see every admission before them */
+    if (e == hipSuccess && s->admitted_pending) e = hipStreamWaitEvent(L.stream, s->admitted, 0);
     if (e == hipSuccess) {
         std::memcpy(L.h_items, items.data(), sizeof(ItemDesc) * items.size());
-        for (size_t c = 0; c < L.completing.size(); ++c) {
-            L.h_items[items.size() + c] = L.completing[c]->desc;
-            L.h_base[c] = L.completing_base[c];
-        }
         std::memcpy(L.h_tiles, tiles.data(), sizeof(TileRef) * tiles.size());
-        e = hipMemcpyAsync(L.d_items, L.h_items, sizeof(ItemDesc) * n_items, hipMemcpyHostToDevice, s->stream);
+        e = hipMemcpyAsync(L.d_items, L.h_items, sizeof(ItemDesc) * items.size(), hipMemcpyHostToDevice,
+                           L.stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(L.d_tiles, L.h_tiles, sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice,
-                           s->stream);
-    if (e == hipSuccess && !L.completing.empty())
-        e = hipMemcpyAsync(L.d_base, L.h_base, sizeof(int64_t) * L.completing.size(),
-                           hipMemcpyHostToDevice, s->stream);
-    /* fork: one persistent launch per order on the branch streams */
-    if (e == hipSuccess) e = hipEventRecord(L.fork, s->stream);
-    bool used[kBranches] = {false, false, false, false};
+                           L.stream);
     for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
-        const int b = (int)(g % kBranches);
-        if (!used[b]) {
-            e = hipStreamWaitEvent(s->branch[b], L.fork, 0);
-            used[b] = true;
-        }
         const int32_t grid = s->n_cu * batch_blocks_per_cu(groups[g].order);
-        if (e == hipSuccess)
-            e = launch_batch(groups[g].order, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
-                             s->branch[b]);
+        e = launch_batch(groups[g].order, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
+                         L.stream);
     }
-    for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
-        if (!used[b]) continue;
-        e = hipEventRecord(L.join[b], s->branch[b]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, L.join[b], 0);
-    }
-    /* completions: per-shift reduction and copy of the sums to the host */
-    if (e == hipSuccess && !L.completing.empty()) {
-        int32_t kmax = 1;
-        for (auto &r : L.completing) kmax = std::max(kmax, r->desc.n_shifts);
-        e = launch_shift_reduce(L.d_items + items.size(), (int32_t)L.completing.size(), L.d_base,
-                                L.d_sums, kmax, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(L.h_sums, L.d_sums, sizeof(double) * 2 * sums, hipMemcpyDeviceToHost,
-                               s->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(L.done, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(L.done, L.stream);
     if (e != hipSuccess) {
         const qqmc_status st = hip_error(e, "server launch");
-        for (auto &r : L.completing) r->status = st;
-        hipEventRecord(L.done, s->stream);
+        for (auto &pr : L.issued) pr.first->status = st;
+        hipEventRecord(L.done, L.stream);
     }
     L.busy = true;
     L.seq = s->next_seq++;
     return true;
 }
 
-/* Waits for launch L (lock released meanwhile) and finishes the requests it
- * completed. */
-void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
+/* Reduces the per-shift sums of finished requests on the completion stream,
+ * copies them back and releases their device buffers (lock held). */
+void complete(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin)
 {
-    lk.unlock();
-    hipEventSynchronize(L.done);
-    lk.lock();
-    L.busy = false;
+    if (fin.empty()) return;
+    Completion &C = s->comp;
+    std::vector<int64_t> base(fin.size());
+    int64_t sums = 0;
+    int32_t kmax = 1;
+    for (size_t c = 0; c < fin.size(); ++c) {
+        base[c] = sums;
+        sums += fin[c]->desc.n_shifts;
+        kmax = std::max(kmax, fin[c]->desc.n_shifts);
+    }
+    hipError_t e = grow_pair(&C.h_items, &C.d_items, &C.cap_items, fin.size());
+    if (e == hipSuccess) e = grow_pair(&C.h_base, &C.d_base, &C.cap_base, fin.size());
+    if (e == hipSuccess) e = grow_pair(&C.h_sums, &C.d_sums, &C.cap_sums, 2 * (size_t)sums);
+    if (e == hipSuccess) {
+        for (size_t c = 0; c < fin.size(); ++c) {
+            C.h_items[c] = fin[c]->desc;
+            C.h_base[c] = base[c];
+        }
+        e = hipMemcpyAsync(C.d_items, C.h_items, sizeof(ItemDesc) * fin.size(), hipMemcpyHostToDevice,
+                           C.stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(C.d_base, C.h_base, sizeof(int64_t) * fin.size(), hipMemcpyHostToDevice, C.stream);
+    if (e == hipSuccess)
+        e = launch_shift_reduce(C.d_items, (int32_t)fin.size(), C.d_base, C.d_sums, kmax, C.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(C.h_sums, C.d_sums, sizeof(double) * 2 * sums, hipMemcpyDeviceToHost, C.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(C.stream);
+    const qqmc_status st = e == hipSuccess ? QQMC_OK : hip_error(e, "server completion");
     const double now = s->now();
-    for (size_t c = 0; c < L.completing.size(); ++c) {
-        auto &r = L.completing[c];
+    for (size_t c = 0; c < fin.size(); ++c) {
+        auto &r = fin[c];
+        if (r->status == QQMC_OK && st != QQMC_OK) r->status = st;
         if (r->status == QQMC_OK) {
             const int K = r->desc.n_shifts;
             const double N = (double)r->desc.mask + 1.0;
-            const double *sums = L.h_sums + 2 * L.completing_base[c];
+            const double *v = C.h_sums + 2 * base[c];
             r->q_shift.resize(2 * (size_t)K);
             double mr = 0.0, mi = 0.0;
             for (int k = 0; k < K; ++k) {
-                r->q_shift[2 * k] = sums[2 * k] / N;
-                r->q_shift[2 * k + 1] = sums[2 * k + 1] / N;
+                r->q_shift[2 * k] = v[2 * k] / N;
+                r->q_shift[2 * k + 1] = v[2 * k + 1] / N;
                 mr += r->q_shift[2 * k];
                 mi += r->q_shift[2 * k + 1];
             }
@@ -362,8 +364,8 @@ void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
             for (int k = 0; k < K; ++k) ss += (r->q_shift[2 * k] - mr) * (r->q_shift[2 * k] - mr);
             r->q_stderr = K > 1 ? std::sqrt(ss / (K - 1)) / std::sqrt((double)K) : std::nan("");
         }
-        hipFreeAsync(r->d_shifts, s->stream);
-        hipFreeAsync(r->d_tiles, s->stream);
+        hipFreeAsync(r->d_shifts, C.stream);
+        hipFreeAsync(r->d_tiles, C.stream);
         r->d_shifts = r->d_tiles = nullptr;
         s->used -= request_bytes(*r, false);
         auto it = s->tables.find(r->key);
@@ -371,14 +373,28 @@ void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
         r->t_done = now;
         r->finished = true;
     }
-    if (!L.completing.empty()) {
-        std::vector<std::shared_ptr<Request>> still;
-        for (auto &r : s->active)
-            if (!r->finished) still.push_back(r);
-        s->active.swap(still);
-        L.completing.clear();
-        s->cv_done.notify_all();
+    std::vector<std::shared_ptr<Request>> still;
+    for (auto &r : s->active)
+        if (!r->finished) still.push_back(r);
+    s->active.swap(still);
+    s->cv_done.notify_all();
+}
+
+/* Waits for launch L (lock released meanwhile) and completes the requests
+ * whose last tiles it ran. */
+void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
+{
+    lk.unlock();
+    hipEventSynchronize(L.done);
+    lk.lock();
+    L.busy = false;
+    std::vector<std::shared_ptr<Request>> fin;
+    for (auto &pr : L.issued) {
+        pr.first->done_tiles += pr.second;
+        if (pr.first->done_tiles == pr.first->desc.n_tiles) fin.push_back(pr.first);
     }
+    L.issued.clear();
+    complete(s, fin);
 }
 
 void worker_loop(qqmc_server_s *s)
@@ -388,7 +404,7 @@ void worker_loop(qqmc_server_s *s)
     for (;;) {
         admit(s);
         int slot = -1;
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < kSlots; ++i)
             if (!s->launches[i].busy) {
                 slot = i;
                 break;
@@ -396,7 +412,7 @@ void worker_loop(qqmc_server_s *s)
         if (slot >= 0 && issue(s, s->launches[slot])) continue;
         /* nothing to issue now: retire the oldest launch in flight */
         int oldest = -1;
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < kSlots; ++i)
             if (s->launches[i].busy && (oldest < 0 || s->launches[i].seq < s->launches[oldest].seq))
                 oldest = i;
         if (oldest >= 0) {
@@ -433,15 +449,13 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     s->max_slots = max_slots;
     s->tile_len = 1024;
     hipGetDevice(&s->device);
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    for (int b = 0; b < kBranches && e == hipSuccess; ++b)
-        e = hipStreamCreateWithFlags(&s->branch[b], hipStreamNonBlocking);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    hipError_t e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->comp.stream, hipStreamNonBlocking);
+    for (int i = 0; i < kSlots && e == hipSuccess; ++i) {
         Launch &L = s->launches[i];
-        e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming);
-        for (int b = 0; b < kBranches && e == hipSuccess; ++b)
-            e = hipEventCreateWithFlags(&L.join[b], hipEventDisableTiming);
+        e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         delete s;
@@ -451,7 +465,7 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     hipGetDeviceProperties(&prop, s->device);
     s->n_cu = prop.multiProcessorCount;
     /* cost budget of one launch: enough order-8 tiles (or batch_tiles tiles)
-     * to give every resident workgroup about four */
+     * to give every resident workgroup about four (a few milliseconds) */
     ItemDesc ref;
     std::memset(&ref, 0, sizeof(ref));
     ref.order = 8;
@@ -537,30 +551,33 @@ void qqmc_server_destroy(qqmc_server s)
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    hipStreamSynchronize(s->stream);
     for (auto &L : s->launches) {
+        if (L.stream) hipStreamSynchronize(L.stream);
         if (L.done) hipEventDestroy(L.done);
-        if (L.fork) hipEventDestroy(L.fork);
-        for (auto &j : L.join)
-            if (j) hipEventDestroy(j);
         if (L.h_items) hipHostFree(L.h_items);
         if (L.d_items) hipFree(L.d_items);
         if (L.h_tiles) hipHostFree(L.h_tiles);
         if (L.d_tiles) hipFree(L.d_tiles);
-        if (L.h_base) hipHostFree(L.h_base);
-        if (L.d_base) hipFree(L.d_base);
-        if (L.h_sums) hipHostFree(L.h_sums);
-        if (L.d_sums) hipFree(L.d_sums);
+        if (L.stream) hipStreamDestroy(L.stream);
     }
+    Completion &C = s->comp;
+    if (C.stream) hipStreamSynchronize(C.stream);
+    if (C.h_items) hipHostFree(C.h_items);
+    if (C.d_items) hipFree(C.d_items);
+    if (C.h_base) hipHostFree(C.h_base);
+    if (C.d_base) hipFree(C.d_base);
+    if (C.h_sums) hipHostFree(C.h_sums);
+    if (C.d_sums) hipFree(C.d_sums);
+    if (s->admit_stream) hipStreamSynchronize(s->admit_stream);
     for (auto &kv : s->all) {
         auto &r = kv.second;
         if (r->d_shifts) hipFree(r->d_shifts);
         if (r->d_tiles) hipFree(r->d_tiles);
     }
     for (auto &kv : s->tables) qqmc_free_tables(kv.second.t);
-    for (auto &b : s->branch)
-        if (b) hipStreamDestroy(b);
-    if (s->stream) hipStreamDestroy(s->stream);
+    if (C.stream) hipStreamDestroy(C.stream);
+    if (s->admitted) hipEventDestroy(s->admitted);
+    if (s->admit_stream) hipStreamDestroy(s->admit_stream);
     delete s;
 }
 

@@ -156,16 +156,40 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         const bool active = item < n_items;
         const int pt = active ? item / Gm::IPP : 0;
         const int top = active ? item % Gm::IPP : 0;
-        pairv *prg = s_pairs + grp * Gm::NP;
-        const double *tm = s_times + pt * N;
-        for (int q = sub; q < Gm::NP; q += Gm::G) {
-            int j = 1;
-            while ((j + 1) * j / 2 <= q) ++j;
-            const int i = q - j * (j - 1) / 2;
-            const double tj = j == N ? env.t_meas : tm[j];
-            prg[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+        pairv *prg;
+        if constexpr (Gm::IPP == 1) {
+            /* one point per group: the group's lanes build its pair table */
+            prg = s_pairs + grp * Gm::NP;
+            const double *tm = s_times + pt * N;
+            for (int q = sub; q < Gm::NP; q += Gm::G) {
+                int j = 1;
+                while ((j + 1) * j / 2 <= q) ++j;
+                const int i = q - j * (j - 1) / 2;
+                const double tj = j == N ? env.t_meas : tm[j];
+                prg[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+            }
+            __syncthreads();
+        } else {
+            /* several items share a point: PTS distinct points per round
+             * (base is a multiple of IPP whenever PTS > 1); their pair
+             * tables are built by the whole wave when the points change */
+            constexpr int PTS = Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1;
+            prg = s_pairs + (grp / Gm::IPP) * Gm::NP;
+            if (PTS > 1 || base % Gm::IPP == 0) {
+                const int first = base / Gm::IPP;
+                for (int q = lane; q < PTS * Gm::NP; q += WAVE) {
+                    const int slot = q / Gm::NP, qq = q % Gm::NP;
+                    const int p = first + slot < cnt ? first + slot : 0;
+                    const double *tm = s_times + p * N;
+                    int j = 1;
+                    while ((j + 1) * j / 2 <= qq) ++j;
+                    const int i = qq - j * (j - 1) / 2;
+                    const double tj = j == N ? env.t_meas : tm[j];
+                    s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
         cplx prod = cmk(1.0, 0.0);
         int sgn = 0;
         BlockSrc<N> src;
@@ -465,13 +489,15 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
 template <int N>
-__global__ void __launch_bounds__(64, 2) batch_kernel(const ItemDesc *items, const TileRef *tiles,
-                                                   int64_t n_tiles)
+__global__ void __launch_bounds__(64, 2) batch_kernel(const ItemDesc *__restrict__ items,
+                                                      const TileRef *__restrict__ tiles,
+                                                      int64_t n_tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
-        const ItemDesc &it = items[ref.item];
+        /* by value: the descriptor lives in registers for the whole tile */
+        const ItemDesc it = items[ref.item];
         const cplx v = order_tile<N>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;

@@ -54,6 +54,17 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+/* Later point j of the pair with triangular index q = j(j-1)/2 + i, i < j:
+ * the largest j with j(j-1)/2 <= q (float square root is exact enough for
+ * q < 2^20; the two integer corrections make it exact regardless). */
+__device__ __forceinline__ int pair_hi(int q)
+{
+    int j = (int)((1.0f + sqrtf(8.0f * (float)q + 1.0f)) * 0.5f);
+    if (j * (j - 1) / 2 > q) --j;
+    if ((j + 1) * j / 2 <= q) ++j;
+    return j;
+}
+
 /* -2 i^{n+1} S: the charge prefactor (spin sum 2, i^n of the expansion, the
  * extra -i of <n> = -i g^<). */
 template <int N> __device__ __forceinline__ cplx charge_prefactor(cplx s)
@@ -158,15 +169,26 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         const int top = active ? item % Gm::IPP : 0;
         pairv *prg;
         if constexpr (Gm::IPP == 1) {
-            /* one point per group: the group's lanes build its pair table */
+            /* one point per group: the group's lanes build its pair table;
+             * the loop is unrolled so every table load is issued before the
+             * first interpolation waits */
             prg = s_pairs + grp * Gm::NP;
             const double *tm = s_times + pt * N;
-            for (int q = sub; q < Gm::NP; q += Gm::G) {
-                int j = 1;
-                while ((j + 1) * j / 2 <= q) ++j;
-                const int i = q - j * (j - 1) / 2;
-                const double tj = j == N ? env.t_meas : tm[j];
-                prg[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+            constexpr int PER = (Gm::NP + Gm::G - 1) / Gm::G;
+            pairv val[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int q = sub + k * Gm::G;
+                if (q < Gm::NP) {
+                    const int j = pair_hi(q), i = q - j * (j - 1) / 2;
+                    const double tj = j == N ? env.t_meas : tm[j];
+                    val[k] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int q = sub + k * Gm::G;
+                if (q < Gm::NP) prg[q] = val[k];
             }
             __syncthreads();
         } else {
@@ -181,9 +203,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                     const int slot = q / Gm::NP, qq = q % Gm::NP;
                     const int p = first + slot < cnt ? first + slot : 0;
                     const double *tm = s_times + p * N;
-                    int j = 1;
-                    while ((j + 1) * j / 2 <= qq) ++j;
-                    const int i = qq - j * (j - 1) / 2;
+                    const int j = pair_hi(qq), i = qq - j * (j - 1) / 2;
                     const double tj = j == N ? env.t_meas : tm[j];
                     s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
                 }

@@ -9,11 +9,11 @@
  *               are built on the device by a kernel, per-request buffers
  *               come from the stream-ordered allocator, all on an admission
  *               stream, so admission never waits for the GPU;
- *   batching    every launch takes tiles from all admitted requests in turn
- *               (round robin, up to a per-launch cost budget), so requests
- *               that arrive while others run share the next launches.  The
- *               tiles of a launch are grouped by order, one persistent launch
- *               of that order's kernel per group;
+ *   batching    every launch is one persistent kernel of one order; the
+ *               order rotates over the orders with pending work, and the
+ *               admitted requests of that order take tiles in turn (round
+ *               robin, up to a per-launch cost budget), so requests that
+ *               arrive while others run share the next launches;
  *   overlap     three launches are in flight on three streams, so the tail of
  *               one launch overlaps the next and the host prepares launches
  *               while the GPU runs;
@@ -124,6 +124,7 @@ struct qqmc_server_s {
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1, use_clock = 0, next_seq = 1;
+    int last_order = 0;
     std::deque<std::shared_ptr<qqmc::Request>> waiting;
     std::vector<std::shared_ptr<qqmc::Request>> active;
     std::map<uint64_t, std::shared_ptr<qqmc::Request>> all;
@@ -229,27 +230,41 @@ void admit(qqmc_server_s *s)
  * held).  Returns false if there was nothing to issue. */
 bool issue(qqmc_server_s *s, Launch &L)
 {
+    /* one order per launch, rotating over the orders with pending tiles, so
+     * every launch is one full persistent kernel; inside the order, requests
+     * in admission order take one tile each per pass up to the cost budget */
+    bool pending[QQMC_MAX_ORDER + 1] = {};
+    for (auto &r : s->active)
+        if (r->next_tile < r->desc.n_tiles) pending[r->desc.order] = true;
+    int order = 0;
+    for (int k = 1; k <= QQMC_MAX_ORDER && !order; ++k) {
+        const int n = (s->last_order + k - 1) % QQMC_MAX_ORDER + 1;
+        if (pending[n]) order = n;
+    }
+    if (!order) return false;
+    s->last_order = order;
     std::vector<std::shared_ptr<Request>> open;
     for (auto &r : s->active)
-        if (r->next_tile < r->desc.n_tiles) open.push_back(r);
-    if (open.empty()) return false;
+        if (r->desc.order == order && r->next_tile < r->desc.n_tiles) open.push_back(r);
     std::vector<double> cost(open.size());
     std::vector<int64_t> take(open.size(), 0);
     for (size_t i = 0; i < open.size(); ++i) cost[i] = tile_cost(open[i]->desc);
-    /* round robin, one tile per request per pass, until the cost budget */
+    /* at least two tiles per resident workgroup, so the launch fills the GPU */
+    const int64_t min_tiles = 2 * (int64_t)s->n_cu * batch_blocks_per_cu(order);
     double spent = 0.0;
+    int64_t taken = 0;
     bool progress = true;
-    while (progress && spent < s->launch_cost) {
+    while (progress && (spent < s->launch_cost || taken < min_tiles)) {
         progress = false;
-        for (size_t i = 0; i < open.size() && spent < s->launch_cost; ++i) {
+        for (size_t i = 0; i < open.size() && (spent < s->launch_cost || taken < min_tiles); ++i) {
             if (open[i]->next_tile + take[i] < open[i]->desc.n_tiles) {
                 take[i] += 1;
                 spent += cost[i];
+                taken += 1;
                 progress = true;
             }
         }
     }
-    /* items of the launch, tiles grouped by order */
     std::vector<ItemDesc> items;
     std::vector<std::vector<TileRef>> by(QQMC_MAX_ORDER + 1);
     L.issued.clear();

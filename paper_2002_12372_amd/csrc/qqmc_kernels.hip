@@ -36,8 +36,12 @@ template <int N> struct Lds {
     static constexpr int times = 0;                                    /* 64*N doubles   */
     static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
     static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
-    static constexpr int pairs = S + 64 * 16;                          /* PPW*NP pairv   */
-    static constexpr int res = pairs + Gm::PPW * Gm::NP * 32;          /* PPW cplx       */
+    /* pair tables: one per item group, or one per distinct point of a
+     * round when several items share a point */
+    static constexpr int tables =
+        Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
+    static constexpr int pairs = S + 64 * 16;                          /* tables*NP pairv */
+    static constexpr int res = pairs + tables * Gm::NP * 32;           /* PPW cplx       */
     static constexpr int row = res + Gm::PPW * 16;                     /* PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
@@ -103,46 +107,63 @@ __device__ __forceinline__ cplx wave_sum(cplx v)
 /* Environment of the points being evaluated (one parameter point). */
 struct Env {
     const double *tab;
-    double t_half, h, t_meas;
+    double t_half, inv_h, t_meas;
     cplx g0;
     int n_grid;
 };
 
-/* The first OFF = n - 8 eliminations of a work item (n > 8), done by the 16
- * lanes of the item's group with one matrix row per lane (right-looking, no
- * pivoting, index prefix `top`).  Leaves the 9 x 9 trailing correction block
- * in s_c0 and returns the product of the OFF pivots. */
+/* The first OFF = n - 8 eliminations of a work item (n > 8), done by the G
+ * lanes of the item's group with whole matrix rows per lane (row r on lane
+ * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
+ * 9 x 9 trailing correction block in s_c0 and returns the product of the
+ * OFF pivots. */
 template <int N>
-__device__ cplx top_block(const pairv *pr, int top, int r, cplx g0, cplx *s_row,
+__device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_row,
                           cplx *s_c0)
 {
     using Gm = Geo<N>;
-    constexpr int OFF = Gm::OFF, K = Gm::K;
-    cplx crow[N + 1];
+    constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
+    constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
+    cplx crow[RPL][N + 1];
 #pragma unroll
-    for (int j = 0; j <= N; ++j) crow[j] = cmk(0.0, 0.0);
+    for (int m = 0; m < RPL; ++m)
+#pragma unroll
+        for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
     cplx prod = cmk(1.0, 0.0);
 #pragma unroll
     for (int k = 0; k < OFF; ++k) {
         const int b = (top >> (OFF - 1 - k)) & 1;
-        if (r == k) {
-            s_row[k] = csub(g0, crow[k]);
 #pragma unroll
-            for (int j = k + 1; j <= N; ++j) s_row[j] = csub(wick_entry(pr, k, j, b), crow[j]);
+        for (int m = 0; m < RPL; ++m) {
+            if (sub + m * G == k) {
+                s_row[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j)
+                    s_row[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
+            }
         }
         __syncthreads();
         const cplx p = s_row[k];
-        if (r > k && r <= N) {
-            const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[k]), crecip(p));
+        const cplx rp = crecip_nr(p);
 #pragma unroll
-            for (int j = k + 1; j <= N; ++j) crow[j] = cfma(ch, s_row[j], crow[j]);
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r > k && r <= N) {
+                const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[m][k]), rp);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) crow[m][j] = cfma(ch, s_row[j], crow[m][j]);
+            }
         }
         prod = cmul(prod, p);
         __syncthreads();
     }
-    if (r >= OFF && r <= N) {
 #pragma unroll
-        for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[j];
+    for (int m = 0; m < RPL; ++m) {
+        const int r = sub + m * G;
+        if (r >= OFF && r <= N) {
+#pragma unroll
+            for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[m][j];
+        }
     }
     __syncthreads();
     return prod;
@@ -182,7 +203,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                 if (q < Gm::NP) {
                     const int j = pair_hi(q), i = q - j * (j - 1) / 2;
                     const double tj = j == N ? env.t_meas : tm[j];
-                    val[k] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+                    val[k] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
                 }
             }
 #pragma unroll
@@ -205,7 +226,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                     const double *tm = s_times + p * N;
                     const int j = pair_hi(qq), i = qq - j * (j - 1) / 2;
                     const double tj = j == N ? env.t_meas : tm[j];
-                    s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, tj - tm[i]);
+                    s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
                 }
                 __syncthreads();
             }
@@ -260,7 +281,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 #pragma unroll
     for (int j = 0; j < N; ++j) shift[j] = sh[j];
     Env env;
-    env.tab = it.tab; env.t_half = it.t_half; env.h = it.h; env.t_meas = it.t_meas;
+    env.tab = it.tab; env.t_half = it.t_half; env.inv_h = 1.0 / it.h; env.t_meas = it.t_meas;
     env.g0 = cmk(it.g0x, it.g0y); env.n_grid = it.n_grid;
     Kahan acc;
     for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
@@ -307,7 +328,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 }
 
 template <int N>
-__global__ void __launch_bounds__(64, 2) order_kernel(ItemDesc it)
+__global__ void __launch_bounds__(64, Geo<N>::WPS) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
@@ -354,7 +375,7 @@ __global__ void __launch_bounds__(256) shift_reduce_kernel(const ItemDesc *items
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
 template <int N>
-__global__ void __launch_bounds__(64, 2) points_tree_kernel(Env env, const double *u,
+__global__ void __launch_bounds__(64, Geo<N>::WPS) points_tree_kernel(Env env, const double *u,
                                                         int64_t n_points, double *f)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -447,7 +468,7 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
         __syncthreads();
         for (int q = lane; q < NP1 * NP1; q += WAVE) {
             const int r = q / NP1, c = q % NP1;
-            s_g[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.h, s_tm[r] - s_tm[c]);
+            s_g[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, s_tm[r] - s_tm[c]);
         }
         __syncthreads();
         Kahan acc;
@@ -509,7 +530,7 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
 template <int N>
-__global__ void __launch_bounds__(64, 2) batch_kernel(const ItemDesc *__restrict__ items,
+__global__ void __launch_bounds__(64, Geo<N>::WPS) batch_kernel(const ItemDesc *__restrict__ items,
                                                       const TileRef *__restrict__ tiles,
                                                       int64_t n_tiles)
 {
@@ -638,7 +659,7 @@ Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double 
              double t_meas)
 {
     Env e;
-    e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.h = h; e.t_meas = t_meas;
+    e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.inv_h = 1.0 / h; e.t_meas = t_meas;
     e.g0 = cmk(0.0, g0y);
     return e;
 }

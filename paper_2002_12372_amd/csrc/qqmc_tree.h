@@ -31,8 +31,9 @@
  *          with the first n + 1 - K eliminations done cooperatively before);
  *   path   T levels eliminated per lane, left-looking, for the lane's own
  *          index prefix (lane number within the item);
- *   tree   the remaining B = K - 1 - T <= 4 levels walked depth first with
- *          the Schur complements held in registers.
+ *   tree   the remaining K - 1 - T <= 5 levels walked depth first with
+ *          the Schur complements held in registers (the subtree of a lane
+ *          starts from a block of at most 6 x 6).
  * Everything here is straight-line code for a compile-time order n.
  */
 #ifndef QQMC_TREE_H
@@ -78,6 +79,29 @@ QQMC_HD cplx crecip(cplx a)
 }
 QQMC_HD cplx csel(int b, cplx one, cplx zero) { return b ? one : zero; }
 
+/* 1/a from the hardware reciprocal estimate refined by two Newton steps
+ * (e = 1 - a r, r <- r + r e; each step squares the relative error), about
+ * half the instructions of the IEEE division sequence.  Pivots here are
+ * O(1) complex numbers, far from the denormal and overflow ranges that the
+ * division sequence rescales for. */
+QQMC_HD double rcp_nr(double a)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / a;
+#endif
+}
+QQMC_HD cplx crecip_nr(cplx a)
+{
+    const double d = rcp_nr(fma(a.x, a.x, a.y * a.y));
+    return cmk(a.x * d, -a.y * d);
+}
+
 /* g^<(tau), g^>(tau) for a pair of points, tau = later - earlier > 0 */
 struct pairv {
     cplx gl, gg;
@@ -89,11 +113,16 @@ QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
 template <int N> struct Geo {
     static constexpr int K = (N < 8 ? N : 8) + 1;      /* block size          */
     static constexpr int OFF = N + 1 - K;              /* cooperative levels  */
-    static constexpr int T = (K - 1 > 4) ? K - 5 : 0;  /* per-lane path       */
+    static constexpr int B = 5;                        /* register-tree depth */
+    static constexpr int T = (K - 1 > B) ? K - 1 - B : 0; /* per-lane path    */
     static constexpr int G = 1 << T;                   /* lanes per item      */
     static constexpr int PPW = 64 / G;                 /* items per wave      */
     static constexpr int IPP = 1 << OFF;               /* items per point     */
     static constexpr int NP = N * (N + 1) / 2;         /* pair-table length   */
+    /* waves per SIMD the kernels are compiled for: a depth-5 register tree
+     * starts from a 6 x 6 block and needs the whole register file of one
+     * wave (architectural plus accumulation registers, no scratch) */
+    static constexpr int WPS = (K - T > 5) ? 1 : 2;
 };
 
 template <int M> struct Blk {
@@ -102,30 +131,29 @@ template <int M> struct Blk {
 
 /* Depth-first walk below block level L (block indices L..K-1 remain).  C is
  * the accumulated Schur correction of the trailing block, so the current
- * trailing matrix is (Wick entries) - C.  prod = product of the pivots
- * eliminated so far, sgn = parity of the indices fixed so far.  A node
- * builds the correction blocks of BOTH children (indices 0 and 1 of the
+ * trailing matrix is (Wick entries) - C.  Returns the signed sum over the
+ * node's leaves relative to the node: a leaf pair's term carries the square
+ * of every pivot above it, so with p this node's pivot
+ *     V(node) = p^2 (V(child 0) - V(child 1))
+ * and the caller multiplies by the square of the pivots above the node.  A
+ * node builds the correction blocks of BOTH children (indices 0 and 1 of the
  * level's point) before descending, so while the first child's subtree runs
  * only the second child's (m-1) x (m-1) block is held, not the m x m parent. */
 template <int N, int L>
-QQMC_HD void subtree(const Blk<Geo<N>::K - L> &C, cplx prod, int sgn,
-                     const pairv *pr, cplx g0, cplx &acc)
+QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
     const cplx p = csub(g0, C.v[0][0]);
     if constexpr (M == 2) {
         /* latest vertex and the measurement: the two leaves differ only in
          * the last pivot g0 - C11 - col_b row_b / p, so
-         * sum_b (-1)^b dn_b up_b = prod^2 p (col_1 row_1 - col_0 row_0). */
+         * sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0). */
         const pairv P = pr[pidx(OFF + L, N)];
         const cplx col0 = csub(P.gg, C.v[1][0]), row0 = csub(cnc(P.gl), C.v[0][1]);
         const cplx col1 = csub(P.gl, C.v[1][0]), row1 = csub(cnc(P.gg), C.v[0][1]);
-        const cplx d = cfms(col0, row0, cmul(col1, row1));
-        const cplx term = cmul(cmul(cmul(prod, prod), p), d);
-        acc = sgn ? csub(acc, term) : cadd(acc, term);
+        return cmul(p, cfms(col0, row0, cmul(col1, row1)));
     } else {
-        const cplx r = crecip(p);
-        const cplx np = cmul(prod, p);
+        const cplx r = crecip_nr(p);
         Blk<M - 1> D0, D1;
         {
             /* pair (L, L+i) holds (g^<, g^>): index 0 takes column g^> and row
@@ -149,8 +177,9 @@ QQMC_HD void subtree(const Blk<Geo<N>::K - L> &C, cplx prod, int sgn,
                 }
             }
         }
-        subtree<N, L + 1>(D0, np, sgn, pr, g0, acc);
-        subtree<N, L + 1>(D1, np, sgn ^ 1, pr, g0, acc);
+        const cplx v0 = subtree<N, L + 1>(D0, pr, g0);
+        const cplx v1 = subtree<N, L + 1>(D1, pr, g0);
+        return cmul(cmul(p, p), csub(v0, v1));
     }
 }
 
@@ -178,7 +207,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                       int sgn, cplx g0)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, T = Geo<N>::T;
-    cplx acc = cmk(0.0, 0.0);
+    cplx v;
     if constexpr (T == 0) {
         (void)pre;
         Blk<K> C;
@@ -186,7 +215,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        subtree<N, 0>(C, prod, sgn, pr, g0, acc);
+        v = subtree<N, 0>(C, pr, g0);
     } else {
         cplx chat[T][K], rowv[T][K];
 #pragma unroll
@@ -196,12 +225,14 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
             cplx pk = csub(g0, C0.at(k, k));
 #pragma unroll
             for (int l = 0; l < k; ++l) pk = cfms(chat[l][k], rowv[l][k], pk);
-            const cplx r = crecip(pk);
+            const cplx r = crecip_nr(pk);
 #pragma unroll
             for (int i = k + 1; i < K; ++i) {
-                const pairv P = pr[pidx(OFF + k, OFF + i)];
-                cplx col = csub(csel(b, P.gl, P.gg), C0.at(i, k));
-                cplx row = csub(cnc(csel(b, P.gg, P.gl)), C0.at(k, i));
+                /* the index picks the table half by address: index 1 takes
+                 * column g^< and row -conj(g^>), index 0 the other halves */
+                const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
+                cplx col = csub(P[b ^ 1], C0.at(i, k));
+                cplx row = csub(cnc(P[b]), C0.at(k, i));
 #pragma unroll
                 for (int l = 0; l < k; ++l) {
                     col = cfms(chat[l][i], rowv[l][k], col);
@@ -222,9 +253,10 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                 for (int l = 0; l < T; ++l) c = cfma(chat[l][i], rowv[l][j], c);
                 C.v[i - T][j - T] = c;
             }
-        subtree<N, T>(C, prod, sgn, pr, g0, acc);
+        v = subtree<N, T>(C, pr, g0);
     }
-    return acc;
+    v = cmul(cmul(prod, prod), v);
+    return sgn ? cmk(-v.x, -v.y) : v;
 }
 
 /* Wick entry (i, j), i != j, of global elimination indices for index b of
@@ -239,13 +271,13 @@ QQMC_HD cplx wick_entry(const pairv *pr, int i, int j, int b)
     return csel(b, P.gl, P.gg);
 }
 
-/* Linear interpolation on the uniform grid tau_j = -t_half + j h (index and
- * fraction clamped, so values outside the grid hold the end values).  The
- * table stores (g^<, g^>) per node as four doubles. */
-QQMC_HD pairv interp_pair(const double *tab, int n_grid, double t_half, double h,
+/* Linear interpolation on the uniform grid tau_j = -t_half + j h, given
+ * inv_h = 1/h (index and fraction clamped, so values outside the grid hold
+ * the end values).  The table stores (g^<, g^>) per node as four doubles. */
+QQMC_HD pairv interp_pair(const double *tab, int n_grid, double t_half, double inv_h,
                           double tau)
 {
-    const double s = (tau + t_half) / h;
+    const double s = (tau + t_half) * inv_h;
     long j = (long)floor(s);
     if (j < 0) j = 0;
     if (j > n_grid - 2) j = n_grid - 2;

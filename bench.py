@@ -259,7 +259,7 @@ def run_serving(args):
         K = r.job.shifts.shape[0]
         buf = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
         qqmc.eval_order_async(tb, r.job, 10.0, buf, None,
-                              tile_len=min(1024, 1 << r.job.log2_n), stream=stream)
+                              tile_len=min(qqmc.SERVER_TILE_LEN, 1 << r.job.log2_n), stream=stream)
         h = buf.cpu().numpy()
         q = (h[0::2] + 1j * h[1::2]) / (1 << r.job.log2_n)
         te = time.perf_counter()

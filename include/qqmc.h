@@ -168,9 +168,10 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
 
 /* ---- Batched form -------------------------------------------------------
  * Many (parameter point, order) integrals in one persistent launch.  Each
- * item is estimated exactly as qqmc_eval_order would (the same tile
- * decomposition, hence the same per-shift sums bit for bit).  The plan owns
- * device buffers and a captured HIP graph; qqmc_plan_run replays it. */
+ * item is estimated exactly as qqmc_eval_order_async estimates it at the
+ * plan's tile_len (the same tile decomposition, hence the same per-shift
+ * sums bit for bit).  The plan owns device buffers and a captured HIP graph;
+ * qqmc_plan_run replays it. */
 typedef struct {
     qqmc_tables tables;
     qqmc_order order;      /* shifts are copied at plan creation */
@@ -179,7 +180,9 @@ typedef struct {
 typedef struct qqmc_plan_s *qqmc_plan;
 
 /* tile_len: lattice indices per tile (0 = autotuned); grid_blocks:
- * persistent workgroups (0 = autotuned). */
+ * persistent workgroups per order-8 launch, scaled by residency for other
+ * orders (0 = autotuned, which may also choose one workgroup per tile; then
+ * qqmc_plan_info reports grid_blocks 0). */
 qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items,
                              int32_t tile_len, int32_t grid_blocks,
                              void *stream, qqmc_plan *out);
@@ -198,8 +201,11 @@ void qqmc_plan_destroy(qqmc_plan p);
  * in hbm_budget_bytes and a slot is free, keeps tables and partial sums on
  * the device, and launches batches that mix the pending tiles of every
  * admitted request (continuous batching: requests that arrive while others
- * run join the next batch).  Each request's result is the same, bit for bit,
- * as qqmc_eval_order on the same input. */
+ * run join the next batch).  A request is cut into tiles of
+ * min(QQMC_SERVER_TILE_LEN, N) lattice indices, and its per-shift sums are
+ * the same, bit for bit, as those of qqmc_eval_order_async on the same input
+ * with that tile_len. */
+#define QQMC_SERVER_TILE_LEN 256
 typedef struct qqmc_server_s *qqmc_server;
 
 /* max_slots: requests resident at once; batch_tiles: tiles per launch

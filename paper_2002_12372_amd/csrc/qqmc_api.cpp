@@ -77,8 +77,10 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
 
 int32_t default_tile_len(const ItemDesc &d, int64_t N)
 {
+    /* about 64 tiles per resident single-wave workgroup (1024 on 256 CUs)
+     * keeps the last round of tiles short */
     int64_t t = 2048;
-    while (t > 64 && (int64_t)d.n_shifts * (N / t) < 16384) t /= 2;
+    while (t > 64 && (int64_t)d.n_shifts * (N / t) < 65536) t /= 2;
     if (t > N) t = N;
     return (int32_t)t;
 }

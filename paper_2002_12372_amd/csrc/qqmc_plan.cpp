@@ -236,7 +236,12 @@ hipError_t enqueue(qqmc_plan_s *p, const std::vector<Group> &groups, const TileR
             e = hipStreamWaitEvent(b, p->fork, 0);
             used[g.branch] = true;
         }
-        int32_t grid = (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.order));
+        /* share > 0: that fraction of the order's resident workgroups, each
+         * walking a strided share of the tiles; share 0: one workgroup per
+         * tile, handed out by the hardware dispatcher */
+        const int32_t grid =
+            share > 0.0 ? (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.order))
+                        : (int32_t)std::min<int64_t>(g.count, INT32_MAX);
         if (e == hipSuccess) e = launch_batch(g.order, p->buf.items, d_tiles + g.offset, g.count, grid, b);
     }
     for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
@@ -363,8 +368,8 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
     /* grid_blocks given: it caps the workgroups of every order's launch,
      * expressed as a share of that order's full residency */
     std::vector<int32_t> tls = tile_len ? std::vector<int32_t>{tile_len}
-                                        : std::vector<int32_t>{256, 512, 1024, 2048};
-    std::vector<double> shares = {1.0, 0.5};
+                                        : std::vector<int32_t>{128, 256, 512, 1024, 2048};
+    std::vector<double> shares = {1.0, 0.5, 0.0};
     if (grid_blocks) shares = {std::min(1.0, (double)grid_blocks / (p->n_cu * batch_blocks_per_cu(8)))};
     int32_t best_tl = tls[0];
     double best_share = shares[0];
@@ -386,7 +391,9 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
         }
     }
     p->grid_share = best_share;
-    p->grid_blocks = (int32_t)std::max(1.0, best_share * p->n_cu * batch_blocks_per_cu(8));
+    p->grid_blocks = best_share > 0.0
+                         ? (int32_t)std::max(1.0, best_share * p->n_cu * batch_blocks_per_cu(8))
+                         : 0;
     if (qqmc_status st = layout(p, best_tl)) {
         delete p;
         return st;

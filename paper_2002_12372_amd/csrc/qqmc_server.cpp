@@ -112,7 +112,7 @@ template <typename T> hipError_t grow_pair(T **h, T **d, size_t *cap, size_t nee
 
 struct qqmc_server_s {
     size_t budget = 0, used = 0;
-    int32_t max_slots = 1, tile_len = 1024;
+    int32_t max_slots = 1, tile_len = QQMC_SERVER_TILE_LEN;
     double launch_cost = 0.0;
     int device = 0, n_cu = 1;
     hipStream_t admit_stream = nullptr;
@@ -249,8 +249,9 @@ bool issue(qqmc_server_s *s, Launch &L)
     std::vector<double> cost(open.size());
     std::vector<int64_t> take(open.size(), 0);
     for (size_t i = 0; i < open.size(); ++i) cost[i] = tile_cost(open[i]->desc);
-    /* at least two tiles per resident workgroup, so the launch fills the GPU */
-    const int64_t min_tiles = 2 * (int64_t)s->n_cu * batch_blocks_per_cu(order);
+    /* at least eight tiles per resident workgroup, so the launch fills the
+     * GPU and its last round of tiles is short */
+    const int64_t min_tiles = 8 * (int64_t)s->n_cu * batch_blocks_per_cu(order);
     double spent = 0.0;
     int64_t taken = 0;
     bool progress = true;
@@ -306,8 +307,11 @@ bool issue(qqmc_server_s *s, Launch &L)
     if (e == hipSuccess)
         e = hipMemcpyAsync(L.d_tiles, L.h_tiles, sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice,
                            L.stream);
+    /* one workgroup per tile: the hardware dispatcher hands tiles to compute
+     * units as they free up, which evens out the uneven tile costs better
+     * than a fixed persistent grid */
     for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
-        const int32_t grid = s->n_cu * batch_blocks_per_cu(groups[g].order);
+        const int32_t grid = (int32_t)std::min<int64_t>(groups[g].cnt, INT32_MAX);
         e = launch_batch(groups[g].order, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
                          L.stream);
     }
@@ -462,7 +466,7 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     if (!s) return set_error(QQMC_ENOMEM, "host allocation failed");
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
-    s->tile_len = 1024;
+    s->tile_len = QQMC_SERVER_TILE_LEN;
     hipGetDevice(&s->device);
     hipError_t e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming);
@@ -480,15 +484,15 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     hipGetDeviceProperties(&prop, s->device);
     s->n_cu = prop.multiProcessorCount;
     /* cost budget of one launch: enough order-8 tiles (or batch_tiles tiles)
-     * to give every resident workgroup about four (a few milliseconds) */
+     * to give every resident workgroup about sixteen (a few milliseconds) */
     ItemDesc ref;
     std::memset(&ref, 0, sizeof(ref));
     ref.order = 8;
     ref.mode = QQMC_MODE_CHARGE;
-    ref.tile_len = 1024;
+    ref.tile_len = QQMC_SERVER_TILE_LEN;
     ref.t_meas = 10.0;
     ref.tau = 1.0;
-    const int32_t bt = batch_tiles ? batch_tiles : 4 * s->n_cu * batch_blocks_per_cu(8);
+    const int32_t bt = batch_tiles ? batch_tiles : 16 * s->n_cu * batch_blocks_per_cu(8);
     s->launch_cost = tile_cost(ref) * bt;
     s->t0 = std::chrono::steady_clock::now();
     s->worker = std::thread(worker_loop, s);

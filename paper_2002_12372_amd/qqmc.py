@@ -20,6 +20,7 @@ EINVAL, ENOMEM, EDEVICE, EADMIT, ENOTICKET = -1, -2, -3, -4, -5
 MODE_CHARGE, MODE_MODEL, MODE_CONSTANT = 0, 1, 2
 METHOD_TREE, METHOD_DIRECT = 0, 1
 MAX_ORDER = 14
+SERVER_TILE_LEN = 256   # QQMC_SERVER_TILE_LEN
 
 
 class QQMCError(RuntimeError):

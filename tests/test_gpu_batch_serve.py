@@ -72,7 +72,7 @@ def test_plan_autotuned(q):
     dots, tabs, entries = _entries(q)
     plan = q.plan_create(entries, T_MEAS)
     info = q.plan_info(plan)
-    assert info["tile_len"] in (256, 512, 1024, 2048) and info["grid_blocks"] > 0
+    assert info["tile_len"] in (128, 256, 512, 1024, 2048) and info["grid_blocks"] >= 0
     q.plan_run(plan)
     res = q.plan_results(plan)
     for (tb, job), got in zip(entries, res):
@@ -96,7 +96,7 @@ def test_server_results_equal_solo_runs(q):
     assert len(out) == len(tickets)
     for t, r in zip(tickets, trace):
         tb = q.make_tables(r.dot)
-        ref = _solo(q, tb, r.job, 1024)
+        ref = _solo(q, tb, r.job, q.SERVER_TILE_LEN)
         assert np.array_equal(out[t]["q_shift"], ref)
         assert out[t]["t_done"] >= out[t]["t_submit"]
     with pytest.raises(q.QQMCError):

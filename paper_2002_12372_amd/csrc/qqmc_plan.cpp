@@ -270,11 +270,12 @@ qqmc_status capture(qqmc_plan_s *p)
 }
 
 /* Times the plan on a subsample (every k-th tile of each group) with the
- * given workgroup share; seconds per lattice point. */
+ * given workgroup share; seconds per lattice point.  The subsample is the
+ * same fraction of the work for every tile length (a quarter, less for
+ * very large plans), so launch overheads weigh alike in every probe. */
 double probe(qqmc_plan_s *p, double share)
 {
-    const int64_t want = 4096;
-    const int64_t step = p->n_tiles > want ? p->n_tiles / want : 1;
+    const int64_t step = std::max<int64_t>(4, p->n_points / ((int64_t)1 << 26));
     std::vector<TileRef> sub;
     std::vector<Group> groups;
     double pts = 0.0;
@@ -368,7 +369,7 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
     /* grid_blocks given: it caps the workgroups of every order's launch,
      * expressed as a share of that order's full residency */
     std::vector<int32_t> tls = tile_len ? std::vector<int32_t>{tile_len}
-                                        : std::vector<int32_t>{128, 256, 512, 1024, 2048};
+                                        : std::vector<int32_t>{64, 128, 256, 512, 1024, 2048};
     std::vector<double> shares = {1.0, 0.5, 0.0};
     if (grid_blocks) shares = {std::min(1.0, (double)grid_blocks / (p->n_cu * batch_blocks_per_cu(8)))};
     int32_t best_tl = tls[0];

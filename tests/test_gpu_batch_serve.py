@@ -72,7 +72,7 @@ def test_plan_autotuned(q):
     dots, tabs, entries = _entries(q)
     plan = q.plan_create(entries, T_MEAS)
     info = q.plan_info(plan)
-    assert info["tile_len"] in (128, 256, 512, 1024, 2048) and info["grid_blocks"] >= 0
+    assert info["tile_len"] in (64, 128, 256, 512, 1024, 2048) and info["grid_blocks"] >= 0
     q.plan_run(plan)
     res = q.plan_results(plan)
     for (tb, job), got in zip(entries, res):

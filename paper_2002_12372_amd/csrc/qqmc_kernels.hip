@@ -41,8 +41,7 @@ template <int N> struct Lds {
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
     static constexpr int pairs = S + 64 * 16;                          /* tables*NP pairv */
-    static constexpr int res = pairs + tables * Gm::NP * 32;           /* PPW cplx       */
-    static constexpr int row = res + Gm::PPW * 16;                     /* PPW*(N+1) cplx */
+    static constexpr int row = pairs + tables * Gm::NP * 32;           /* PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
 };
@@ -50,6 +49,17 @@ template <int N> struct Lds {
 __device__ __forceinline__ double shfl_xor_d(double v, int m)
 {
     return __shfl_xor(v, m, WAVE);
+}
+
+/* Ordering point for the single-wave workgroups of the tree kernels: the
+ * local-memory operations of one wave execute in program order, so lanes
+ * exchanging data through local memory need only keep the compiler from
+ * moving memory operations across this point -- no hardware barrier and no
+ * wait for outstanding local-memory operations.  Every kernel that uses it
+ * is launched with exactly one 64-lane wave per workgroup. */
+__device__ __forceinline__ void wave_sync()
+{
+    asm volatile("" ::: "memory");
 }
 
 __device__ __forceinline__ int lane_rank(uint64_t mask)
@@ -136,13 +146,18 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
 #pragma unroll
         for (int m = 0; m < RPL; ++m) {
             if (sub + m * G == k) {
+                /* every table read before the first store, so the reads
+                 * are issued together rather than each behind a store it
+                 * might alias */
+                cplx v[N + 1];
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) v[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
                 s_row[k] = csub(g0, crow[m][k]);
 #pragma unroll
-                for (int j = k + 1; j <= N; ++j)
-                    s_row[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
+                for (int j = k + 1; j <= N; ++j) s_row[j] = v[j];
             }
         }
-        __syncthreads();
+        wave_sync();
         const cplx p = s_row[k];
         const cplx rp = crecip_nr(p);
 #pragma unroll
@@ -155,7 +170,7 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
             }
         }
         prod = cmul(prod, p);
-        __syncthreads();
+        wave_sync();
     }
 #pragma unroll
     for (int m = 0; m < RPL; ++m) {
@@ -165,7 +180,7 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
             for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[m][j];
         }
     }
-    __syncthreads();
+    wave_sync();
     return prod;
 }
 
@@ -179,7 +194,6 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
     const double *s_times = reinterpret_cast<const double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
     pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
-    cplx *s_res = reinterpret_cast<cplx *>(lds + L::res);
     const int lane = threadIdx.x;
     const int grp = lane / Gm::G, sub = lane % Gm::G;
     const int n_items = cnt * Gm::IPP;
@@ -211,7 +225,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                 const int q = sub + k * Gm::G;
                 if (q < Gm::NP) prg[q] = val[k];
             }
-            __syncthreads();
+            wave_sync();
         } else {
             /* several items share a point: PTS distinct points per round
              * (base is a multiple of IPP whenever PTS > 1); their pair
@@ -228,7 +242,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                     const double tj = j == N ? env.t_meas : tm[j];
                     s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
         cplx prod = cmk(1.0, 0.0);
@@ -243,24 +257,21 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             src.c = s_c0;
         }
         cplx s = lane_sum<N>(prg, src, sub, prod, sgn, env.g0);
+        /* sum over the lanes of a group, then over the groups of the round
+         * that share a point: they are SPAN aligned consecutive lanes, all
+         * active or all idle (points hold IPP consecutive items and rounds
+         * start at multiples of PPW) */
+        constexpr int SPAN = Gm::G * (Gm::IPP < Gm::PPW ? Gm::IPP : Gm::PPW);
 #pragma unroll
-        for (int m = 1; m < Gm::G; m <<= 1) {
+        for (int m = 1; m < SPAN; m <<= 1) {
             s.x += shfl_xor_d(s.x, m);
             s.y += shfl_xor_d(s.y, m);
         }
-        if constexpr (Gm::IPP == 1) {
-            if (sub == 0 && active) s_S[pt] = s;
-        } else {
-            if (sub == 0) s_res[grp] = s;
-            __syncthreads();
-            if (lane == 0) {
-                for (int g = 0; g < Gm::PPW; ++g) {
-                    const int it = base + g;
-                    if (it < n_items) s_S[it / Gm::IPP] = cadd(s_S[it / Gm::IPP], s_res[g]);
-                }
-            }
+        if (lane % SPAN == 0 && active) {
+            if constexpr (Gm::IPP == 1) s_S[pt] = s;
+            else s_S[pt] = cadd(s_S[pt], s);
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -315,14 +326,14 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             s_w[rk] = W;
             s_S[rk] = cmk(0.0, 0.0);
         }
-        __syncthreads();
+        wave_sync();
         keldysh_points<N>(cnt, env, lds);
         if (lane < cnt) {
             const cplx f = charge_prefactor<N>(s_S[lane]);
             const double w = s_w[lane];
             acc.add(cmk(f.x * w, f.y * w));
         }
-        __syncthreads();
+        wave_sync();
     }
     return wave_sum(acc.value());
 }
@@ -405,7 +416,7 @@ __global__ void __launch_bounds__(64, Geo<N>::WPS) points_tree_kernel(Env env, c
             for (int k = 0; k < N; ++k) s_times[rk * N + k] = ur[N - 1 - k];
             s_S[rk] = cmk(0.0, 0.0);
         }
-        __syncthreads();
+        wave_sync();
         keldysh_points<N>(cnt, env, lds);
         if (row < n_points) {
             cplx v = cmk(__builtin_nan(""), __builtin_nan(""));
@@ -413,7 +424,7 @@ __global__ void __launch_bounds__(64, Geo<N>::WPS) points_tree_kernel(Env env, c
             f[2 * row] = v.x;
             f[2 * row + 1] = v.y;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 

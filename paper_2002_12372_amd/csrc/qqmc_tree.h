@@ -260,15 +260,12 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
 }
 
 /* Wick entry (i, j), i != j, of global elimination indices for index b of
- * the earlier point min(i, j). */
+ * the earlier point min(i, j); the index picks the table half by address
+ * (upper entries -conj(b ? g^> : g^<), lower entries b ? g^< : g^>). */
 QQMC_HD cplx wick_entry(const pairv *pr, int i, int j, int b)
 {
-    if (i < j) {
-        const pairv P = pr[pidx(i, j)];
-        return cnc(csel(b, P.gg, P.gl));
-    }
-    const pairv P = pr[pidx(j, i)];
-    return csel(b, P.gl, P.gg);
+    if (i < j) return cnc((&pr[pidx(i, j)].gl)[b]);
+    return (&pr[pidx(j, i)].gl)[b ^ 1];
 }
 
 /* Linear interpolation on the uniform grid tau_j = -t_half + j h, given

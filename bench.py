@@ -68,9 +68,16 @@ def cpu_baseline(order, log2_n, lattice_a, shifts, count):
     oracle.eval_sums(tb, d.t_meas, order, log2_n, lattice_a, shifts[:1], 1.0, 0, 0, count,
                      n_threads=threads)
     dt = time.perf_counter() - t0
+    one = max(count // 64, 64)
+    t0 = time.perf_counter()
+    oracle.eval_sums(tb, d.t_meas, order, log2_n, lattice_a, shifts[:1], 1.0, 0, 0, one,
+                     n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": count / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": "lattice indices 0..%d of shift 0 (order %d, same dot and lattice), "
-                      "%d OpenMP threads, %.1f s" % (count - 1, order, threads, dt)}
+                      "%d OpenMP threads, %.1f s" % (count - 1, order, threads, dt),
+            "one_core": {"value": one / dt1, "sample": "indices 0..%d, 1 thread, %.1f s"
+                                                      % (one - 1, dt1)}}
 
 
 def timed_steps(fn, steps, warmup, stream):
@@ -289,6 +296,31 @@ def run_serving(args):
         "capacity_req_per_s_estimate": capacity,
         "results_bitwise_equal_served_vs_plain": bool(same),
     }
+    if args.find_capacity > 0:
+        # bisection on the arrival rate: a rate is sustained when the queue
+        # drains within 10% of the arrival window after the last arrival
+        lo, hi = 0.25 * capacity, 1.5 * capacity
+        steps = []
+        for _ in range(args.find_capacity):
+            mid = 0.5 * (lo + hi)
+            scale = mid / args.rate
+            lat_b, span_b, _ = serve(scale)
+            window = trace[-1].arrival_s / scale
+            ok = span_b - window <= 0.1 * window
+            steps.append({"rate_req_per_s": mid, "p99_s": float(np.percentile(lat_b, 99)),
+                          "drain_s": span_b - window, "sustained": bool(ok)})
+            print("capacity probe %.2f req/s: drain %.2f s of %.2f s window -> %s"
+                  % (mid, span_b - window, window, ok), file=sys.stderr, flush=True)
+            if ok:
+                lo = mid
+            else:
+                hi = mid
+        scale = 0.8 * lo / args.rate
+        lat_c, span_c, _ = serve(scale)
+        out["max_sustained_rate"] = {
+            "rate_req_per_s": lo, "bisection": steps,
+            "at_0.8x": {"rate_req_per_s": 0.8 * lo, "p50_s": float(np.percentile(lat_c, 50)),
+                        "p99_s": float(np.percentile(lat_c, 99)), "makespan_s": span_c}}
     if args.serve_at_fraction > 0:
         scale = capacity * args.serve_at_fraction / args.rate
         lat_f, span_f, _ = serve(scale)
@@ -341,7 +373,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--shifts", type=int, default=32)
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes first (a reference "
@@ -354,6 +386,8 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=int, default=16)
     ap.add_argument("--serve-at-fraction", type=float, default=0.0)
+    ap.add_argument("--find-capacity", type=int, default=0,
+                    help="serving: bisection steps for the highest sustained arrival rate")
     ap.add_argument("--stress-log2n", type=int, default=18)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -41,9 +41,11 @@ def warp_flops(n):
 
 
 def geometry(n):
+    """Block size K, cooperative top levels, per-lane path levels T (each
+    lane walks a register tree of depth at most 5)."""
     K = min(n, 8) + 1
     off = n + 1 - K
-    T = K - 5 if K - 1 > 4 else 0
+    T = K - 6 if K - 1 > 5 else 0
     return K, off, T
 
 

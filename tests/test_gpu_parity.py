@@ -175,16 +175,42 @@ def test_constant_mode_full_size(q, tiny_tables):
     assert abs(mean.real - exact) < 5 * se
 
 
+def test_high_order_stored_oracle_values(q, oracle_mod):
+    """Orders 10..14 at N = 2^14, two shifts, stress dot: every Q^{(s)}
+    against the oracle values stored by tests/golden/make_high_order.py (the
+    oracle needs minutes for these, so they are computed once)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "high_order_q.json")
+    with open(path) as f:
+        g = json.load(f)
+    d = g["dot"]
+    tb = oracle_mod.Tables(d["eps_d"], d["gamma"], d["beta"], d["bias_v"], d["n_grid"],
+                           d["t_half"])
+    gt = _upload(q, tb)
+    for rec in g["orders"]:
+        n = rec["order"]
+        job = order_job(g["seed"], n, g["log2_n"], g["n_shifts"])
+        assert job.lattice_a == rec["lattice_a"]
+        assert np.array_equal(job.shifts, np.array(rec["shifts"]))
+        qs, _, _ = q.eval_order(gt, job, g["t_meas"])
+        qo = np.array([complex(re, im) for re, im in rec["q_shift"]])
+        _compare_q(qs, qo, "stored n=%d" % n)
+
+
 def test_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
-    """n = 8, N = 2^20, 32 shifts, the launch configuration of the benchmark:
-    sampled tile sums against the oracle over the same index ranges, and the
-    tile sums of each shift add up to its shift sum."""
+    """n = 8, N = 2^20, 32 shifts, the launch configuration of the benchmark
+    (the library's default tile length): sampled tile sums against the oracle
+    over the same index ranges, and the tile sums of each shift add up to its
+    shift sum."""
     gt = _upload(q, tiny_tables)
     job = order_job(1, 8, 20, 32)
-    tile_len = 1024
-    nt = q.n_tiles(job, tile_len)
-    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
     sums = torch.zeros(2 * 32, dtype=torch.float64, device="cuda")
+    nt = q.eval_order_async(gt, job, 10.0, sums, None)
+    torch.cuda.synchronize()
+    tile_len = (1 << 20) * 32 // nt
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
     q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
     torch.cuda.synchronize()
     th = tiles.cpu().numpy()
@@ -196,7 +222,7 @@ def test_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
         part = tc[s * per:(s + 1) * per]
         assert abs(part.sum() - sc[s]) <= 1e-12 * np.sum(np.abs(part))
     rng = np.random.default_rng(99)
-    for k in rng.choice(nt, size=3, replace=False):
+    for k in rng.choice(nt, size=16, replace=False):
         s, i0 = divmod(int(k), per)
         ref = oracle_mod.eval_sums(tiny_tables, 10.0, 8, 20, job.lattice_a, job.shifts[s:s + 1],
                                    1.0, 0, i0 * tile_len, (i0 + 1) * tile_len)[0]

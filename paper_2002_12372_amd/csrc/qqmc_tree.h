@@ -70,6 +70,11 @@ QQMC_HD cplx cfms(cplx a, cplx b, cplx c)
 {
     return cmk(fma(-a.x, b.x, fma(a.y, b.y, c.x)), fma(-a.x, b.y, fma(-a.y, b.x, c.y)));
 }
+/* c + conj(a)*b */
+QQMC_HD cplx cfmac(cplx a, cplx b, cplx c)
+{
+    return cmk(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
 /* -conj(a) */
 QQMC_HD cplx cnc(cplx a) { return cmk(-a.x, a.y); }
 QQMC_HD cplx crecip(cplx a)
@@ -129,6 +134,22 @@ template <int M> struct Blk {
     cplx v[M][M];
 };
 
+/* The last vertex's pair (n-1, measurement), the same for every leaf of a
+ * point: with col_b / row_b its column and row entries minus the block
+ * corrections C10 / C01,
+ *   col_1 row_1 - col_0 row_0 = a + s C01 + conj(s) C10,
+ *   a = g^< (-conj g^>) - g^> (-conj g^<),  s = g^> - g^<. */
+struct LeafK {
+    cplx a, s;
+};
+QQMC_HD LeafK leaf_constants(const pairv &P)
+{
+    LeafK k;
+    k.a = cfms(P.gg, cnc(P.gl), cmul(P.gl, cnc(P.gg)));
+    k.s = csub(P.gg, P.gl);
+    return k;
+}
+
 /* Depth-first walk below block level L (block indices L..K-1 remain).  C is
  * the accumulated Schur correction of the trailing block, so the current
  * trailing matrix is (Wick entries) - C.  Returns the signed sum over the
@@ -140,18 +161,40 @@ template <int M> struct Blk {
  * level's point) before descending, so while the first child's subtree runs
  * only the second child's (m-1) x (m-1) block is held, not the m x m parent. */
 template <int N, int L>
-QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0)
+QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, const LeafK &lk)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
     const cplx p = csub(g0, C.v[0][0]);
     if constexpr (M == 2) {
         /* latest vertex and the measurement: the two leaves differ only in
          * the last pivot g0 - C11 - col_b row_b / p, so
-         * sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0). */
-        const pairv P = pr[pidx(OFF + L, N)];
-        const cplx col0 = csub(P.gg, C.v[1][0]), row0 = csub(cnc(P.gl), C.v[0][1]);
-        const cplx col1 = csub(P.gl, C.v[1][0]), row1 = csub(cnc(P.gg), C.v[0][1]);
-        return cmul(p, cfms(col0, row0, cmul(col1, row1)));
+         * sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0),
+         * the bracket expanded with the point's leaf constants */
+        (void)pr;
+        return cmul(p, cfmac(lk.s, C.v[1][0], cfma(lk.s, C.v[0][1], lk.a)));
+    } else if constexpr (M == 3) {
+        /* vertices u (this level), w (the last one) and the measurement m,
+         * by cofactors instead of elimination (no reciprocal): with S the
+         * 3x3 trailing matrix for index b of u,
+         *   sum_{b_w} (-1)^{b_w} det S = S_uu d + S_uw S_mu conj(s) + S_um S_wu s
+         * (the S_mm terms cancel, d as in the leaf with this node's C12, C21),
+         * multiplied by the 2x2 vertex determinant S_uu S_ww - S_uw S_wu. */
+        const pairv Pw = pr[pidx(OFF + L, OFF + L + 1)];
+        const pairv Pm = pr[pidx(OFF + L, N)];
+        const cplx sww = csub(g0, C.v[1][1]);
+        const cplx spp = cmul(p, sww);
+        const cplx sd = cmul(p, cfmac(lk.s, C.v[2][1], cfma(lk.s, C.v[1][2], lk.a)));
+        cplx t[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const cplx suw = csub(cnc(b ? Pw.gg : Pw.gl), C.v[0][1]);
+            const cplx swu = csub(b ? Pw.gl : Pw.gg, C.v[1][0]);
+            const cplx sum_ = csub(cnc(b ? Pm.gg : Pm.gl), C.v[0][2]);
+            const cplx smu = csub(b ? Pm.gl : Pm.gg, C.v[2][0]);
+            const cplx delta = cfma(cmul(sum_, swu), lk.s, cfmac(lk.s, cmul(suw, smu), sd));
+            t[b] = cmul(cfms(suw, swu, spp), delta);
+        }
+        return csub(t[0], t[1]);
     } else {
         const cplx r = crecip_nr(p);
         Blk<M - 1> D0, D1;
@@ -177,8 +220,8 @@ QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0)
                 }
             }
         }
-        const cplx v0 = subtree<N, L + 1>(D0, pr, g0);
-        const cplx v1 = subtree<N, L + 1>(D1, pr, g0);
+        const cplx v0 = subtree<N, L + 1>(D0, pr, g0, lk);
+        const cplx v1 = subtree<N, L + 1>(D1, pr, g0, lk);
         return cmul(cmul(p, p), csub(v0, v1));
     }
 }
@@ -207,6 +250,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                       int sgn, cplx g0)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, T = Geo<N>::T;
+    const LeafK lk = leaf_constants(pr[pidx(N - 1, N)]);
     cplx v;
     if constexpr (T == 0) {
         (void)pre;
@@ -215,7 +259,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        v = subtree<N, 0>(C, pr, g0);
+        v = subtree<N, 0>(C, pr, g0, lk);
     } else {
         cplx chat[T][K], rowv[T][K];
 #pragma unroll
@@ -253,7 +297,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                 for (int l = 0; l < T; ++l) c = cfma(chat[l][i], rowv[l][j], c);
                 C.v[i - T][j - T] = c;
             }
-        v = subtree<N, T>(C, pr, g0);
+        v = subtree<N, T>(C, pr, g0, lk);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;

@@ -5,33 +5,44 @@ and divide count 1, a fused multiply-add counts 2, negation and selection
 count 0.  Complex helpers: add/sub 2, multiply 6, multiply-add 8, reciprocal
 6 (|p|^2, one division, two products).
 
-``tree_flops(n)`` is the work of the elimination tree over the 2^n Keldysh
-index vectors of ONE point with every tree node visited exactly once (the
-work the method needs); ``lane_flops(n)`` is what the kernel actually issues,
-including the per-lane recomputation of the top levels (for efficiency
-accounting only).
+``tree_flops(n)`` is the work of the tree over the 2^n Keldysh index vectors
+of ONE point with every tree node visited exactly once, in the form the
+kernel evaluates it: elimination nodes down to 4x4 blocks, the 3x3 nodes by
+cofactors, the leaf bracket from per-point constants (the work the method
+needs).  ``lane_flops(n)`` is what the kernel actually issues, including the
+per-lane recomputation of the levels above each lane's subtree (for
+efficiency accounting only).
 """
 
 
 def _node(m):
-    """Tree node holding an m x m trailing block, m > 2: pivot, reciprocal,
-    pivot product, and for both indices the pivot row/column and the rank-1
-    update of the (m-1)^2 child block."""
-    return 2 + 6 + 6 + 2 * (2 * (m - 1) + 8 * (m - 1) + 8 * (m - 1) ** 2)
+    """Elimination node holding an m x m trailing block, m >= 4: pivot,
+    reciprocal, for both indices the pivot row/column and the rank-1 update
+    of the (m-1)^2 child block except its measurement diagonal (never read),
+    and the relative sum p^2 (V_0 - V_1)."""
+    return 2 + 6 + 2 * (2 * (m - 1) + 8 * (m - 1) + 8 * ((m - 1) ** 2 - 1)) + 14
 
 
-LEAF_PAIR = 2 + 8 + 6 + 8 + 18 + 2   # last vertex + measurement, both indices
-PAIR_LOOKUP = 16                     # two interpolations (g^<, g^>) per pair
-POINT_EPILOGUE = 12                  # prefactor, weight, compensated add
+# 3x3 node by cofactors: S_ww, p S_ww, p d (d from the leaf constants), and
+# for both indices of u four entries, two products, the bracket, the 2x2
+# determinant and the product; then the difference.
+NODE3 = 2 + 6 + (16 + 6) + 2 * (8 + 12 + 16 + 8 + 6) + 2
+ROOT2 = 2 + 16 + 6          # n = 1: the single leaf pair at the root
+LEAF_CONSTANTS = 14 + 2     # a and s of the last vertex pair, once per point
+PAIR_LOOKUP = 16            # two interpolations (g^<, g^>) per pair
+POINT_EPILOGUE = 12         # prefactor, weight, compensated add
 
 
 def tree_flops(n):
     """Per point inside the domain."""
-    total = 0
-    for k in range(n - 1):           # levels with blocks of size n+1-k > 2
-        total += (1 << k) * _node(n + 1 - k)
-    total += (1 << (n - 1)) * LEAF_PAIR
-    return total + PAIR_LOOKUP * n * (n + 1) // 2 + POINT_EPILOGUE
+    if n == 1:
+        total = ROOT2
+    else:
+        total = 0
+        for k in range(n - 2):           # blocks of size n+1-k >= 4
+            total += (1 << k) * _node(n + 1 - k)
+        total += (1 << (n - 2)) * NODE3
+    return total + LEAF_CONSTANTS + PAIR_LOOKUP * n * (n + 1) // 2 + POINT_EPILOGUE
 
 
 def warp_flops(n):
@@ -55,12 +66,16 @@ def lane_flops(n):
     path = 0
     for k in range(T):
         path += 2 + 8 * k + 6 + (K - 1 - k) * (10 + 16 * k) + 6
-    ct = (K - T) ** 2 * 8 * T
+    ct = ((K - T) ** 2 - 1) * 8 * T
     sub = 0
-    for lvl in range(T, K - 2):
-        sub += (1 << (lvl - T)) * _node(K - lvl)
-    sub += (1 << (K - 2 - T)) * LEAF_PAIR
-    per_item = (1 << T) * (path + ct + sub)
+    if K == 2:
+        sub = ROOT2
+    else:
+        for lvl in range(T, K - 3):
+            sub += (1 << (lvl - T)) * _node(K - lvl)
+        sub += (1 << (K - 3 - T)) * NODE3
+    per_lane = path + ct + sub + 12 + LEAF_CONSTANTS   # final prod^2 scaling
+    per_item = (1 << T) * per_lane
     top = 0
     for k in range(off):
         rows = n - k

@@ -74,8 +74,9 @@ struct Group {
 } // namespace
 
 /* Relative cost of one tile: warp for every point, the Keldysh sum (about
- * 140 FP64 operations per index vector plus O(n^2) setup) for the points
- * inside the domain. */
+ * 140 issued FP64 operations per index vector, the tree's work plus the
+ * lanes' repeated set-up, plus O(n^2) per point) for the points inside the
+ * domain.  Only ratios matter: it orders tiles and sizes launches. */
 double tile_cost(const ItemDesc &d)
 {
     const double frac = d.mode == QQMC_MODE_CHARGE ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;

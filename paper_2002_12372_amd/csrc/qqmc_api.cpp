@@ -351,6 +351,9 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, const 
     if (n_points > 0 && (!u || !f)) return set_error(QQMC_EINVAL, "NULL buffer");
     if (!(t_meas > 0.0) || !(t_meas <= t->t_half))
         return set_error(QQMC_EINVAL, "t_meas must satisfy 0 < t_meas <= t_half");
+    if (method != QQMC_METHOD_TREE && method != QQMC_METHOD_DIRECT)
+        return set_error(QQMC_EINVAL, "unknown method");
+    if (n_points == 0) return QQMC_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (method == QQMC_METHOD_TREE)

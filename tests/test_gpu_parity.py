@@ -229,6 +229,38 @@ def test_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
         assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13
 
 
+def test_eval_points_empty(q, tiny_tables):
+    """No points: both methods return without touching the (empty) buffers."""
+    gt = _upload(q, tiny_tables)
+    u = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    f = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    for m in (q.METHOD_TREE, q.METHOD_DIRECT):
+        q.eval_points(gt, 4, 10.0, u, f, method=m)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [1, 8, 9])
+def test_eval_order_smallest_lattice(q, oracle_mod, tiny_tables, n):
+    """N = 2^6, the smallest lattice: a single 64-index tile per shift, one
+    shift; the estimate against the oracle (the default tile length is
+    clamped to N)."""
+    gt = _upload(q, tiny_tables)
+    job = order_job(5, n, 6, 1)
+    qs, _, _ = q.eval_order(gt, job, 10.0)
+    qo, _, _ = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                     job.shifts, job.model_tau)
+    _compare_q(qs, qo, "N=64 n=%d" % n)
+
+
+def test_model_mode_largest_lattice_and_order(q, tiny_tables):
+    """N = 2^24 and order 14, the largest accepted: with f := p_n every warped
+    sample is tau^n, so the estimate is tau^n up to rounding."""
+    gt = _upload(q, tiny_tables)
+    job = order_job(2, 14, 24, 1, model_tau=0.9, mode=q.MODE_MODEL)
+    qs, _, _ = q.eval_order(gt, job, 10.0)
+    assert abs(qs[0] - 0.9 ** 14) <= 1e-12 * 0.9 ** 14
+
+
 def test_eval_order_is_deterministic(q, tiny_tables):
     gt = _upload(q, tiny_tables)
     job = order_job(7, 6, 14, 8)

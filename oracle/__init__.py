@@ -57,6 +57,15 @@ def _load():
                                      i64, i64, i, P]
     lib.oracle_eval_sums.restype = i
     lib.oracle_max_threads.restype = i
+    lib.oracle_eval_sums_model.argtypes = [P, P, i, d, d, d, i, i, u64, i, P, d, P, i, i,
+                                           i64, i64, i, P]
+    lib.oracle_eval_sums_model.restype = i
+    lib.oracle_learn_model.argtypes = [P, P, i, d, d, d, i, i, u64, P, d, i, d, d, i, P, P]
+    lib.oracle_learn_model.restype = i
+    lib.oracle_model_from_hist.argtypes = [i, i, P, d, d, P]
+    lib.oracle_model_from_hist.restype = i
+    lib.oracle_model_inverse.argtypes = [P, i, d, P]
+    lib.oracle_model_inverse.restype = d
     _lib = lib
     return lib
 
@@ -172,33 +181,69 @@ def warp(x, model_tau, t_meas):
 
 
 def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
-              i_begin=0, i_end=None, n_threads=0):
-    """Per-shift sums of fbar over lattice indices [i_begin, i_end)."""
+              i_begin=0, i_end=None, n_threads=0, cdf=None):
+    """Per-shift sums of fbar over lattice indices [i_begin, i_end); cdf: a
+    learned second warp (n x (n_bins+1)) or None."""
     shifts = _f64(shifts)
     K = shifts.shape[0]
     assert shifts.shape == (K, n)
     if i_end is None:
         i_end = 1 << log2_n
     sums = np.zeros(2 * K)
-    rc = _load().oracle_eval_sums(*tables._args(), t_meas, n, log2_n,
-                                  int(lattice_a), K, _p(shifts), model_tau,
-                                  mode, int(i_begin), int(i_end), n_threads,
-                                  _p(sums))
-    if rc != 0:
-        raise ValueError("oracle_eval_sums: bad arguments")
+    if cdf is None:
+        cp, nb = None, 0
+    else:
+        cdf = _f64(cdf)
+        assert cdf.ndim == 2 and cdf.shape[0] == n
+        cp, nb = _p(cdf), cdf.shape[1] - 1
+    rc = _load().oracle_eval_sums_model(*tables._args(), t_meas, n, log2_n,
+                                        int(lattice_a), K, _p(shifts), model_tau,
+                                        cp, nb, mode, int(i_begin), int(i_end), n_threads,
+                                        _p(sums))
+    assert rc == 0
     return sums[0::2] + 1j * sums[1::2]
 
 
 def eval_order(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
-               n_threads=0):
+               n_threads=0, cdf=None):
     """Q^{(s)} for every shift, their mean and standard error (App. G)."""
     N = 1 << log2_n
     q = eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau,
-                  mode, 0, N, n_threads) / N
+                  mode, 0, N, n_threads, cdf) / N
     K = q.shape[0]
     mean = q.mean()
     stderr = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
     return q, mean, stderr
+
+
+def learn_model(tables, t_meas, n, log2_m, lattice_a, shift, model_tau, n_bins,
+                lam, floor_eps, n_threads=0):
+    """Learned second warp (App. I): returns (hist, cdf), shapes
+    (n, n_bins) and (n, n_bins + 1)."""
+    shift = _f64(shift).reshape(n)
+    hist = np.zeros((n, n_bins))
+    cdf = np.zeros((n, n_bins + 1))
+    rc = _load().oracle_learn_model(*tables._args(), t_meas, n, log2_m, int(lattice_a),
+                                    _p(shift), model_tau, n_bins, lam, floor_eps,
+                                    n_threads, _p(hist), _p(cdf))
+    assert rc == 0
+    return hist, cdf
+
+
+def model_from_hist(hist, lam, floor_eps):
+    hist = _f64(hist)
+    n, nb = hist.shape
+    cdf = np.zeros((n, nb + 1))
+    assert _load().oracle_model_from_hist(n, nb, _p(hist), lam, floor_eps, _p(cdf)) == 0
+    return cdf
+
+
+def model_inverse(cdf_row, x):
+    """(w, q(w)) for one coordinate's CDF row."""
+    cdf_row = _f64(cdf_row)
+    w = np.zeros(1)
+    q = _load().oracle_model_inverse(_p(cdf_row), cdf_row.shape[0] - 1, float(x), _p(w))
+    return float(w[0]), float(q)
 
 
 def max_threads():

@@ -448,15 +448,84 @@ int oracle_max_threads(void)
 #endif
 }
 
-int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
-                     double t_half, double n_sigma, double t_meas,
-                     int n, int log2_n, uint64_t lattice_a,
-                     int n_shifts, const double *shifts, double model_tau,
-                     int mode, int64_t i_begin, int64_t i_end, int n_threads,
-                     double *sums)
+double oracle_model_inverse(const double *cdf, int n_bins, double x, double *w)
+{
+    int b = 0;
+    for (int k = 1; k < n_bins; ++k)
+        if (cdf[k] <= x) b = k;
+    const double width = cdf[b + 1] - cdf[b];
+    *w = ((double)b + (x - cdf[b]) / width) / (double)n_bins;
+    return (double)n_bins * width;
+}
+
+int oracle_model_from_hist(int n, int n_bins, const double *hist, double lambda,
+                           double floor_eps, double *cdf)
+{
+    if (n < 1 || n_bins < 1 || !(lambda > 0.0) || !(floor_eps >= 0.0) || !(floor_eps <= 1.0))
+        return -1;
+    double *sm = (double *)malloc(sizeof(double) * (size_t)n_bins);
+    if (!sm) return -1;
+    for (int j = 0; j < n; ++j) {
+        const double *h = hist + (size_t)j * n_bins;
+        /* Gaussian kernel smoothing K(w, w') = exp(-(w - w')^2 / lambda^2)
+         * over the bin centres, normalised by the kernel weights */
+        double total = 0.0;
+        for (int b = 0; b < n_bins; ++b) {
+            const double wb = (b + 0.5) / n_bins;
+            double num = 0.0, den = 0.0;
+            for (int k = 0; k < n_bins; ++k) {
+                const double d = (wb - (k + 0.5) / n_bins) / lambda;
+                const double K = exp(-d * d);
+                num += K * h[k];
+                den += K;
+            }
+            sm[b] = num / den;
+            total += sm[b] / n_bins;
+        }
+        double *c = cdf + (size_t)j * (n_bins + 1);
+        c[0] = 0.0;
+        for (int b = 0; b < n_bins; ++b) {
+            const double p = total > 0.0 ? sm[b] / total : 1.0;
+            const double q = (1.0 - floor_eps) * p + floor_eps;
+            c[b + 1] = c[b] + q / n_bins;
+        }
+        const double end = c[n_bins];
+        for (int b = 1; b < n_bins; ++b) c[b] /= end;
+        c[n_bins] = 1.0;
+    }
+    free(sm);
+    return 0;
+}
+
+/* The first warp followed by the learned one: x -> w -> (u, W). */
+static int warp_model(int n, const double *x, const double *cdf, int n_bins,
+                      double model_tau, double t_meas, double *u, double *W,
+                      double *qprod)
+{
+    double w[32];
+    double q = 1.0;
+    for (int j = 0; j < n; ++j) {
+        if (cdf)
+            q *= oracle_model_inverse(cdf + (size_t)j * (n_bins + 1), n_bins, x[j], &w[j]);
+        else
+            w[j] = x[j];
+    }
+    const int inside = oracle_warp(n, w, model_tau, t_meas, u, W);
+    *W /= q;
+    *qprod = q;
+    return inside;
+}
+
+int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
+                           double t_half, double n_sigma, double t_meas,
+                           int n, int log2_n, uint64_t lattice_a,
+                           int n_shifts, const double *shifts, double model_tau,
+                           const double *cdf, int n_bins,
+                           int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                           double *sums)
 {
     if (n < 1 || n > 24 || log2_n < 1 || log2_n > 40 || i_end < i_begin ||
-        i_begin < 0 || n_shifts < 1 || mode < 0 || mode > 2)
+        i_begin < 0 || n_shifts < 1 || mode < 0 || mode > 2 || (cdf && n_bins < 1))
         return -1;
     int64_t cnt = i_end - i_begin;
     double *vals = (double *)malloc(sizeof(double) * 2 * (size_t)(cnt > 0 ? cnt : 1));
@@ -469,18 +538,18 @@ int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
         const double *sh = shifts + (size_t)s * n;
         #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
         for (int64_t q = 0; q < cnt; ++q) {
-            double x[32], u[32], W, S[2], M;
+            double x[32], u[32], W, S[2], M, qp;
             oracle_lattice_point((uint64_t)(i_begin + q), n, log2_n, lattice_a, sh, x);
-            int inside = oracle_warp(n, x, model_tau, t_meas, u, &W);
+            int inside = warp_model(n, x, cdf, n_bins, model_tau, t_meas, u, &W, &qp);
             cplx f = 0.0;
             if (mode == 1) {
-                /* f := p_n on the whole v-domain: f/p * C = C */
+                /* f := p_n q on the whole v-domain: f W = C */
                 double p = 1.0, prev = t_meas;
                 for (int m = 0; m < n; ++m) {
                     p *= exp(-(prev - u[m]) / model_tau);
                     prev = u[m];
                 }
-                f = p * W;
+                f = p * qp * W;
             } else if (inside) {
                 if (mode == 2) {
                     f = W;
@@ -505,4 +574,65 @@ int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
     }
     free(vals);
     return 0;
+}
+
+int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
+                     double t_half, double n_sigma, double t_meas,
+                     int n, int log2_n, uint64_t lattice_a,
+                     int n_shifts, const double *shifts, double model_tau,
+                     int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                     double *sums)
+{
+    return oracle_eval_sums_model(gl, gg, n_grid, t_half, n_sigma, t_meas, n, log2_n,
+                                  lattice_a, n_shifts, shifts, model_tau, NULL, 0, mode,
+                                  i_begin, i_end, n_threads, sums);
+}
+
+int oracle_learn_model(const double *gl, const double *gg, int n_grid,
+                       double t_half, double n_sigma, double t_meas,
+                       int n, int log2_m, uint64_t lattice_a,
+                       const double *shift, double model_tau, int n_bins,
+                       double lambda, double floor_eps, int n_threads,
+                       double *hist, double *cdf)
+{
+    if (n < 1 || n > 24 || log2_m < 1 || log2_m > 30 || n_bins < 1) return -1;
+    const int64_t M = (int64_t)1 << log2_m;
+    double *vals = (double *)malloc(sizeof(double) * (size_t)M);
+    double *h = (double *)calloc((size_t)n * n_bins, sizeof(double));
+    if (!vals || !h) {
+        free(vals);
+        free(h);
+        return -1;
+    }
+    int nt = n_threads > 0 ? n_threads : oracle_max_threads();
+    cplx ipow = 1.0;
+    for (int k = 0; k < n + 1; ++k) ipow *= I;
+    /* samples of f~ over the unit cube after the exponential warp */
+    #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int64_t i = 0; i < M; ++i) {
+        double x[32], u[32], W, S[2], Mass;
+        oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
+        double v = 0.0;
+        if (oracle_warp(n, x, model_tau, t_meas, u, &W)) {
+            oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, t_meas, n, u, S, &Mass);
+            v = fabs(creal(-2.0 * ipow * (S[0] + I * S[1]) * W));
+        }
+        vals[i] = v;
+    }
+    /* projection on each coordinate: bin sums in index order */
+    for (int64_t i = 0; i < M; ++i) {
+        if (vals[i] == 0.0) continue;
+        double x[32];
+        oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
+        for (int j = 0; j < n; ++j) {
+            int b = (int)(x[j] * n_bins);
+            if (b > n_bins - 1) b = n_bins - 1;
+            h[(size_t)j * n_bins + b] += vals[i];
+        }
+    }
+    if (hist) memcpy(hist, h, sizeof(double) * (size_t)n * n_bins);
+    const int rc = oracle_model_from_hist(n, n_bins, h, lambda, floor_eps, cdf);
+    free(vals);
+    free(h);
+    return rc;
 }

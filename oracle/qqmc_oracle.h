@@ -91,6 +91,55 @@ int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
 /* Number of OpenMP threads the oracle would use for n_threads <= 0. */
 int oracle_max_threads(void);
 
+/* ---- Learned second warp (App. I, "Learning h^(i) from the integrand") ----
+ * After the exponential warp the integrand over the unit cube is
+ * f~(w) = fbar(u(w)) (Jacobian C/p_n included).  The second warp maps a
+ * lattice point x to w coordinate by coordinate through the inverse CDF of a
+ * density q_j on [0, 1), piecewise constant on n_bins equal bins; the weight
+ * gains a factor 1/prod_j q_j(w_j).  A model is stored as its CDF at the bin
+ * edges, cdf[j*(n_bins+1) + b], b = 0..n_bins, cdf[...0] = 0, cdf[...n_bins]
+ * = 1.
+ *
+ * Readings (the appendix leaves them open): the projection bins |Re f~|
+ * (a density must be non-negative; Q_n is real); bins are [b, b+1)/n_bins
+ * with centres (b + 1/2)/n_bins, where the kernel smoothing is evaluated;
+ * the smoothed projection is normalised to a density p_j and mixed with the
+ * uniform density, q_j = (1 - floor_eps) p_j + floor_eps, so every bin keeps
+ * a positive weight; an empty projection gives the uniform density. */
+
+/* Learns a model from the lattice points i < 2^log2_m of one shift (the
+ * exponential warp with model_tau as the first warp, the charge integrand of
+ * mode 0): hist (n*n_bins, may be NULL) receives the projected |Re f~| sums
+ * per coordinate and bin, cdf (n*(n_bins+1)) the model.  Returns 0, or -1 on
+ * bad arguments. */
+int oracle_learn_model(const double *gl, const double *gg, int n_grid,
+                       double t_half, double n_sigma, double t_meas,
+                       int n, int log2_m, uint64_t lattice_a,
+                       const double *shift, double model_tau, int n_bins,
+                       double lambda, double floor_eps, int n_threads,
+                       double *hist, double *cdf);
+
+/* Builds a model from given per-coordinate projections (n*n_bins values):
+ * smoothing, normalisation, floor and CDF as in oracle_learn_model. */
+int oracle_model_from_hist(int n, int n_bins, const double *hist, double lambda,
+                           double floor_eps, double *cdf);
+
+/* Inverse CDF of one coordinate: w = F^{-1}(x) for x in [0, 1); returns the
+ * density q(w).  The bin is the last b with cdf[b] <= x. */
+double oracle_model_inverse(const double *cdf, int n_bins, double x, double *w);
+
+/* oracle_eval_sums with the learned second warp in front of the exponential
+ * one (cdf == NULL: none, identical to oracle_eval_sums).  In mode 1 the
+ * model function is the combined one, p_n(u) prod_j q_j(w_j), so every sample
+ * still equals C. */
+int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
+                           double t_half, double n_sigma, double t_meas,
+                           int n, int log2_n, uint64_t lattice_a,
+                           int n_shifts, const double *shifts, double model_tau,
+                           const double *cdf, int n_bins,
+                           int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                           double *sums);
+
 #ifdef __cplusplus
 }
 #endif

@@ -327,13 +327,19 @@ def test_q1_closed_form(oracle_mod, tiny_tables):
     assert abs(mean.imag) < 1e-12
 
 
-def test_q2_two_dimensional_quadrature(oracle_mod, tiny_tables):
-    """Q_2 by nested adaptive quadrature over the ordered simplex agrees with
-    the warped lattice estimate within its randomised-QMC error bar."""
+@pytest.fixture(scope="module")
+def q2_quadrature(oracle_mod, tiny_tables):
+    """Q_2 by nested adaptive quadrature over the ordered simplex."""
     def inner(u1):
         return integrate.quad(lambda u2: oracle_mod.integrand(tiny_tables, 10.0, [u1, u2])[0].real,
                               0, u1, epsabs=1e-11, epsrel=1e-10, limit=200)[0]
-    quad = integrate.quad(inner, 0, 10.0, epsabs=1e-10, epsrel=1e-9, limit=200)[0]
+    return integrate.quad(inner, 0, 10.0, epsabs=1e-10, epsrel=1e-9, limit=200)[0]
+
+
+def test_q2_two_dimensional_quadrature(oracle_mod, tiny_tables, q2_quadrature):
+    """Q_2 by nested adaptive quadrature over the ordered simplex agrees with
+    the warped lattice estimate within its randomised-QMC error bar."""
+    quad = q2_quadrature
     job = order_job(1, 2, 14, 16)
     q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, 2, job.log2_n,
                                         job.lattice_a, job.shifts, 1.0)
@@ -371,3 +377,117 @@ def test_bethe_orders_close_at_low_temperature(oracle_mod, tiny_tables):
         q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n,
                                             job.lattice_a, job.shifts, 1.0)
         assert abs(mean.real / bethe[n] - 1.0) < tol, (n, mean, bethe[n])
+
+
+# --------------------------------------------------------------------------
+# Learned second warp (App. I, "Learning h^(i) from the integrand")
+# --------------------------------------------------------------------------
+def _learn(oracle_mod, tables, n, log2_m=10, n_bins=50, lam=0.05, floor_eps=1e-3, seed=21):
+    job = order_job(seed, n, log2_m, 1)
+    return oracle_mod.learn_model(tables, 10.0, n, log2_m, job.lattice_a, job.shifts[0],
+                                  1.0, n_bins, lam, floor_eps)
+
+
+def test_model_projection_brute_force(oracle_mod, tiny_tables):
+    """The per-coordinate projection of |Re f~| over 64 lattice points, redone
+    here point by point from the integrand, the warp and the lattice."""
+    n, log2_m, n_bins = 3, 6, 8
+    job = order_job(21, n, log2_m, 1)
+    hist, _ = oracle_mod.learn_model(tiny_tables, 10.0, n, log2_m, job.lattice_a,
+                                     job.shifts[0], 1.0, n_bins, 0.05, 1e-3)
+    ref = np.zeros((n, n_bins))
+    for i in range(1 << log2_m):
+        x = oracle_mod.lattice_point(i, n, log2_m, job.lattice_a, job.shifts[0])
+        u, W, inside = oracle_mod.warp(x, 1.0, 10.0)
+        if not inside:
+            continue
+        f, _ = oracle_mod.integrand(tiny_tables, 10.0, u)
+        for j in range(n):
+            ref[j, min(int(x[j] * n_bins), n_bins - 1)] += abs((f * W).real)
+    assert np.allclose(hist, ref, rtol=1e-12, atol=0)
+
+
+def test_model_cdf_is_a_distribution(oracle_mod, tiny_tables):
+    _, cdf = _learn(oracle_mod, tiny_tables, 4)
+    nb = cdf.shape[1] - 1
+    assert np.all(cdf[:, 0] == 0.0) and np.all(cdf[:, -1] == 1.0)
+    q = nb * np.diff(cdf, axis=1)
+    assert np.all(q >= 1e-3 * (1 - 1e-12))           # the uniform floor
+    assert np.allclose(q.sum(axis=1) / nb, 1.0, rtol=1e-13)
+
+
+def test_model_smoothing_limits(oracle_mod):
+    """lambda -> 0 keeps the binned projection (only the floor is mixed in);
+    lambda -> infinity flattens it to the uniform density."""
+    rng = np.random.default_rng(3)
+    hist = rng.random((2, 12)) + 0.1
+    eps = 0.01
+    cdf = oracle_mod.model_from_hist(hist, 1e-6, eps)
+    p = hist / hist.mean(axis=1, keepdims=True)
+    q = (1 - eps) * p + eps
+    ref = np.concatenate([np.zeros((2, 1)), np.cumsum(q, axis=1) / 12], axis=1)
+    ref /= ref[:, -1:]
+    assert np.allclose(cdf, ref, rtol=1e-13, atol=1e-15)
+    flat = oracle_mod.model_from_hist(hist, 1e6, eps)
+    assert np.allclose(flat, np.linspace(0, 1, 13)[None, :], rtol=0, atol=1e-12)
+
+
+def test_model_inverse_round_trip(oracle_mod, tiny_tables):
+    """F(F^{-1}(x)) = x with F the piecewise-linear CDF (numpy interpolation),
+    and q(w) the slope of F on w's bin."""
+    _, cdf = _learn(oracle_mod, tiny_tables, 3)
+    nb = cdf.shape[1] - 1
+    edges = np.linspace(0.0, 1.0, nb + 1)
+    rng = np.random.default_rng(5)
+    for j in range(3):
+        for x in np.concatenate([rng.random(50), cdf[j, :-1]]):
+            w, q = oracle_mod.model_inverse(cdf[j], x)
+            assert 0.0 <= w < 1.0
+            assert abs(np.interp(w, edges, cdf[j]) - x) < 1e-14
+            b = min(int(np.searchsorted(cdf[j], x, side="right")) - 1, nb - 1)
+            assert abs(w * nb - b) <= 1.0 + 1e-12 and abs(q - nb * (cdf[j, b + 1] - cdf[j, b])) <= 1e-12 * q
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_learned_model_mode_is_exact(oracle_mod, tiny_tables, n):
+    """With f := p_n prod_j q_j (the combined model), every sample is C = tau^n:
+    the Jacobian of the second warp is exactly 1/prod_j q_j."""
+    _, cdf = _learn(oracle_mod, tiny_tables, n)
+    job = order_job(5, n, 10, 4, mode=1)
+    q, _, _ = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                    job.shifts, 1.0, mode=1, cdf=cdf)
+    assert np.max(np.abs(q - 1.0)) <= 1e-12
+
+
+def test_flat_model_reduces_to_the_exponential_warp(oracle_mod, tiny_tables):
+    """A uniform second warp (lambda -> infinity, no floor needed) is the
+    identity: the estimates equal the exponential-warp ones."""
+    n = 3
+    hist = np.ones((n, 20))
+    cdf = oracle_mod.model_from_hist(hist, 1e6, 0.0)
+    job = order_job(7, n, 10, 4)
+    a, _, _ = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                    job.shifts, 1.0)
+    b, _, _ = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                    job.shifts, 1.0, cdf=cdf)
+    assert np.allclose(a, b, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_learned_warp_constant_integrand_gives_simplex_volume(oracle_mod, tiny_tables, n):
+    _, cdf = _learn(oracle_mod, tiny_tables, n)
+    job = order_job(6, n, 14, 16, mode=2)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, n, job.log2_n, job.lattice_a,
+                                        job.shifts, 1.0, mode=2, cdf=cdf)
+    exact = 10.0 ** n / math.factorial(n)
+    assert abs(mean.real - exact) < 5 * se + 1e-9 * exact
+
+
+def test_learned_warp_q2_against_quadrature(oracle_mod, tiny_tables, q2_quadrature):
+    """Q_2 through the learned warp agrees with nested adaptive quadrature."""
+    quad = q2_quadrature
+    _, cdf = _learn(oracle_mod, tiny_tables, 2, log2_m=12)
+    job = order_job(1, 2, 14, 16)
+    q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, 2, job.log2_n, job.lattice_a,
+                                        job.shifts, 1.0, cdf=cdf)
+    assert abs(mean.real - quad) < 5 * se + 1e-8

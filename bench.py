@@ -362,12 +362,62 @@ def run_stress(args):
           flush=True)
 
 
+def run_learned(args):
+    """The learned second warp (App. I) on the plain workload: learning cost,
+    throughput through the learned warp, and the spread of the shift
+    estimates against the exponential warp alone, for two first-warp taus."""
+    import torch
+    from paper_2002_12372_amd import qqmc
+    from qqmc_inputs import TINY_DOT as d, order_job
+
+    n = args.order
+    stream = torch.cuda.current_stream()
+    tables = qqmc.make_tables(d)
+    points = (1 << args.log2n) * args.shifts
+    rows = []
+    for tau in (1.0, 1.5):
+        lj = order_job(41, n, args.learn_log2m, 1, model_tau=tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = qqmc.learn_model(tables, n, args.learn_log2m, lj.lattice_a, lj.shifts[0], tau,
+                                 d.t_meas, args.learn_bins, args.learn_lambda, 1e-3)
+        t_learn = time.perf_counter() - t0
+        job = order_job(1, n, args.log2n, args.shifts, model_tau=tau)
+        sums = torch.zeros(2 * args.shifts, dtype=torch.float64, device="cuda")
+
+        def step(m):
+            qqmc.eval_order_async(tables, job, d.t_meas, sums, None, stream=stream, model=m)
+
+        wall_e, _ = timed_steps(lambda: step(None), args.steps, args.warmup, stream)
+        qe, me, se_e = qqmc.eval_order(tables, job, d.t_meas)
+        wall_l, _ = timed_steps(lambda: step(model), args.steps, args.warmup, stream)
+        ql, ml, se_l = qqmc.eval_order(tables, job, d.t_meas, model=model)
+        rows.append({"tau": tau, "learn_s": t_learn,
+                     "exponential": {"points_per_s": points * args.steps / wall_e,
+                                     "Q": me.real, "stderr": se_e},
+                     "learned": {"points_per_s": points * args.steps / wall_l,
+                                 "Q": ml.real, "stderr": se_l},
+                     "stderr_ratio": se_e / se_l})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        model.close()
+    print(json.dumps({
+        "metric": "learned-warp Keldysh-summed integrand points/s at n=%d FP64; stderr vs "
+                  "exponential warp" % n,
+        "value": rows[0]["learned"]["points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic", "rows": rows,
+        "config": {"workload": "plain dot (Gamma=1, eps_d=0, beta=20, V=0, t=10), order %d, "
+                               "N=2^%d x %d shifts; model learned from 2^%d points, %d bins, "
+                               "lambda %.3g, floor 1e-3"
+                               % (n, args.log2n, args.shifts, args.learn_log2m, args.learn_bins,
+                                  args.learn_lambda)}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["plain", "batched", "serving", "stress"],
+    ap.add_argument("--workload", choices=["plain", "batched", "serving", "stress", "learned"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--log2n", type=int, default=20)
@@ -389,6 +439,9 @@ def main():
     ap.add_argument("--find-capacity", type=int, default=0,
                     help="serving: bisection steps for the highest sustained arrival rate")
     ap.add_argument("--stress-log2n", type=int, default=18)
+    ap.add_argument("--learn-log2m", type=int, default=16)
+    ap.add_argument("--learn-bins", type=int, default=100)
+    ap.add_argument("--learn-lambda", type=float, default=0.05)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -397,7 +450,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     {"plain": run_plain, "batched": run_batched, "serving": run_serving,
-     "stress": run_stress}[args.workload](args)
+     "stress": run_stress, "learned": run_learned}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -67,10 +67,18 @@ enum {
     QQMC_MODE_CONSTANT = 2  /* f := 1 on the ordered simplex: t^n/n!          */
 };
 
+/* A learned second warp (App. I, "Learning h^(i) from the integrand"): per
+ * coordinate a density q_j on [0, 1), piecewise constant on n_bins equal
+ * bins, applied to the lattice point before the exponential warp
+ * (w_j = F_j^{-1}(x_j), weight divided by prod_j q_j(w_j)).  Opaque handle
+ * owning device memory; see qqmc_learn_model. */
+typedef struct qqmc_model_s *qqmc_model;
+
 /* One order-n integral (Eq. (warped_int2)): N = 2^log2_n points of the rank-1
  * lattice with generating vector (1, a, a^2, ...) mod N, each shifted by the
  * n_shifts rows of `shifts`, warped with h(v) = exp(-v/model_tau)
- * (Eq. (hi_expo)) towards the measurement time t_meas. */
+ * (Eq. (hi_expo)) towards the measurement time t_meas, optionally after a
+ * learned second warp. */
 typedef struct {
     int32_t order;          /* n, 1 .. QQMC_MAX_ORDER                         */
     int32_t log2_n;         /* 6 .. 24                                        */
@@ -80,7 +88,10 @@ typedef struct {
                                copied during the call                          */
     double model_tau;       /* tau > 0                                        */
     double t_meas;          /* measurement time t, 0 < t <= table t_half      */
-    int32_t mode;           /* QQMC_MODE_*                                    */
+    int32_t mode;           /* QQMC_MODE_*; with a model, QQMC_MODE_MODEL uses
+                               the combined model p_n(u) prod_j q_j(w_j)       */
+    qqmc_model model;       /* learned second warp of the same order, or NULL;
+                               must stay valid until the work using it ends  */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
@@ -128,8 +139,8 @@ void qqmc_free_tables(qqmc_tables t);
  *   q_stderr host, 1 double: sample standard deviation of Re Q^{(s)} over
  *            shifts / sqrt(K); NaN for K = 1 (may be NULL)
  * EINVAL on any out-of-range field, an even or out-of-range lattice_a, a
- * shift outside [0, 1) or t_meas > t_half.  Q_n is real; the imaginary part
- * is a rounding diagnostic. */
+ * shift outside [0, 1), t_meas > t_half or a model of another order.  Q_n is
+ * real; the imaginary part is a rounding diagnostic. */
 qqmc_status qqmc_eval_order(qqmc_tables t, const qqmc_order *ord,
                             void *stream, double *q_shift, double *q_mean,
                             double *q_stderr);
@@ -165,6 +176,48 @@ enum { QQMC_METHOD_TREE = 0, QQMC_METHOD_DIRECT = 1 };
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
                              const double *u, int64_t n_points,
                              int32_t method, double *f, void *stream);
+
+/* ---- Learned second warp (App. I) ---------------------------------------
+ * Learning: the library evaluates the order-n integrand f~ (exponential warp
+ * with model_tau, charge mode, Jacobian included) at the 2^log2_m points of
+ * one shifted lattice on the GPU, projects |Re f~| onto each coordinate of
+ * the unit cube with n_bins equal bins, smooths each projection with the
+ * Gaussian kernel exp(-(w - w')^2 / lambda^2) over the bin centres,
+ * normalises it to a density, mixes in the uniform density with weight
+ * floor_eps (every bin keeps a positive weight) and stores the CDF at the bin
+ * edges. */
+typedef struct {
+    int32_t order;          /* n, 1 .. QQMC_MAX_ORDER                         */
+    int32_t log2_m;         /* learning sample M = 2^log2_m, 6 .. 24          */
+    uint64_t lattice_a;     /* odd Korobov multiplier of the sample lattice   */
+    const double *shift;    /* host, order doubles in [0, 1)                  */
+    double model_tau;       /* first (exponential) warp, > 0                  */
+    double t_meas;          /* 0 < t_meas <= table t_half                     */
+    int32_t n_bins;         /* 1 .. 4096                                      */
+    double lambda;          /* kernel width > 0                               */
+    double floor_eps;       /* uniform weight in [0, 1]                       */
+} qqmc_learn_params;
+
+/* Learns a model on the current device; synchronises `stream`.  EINVAL on
+ * any out-of-range field, ENOMEM / EDEVICE on allocation or HIP failure. */
+qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p,
+                             void *stream, qqmc_model *out);
+
+/* Wraps a caller-supplied model: cdf host, order x (n_bins + 1) row-major,
+ * each row non-decreasing from 0 to 1 with positive bin widths (copied). */
+qqmc_status qqmc_model_from_host(int32_t order, int32_t n_bins,
+                                 const double *cdf, void *stream,
+                                 qqmc_model *out);
+
+/* Copies a model back: order and n_bins (either may be NULL), cdf host
+ * order x (n_bins + 1) (may be NULL), hist host order x n_bins projected
+ * sums of the learning sample, zeros for a model from the host (may be
+ * NULL). */
+qqmc_status qqmc_model_export(qqmc_model m, int32_t *order, int32_t *n_bins,
+                              double *cdf, double *hist);
+
+/* Releases the handle and its device memory.  NULL is ignored. */
+void qqmc_free_model(qqmc_model m);
 
 /* ---- Batched form -------------------------------------------------------
  * Many (parameter point, order) integrals in one persistent launch.  Each

@@ -200,7 +200,8 @@ def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
                                         int(lattice_a), K, _p(shifts), model_tau,
                                         cp, nb, mode, int(i_begin), int(i_end), n_threads,
                                         _p(sums))
-    assert rc == 0
+    if rc != 0:
+        raise ValueError("oracle_eval_sums_model: bad arguments")
     return sums[0::2] + 1j * sums[1::2]
 
 

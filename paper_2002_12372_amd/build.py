@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqqmc.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["qqmc_kernels.hip", "qqmc_api.cpp", "qqmc_tables.cpp", "qqmc_plan.cpp",
+SOURCES = ["qqmc_kernels.hip", "qqmc_api.cpp", "qqmc_tables.cpp", "qqmc_plan.cpp", "qqmc_model.cpp",
            "qqmc_server.cpp"]
 
 # gfx950 only; packed-FP32 instructions are kept out of the generated code.

@@ -51,6 +51,8 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
         return set_error(QQMC_EINVAL, "t_meas must satisfy 0 < t_meas <= t_half of the tables");
     if (ord->mode < QQMC_MODE_CHARGE || ord->mode > QQMC_MODE_CONSTANT)
         return set_error(QQMC_EINVAL, "unknown mode");
+    if (ord->model && (ord->model->order != n || !ord->model->d_cdf))
+        return set_error(QQMC_EINVAL, "model of another order");
     const size_t ns = (size_t)ord->n_shifts * (size_t)n;
     out->shifts.assign(ord->shifts, ord->shifts + ns);
     for (double v : out->shifts)
@@ -71,6 +73,10 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
     for (int j = 0; j < n; ++j) {
         d.z[j] = (uint32_t)z;
         z = (z * ord->lattice_a) % N;
+    }
+    if (ord->model) {
+        d.model_cdf = ord->model->d_cdf;
+        d.model_bins = ord->model->n_bins;
     }
     return QQMC_OK;
 }

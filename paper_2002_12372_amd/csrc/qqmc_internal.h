@@ -27,6 +27,10 @@ struct ItemDesc {
     int32_t tile_len, tiles_per_shift;
     int64_t n_tiles;
     double *tile_sums;       /* device, 2 per tile, or null                 */
+    const double *model_cdf; /* device: learned warp, order x (bins + 1), or null */
+    int32_t model_bins;
+    int32_t pad_;
+    double *sample_out;      /* device: per-point Re fbar (learning pass), or null */
 };
 
 /* Entry of the batched tile list: which item, which tile of it. */
@@ -55,6 +59,9 @@ hipError_t launch_points_direct(const double *tab, int32_t n_grid,
 hipError_t launch_batch(int32_t order, const ItemDesc *items_dev,
                         const TileRef *tiles_dev, int64_t n_tiles,
                         int32_t grid_blocks, hipStream_t s);
+/* Learning pass: per-point Re fbar of the lattice points of tile range
+ * [0, it.n_tiles) into it.sample_out. */
+hipError_t launch_sample(const ItemDesc &it, hipStream_t s);
 hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_d,
                          double gamma, double beta, double bias_v, double n_sigma,
                          hipStream_t s);
@@ -89,6 +96,14 @@ struct qqmc_tables_s {
     double *d_tab = nullptr;   /* 4*n_grid doubles: (g<re, g<im, g>re, g>im) */
     int32_t n_grid = 0;
     double t_half = 0.0, h = 0.0, n_sigma = 0.0;
+    int device = 0;
+};
+
+struct qqmc_model_s {
+    double *d_cdf = nullptr;   /* order x (n_bins + 1) doubles                */
+    int32_t order = 0, n_bins = 0;
+    std::vector<double> cdf;   /* host copy                                   */
+    std::vector<double> hist;  /* projected sums of the learning sample       */
     int device = 0;
 };
 

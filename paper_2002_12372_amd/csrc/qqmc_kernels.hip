@@ -36,11 +36,12 @@ template <int N> struct Lds {
     static constexpr int times = 0;                                    /* 64*N doubles   */
     static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
     static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
+    static constexpr int ids = S + 64 * 16;                            /* 64 int32       */
     /* pair tables: one per item group, or one per distinct point of a
      * round when several items share a point */
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
-    static constexpr int pairs = S + 64 * 16;                          /* tables*NP pairv */
+    static constexpr int pairs = ids + 64 * 4;                         /* tables*NP pairv */
     static constexpr int row = pairs + tables * Gm::NP * 32;           /* PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
@@ -275,15 +276,38 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
     }
 }
 
+/* Inverse CDF of one coordinate's learned density (App. I): piecewise
+ * constant on `bins` equal bins of [0, 1), CDF c[0..bins] at the bin edges.
+ * Sets w with F(w) = x and returns the density q(w); the bin is the last b
+ * with c[b] <= x (binary search, c non-decreasing, c[0] = 0 <= x < 1). */
+__device__ __forceinline__ double model_inverse(const double *__restrict__ c, int bins, double x,
+                                                double &w)
+{
+    int lo = 0, hi = bins;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    const double c0 = c[lo], width = c[lo + 1] - c0;
+    w = ((double)lo + (x - c0) / width) / (double)bins;
+    return (double)bins * width;
+}
+
 /* One work tile of one order-n integral: sum of fbar over 64*c lattice
- * indices of one shift.  Returns the wave's sum (same bits in every lane). */
-template <int N>
+ * indices of one shift.  Returns the wave's sum (same bits in every lane).
+ * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
+ * learning pass): also writes Re fbar of every lattice index of the tile to
+ * it.sample_out. */
+template <int N, bool MODEL, bool SAMPLE = false>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
     using L = Lds<N>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     double *s_w = reinterpret_cast<double *>(lds + L::w);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    int32_t *s_ids = reinterpret_cast<int32_t *>(lds + L::ids);
+    (void)s_ids;
     const int lane = threadIdx.x;
     const int s = (int)(tile / it.tiles_per_shift);
     const uint32_t i0 = (uint32_t)(tile % it.tiles_per_shift) * (uint32_t)it.tile_len;
@@ -299,21 +323,26 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
         const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
         /* rank-1 lattice point, then u_m = u_{m-1} - v_m, v_m = -tau log(1-x_m) */
         double u[N];
-        double prev = it.t_meas, p = 1.0;
+        double prev = it.t_meas, p = 1.0, qm = 1.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const uint32_t m = (idx * it.z[j]) & it.mask;
             double y = (double)m * it.inv_n + shift[j];
             if (y >= 1.0) y -= 1.0;
+            /* learned second warp: y -> w = F_j^{-1}(y), weight / q_j(w) */
+            if constexpr (MODEL)
+                qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
             const double v = -it.tau * log1p(-y);
             u[j] = prev - v;
             p *= exp(-(prev - u[j]) / it.tau);
             prev = u[j];
         }
-        const double W = it.tau_n / p;
+        double W = it.tau_n / p;
+        if constexpr (MODEL) W /= qm;
         const bool inside = u[N - 1] > 0.0;
         if (it.mode != QQMC_MODE_CHARGE) {
-            if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * W, 0.0));
+            /* the model function is the combined one, p_n prod_j q_j */
+            if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * qm * W, 0.0));
             else if (inside) acc.add(cmk(W, 0.0));
             continue;
         }
@@ -325,6 +354,9 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             for (int k = 0; k < N; ++k) s_times[rk * N + k] = u[N - 1 - k];
             s_w[rk] = W;
             s_S[rk] = cmk(0.0, 0.0);
+            if constexpr (SAMPLE) s_ids[rk] = (int32_t)idx;
+        } else if constexpr (SAMPLE) {
+            it.sample_out[idx] = 0.0;
         }
         wave_sync();
         keldysh_points<N>(cnt, env, lds);
@@ -332,23 +364,35 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             const cplx f = charge_prefactor<N>(s_S[lane]);
             const double w = s_w[lane];
             acc.add(cmk(f.x * w, f.y * w));
+            if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
         }
         wave_sync();
     }
     return wave_sum(acc.value());
 }
 
-template <int N>
+template <int N, bool MODEL>
 __global__ void __launch_bounds__(64, Geo<N>::WPS) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
-        const cplx v = order_tile<N>(it, tile, lds);
+        const cplx v = order_tile<N, MODEL>(it, tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * tile] = v.x;
             it.tile_sums[2 * tile + 1] = v.y;
         }
     }
+}
+
+/* Learning pass of the learned second warp (App. I): Re fbar of every
+ * lattice index of the item's tiles into it.sample_out (exponential warp
+ * only, charge mode). */
+template <int N>
+__global__ void __launch_bounds__(64, Geo<N>::WPS) sample_kernel(ItemDesc it)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x)
+        (void)order_tile<N, false, true>(it, tile, lds);
 }
 
 /* Per-shift sums of the tile partials, fixed order: thread j adds tiles
@@ -550,7 +594,8 @@ __global__ void __launch_bounds__(64, Geo<N>::WPS) batch_kernel(const ItemDesc *
         const TileRef ref = tiles[t];
         /* by value: the descriptor lives in registers for the whole tile */
         const ItemDesc it = items[ref.item];
-        const cplx v = order_tile<N>(it, ref.tile, lds);
+        const cplx v = it.model_cdf ? order_tile<N, true>(it, ref.tile, lds)
+                                    : order_tile<N, false>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;
             it.tile_sums[2 * ref.tile + 1] = v.y;
@@ -635,7 +680,21 @@ template <int N> struct OrderLaunch {
     static hipError_t run(const ItemDesc &it, hipStream_t s)
     {
         const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-        hipLaunchKernelGGL(order_kernel<N>, dim3((unsigned)blocks), dim3(64),
+        if (it.model_cdf)
+            hipLaunchKernelGGL((order_kernel<N, true>), dim3((unsigned)blocks), dim3(64),
+                               Lds<N>::bytes, s, it);
+        else
+            hipLaunchKernelGGL((order_kernel<N, false>), dim3((unsigned)blocks), dim3(64),
+                               Lds<N>::bytes, s, it);
+        return hipGetLastError();
+    }
+};
+
+template <int N> struct SampleLaunch {
+    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    {
+        const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
+        hipLaunchKernelGGL(sample_kernel<N>, dim3((unsigned)blocks), dim3(64),
                            Lds<N>::bytes, s, it);
         return hipGetLastError();
     }
@@ -689,6 +748,11 @@ hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_
 hipError_t launch_order(const ItemDesc &it, hipStream_t s)
 {
     return dispatch<OrderLaunch>(it.order, it, s);
+}
+
+hipError_t launch_sample(const ItemDesc &it, hipStream_t s)
+{
+    return dispatch<SampleLaunch>(it.order, it, s);
 }
 
 hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,

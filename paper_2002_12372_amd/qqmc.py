@@ -40,7 +40,15 @@ class qqmc_order(ctypes.Structure):
                 ("lattice_a", ctypes.c_uint64), ("n_shifts", ctypes.c_int32),
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("model", ctypes.c_void_p)]
+
+
+class qqmc_learn_params(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("log2_m", ctypes.c_int32),
+                ("lattice_a", ctypes.c_uint64), ("shift", ctypes.POINTER(ctypes.c_double)),
+                ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
+                ("n_bins", ctypes.c_int32), ("lam", ctypes.c_double),
+                ("floor_eps", ctypes.c_double)]
 
 
 class qqmc_batch_item(ctypes.Structure):
@@ -75,6 +83,10 @@ SIGNATURES = [
     ("qqmc_server_now", _d, [_vp]),
     ("qqmc_server_drain", _i32, [_vp]),
     ("qqmc_server_destroy", None, [_vp]),
+    ("qqmc_learn_model", _i32, [_vp, _P(qqmc_learn_params), _vp, _P(_vp)]),
+    ("qqmc_model_from_host", _i32, [_i32, _i32, _PD, _vp, _P(_vp)]),
+    ("qqmc_model_export", _i32, [_vp, _P(_i32), _P(_i32), _PD, _PD]),
+    ("qqmc_free_model", None, [_vp]),
     ("qqmc_last_error", ctypes.c_char_p, []),
 ]
 
@@ -169,19 +181,66 @@ def tables_export(tables):
     return gl, gg, ns.value
 
 
-def make_order(job, t_meas):
-    """job: qqmc_inputs.OrderJob.  The returned struct keeps the shift array
-    alive through the attribute ``_keep``."""
+def make_order(job, t_meas, model=None):
+    """job: qqmc_inputs.OrderJob; model: a Model of the same order or None.
+    The returned struct keeps the shift array alive through ``_keep``."""
     sh = np.ascontiguousarray(job.shifts, dtype=np.float64)
     o = qqmc_order(job.order, job.log2_n, job.lattice_a, sh.shape[0], _pd(sh),
-                   job.model_tau, t_meas, job.mode)
-    o._keep = sh
+                   job.model_tau, t_meas, job.mode,
+                   model.handle if model is not None else None)
+    o._keep = (sh, model)
     return o
 
 
-def eval_order(tables, job, t_meas, stream=None):
+class Model:
+    """Learned second warp (App. I): per-coordinate CDFs at the bin edges."""
+
+    def __init__(self, handle):
+        self.handle = ctypes.c_void_p(handle)
+
+    def export(self):
+        """(cdf, hist) numpy arrays, shapes (order, n_bins + 1), (order, n_bins)."""
+        n, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qqmc_model_export(self.handle, ctypes.byref(n), ctypes.byref(nb), None, None))
+        cdf = np.zeros((n.value, nb.value + 1))
+        hist = np.zeros((n.value, nb.value))
+        _check(lib().qqmc_model_export(self.handle, None, None, _pd(cdf), _pd(hist)))
+        return cdf, hist
+
+    def close(self):
+        if self.handle:
+            lib().qqmc_free_model(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def learn_model(tables, order, log2_m, lattice_a, shift, model_tau, t_meas, n_bins=100,
+                lam=0.05, floor_eps=1e-3, stream=None):
+    sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64).reshape(order))
+    p = qqmc_learn_params(order, log2_m, lattice_a, _pd(sh), model_tau, t_meas, n_bins,
+                          lam, floor_eps)
+    h = ctypes.c_void_p()
+    _check(lib().qqmc_learn_model(tables.handle, ctypes.byref(p), _stream(stream),
+                                  ctypes.byref(h)))
+    return Model(h.value)
+
+
+def model_from_host(cdf, stream=None):
+    cdf = np.ascontiguousarray(cdf, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().qqmc_model_from_host(cdf.shape[0], cdf.shape[1] - 1, _pd(cdf),
+                                      _stream(stream), ctypes.byref(h)))
+    return Model(h.value)
+
+
+def eval_order(tables, job, t_meas, stream=None, model=None):
     """(q_shift complex[K], q_mean complex, q_stderr float)."""
-    o = make_order(job, t_meas)
+    o = make_order(job, t_meas, model)
     K = o.n_shifts
     q = np.zeros(2 * K)
     m = np.zeros(2)
@@ -191,9 +250,10 @@ def eval_order(tables, job, t_meas, stream=None):
     return q[0::2] + 1j * q[1::2], m[0] + 1j * m[1], se.value
 
 
-def eval_order_async(tables, job, t_meas, shift_sums, tile_sums=None, tile_len=0, stream=None):
+def eval_order_async(tables, job, t_meas, shift_sums, tile_sums=None, tile_len=0, stream=None,
+                     model=None):
     """shift_sums / tile_sums: float64 CUDA tensors (2*K, 2*n_tiles)."""
-    o = make_order(job, t_meas)
+    o = make_order(job, t_meas, model)
     nt = ctypes.c_int64()
     _check(lib().qqmc_eval_order_async(
         tables.handle, ctypes.byref(o), int(tile_len), _stream(stream),
@@ -229,18 +289,19 @@ class Plan:
 
 
 def plan_create(entries, t_meas, tile_len=0, grid_blocks=0, stream=None):
-    """entries: list of (Tables, OrderJob)."""
+    """entries: list of (Tables, OrderJob) or (Tables, OrderJob, Model)."""
     arr = (qqmc_batch_item * len(entries))()
     keep = []
-    for k, (tb, job) in enumerate(entries):
-        o = make_order(job, t_meas)
+    for k, entry in enumerate(entries):
+        tb, job = entry[0], entry[1]
+        o = make_order(job, t_meas, entry[2] if len(entry) > 2 else None)
         keep.append((tb, o))
         arr[k].tables = tb.handle
         arr[k].order = o
     h = ctypes.c_void_p()
     _check(lib().qqmc_plan_create(arr, len(entries), int(tile_len), int(grid_blocks),
                                   _stream(stream), ctypes.byref(h)))
-    return Plan(h.value, keep, [job.shifts.shape[0] for _, job in entries])
+    return Plan(h.value, keep, [e[1].shifts.shape[0] for e in entries])
 
 
 def plan_run(plan, stream=None):
@@ -274,17 +335,18 @@ class Server:
         self.handle = h
         self._n_shifts = {}
 
-    def submit(self, dot, job, t_meas):
+    def submit(self, dot, job, t_meas, model=None):
+        """model (optional) is kept alive here until the request is polled done."""
         cd = make_dot(dot)
-        o = make_order(job, t_meas)
+        o = make_order(job, t_meas, model)
         t = ctypes.c_uint64()
         _check(lib().qqmc_submit(self.handle, ctypes.byref(cd), ctypes.byref(o), ctypes.byref(t)))
-        self._n_shifts[t.value] = o.n_shifts
+        self._n_shifts[t.value] = (o.n_shifts, model)
         return t.value
 
     def poll(self, ticket):
         """None while pending; else dict(q_shift, q_mean, q_stderr, t_submit, t_done)."""
-        K = self._n_shifts.get(ticket, 1)
+        K = self._n_shifts.get(ticket, (1, None))[0]
         q = np.zeros(2 * K)
         m = np.zeros(2)
         se, ts, td = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -412,12 +412,43 @@ def run_learned(args):
                                   args.learn_lambda)}}), flush=True)
 
 
+def run_bethe(args):
+    """The paper's benchmark (T = 0, eps_d = 0, V = 0, Gamma = 1, t = 30,
+    tau = 0.95): Q_n for n = 1..12 against the printed Bethe-ansatz
+    coefficients (tests/golden/bethe_qn.txt)."""
+    from paper_2002_12372_amd import qqmc
+    from qqmc_inputs import BETHE_DOT as d, order_job
+
+    with open(os.path.join(ROOT, "tests", "golden", "bethe_qn.txt")) as f:
+        bethe = {int(a): float(b) for a, b in (l.split() for l in f
+                                               if l.strip() and not l.startswith("#"))}
+    t0 = time.perf_counter()
+    tables = qqmc.make_tables(d)
+    t_tab = time.perf_counter() - t0
+    rows = []
+    for n in range(1, 13):
+        job = order_job(1, n, args.log2n, 16, model_tau=0.95)
+        t0 = time.perf_counter()
+        q, mean, se = qqmc.eval_order(tables, job, d.t_meas)
+        dt = time.perf_counter() - t0
+        rows.append({"order": n, "Q": mean.real, "stderr": se, "bethe": bethe[n],
+                     "rel_err": abs(mean.real - bethe[n]) / abs(bethe[n]),
+                     "sigmas": (mean.real - bethe[n]) / se, "seconds": dt})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "Bethe-ansatz benchmark Q_n, n=1..12", "rows": rows,
+                      "tables_s": t_tab,
+                      "config": {"workload": "T=0, eps_d=0, V=0, Gamma=1, t=30, tau=0.95, "
+                                             "N=2^%d x 16 shifts, grid 65536 on [-30, 30]"
+                                             % args.log2n}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["plain", "batched", "serving", "stress", "learned"],
+    ap.add_argument("--workload",
+                    choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--log2n", type=int, default=20)
@@ -450,7 +481,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     {"plain": run_plain, "batched": run_batched, "serving": run_serving,
-     "stress": run_stress, "learned": run_learned}[args.workload](args)
+     "stress": run_stress, "learned": run_learned, "bethe": run_bethe}[args.workload](args)
 
 
 if __name__ == "__main__":

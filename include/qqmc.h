@@ -51,7 +51,7 @@ typedef enum {
 typedef struct {
     double eps_d;    /* dot level                                           */
     double gamma;    /* tunnelling rate Gamma > 0                           */
-    double beta;     /* inverse temperature > 0                             */
+    double beta;     /* inverse temperature > 0; +INFINITY for T = 0        */
     double bias_v;   /* symmetric bias V between the two leads              */
     double t_half;   /* half-range of the table grid (>= measurement time)  */
     int32_t n_grid;  /* number of grid points, 2 .. 2^24                    */
@@ -100,8 +100,12 @@ typedef struct {
 /* Builds g^<(tau_j), g^>(tau_j) on the current device (exact residue series
  * over the Matsubara poles, one workgroup per grid node, launched on
  * `stream`; the handle is usable by later work on the same stream) and
- * n_sigma = -i g^<(0) on the host (digamma closed form).  EINVAL for
- * gamma <= 0, beta <= 0, t_half <= 0 or n_grid outside 2..2^24. */
+ * n_sigma = -i g^<(0) on the host (digamma closed form).  At T = 0
+ * (beta = +INFINITY) the grid is computed on the host from the Fourier
+ * integral along a path deformed into the lower half plane (App. E,
+ * "Precision calculation") and uploaded, n_sigma from the arctan closed
+ * form.  EINVAL for gamma <= 0, beta <= 0 or NaN, t_half <= 0 or n_grid
+ * outside 2..2^24. */
 qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream,
                              qqmc_tables *out);
 

@@ -147,6 +147,87 @@ static void gauss_legendre(int m, double *x, double *w)
     }
 }
 
+/* ---- Zero temperature (beta = +infinity), App. E "Precision calculation":
+ * the Fourier integrals Int zeta(omega) theta(mu - omega) e^{-i omega tau}
+ * with zeta = A/2pi are taken along a deformed path.  For tau > 0 the factor
+ * e^{-i omega tau} decays in the lower half plane, so the part of the real
+ * axis left of a point c (chosen left of mu and of the pole eps_d - i Gamma,
+ * none enclosed) is replaced by the vertical half-line c - i s, s >= 0:
+ *   Int_{-inf}^{c} zeta e^{-i omega tau} d omega
+ *       = i e^{-i c tau} Int_0^inf zeta(c - i s) e^{-s tau} ds,
+ * and the remaining segment [c, mu] stays on the real axis.  The same with a
+ * point right of mu gives the part above mu (for g^>):
+ *   Int_{c}^{inf} zeta e^{-i omega tau} d omega
+ *       = -i e^{-i c tau} Int_0^inf zeta(c - i s) e^{-s tau} ds.
+ * Both integrals are composite Gauss-Legendre sums (panels of width 0.05 on
+ * the real segment; geometrically growing panels on the half-line). */
+static cplx zeta_c(double eps_d, double gamma, cplx w)
+{
+    cplx d = w - eps_d;
+    return gamma / M_PI / (d * d + gamma * gamma);
+}
+
+static cplx segment_T0(double eps_d, double gamma, double a, double b, double tau)
+{
+    enum { M = 20 };
+    double gx[M], gw[M];
+    gauss_legendre(M, gx, gw);
+    long panels = (long)ceil((b - a) / 0.05);
+    if (panels < 1) panels = 1;
+    double width = (b - a) / panels;
+    cplx acc = 0.0;
+    for (long p = 0; p < panels; ++p) {
+        double lo = a + p * width;
+        cplx part = 0.0;
+        for (int q = 0; q < M; ++q) {
+            double w = lo + 0.5 * width * (gx[q] + 1.0);
+            part += gw[q] * zeta_c(eps_d, gamma, w) * cexp(-I * w * tau);
+        }
+        acc += 0.5 * width * part;
+    }
+    return acc;
+}
+
+/* Int_0^inf zeta(c - i s) e^{-s tau} ds */
+static cplx halfline_T0(double eps_d, double gamma, double c, double tau)
+{
+    enum { M = 20 };
+    double gx[M], gw[M];
+    gauss_legendre(M, gx, gw);
+    double smax = 60.0 / tau, lo = 0.0, width = 0.05 < 0.5 / tau ? 0.05 : 0.5 / tau;
+    cplx acc = 0.0;
+    while (lo < smax) {
+        cplx part = 0.0;
+        for (int q = 0; q < M; ++q) {
+            double s = lo + 0.5 * width * (gx[q] + 1.0);
+            part += gw[q] * zeta_c(eps_d, gamma, c - I * s) * exp(-s * tau);
+        }
+        acc += 0.5 * width * part;
+        lo += width;
+        width *= 1.25;
+    }
+    return acc;
+}
+
+static void gf_positive_tau_T0(double eps_d, double gamma, double bias_v, double tau,
+                               cplx *glt, cplx *ggt)
+{
+    cplx sum_l = 0.0, sum_g = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        double mu = side == 0 ? 0.5 * bias_v : -0.5 * bias_v;
+        double cl = (mu < eps_d ? mu : eps_d) - gamma - 1.0;
+        double cr = (mu > eps_d ? mu : eps_d) + gamma + 1.0;
+        cplx below = I * cexp(-I * cl * tau) * halfline_T0(eps_d, gamma, cl, tau) +
+                     segment_T0(eps_d, gamma, cl, mu, tau);
+        cplx above = segment_T0(eps_d, gamma, mu, cr, tau) -
+                     I * cexp(-I * cr * tau) * halfline_T0(eps_d, gamma, cr, tau);
+        sum_l += below;
+        sum_g += above;
+    }
+    *glt = I * 0.5 * sum_l;
+    *ggt = -I * 0.5 * sum_g;
+}
+
 /* n(mu) = Int domega/2pi A(omega) n_F(omega - mu), written as the exact
  * zero-temperature part plus an exponentially convergent remainder:
  *   n(mu) = 1/2 + atan((mu - eps_d)/Gamma)/pi
@@ -177,6 +258,9 @@ static double occupation_one_lead(double eps_d, double gamma, double beta,
 
 double oracle_n_sigma(double eps_d, double gamma, double beta, double bias_v)
 {
+    if (isinf(beta))
+        return 0.5 * (1.0 + (atan((0.5 * bias_v - eps_d) / gamma) +
+                             atan((-0.5 * bias_v - eps_d) / gamma)) / M_PI);
     return 0.5 * (occupation_one_lead(eps_d, gamma, beta, 0.5 * bias_v) +
                   occupation_one_lead(eps_d, gamma, beta, -0.5 * bias_v));
 }
@@ -185,14 +269,17 @@ void oracle_gf_direct(double eps_d, double gamma, double beta, double bias_v,
                       double tau, double *out)
 {
     cplx l, g;
-    if (tau > 0.0) {
-        gf_positive_tau(eps_d, gamma, beta, bias_v, tau, &l, &g);
-    } else if (tau < 0.0) {
-        /* g(-tau) = -conj(g(tau)): the Fourier integral of i * (real
-         * spectral weight) is hermitian in this sense. */
-        gf_positive_tau(eps_d, gamma, beta, bias_v, -tau, &l, &g);
-        l = -conj(l);
-        g = -conj(g);
+    if (tau != 0.0) {
+        if (isinf(beta))
+            gf_positive_tau_T0(eps_d, gamma, bias_v, fabs(tau), &l, &g);
+        else
+            gf_positive_tau(eps_d, gamma, beta, bias_v, fabs(tau), &l, &g);
+        if (tau < 0.0) {
+            /* g(-tau) = -conj(g(tau)): the Fourier integral of i * (real
+             * spectral weight) is hermitian in this sense. */
+            l = -conj(l);
+            g = -conj(g);
+        }
     } else {
         double ns = oracle_n_sigma(eps_d, gamma, beta, bias_v);
         l = I * ns;

@@ -158,9 +158,10 @@ static qqmc_status check_dot(const qqmc_dot *dot)
 {
     if (!dot) return set_error(QQMC_EINVAL, "NULL argument");
     if (!(dot->gamma > 0.0) || !(dot->beta > 0.0) || !(dot->t_half > 0.0) ||
-        !std::isfinite(dot->eps_d) || !std::isfinite(dot->bias_v) ||
-        !std::isfinite(dot->beta) || !std::isfinite(dot->gamma) || !std::isfinite(dot->t_half))
-        return set_error(QQMC_EINVAL, "gamma, beta and t_half must be positive and finite");
+        !std::isfinite(dot->eps_d) || !std::isfinite(dot->bias_v) || std::isnan(dot->beta) ||
+        !std::isfinite(dot->gamma) || !std::isfinite(dot->t_half))
+        return set_error(QQMC_EINVAL,
+                         "gamma, t_half must be positive and finite, beta positive (+inf: T = 0)");
     if (dot->n_grid < 2 || dot->n_grid > (1 << 24))
         return set_error(QQMC_EINVAL, "n_grid must be in 2..2^24");
     return QQMC_OK;
@@ -189,6 +190,14 @@ qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out
     if (qqmc_status st = check_dot(dot)) return st;
     if (!out) return set_error(QQMC_EINVAL, "NULL argument");
     const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
+    hipStream_t s = (hipStream_t)stream;
+    if (std::isinf(dot->beta)) {
+        /* zero temperature: contour quadrature on the host, then upload */
+        std::vector<double> tab(4 * (size_t)dot->n_grid);
+        build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,
+                          dot->t_half, ns, tab.data());
+        return upload_tables(tab.data(), dot->n_grid, dot->t_half, ns, s, out);
+    }
     auto *t = new (std::nothrow) qqmc_tables_s();
     if (!t) return set_error(QQMC_ENOMEM, "host allocation failed");
     hipGetDevice(&t->device);
@@ -196,7 +205,6 @@ qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out
     t->t_half = dot->t_half;
     t->h = 2.0 * dot->t_half / (dot->n_grid - 1);
     t->n_sigma = ns;
-    hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMalloc(&t->d_tab, sizeof(double) * 4 * (size_t)dot->n_grid);
     if (e == hipSuccess)
         e = launch_tables(t->d_tab, dot->n_grid, dot->t_half, dot->eps_d, dot->gamma, dot->beta,

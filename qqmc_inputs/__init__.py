@@ -114,6 +114,12 @@ def plain_jobs(seed: int = 1, orders=range(1, 9)) -> List[OrderJob]:
 
 STRESS_DOT = Dot(eps_d=-0.5, gamma=1.0, beta=20.0, bias_v=0.2)
 
+# The paper's own benchmark configuration (main text, "Benchmark"): T = 0,
+# eps_d = 0, wide band, Gamma = 1, measurement at t = 30, where the printed
+# Bethe-ansatz coefficients apply; a finer grid on [-30, 30].
+BETHE_DOT = Dot(eps_d=0.0, gamma=1.0, beta=float("inf"), bias_v=0.0, t_meas=30.0,
+                n_grid=65536, t_half=30.0)
+
 
 def stress_jobs(seed: int = 4, orders=range(11, 15)) -> List[OrderJob]:
     """Orders 11..14, N = 2^18, 16 shifts."""

@@ -20,7 +20,8 @@ from qqmc_inputs import Dot, order_job, TINY_DOT, STRESS_DOT
 
 pytestmark = pytest.mark.gpu
 
-DOTS = [TINY_DOT, STRESS_DOT, Dot(2.5, 0.5, 20.0, 1.0), Dot(-2.2, 2.0, 20.0, 0.5)]
+DOTS = [TINY_DOT, STRESS_DOT, Dot(2.5, 0.5, 20.0, 1.0), Dot(-2.2, 2.0, 20.0, 0.5),
+        Dot(0.3, 1.0, math.inf, 0.6)]
 
 
 @pytest.fixture(scope="module")

@@ -491,3 +491,82 @@ def test_learned_warp_q2_against_quadrature(oracle_mod, tiny_tables, q2_quadratu
     q, mean, se = oracle_mod.eval_order(tiny_tables, 10.0, 2, job.log2_n, job.lattice_a,
                                         job.shifts, 1.0, cdf=cdf)
     assert abs(mean.real - quad) < 5 * se + 1e-8
+
+
+# --------------------------------------------------------------------------
+# Zero temperature (App. E "Precision calculation"; the paper's benchmark)
+# --------------------------------------------------------------------------
+def _e1_lesser_T0(eps, gam, V, tau):
+    """g^<(tau > 0) at T = 0 from the exponential integral (mpmath's E1):
+    Int_{-inf}^{mu} A/2pi e^{-i w tau} = [F(z1) - F(z2)] / 2 pi i with
+    z = eps +- i Gamma, F(z) = -e^{-i mu tau} e^{i b tau} [E1(i b tau) + 2 pi i
+    if Re < 0 <= Im of i b tau], b = mu - z."""
+    def G(b):
+        t0 = 1j * b * tau
+        e = mpmath.e1(t0)
+        if mpmath.re(t0) < 0 and mpmath.im(t0) >= 0:
+            e += 2j * mpmath.pi
+        return mpmath.exp(1j * b * tau) * e
+
+    def below(mu):
+        F = lambda z: -mpmath.exp(-1j * mu * tau) * G(mu - z)
+        return (F(eps + 1j * gam) - F(eps - 1j * gam)) / (2j * mpmath.pi)
+    return complex(0.5j * (below(V / 2) + below(-V / 2)))
+
+
+@pytest.mark.parametrize("d", [Dot(0.0, 1.0, math.inf, 0.0), Dot(0.7, 0.5, math.inf, 1.0),
+                               Dot(-2.5, 2.0, math.inf, 0.5)])
+@pytest.mark.parametrize("tau", [0.003, 0.37, 4.2, 29.0, -1.5])
+def test_zero_temperature_gf_exponential_integral(oracle_mod, d, tau):
+    """The deformed-contour quadrature against the E1 closed form, and
+    g^> - g^< = -i e^{-i eps tau - Gamma |tau|}."""
+    mpmath.mp.dps = 30
+    gl, gg = oracle_mod.gf_direct(d.eps_d, d.gamma, d.beta, d.bias_v, tau)
+    ref = _e1_lesser_T0(d.eps_d, d.gamma, d.bias_v, abs(tau))
+    if tau < 0:
+        ref = -ref.conjugate()
+    assert abs(gl - ref) < 1e-13
+    assert abs((gg - gl) - (-1j) * np.exp(-1j * d.eps_d * tau - d.gamma * abs(tau))) < 1e-13
+
+
+def test_zero_temperature_occupation_is_the_digamma_limit(oracle_mod):
+    mpmath.mp.dps = 30
+    for eps, gam, V in [(0.0, 1.0, 0.0), (0.7, 0.5, 1.0), (-2.5, 2.0, 0.5)]:
+        beta = 1e9
+        ref = 0.0
+        for mu in (V / 2, -V / 2):
+            z = 0.5 + beta * (gam + 1j * (eps - mu)) / (2 * mpmath.pi)
+            ref += 0.5 * (0.5 - float(mpmath.im(mpmath.digamma(z))) / math.pi)
+        assert abs(oracle_mod.n_sigma(eps, gam, math.inf, V) - ref) < 1e-8
+
+
+@pytest.fixture(scope="module")
+def bethe_tables(oracle_mod):
+    """The paper's benchmark: T = 0, eps_d = 0, V = 0, Gamma = 1, wide band;
+    grid [-30, 30] with 65536 nodes for t = 30."""
+    return oracle_mod.Tables(0.0, 1.0, math.inf, 0.0, 65536, 30.0)
+
+
+def _bethe():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bethe_qn.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return {int(a): float(b) for a, b in rows}
+
+
+def test_bethe_q1_by_quadrature(oracle_mod, bethe_tables):
+    """Q_1 at t = 30 (adaptive quadrature of the order-1 integrand) against
+    the printed Bethe-ansatz -1/pi."""
+    q = integrate.quad(lambda u: oracle_mod.integrand(bethe_tables, 30.0, [u])[0].real,
+                       0, 30.0, limit=400, epsabs=1e-13, epsrel=1e-12)[0]
+    assert abs(q - _bethe()[1]) < 2e-6
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_bethe_low_orders_by_qmc(oracle_mod, bethe_tables, n):
+    """Q_2..Q_4 at t = 30 (N = 2^14 x 16 shifts, tau = 0.95 as in the paper)
+    within their randomised-QMC error bars of the printed Bethe values."""
+    job = order_job(1, n, 14, 16, model_tau=0.95)
+    q, mean, se = oracle_mod.eval_order(bethe_tables, 30.0, n, job.log2_n, job.lattice_a,
+                                        job.shifts, 0.95)
+    assert abs(mean.real - _bethe()[n]) < 5 * se + 2e-6

@@ -48,19 +48,19 @@ def _load():
     lib.oracle_gf_direct.argtypes = [d, d, d, d, d, P]
     lib.oracle_interp.argtypes = [P, i, d, d, P]
     lib.oracle_det.argtypes = [i, P, P]
-    lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, i, P, PI, P]
-    lib.oracle_keldysh_sum.argtypes = [P, P, i, d, d, d, i, P, P, P]
+    lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, d, i, P, PI, P]
+    lib.oracle_keldysh_sum.argtypes = [P, P, i, d, d, d, d, i, P, P, P]
     lib.oracle_lattice_point.argtypes = [u64, i, i, u64, P, P]
     lib.oracle_warp.argtypes = [i, P, d, d, P, P]
     lib.oracle_warp.restype = i
-    lib.oracle_eval_sums.argtypes = [P, P, i, d, d, d, i, i, u64, i, P, d, i,
+    lib.oracle_eval_sums.argtypes = [P, P, i, d, d, d, d, i, i, u64, i, P, d, i,
                                      i64, i64, i, P]
     lib.oracle_eval_sums.restype = i
     lib.oracle_max_threads.restype = i
-    lib.oracle_eval_sums_model.argtypes = [P, P, i, d, d, d, i, i, u64, i, P, d, P, i, i,
+    lib.oracle_eval_sums_model.argtypes = [P, P, i, d, d, d, d, i, i, u64, i, P, d, P, i, i,
                                            i64, i64, i, P]
     lib.oracle_eval_sums_model.restype = i
-    lib.oracle_learn_model.argtypes = [P, P, i, d, d, d, i, i, u64, P, d, i, d, d, i, P, P]
+    lib.oracle_learn_model.argtypes = [P, P, i, d, d, d, d, i, i, u64, P, d, i, d, d, i, P, P]
     lib.oracle_learn_model.restype = i
     lib.oracle_model_from_hist.argtypes = [i, i, P, d, d, P]
     lib.oracle_model_from_hist.restype = i
@@ -112,8 +112,10 @@ class Tables:
         _load().oracle_interp(_p(tab), self.n_grid, self.t_half, float(tau), _p(out))
         return out[0] + 1j * out[1]
 
-    def _args(self):
-        return (_p(self.gl), _p(self.gg), self.n_grid, self.t_half, self.n_sigma)
+    def _args(self, alpha=0.0):
+        """Table arguments of the C functions; alpha shifts every vertex
+        diagonal by -i alpha (App. E)."""
+        return (_p(self.gl), _p(self.gg), self.n_grid, self.t_half, self.n_sigma, float(alpha))
 
 
 def n_sigma(eps_d, gamma, beta, bias_v):
@@ -135,31 +137,31 @@ def det(mat):
     return out[0] + 1j * out[1]
 
 
-def wick_matrix(tables, t_meas, u, a):
+def wick_matrix(tables, t_meas, u, a, alpha=0.0):
     u = _f64(u)
     n = u.shape[0]
     av = np.ascontiguousarray(a, dtype=np.int32)
     out = np.zeros(2 * (n + 1) ** 2)
-    _load().oracle_wick_matrix(*tables._args(), t_meas, n, _p(u),
+    _load().oracle_wick_matrix(*tables._args(alpha), t_meas, n, _p(u),
                                av.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                _p(out))
     c = out[0::2] + 1j * out[1::2]
     return c.reshape(n + 1, n + 1)
 
 
-def keldysh_sum(tables, t_meas, u):
+def keldysh_sum(tables, t_meas, u, alpha=0.0):
     """S(u) and the term mass M(u) for one point u = (u_1..u_n)."""
     u = _f64(u)
     S = np.zeros(2)
     M = ctypes.c_double()
-    _load().oracle_keldysh_sum(*tables._args(), t_meas, u.shape[0], _p(u),
+    _load().oracle_keldysh_sum(*tables._args(alpha), t_meas, u.shape[0], _p(u),
                                _p(S), ctypes.byref(M))
     return S[0] + 1j * S[1], M.value
 
 
-def integrand(tables, t_meas, u):
+def integrand(tables, t_meas, u, alpha=0.0):
     """f_n(u) = -2 i^{n+1} S(u): integrand of Q_n over the ordered simplex."""
-    S, M = keldysh_sum(tables, t_meas, u)
+    S, M = keldysh_sum(tables, t_meas, u, alpha)
     n = len(u)
     return -2.0 * (1j ** (n + 1)) * S, 2.0 * M
 
@@ -181,7 +183,7 @@ def warp(x, model_tau, t_meas):
 
 
 def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
-              i_begin=0, i_end=None, n_threads=0, cdf=None):
+              i_begin=0, i_end=None, n_threads=0, cdf=None, alpha=0.0):
     """Per-shift sums of fbar over lattice indices [i_begin, i_end); cdf: a
     learned second warp (n x (n_bins+1)) or None."""
     shifts = _f64(shifts)
@@ -196,7 +198,7 @@ def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
         cdf = _f64(cdf)
         assert cdf.ndim == 2 and cdf.shape[0] == n
         cp, nb = _p(cdf), cdf.shape[1] - 1
-    rc = _load().oracle_eval_sums_model(*tables._args(), t_meas, n, log2_n,
+    rc = _load().oracle_eval_sums_model(*tables._args(alpha), t_meas, n, log2_n,
                                         int(lattice_a), K, _p(shifts), model_tau,
                                         cp, nb, mode, int(i_begin), int(i_end), n_threads,
                                         _p(sums))
@@ -206,11 +208,11 @@ def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
 
 
 def eval_order(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
-               n_threads=0, cdf=None):
+               n_threads=0, cdf=None, alpha=0.0):
     """Q^{(s)} for every shift, their mean and standard error (App. G)."""
     N = 1 << log2_n
     q = eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau,
-                  mode, 0, N, n_threads, cdf) / N
+                  mode, 0, N, n_threads, cdf, alpha) / N
     K = q.shape[0]
     mean = q.mean()
     stderr = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
@@ -218,13 +220,13 @@ def eval_order(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
 
 
 def learn_model(tables, t_meas, n, log2_m, lattice_a, shift, model_tau, n_bins,
-                lam, floor_eps, n_threads=0):
+                lam, floor_eps, n_threads=0, alpha=0.0):
     """Learned second warp (App. I): returns (hist, cdf), shapes
     (n, n_bins) and (n, n_bins + 1)."""
     shift = _f64(shift).reshape(n)
     hist = np.zeros((n, n_bins))
     cdf = np.zeros((n, n_bins + 1))
-    rc = _load().oracle_learn_model(*tables._args(), t_meas, n, log2_m, int(lattice_a),
+    rc = _load().oracle_learn_model(*tables._args(alpha), t_meas, n, log2_m, int(lattice_a),
                                     _p(shift), model_tau, n_bins, lam, floor_eps,
                                     n_threads, _p(hist), _p(cdf))
     assert rc == 0

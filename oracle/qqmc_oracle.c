@@ -16,6 +16,10 @@
  *  - Every equal-time (diagonal) Wick entry is g^<(0), whatever the Keldysh
  *    index; off-diagonal entries follow the 2x2 Keldysh rule of App. E with a
  *    strict inequality d > 0 for the time ordering.
+ *  - With the alpha-shifted interaction U (n_up - alpha)(n_dn - alpha)
+ *    (App. E, "Model"), the diagonal entry of every vertex is shifted by
+ *    -i alpha, in both determinants; the measurement point's diagonal entry
+ *    keeps g^<(0) (App. E, after the definition of the Wick determinant).
  *  - Q_n = -2 i^{n+1} * integral over 0 < u_n < ... < u_1 < t of S(u): the
  *    factor 2 is the spin sum of Q, the 1/n! of Eq. (integral_gf) is absorbed
  *    by restricting to the time-ordered simplex (S is symmetric).
@@ -386,20 +390,21 @@ void oracle_det(int m, const double *a, double *out)
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int n;            /* number of vertices                                 */
-    cplx g0;          /* exact equal-time value g^<(0) = i n_sigma           */
+    cplx g0;          /* vertex diagonal g^<(0) - i alpha = i (n_sigma - alpha) */
+    cplx gm;          /* measurement diagonal g^<(0) = i n_sigma             */
     const cplx *gl_d; /* (n+1)^2: g^<(tau_r - tau_c), point 0 = measurement  */
     const cplx *gg_d; /* (n+1)^2: g^>(tau_r - tau_c)                         */
     const double *tm; /* (n+1): times, tm[0] = t, tm[k] = u_k                */
 } wick_ctx;
 
-static cplx keldysh_entry(const wick_ctx *w, int r, int alpha, int c, int beta_)
+static cplx keldysh_entry(const wick_ctx *w, int r, int a_r, int c, int a_c)
 {
     int np1 = w->n + 1;
     double d = w->tm[r] - w->tm[c];
     cplx gl = w->gl_d[r * np1 + c], gg = w->gg_d[r * np1 + c];
-    if (alpha == 0 && beta_ == 0) return d > 0.0 ? gg : gl;
-    if (alpha == 0 && beta_ == 1) return gl;
-    if (alpha == 1 && beta_ == 0) return gg;
+    if (a_r == 0 && a_c == 0) return d > 0.0 ? gg : gl;
+    if (a_r == 0 && a_c == 1) return gl;
+    if (a_r == 1 && a_c == 0) return gg;
     return d > 0.0 ? gl : gg;
 }
 
@@ -409,7 +414,7 @@ static void build_up(const wick_ctx *w, const int *a, cplx *m)
     int np1 = w->n + 1;
     for (int r = 0; r < np1; ++r) {
         for (int c = 0; c < np1; ++c) {
-            if (r == c) { m[r * np1 + c] = w->g0; continue; }
+            if (r == c) { m[r * np1 + c] = r == 0 ? w->gm : w->g0; continue; }
             int ar = r == 0 ? 0 : a[r - 1];
             int ac = c == 0 ? 1 : a[c - 1];
             m[r * np1 + c] = keldysh_entry(w, r, ar, c, ac);
@@ -431,7 +436,7 @@ static void fill_pair_values(const double *gl, const double *gg, int n_grid,
 }
 
 void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
-                        double t_half, double n_sigma, double t_meas,
+                        double t_half, double n_sigma, double alpha, double t_meas,
                         int n, const double *u, const int *a, double *out)
 {
     int np1 = n + 1;
@@ -442,7 +447,7 @@ void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
     tm[0] = t_meas;
     for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
     fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
-    wick_ctx w = { n, I * n_sigma, gl_d, gg_d, tm };
+    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm };
     build_up(&w, a, m);
     for (int i = 0; i < np1 * np1; ++i) {
         out[2 * i] = creal(m[i]);
@@ -455,7 +460,7 @@ void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
  * (bit k-1 of the counter is a_k), of (-1)^{sum a} det_up(a) det_dn(a),
  * where det_dn is the vertex block (rows/columns 1..n) of the up matrix. */
 void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
-                        double t_half, double n_sigma, double t_meas,
+                        double t_half, double n_sigma, double alpha, double t_meas,
                         int n, const double *u, double *S_out, double *M_out)
 {
     int np1 = n + 1;
@@ -465,7 +470,7 @@ void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
     tm[0] = t_meas;
     for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
     fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
-    wick_ctx w = { n, I * n_sigma, gl_d, gg_d, tm };
+    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm };
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0, mass = 0.0;
     for (long mask = 0; mask < (1L << n); ++mask) {
         int parity = 0;
@@ -604,7 +609,7 @@ static int warp_model(int n, const double *x, const double *cdf, int n_bins,
 }
 
 int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
-                           double t_half, double n_sigma, double t_meas,
+                           double t_half, double n_sigma, double alpha, double t_meas,
                            int n, int log2_n, uint64_t lattice_a,
                            int n_shifts, const double *shifts, double model_tau,
                            const double *cdf, int n_bins,
@@ -641,7 +646,7 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
                 if (mode == 2) {
                     f = W;
                 } else {
-                    oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, t_meas,
+                    oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas,
                                        n, u, S, &M);
                     f = -2.0 * ipow * (S[0] + I * S[1]) * W;
                 }
@@ -664,19 +669,19 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
 }
 
 int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
-                     double t_half, double n_sigma, double t_meas,
+                     double t_half, double n_sigma, double alpha, double t_meas,
                      int n, int log2_n, uint64_t lattice_a,
                      int n_shifts, const double *shifts, double model_tau,
                      int mode, int64_t i_begin, int64_t i_end, int n_threads,
                      double *sums)
 {
-    return oracle_eval_sums_model(gl, gg, n_grid, t_half, n_sigma, t_meas, n, log2_n,
+    return oracle_eval_sums_model(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, log2_n,
                                   lattice_a, n_shifts, shifts, model_tau, NULL, 0, mode,
                                   i_begin, i_end, n_threads, sums);
 }
 
 int oracle_learn_model(const double *gl, const double *gg, int n_grid,
-                       double t_half, double n_sigma, double t_meas,
+                       double t_half, double n_sigma, double alpha, double t_meas,
                        int n, int log2_m, uint64_t lattice_a,
                        const double *shift, double model_tau, int n_bins,
                        double lambda, double floor_eps, int n_threads,
@@ -701,7 +706,7 @@ int oracle_learn_model(const double *gl, const double *gg, int n_grid,
         oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
         double v = 0.0;
         if (oracle_warp(n, x, model_tau, t_meas, u, &W)) {
-            oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, t_meas, n, u, S, &Mass);
+            oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, u, S, &Mass);
             v = fabs(creal(-2.0 * ipow * (S[0] + I * S[1]) * W));
         }
         vals[i] = v;

@@ -52,7 +52,7 @@ void oracle_det(int m, const double *a, double *out);
  * measurement point, rows/columns 1..n are the vertices U_1..U_n.  The
  * n x n spin-down matrix is its lower-right block.  out: 2*(n+1)^2 doubles. */
 void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
-                        double t_half, double n_sigma, double t_meas,
+                        double t_half, double n_sigma, double alpha, double t_meas,
                         int n, const double *u, const int *a, double *out);
 
 /* Keldysh sum S(u) = sum_a (-1)^{sum a} det_up(a) det_dn(a) over all 2^n
@@ -60,7 +60,7 @@ void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
  * M(u) = sum_a |det_up(a) det_dn(a)|.  u[0..n-1] = (u_1..u_n), any order.
  * S_out = (re, im). */
 void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
-                        double t_half, double n_sigma, double t_meas,
+                        double t_half, double n_sigma, double alpha, double t_meas,
                         int n, const double *u, double *S_out, double *M_out);
 
 /* Rank-1 (Korobov) lattice point with a random shift:
@@ -82,7 +82,7 @@ int oracle_warp(int n, const double *x, double model_tau, double t_meas,
  * cut, every sample equals C); mode 2: f := 1 on the ordered simplex.
  * n_threads <= 0 uses all OpenMP threads.  Returns 0, or -1 on bad args. */
 int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
-                     double t_half, double n_sigma, double t_meas,
+                     double t_half, double n_sigma, double alpha, double t_meas,
                      int n, int log2_n, uint64_t lattice_a,
                      int n_shifts, const double *shifts, double model_tau,
                      int mode, int64_t i_begin, int64_t i_end, int n_threads,
@@ -113,7 +113,7 @@ int oracle_max_threads(void);
  * per coordinate and bin, cdf (n*(n_bins+1)) the model.  Returns 0, or -1 on
  * bad arguments. */
 int oracle_learn_model(const double *gl, const double *gg, int n_grid,
-                       double t_half, double n_sigma, double t_meas,
+                       double t_half, double n_sigma, double alpha, double t_meas,
                        int n, int log2_m, uint64_t lattice_a,
                        const double *shift, double model_tau, int n_bins,
                        double lambda, double floor_eps, int n_threads,
@@ -133,7 +133,7 @@ double oracle_model_inverse(const double *cdf, int n_bins, double x, double *w);
  * model function is the combined one, p_n(u) prod_j q_j(w_j), so every sample
  * still equals C. */
 int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
-                           double t_half, double n_sigma, double t_meas,
+                           double t_half, double n_sigma, double alpha, double t_meas,
                            int n, int log2_n, uint64_t lattice_a,
                            int n_shifts, const double *shifts, double model_tau,
                            const double *cdf, int n_bins,

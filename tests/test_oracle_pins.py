@@ -570,3 +570,144 @@ def test_bethe_low_orders_by_qmc(oracle_mod, bethe_tables, n):
     q, mean, se = oracle_mod.eval_order(bethe_tables, 30.0, n, job.log2_n, job.lattice_a,
                                         job.shifts, 0.95)
     assert abs(mean.real - _bethe()[n]) < 5 * se + 2e-6
+
+
+# ---------------------------------------------------------------------------
+# alpha-shifted interaction U (n_up - alpha)(n_dn - alpha) (App. E, "Model";
+# the diagonal shift is stated after the definition of the Wick determinant).
+# The tables are built at the quadratic level E; the Hamiltonian equals the
+# alpha = 0 one at level E - alpha U plus a constant, so in the stationary
+# state Q^alpha(E; U) = Q^0(E - alpha U; U).  Expanding in U:
+#   Q^a_1 = Q^0_1 - a dQ^0_0/dE
+#   Q^a_2 = Q^0_2 - a dQ^0_1/dE + a^2/2 d2Q^0_0/dE2
+#   Q^a_3 = Q^0_3 - a dQ^0_2/dE + a^2/2 d2Q^0_1/dE2 - a^3/6 d3Q^0_0/dE3
+# with Q^0_0 = 2 n_sigma(E).  beta = 2 and Gamma = 1 make t = 10 stationary
+# (the memory of the initial state decays like e^{-2t}); the fine grid keeps
+# the tables' interpolation error near 1e-7.
+# ---------------------------------------------------------------------------
+ALPHA_E, ALPHA_G, ALPHA_B, ALPHA_V, ALPHA_T = 0.3, 1.0, 2.0, 0.4, 10.0
+
+
+@pytest.fixture(scope="module")
+def alpha_tab(oracle_mod):
+    cache = {}
+
+    def tab(e):
+        if e not in cache:
+            cache[e] = oracle_mod.Tables(e, ALPHA_G, ALPHA_B, ALPHA_V, 32768, 10.0)
+        return cache[e]
+    return tab
+
+
+def _d1(f, x, h):
+    return (8.0 * (f(x + h) - f(x - h)) - (f(x + 2 * h) - f(x - 2 * h))) / (12.0 * h)
+
+
+def _d2(f, x, h):
+    return (-f(x + 2 * h) + 16.0 * f(x + h) - 30.0 * f(x) + 16.0 * f(x - h)
+            - f(x - 2 * h)) / (12.0 * h * h)
+
+
+def _d3(f, x, h):
+    return (-(f(x + 3 * h) - f(x - 3 * h)) + 8.0 * (f(x + 2 * h) - f(x - 2 * h))
+            - 13.0 * (f(x + h) - f(x - h))) / (8.0 * h ** 3)
+
+
+def _q1_quad(oracle_mod, tb):
+    return integrate.quad(lambda u: oracle_mod.integrand(tb, ALPHA_T, [u])[0].real, 0, ALPHA_T,
+                          epsabs=1e-13, epsrel=1e-12, limit=400)[0]
+
+
+def _q0(oracle_mod, e):
+    return 2.0 * oracle_mod.n_sigma(e, ALPHA_G, ALPHA_B, ALPHA_V)
+
+
+@pytest.mark.parametrize("alpha", [0.5, -0.35, 1.2])
+def test_alpha_order1_proportional(oracle_mod, alpha_tab, alpha):
+    """At order 1 the measurement term cancels from the Keldysh sum and the
+    vertex determinant is the shifted diagonal alone, so the integrand scales
+    by (n_sigma - alpha) / n_sigma at every point."""
+    tb = alpha_tab(ALPHA_E)
+    ratio = (tb.n_sigma - alpha) / tb.n_sigma
+    for u in (0.3, 4.4, 9.7):
+        f0 = oracle_mod.integrand(tb, ALPHA_T, [u])[0]
+        fa = oracle_mod.integrand(tb, ALPHA_T, [u], alpha)[0]
+        assert abs(fa - ratio * f0) <= 1e-13 * abs(f0)
+
+
+def test_alpha_wick_diagonals(oracle_mod, alpha_tab):
+    """Vertex diagonals carry i (n_sigma - alpha), the measurement diagonal
+    keeps i n_sigma, and no off-diagonal entry moves."""
+    tb = alpha_tab(ALPHA_E)
+    u, a = [7.0, 3.5, 1.0], [1, 0, 1]
+    m0 = oracle_mod.wick_matrix(tb, ALPHA_T, u, a)
+    ma = oracle_mod.wick_matrix(tb, ALPHA_T, u, a, 0.4)
+    assert ma[0, 0] == 1j * tb.n_sigma
+    for k in range(1, 4):
+        assert ma[k, k] == 1j * (tb.n_sigma - 0.4)
+    off = ~np.eye(4, dtype=bool)
+    assert np.array_equal(ma[off], m0[off])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_alpha_pointwise_degree(oracle_mod, alpha_tab, n):
+    """Each vertex (n_up - a)(n_dn - a) contributes at most one power of a
+    (its a^2 part is a c-number, cancelled between the two branches), so at
+    any point the order-n integrand is a polynomial of degree n in alpha:
+    its (n+1)-th finite difference vanishes to rounding of the term mass,
+    its n-th does not.  Vertices within 2 of the measurement time, where the
+    Keldysh sum cancels least."""
+    tb = alpha_tab(ALPHA_E)
+    rs = np.random.RandomState(40 + n)
+    u = ALPHA_T - np.sort(rs.uniform(0.0, 2.0, n))
+    h = 0.25
+    r = [oracle_mod.integrand(tb, ALPHA_T, u, -0.5 + k * h) for k in range(n + 2)]
+    f = [v[0] for v in r]
+    mass = max(v[1] for v in r)
+    dn1 = sum((-1) ** k * math.comb(n + 1, k) * f[k] for k in range(n + 2))
+    dn = sum((-1) ** k * math.comb(n, k) * f[k] for k in range(n + 1))
+    assert abs(dn1) <= 1e-14 * mass
+    assert abs(dn) > 1e-6 * mass
+
+
+@pytest.mark.parametrize("alpha", [0.5, -0.35])
+def test_alpha_reexpansion_order2(oracle_mod, alpha_tab, alpha):
+    """Q^a_2 - Q^0_2 (paired estimate on one lattice) against
+    -a dQ^0_1/dE + a^2/2 d2Q^0_0/dE2, with Q^0_1 by adaptive quadrature."""
+    d = 2e-3
+    dq1 = _d1(lambda e: _q1_quad(oracle_mod, alpha_tab(e)), ALPHA_E, d)
+    d2q0 = _d2(lambda e: _q0(oracle_mod, e), ALPHA_E, d)
+    pred = -alpha * dq1 + 0.5 * alpha ** 2 * d2q0
+    tb = alpha_tab(ALPHA_E)
+    job = order_job(7, 2, 16, 16)
+    qa, _, _ = oracle_mod.eval_order(tb, ALPHA_T, 2, 16, job.lattice_a, job.shifts, 1.0,
+                                     alpha=alpha)
+    q0, _, _ = oracle_mod.eval_order(tb, ALPHA_T, 2, 16, job.lattice_a, job.shifts, 1.0)
+    diff = (qa - q0).real
+    m, se = diff.mean(), diff.std(ddof=1) / math.sqrt(diff.size)
+    assert abs(m - pred) < 5 * se + 3e-7, (m, se, pred)
+
+
+@pytest.mark.parametrize("alpha", [0.5, -0.35])
+def test_alpha_reexpansion_order3(oracle_mod, alpha_tab, alpha):
+    """Q^a_3 - Q^0_3 against -a dQ^0_2/dE + a^2/2 d2Q^0_1/dE2
+    - a^3/6 d3Q^0_0/dE3; dQ^0_2/dE from lattice estimates at neighbouring
+    levels on one lattice (common random numbers)."""
+    d = 2e-3
+    j2 = order_job(8, 2, 16, 16)
+
+    def q2(e):
+        return oracle_mod.eval_order(alpha_tab(e), ALPHA_T, 2, 16, j2.lattice_a, j2.shifts,
+                                     1.0)[1].real
+    dq2 = _d1(q2, ALPHA_E, d)
+    d2q1 = _d2(lambda e: _q1_quad(oracle_mod, alpha_tab(e)), ALPHA_E, d)
+    d3q0 = _d3(lambda e: _q0(oracle_mod, e), ALPHA_E, d)
+    pred = -alpha * dq2 + 0.5 * alpha ** 2 * d2q1 - alpha ** 3 / 6.0 * d3q0
+    tb = alpha_tab(ALPHA_E)
+    job = order_job(9, 3, 16, 16)
+    qa, _, _ = oracle_mod.eval_order(tb, ALPHA_T, 3, 16, job.lattice_a, job.shifts, 1.0,
+                                     alpha=alpha)
+    q0, _, _ = oracle_mod.eval_order(tb, ALPHA_T, 3, 16, job.lattice_a, job.shifts, 1.0)
+    diff = (qa - q0).real
+    m, se = diff.mean(), diff.std(ddof=1) / math.sqrt(diff.size)
+    assert abs(m - pred) < 5 * se + 1e-6, (m, se, pred)

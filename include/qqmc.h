@@ -92,6 +92,13 @@ typedef struct {
                                the combined model p_n(u) prod_j q_j(w_j)       */
     qqmc_model model;       /* learned second warp of the same order, or NULL;
                                must stay valid until the work using it ends  */
+    double alpha;           /* interaction U (n_up - alpha)(n_dn - alpha)
+                               (App. E, "Model"): every vertex diagonal of the
+                               Wick matrices becomes g^<(0) - i alpha, the
+                               measurement diagonal stays g^<(0); the tables
+                               are built at the quadratic level E_d, whose
+                               one-electron energy is E_d - alpha U; finite;
+                               0 = the plain interaction U n_up n_dn          */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
@@ -167,6 +174,7 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
 
 /* Per-point integrand f_n(u) = -2 i^{n+1} S(u) of Eq. (integral_gf) (the
  * integrand of Q_n over the ordered simplex, without warping weight).
+ *   alpha   interaction shift, as in qqmc_order (finite)
  *   u       device, n_points x order row-major, vertex times (u_1..u_n)
  *   f       device, 2*n_points doubles (re, im)
  *   method  QQMC_METHOD_TREE: the production kernel; requires
@@ -178,7 +186,7 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
  * Asynchronous on `stream`. */
 enum { QQMC_METHOD_TREE = 0, QQMC_METHOD_DIRECT = 1 };
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
-                             const double *u, int64_t n_points,
+                             double alpha, const double *u, int64_t n_points,
                              int32_t method, double *f, void *stream);
 
 /* ---- Learned second warp (App. I) ---------------------------------------
@@ -200,6 +208,8 @@ typedef struct {
     int32_t n_bins;         /* 1 .. 4096                                      */
     double lambda;          /* kernel width > 0                               */
     double floor_eps;       /* uniform weight in [0, 1]                       */
+    double alpha;           /* interaction shift of the learned integrand, as
+                               in qqmc_order                                   */
 } qqmc_learn_params;
 
 /* Learns a model on the current device; synchronises `stream`.  EINVAL on

@@ -56,6 +56,8 @@ def _load():
     lib.oracle_eval_sums.argtypes = [P, P, i, d, d, d, d, i, i, u64, i, P, d, i,
                                      i64, i64, i, P]
     lib.oracle_eval_sums.restype = i
+    lib.oracle_eval_mass.argtypes = [P, P, i, d, d, d, d, i, i, u64, i, P, d, i64, i64, i, P]
+    lib.oracle_eval_mass.restype = i
     lib.oracle_max_threads.restype = i
     lib.oracle_eval_sums_model.argtypes = [P, P, i, d, d, d, d, i, i, u64, i, P, d, P, i, i,
                                            i64, i64, i, P]
@@ -205,6 +207,23 @@ def eval_sums(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,
     if rc != 0:
         raise ValueError("oracle_eval_sums_model: bad arguments")
     return sums[0::2] + 1j * sums[1::2]
+
+
+def eval_mass(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, i_begin=0,
+              i_end=None, n_threads=0, alpha=0.0):
+    """Per-shift term mass sum_i 2 W |terms| of the charge estimate over
+    lattice indices [i_begin, i_end): the scale of rounding in the sums."""
+    shifts = _f64(shifts)
+    K = shifts.shape[0]
+    if i_end is None:
+        i_end = 1 << log2_n
+    mass = np.zeros(K)
+    rc = _load().oracle_eval_mass(*tables._args(alpha), t_meas, n, log2_n, int(lattice_a), K,
+                                  _p(shifts), model_tau, int(i_begin), int(i_end), n_threads,
+                                  _p(mass))
+    if rc != 0:
+        raise ValueError("oracle_eval_mass: bad arguments")
+    return mass
 
 
 def eval_order(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, mode=0,

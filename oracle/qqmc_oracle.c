@@ -668,6 +668,37 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
     return 0;
 }
 
+/* Term mass of the charge estimate (exponential warp): per shift, the sum
+ * over lattice indices [i_begin, i_end) of 2 W(u) M(u), with M the sum over
+ * index vectors of |det_up det_dn|: the scale that rounding in the Keldysh
+ * sum is relative to. */
+int oracle_eval_mass(const double *gl, const double *gg, int n_grid,
+                     double t_half, double n_sigma, double alpha, double t_meas,
+                     int n, int log2_n, uint64_t lattice_a,
+                     int n_shifts, const double *shifts, double model_tau,
+                     int64_t i_begin, int64_t i_end, int n_threads, double *mass)
+{
+    if (n < 1 || n > 24 || log2_n < 1 || log2_n > 40 || i_end < i_begin ||
+        i_begin < 0 || n_shifts < 1)
+        return -1;
+    int nt = n_threads > 0 ? n_threads : oracle_max_threads();
+    for (int s = 0; s < n_shifts; ++s) {
+        const double *sh = shifts + (size_t)s * n;
+        double acc = 0.0;
+        #pragma omp parallel for schedule(dynamic, 4) num_threads(nt) reduction(+:acc)
+        for (int64_t q = i_begin; q < i_end; ++q) {
+            double x[32], u[32], W, S[2], M;
+            oracle_lattice_point((uint64_t)q, n, log2_n, lattice_a, sh, x);
+            if (oracle_warp(n, x, model_tau, t_meas, u, &W)) {
+                oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, u, S, &M);
+                acc += 2.0 * W * M;
+            }
+        }
+        mass[s] = acc;
+    }
+    return 0;
+}
+
 int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
                      double t_half, double n_sigma, double alpha, double t_meas,
                      int n, int log2_n, uint64_t lattice_a,

@@ -89,6 +89,12 @@ int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
                      double *sums);
 
 /* Number of OpenMP threads the oracle would use for n_threads <= 0. */
+int oracle_eval_mass(const double *gl, const double *gg, int n_grid,
+                     double t_half, double n_sigma, double alpha, double t_meas,
+                     int n, int log2_n, uint64_t lattice_a,
+                     int n_shifts, const double *shifts, double model_tau,
+                     int64_t i_begin, int64_t i_end, int n_threads, double *mass);
+
 int oracle_max_threads(void);
 
 /* ---- Learned second warp (App. I, "Learning h^(i) from the integrand") ----

@@ -53,6 +53,7 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
         return set_error(QQMC_EINVAL, "unknown mode");
     if (ord->model && (ord->model->order != n || !ord->model->d_cdf))
         return set_error(QQMC_EINVAL, "model of another order");
+    if (!std::isfinite(ord->alpha)) return set_error(QQMC_EINVAL, "alpha must be finite");
     const size_t ns = (size_t)ord->n_shifts * (size_t)n;
     out->shifts.assign(ord->shifts, ord->shifts + ns);
     for (double v : out->shifts)
@@ -66,6 +67,7 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
     d.inv_n = 1.0 / (double)N;
     d.t_meas = ord->t_meas;
     d.tau = ord->model_tau;
+    d.alpha = ord->alpha;
     double c = 1.0;
     for (int k = 0; k < n; ++k) c *= ord->model_tau;
     d.tau_n = c;
@@ -103,8 +105,10 @@ void fill_item_tables(ItemDesc &d, const qqmc_tables_s *t)
     d.n_grid = t->n_grid;
     d.t_half = t->t_half;
     d.h = t->h;
+    /* every vertex diagonal is g^<(0) - i alpha (App. E); the measurement
+     * diagonal cancels from the Keldysh sum and is never formed here */
     d.g0x = 0.0;
-    d.g0y = t->n_sigma;
+    d.g0y = t->n_sigma - d.alpha;
 }
 
 qqmc_status upload_tables(const double *tab4, int32_t n_grid, double t_half, double n_sigma,
@@ -356,8 +360,9 @@ qqmc_status qqmc_eval_order(qqmc_tables t, const qqmc_order *ord, void *stream,
     return QQMC_OK;
 }
 
-qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, const double *u,
-                             int64_t n_points, int32_t method, double *f, void *stream)
+qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double alpha,
+                             const double *u, int64_t n_points, int32_t method, double *f,
+                             void *stream)
 {
     if (qqmc_status st = check_tables(t)) return st;
     if (order < 1 || order > QQMC_MAX_ORDER) return set_error(QQMC_EINVAL, "bad order");
@@ -365,17 +370,18 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, const 
     if (n_points > 0 && (!u || !f)) return set_error(QQMC_EINVAL, "NULL buffer");
     if (!(t_meas > 0.0) || !(t_meas <= t->t_half))
         return set_error(QQMC_EINVAL, "t_meas must satisfy 0 < t_meas <= t_half");
+    if (!std::isfinite(alpha)) return set_error(QQMC_EINVAL, "alpha must be finite");
     if (method != QQMC_METHOD_TREE && method != QQMC_METHOD_DIRECT)
         return set_error(QQMC_EINVAL, "unknown method");
     if (n_points == 0) return QQMC_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (method == QQMC_METHOD_TREE)
-        e = launch_points_tree(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, order, t_meas,
-                               u, n_points, f, s);
+        e = launch_points_tree(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, alpha, order,
+                               t_meas, u, n_points, f, s);
     else if (method == QQMC_METHOD_DIRECT)
-        e = launch_points_direct(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, order, t_meas,
-                                 u, n_points, f, s);
+        e = launch_points_direct(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, alpha, order,
+                                 t_meas, u, n_points, f, s);
     else
         return set_error(QQMC_EINVAL, "unknown method");
     if (e != hipSuccess) return hip_error(e, "qqmc_eval_points launch");

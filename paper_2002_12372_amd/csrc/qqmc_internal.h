@@ -19,7 +19,7 @@ struct ItemDesc {
     const double *tab;       /* device: (g^<, g^>) per grid node, 4 doubles */
     const double *shifts;    /* device: n_shifts x order                    */
     double t_half, h;        /* grid half-range and spacing                 */
-    double g0x, g0y;         /* g^<(0) = i n_sigma                          */
+    double g0x, g0y;         /* vertex diagonal g^<(0) - i alpha = i (n_sigma - alpha) */
     double t_meas, tau, tau_n, inv_n;
     uint32_t z[QQMC_MAX_ORDER]; /* Korobov generating vector a^j mod N     */
     uint32_t mask;           /* N - 1                                       */
@@ -31,7 +31,19 @@ struct ItemDesc {
     int32_t model_bins;
     int32_t pad_;
     double *sample_out;      /* device: per-point Re fbar (learning pass), or null */
+    double alpha;            /* interaction shift U (n_up - alpha)(n_dn - alpha) */
 };
+
+/* Batched-kernel selector of an item, 1 .. 2 QQMC_MAX_ORDER: its order,
+ * plus QQMC_MAX_ORDER when it runs the paired elimination tree (alpha != 0,
+ * the vertex diagonal may vanish). */
+inline int32_t kernel_key(const ItemDesc &d)
+{
+    return d.order + (d.alpha != 0.0 ? QQMC_MAX_ORDER : 0);
+}
+constexpr int32_t kMaxKernelKey = 2 * QQMC_MAX_ORDER;
+inline int32_t key_order(int32_t key) { return (key - 1) % QQMC_MAX_ORDER + 1; }
+inline bool key_pair(int32_t key) { return key > QQMC_MAX_ORDER; }
 
 /* Entry of the batched tile list: which item, which tile of it. */
 struct TileRef {
@@ -48,15 +60,16 @@ hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
                                double *shift_sums, int32_t total_shifts,
                                hipStream_t s);
 hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half,
-                              double h, double g0y, int32_t order,
+                              double h, double n_sigma, double alpha, int32_t order,
                               double t_meas, const double *u, int64_t n_points,
                               double *f, hipStream_t s);
 hipError_t launch_points_direct(const double *tab, int32_t n_grid,
-                                double t_half, double h, double g0y,
+                                double t_half, double h, double n_sigma, double alpha,
                                 int32_t order, double t_meas, const double *u,
                                 int64_t n_points, double *f, hipStream_t s);
-/* One persistent launch over a tile list whose tiles all have this order. */
-hipError_t launch_batch(int32_t order, const ItemDesc *items_dev,
+/* One persistent launch over a tile list whose items all have this kernel
+ * key. */
+hipError_t launch_batch(int32_t key, const ItemDesc *items_dev,
                         const TileRef *tiles_dev, int64_t n_tiles,
                         int32_t grid_blocks, hipStream_t s);
 /* Learning pass: per-point Re fbar of the lattice points of tile range
@@ -65,7 +78,7 @@ hipError_t launch_sample(const ItemDesc &it, hipStream_t s);
 hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_d,
                          double gamma, double beta, double bias_v, double n_sigma,
                          hipStream_t s);
-int32_t batch_blocks_per_cu(int32_t order);
+int32_t batch_blocks_per_cu(int32_t key);
 /* Relative cost of one tile of an item (qqmc_plan.cpp). */
 double tile_cost(const ItemDesc &d);
 int32_t default_tile_len(const ItemDesc &d, int64_t N);

@@ -31,8 +31,8 @@ namespace {
 
 constexpr int WAVE = 64;
 
-template <int N> struct Lds {
-    using Gm = Geo<N>;
+template <int N, bool PAIR = false> struct Lds {
+    using Gm = Geo<N, PAIR>;
     static constexpr int times = 0;                                    /* 64*N doubles   */
     static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
     static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
@@ -42,8 +42,10 @@ template <int N> struct Lds {
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
     static constexpr int pairs = ids + 64 * 4;                         /* tables*NP pairv */
-    static constexpr int row = pairs + tables * Gm::NP * 32;           /* PPW*(N+1) cplx */
-    static constexpr int c0 = row + (Gm::OFF > 0 ? Gm::PPW * (N + 1) * 16 : 0);
+    /* one broadcast row per group (two for the paired tree) */
+    static constexpr int rows = PAIR ? 2 : 1;
+    static constexpr int row = pairs + tables * Gm::NP * 32;   /* rows*PPW*(N+1) cplx */
+    static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
 };
 
@@ -119,7 +121,8 @@ __device__ __forceinline__ cplx wave_sum(cplx v)
 struct Env {
     const double *tab;
     double t_half, inv_h, t_meas;
-    cplx g0;
+    cplx g0;      /* vertex diagonal i (n_sigma - alpha)                      */
+    cplx gm;      /* measurement diagonal i n_sigma (the direct method only)  */
     int n_grid;
 };
 
@@ -185,13 +188,91 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
     return prod;
 }
 
+/* The paired tree's first OFF eliminations (OFF even, n > 8): pair steps of
+ * vertices (k, k+1) with 2x2 block pivots, rows spread over the G lanes as
+ * in top_block.  The lanes holding rows k and k+1 broadcast them through
+ * s_row (2 (n+1) entries); every lane applies the rank-2 update to its rows
+ * below.  Leaves the K x K trailing correction block in s_c0 and returns the
+ * product of the pivot-block determinants. */
+template <int N>
+__device__ cplx top_block_pair(const pairv *pr, int top, int sub, cplx g0, cplx *s_row,
+                               cplx *s_c0)
+{
+    using Gm = Geo<N, true>;
+    constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
+    constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
+    cplx *s_r0 = s_row, *s_r1 = s_row + (N + 1);
+    cplx crow[RPL][N + 1];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m)
+#pragma unroll
+        for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
+    cplx prod = cmk(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < OFF; k += 2) {
+        const int b = (top >> (OFF - 1 - k)) & 1, bq = (top >> (OFF - 2 - k)) & 1;
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r == k) {
+                cplx v[N + 1];
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) v[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
+                s_r0[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) s_r0[j] = v[j];
+            } else if (r == k + 1) {
+                /* (k+1, k): the earlier point is k, so index b */
+                cplx v[N + 1];
+                v[k] = csub(wick_entry(pr, k + 1, k, b), crow[m][k]);
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j) v[j] = csub(wick_entry(pr, k + 1, j, bq), crow[m][j]);
+                s_r1[k + 1] = csub(g0, crow[m][k + 1]);
+                s_r1[k] = v[k];
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j) s_r1[j] = v[j];
+            }
+        }
+        wave_sync();
+        const cplx a = s_r0[k], be = s_r0[k + 1], ga = s_r1[k], d = s_r1[k + 1];
+        const cplx det = cfms(be, ga, cmul(a, d));
+        const cplx rdet = crecip_nr(det);
+        const cplx dd = cmul(d, rdet), aa = cmul(a, rdet), bb = cmul(be, rdet), gg = cmul(ga, rdet);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r > k + 1 && r <= N) {
+                const cplx u = csub(wick_entry(pr, r, k, b), crow[m][k]);
+                const cplx z = csub(wick_entry(pr, r, k + 1, bq), crow[m][k + 1]);
+                const cplx Ui = cfms(z, gg, cmul(u, dd));
+                const cplx Vi = cfms(u, bb, cmul(z, aa));
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j)
+                    crow[m][j] = cfma(Vi, s_r1[j], cfma(Ui, s_r0[j], crow[m][j]));
+            }
+        }
+        prod = cmul(prod, det);
+        wave_sync();
+    }
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+        const int r = sub + m * G;
+        if (r >= OFF && r <= N) {
+#pragma unroll
+            for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[m][j];
+        }
+    }
+    wave_sync();
+    return prod;
+}
+
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
-template <int N>
+template <int N, bool PAIR = false>
 __device__ void keldysh_points(int cnt, const Env &env, char *lds)
 {
-    using Gm = Geo<N>;
-    using L = Lds<N>;
+    using Gm = Geo<N, PAIR>;
+    using L = Lds<N, PAIR>;
     const double *s_times = reinterpret_cast<const double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
     pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
@@ -248,16 +329,19 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         }
         cplx prod = cmk(1.0, 0.0);
         int sgn = 0;
-        BlockSrc<N> src;
+        BlockSrc<N, PAIR> src;
         src.c = nullptr;
         if constexpr (Gm::OFF > 0) {
-            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * (N + 1);
+            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
-            prod = top_block<N>(prg, top, sub, env.g0, s_row, s_c0);
+            if constexpr (PAIR) prod = top_block_pair<N>(prg, top, sub, env.g0, s_row, s_c0);
+            else prod = top_block<N>(prg, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;
         }
-        cplx s = lane_sum<N>(prg, src, sub, prod, sgn, env.g0);
+        cplx s;
+        if constexpr (PAIR) s = lane_sum_pair<N>(prg, src, sub, prod, sgn, env.g0);
+        else s = lane_sum<N>(prg, src, sub, prod, sgn, env.g0);
         /* sum over the lanes of a group, then over the groups of the round
          * that share a point: they are SPAN aligned consecutive lanes, all
          * active or all idle (points hold IPP consecutive items and rounds
@@ -299,10 +383,10 @@ __device__ __forceinline__ double model_inverse(const double *__restrict__ c, in
  * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
  * learning pass): also writes Re fbar of every lattice index of the tile to
  * it.sample_out. */
-template <int N, bool MODEL, bool SAMPLE = false>
+template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
-    using L = Lds<N>;
+    using L = Lds<N, PAIR>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     double *s_w = reinterpret_cast<double *>(lds + L::w);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
@@ -317,7 +401,8 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     for (int j = 0; j < N; ++j) shift[j] = sh[j];
     Env env;
     env.tab = it.tab; env.t_half = it.t_half; env.inv_h = 1.0 / it.h; env.t_meas = it.t_meas;
-    env.g0 = cmk(it.g0x, it.g0y); env.n_grid = it.n_grid;
+    env.g0 = cmk(it.g0x, it.g0y); env.gm = cmk(it.g0x, it.g0y + it.alpha);
+    env.n_grid = it.n_grid;
     Kahan acc;
     for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
         const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
@@ -359,7 +444,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             it.sample_out[idx] = 0.0;
         }
         wave_sync();
-        keldysh_points<N>(cnt, env, lds);
+        keldysh_points<N, PAIR>(cnt, env, lds);
         if (lane < cnt) {
             const cplx f = charge_prefactor<N>(s_S[lane]);
             const double w = s_w[lane];
@@ -371,12 +456,12 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     return wave_sum(acc.value());
 }
 
-template <int N, bool MODEL>
-__global__ void __launch_bounds__(64, Geo<N>::WPS) order_kernel(ItemDesc it)
+template <int N, bool MODEL, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
-        const cplx v = order_tile<N, MODEL>(it, tile, lds);
+        const cplx v = order_tile<N, MODEL, false, PAIR>(it, tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * tile] = v.x;
             it.tile_sums[2 * tile + 1] = v.y;
@@ -387,12 +472,12 @@ __global__ void __launch_bounds__(64, Geo<N>::WPS) order_kernel(ItemDesc it)
 /* Learning pass of the learned second warp (App. I): Re fbar of every
  * lattice index of the item's tiles into it.sample_out (exponential warp
  * only, charge mode). */
-template <int N>
-__global__ void __launch_bounds__(64, Geo<N>::WPS) sample_kernel(ItemDesc it)
+template <int N, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x)
-        (void)order_tile<N, false, true>(it, tile, lds);
+        (void)order_tile<N, false, true, PAIR>(it, tile, lds);
 }
 
 /* Per-shift sums of the tile partials, fixed order: thread j adds tiles
@@ -429,12 +514,12 @@ __global__ void __launch_bounds__(256) shift_reduce_kernel(const ItemDesc *items
 }
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
-template <int N>
-__global__ void __launch_bounds__(64, Geo<N>::WPS) points_tree_kernel(Env env, const double *u,
-                                                        int64_t n_points, double *f)
+template <int N, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(Env env, const double *u,
+                                                              int64_t n_points, double *f)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    using L = Lds<N>;
+    using L = Lds<N, PAIR>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
     const int lane = threadIdx.x;
@@ -461,7 +546,7 @@ __global__ void __launch_bounds__(64, Geo<N>::WPS) points_tree_kernel(Env env, c
             s_S[rk] = cmk(0.0, 0.0);
         }
         wave_sync();
-        keldysh_points<N>(cnt, env, lds);
+        keldysh_points<N, PAIR>(cnt, env, lds);
         if (row < n_points) {
             cplx v = cmk(__builtin_nan(""), __builtin_nan(""));
             if (ok) v = charge_prefactor<N>(s_S[rk]);
@@ -533,7 +618,7 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
                 for (int c = 0; c < NP1; ++c) {
                     cplx v;
                     if (r == c) {
-                        v = env.g0;
+                        v = r == 0 ? env.gm : env.g0;
                     } else {
                         const int al = r == 0 ? 0 : (a >> (r - 1)) & 1;
                         const int be = c == 0 ? 1 : (a >> (c - 1)) & 1;
@@ -584,18 +669,18 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
  * (A work queue fed by a lane-0 atomic was tried first: the compiler
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
-template <int N>
-__global__ void __launch_bounds__(64, Geo<N>::WPS) batch_kernel(const ItemDesc *__restrict__ items,
-                                                      const TileRef *__restrict__ tiles,
-                                                      int64_t n_tiles)
+template <int N, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
+                                                            const TileRef *__restrict__ tiles,
+                                                            int64_t n_tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
         /* by value: the descriptor lives in registers for the whole tile */
         const ItemDesc it = items[ref.item];
-        const cplx v = it.model_cdf ? order_tile<N, true>(it, ref.tile, lds)
-                                    : order_tile<N, false>(it, ref.tile, lds);
+        const cplx v = it.model_cdf ? order_tile<N, true, false, PAIR>(it, ref.tile, lds)
+                                    : order_tile<N, false, false, PAIR>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;
             it.tile_sums[2 * ref.tile + 1] = v.y;
@@ -676,40 +761,55 @@ hipError_t dispatch(int order, A... args)
     }
 }
 
+/* An item with alpha != 0 runs the paired tree (its vertex diagonal may
+ * vanish); alpha = 0 keeps the scalar tree. */
 template <int N> struct OrderLaunch {
-    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    template <bool PAIR> static hipError_t go(const ItemDesc &it, hipStream_t s)
     {
         const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
         if (it.model_cdf)
-            hipLaunchKernelGGL((order_kernel<N, true>), dim3((unsigned)blocks), dim3(64),
-                               Lds<N>::bytes, s, it);
+            hipLaunchKernelGGL((order_kernel<N, true, PAIR>), dim3((unsigned)blocks), dim3(64),
+                               (Lds<N, PAIR>::bytes), s, it);
         else
-            hipLaunchKernelGGL((order_kernel<N, false>), dim3((unsigned)blocks), dim3(64),
-                               Lds<N>::bytes, s, it);
+            hipLaunchKernelGGL((order_kernel<N, false, PAIR>), dim3((unsigned)blocks), dim3(64),
+                               (Lds<N, PAIR>::bytes), s, it);
         return hipGetLastError();
+    }
+    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    {
+        return it.alpha != 0.0 ? go<true>(it, s) : go<false>(it, s);
     }
 };
 
 template <int N> struct SampleLaunch {
-    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    template <bool PAIR> static hipError_t go(const ItemDesc &it, hipStream_t s)
     {
         const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-        hipLaunchKernelGGL(sample_kernel<N>, dim3((unsigned)blocks), dim3(64),
-                           Lds<N>::bytes, s, it);
+        hipLaunchKernelGGL((sample_kernel<N, PAIR>), dim3((unsigned)blocks), dim3(64),
+                           (Lds<N, PAIR>::bytes), s, it);
         return hipGetLastError();
+    }
+    static hipError_t run(const ItemDesc &it, hipStream_t s)
+    {
+        return it.alpha != 0.0 ? go<true>(it, s) : go<false>(it, s);
     }
 };
 
 template <int N> struct TreePointsLaunch {
-    static hipError_t run(Env env, const double *u, int64_t n_points, double *f,
-                          hipStream_t s)
+    template <bool PAIR>
+    static hipError_t go(Env env, const double *u, int64_t n_points, double *f, hipStream_t s)
     {
         int64_t blocks = (n_points + WAVE - 1) / WAVE;
         if (blocks > 65536) blocks = 65536;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(points_tree_kernel<N>, dim3((unsigned)blocks), dim3(64),
-                           Lds<N>::bytes, s, env, u, n_points, f);
+        hipLaunchKernelGGL((points_tree_kernel<N, PAIR>), dim3((unsigned)blocks), dim3(64),
+                           (Lds<N, PAIR>::bytes), s, env, u, n_points, f);
         return hipGetLastError();
+    }
+    static hipError_t run(Env env, bool pair, const double *u, int64_t n_points, double *f,
+                          hipStream_t s)
+    {
+        return pair ? go<true>(env, u, n_points, f, s) : go<false>(env, u, n_points, f, s);
     }
 };
 
@@ -725,12 +825,13 @@ template <int N> struct DirectPointsLaunch {
     }
 };
 
-Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double g0y,
-             double t_meas)
+Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double n_sigma,
+             double alpha, double t_meas)
 {
     Env e;
     e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.inv_h = 1.0 / h; e.t_meas = t_meas;
-    e.g0 = cmk(0.0, g0y);
+    e.g0 = cmk(0.0, n_sigma - alpha);
+    e.gm = cmk(0.0, n_sigma);
     return e;
 }
 
@@ -765,58 +866,72 @@ hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
 }
 
 hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half, double h,
-                              double g0y, int32_t order, double t_meas, const double *u,
-                              int64_t n_points, double *f, hipStream_t s)
+                              double n_sigma, double alpha, int32_t order, double t_meas,
+                              const double *u, int64_t n_points, double *f, hipStream_t s)
 {
     if (n_points <= 0) return hipSuccess;
-    return dispatch<TreePointsLaunch>(order, make_env(tab, n_grid, t_half, h, g0y, t_meas),
-                                      u, n_points, f, s);
+    return dispatch<TreePointsLaunch>(order,
+                                      make_env(tab, n_grid, t_half, h, n_sigma, alpha, t_meas),
+                                      alpha != 0.0, u, n_points, f, s);
 }
 
 hipError_t launch_points_direct(const double *tab, int32_t n_grid, double t_half,
-                                double h, double g0y, int32_t order, double t_meas,
-                                const double *u, int64_t n_points, double *f,
+                                double h, double n_sigma, double alpha, int32_t order,
+                                double t_meas, const double *u, int64_t n_points, double *f,
                                 hipStream_t s)
 {
     if (n_points <= 0) return hipSuccess;
-    return dispatch<DirectPointsLaunch>(order, make_env(tab, n_grid, t_half, h, g0y, t_meas),
+    return dispatch<DirectPointsLaunch>(order,
+                                        make_env(tab, n_grid, t_half, h, n_sigma, alpha, t_meas),
                                         u, n_points, f, s);
 }
 
 namespace {
 template <int N> struct BatchLaunch {
-    static hipError_t run(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
-                          int32_t grid_blocks, hipStream_t s)
+    template <bool PAIR>
+    static hipError_t go(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
+                         int32_t grid_blocks, hipStream_t s)
     {
         const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
-        hipLaunchKernelGGL(batch_kernel<N>, dim3((unsigned)g), dim3(64), Lds<N>::bytes, s,
-                           items_dev, tiles_dev, n_tiles);
+        hipLaunchKernelGGL((batch_kernel<N, PAIR>), dim3((unsigned)g), dim3(64),
+                           (Lds<N, PAIR>::bytes), s, items_dev, tiles_dev, n_tiles);
         return hipGetLastError();
+    }
+    static hipError_t run(bool pair, const ItemDesc *items_dev, const TileRef *tiles_dev,
+                          int64_t n_tiles, int32_t grid_blocks, hipStream_t s)
+    {
+        return pair ? go<true>(items_dev, tiles_dev, n_tiles, grid_blocks, s)
+                    : go<false>(items_dev, tiles_dev, n_tiles, grid_blocks, s);
     }
 };
 template <int N> struct BatchOcc {
-    static hipError_t run(int32_t *out)
+    template <bool PAIR> static int32_t go()
     {
         int blocks = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<N>, 64,
-                                                                    (size_t)Lds<N>::bytes);
-        *out = (e == hipSuccess && blocks > 0) ? blocks : 1;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &blocks, batch_kernel<N, PAIR>, 64, (size_t)Lds<N, PAIR>::bytes);
+        return (e == hipSuccess && blocks > 0) ? blocks : 1;
+    }
+    static hipError_t run(bool pair, int32_t *out)
+    {
+        *out = pair ? go<true>() : go<false>();
         return hipSuccess;
     }
 };
 } // namespace
 
-hipError_t launch_batch(int32_t order, const ItemDesc *items_dev, const TileRef *tiles_dev,
+hipError_t launch_batch(int32_t key, const ItemDesc *items_dev, const TileRef *tiles_dev,
                         int64_t n_tiles, int32_t grid_blocks, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    return dispatch<BatchLaunch>(order, items_dev, tiles_dev, n_tiles, grid_blocks, s);
+    return dispatch<BatchLaunch>(key_order(key), key_pair(key), items_dev, tiles_dev, n_tiles,
+                                 grid_blocks, s);
 }
 
-int32_t batch_blocks_per_cu(int32_t order)
+int32_t batch_blocks_per_cu(int32_t key)
 {
     int32_t b = 1;
-    if (dispatch<BatchOcc>(order, &b) != hipSuccess) return 1;
+    if (dispatch<BatchOcc>(key_order(key), key_pair(key), &b) != hipSuccess) return 1;
     return b;
 }
 

@@ -91,6 +91,7 @@ qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p, void *st
     o.t_meas = p->t_meas;
     o.mode = QQMC_MODE_CHARGE;
     o.model = nullptr;
+    o.alpha = p->alpha;
     Validated v;
     if (qqmc_status st = validate_order(&o, t->n_grid, t->t_half, &v)) return st;
     ItemDesc &d = v.desc;

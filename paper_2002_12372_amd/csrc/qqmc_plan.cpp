@@ -5,9 +5,10 @@
  * Every item is cut into the same tiles qqmc_eval_order_async uses for the
  * same tile length, so each tile sum, and therefore each per-shift sum, is
  * bitwise the one the single-order launch produces.  Tiles are grouped by
- * order; inside a group they are sorted by decreasing cost (cost model
- * below) and dealt round robin to the resident workgroups of one persistent
- * launch of that order's kernel (workgroup b takes entries b, b + G, ...).
+ * kernel (order, and scalar or paired elimination tree); inside a group they
+ * are sorted by decreasing cost (cost model below) and dealt round robin to
+ * the resident workgroups of one persistent launch of that kernel
+ * (workgroup b takes entries b, b + G, ...).
  * The groups run as concurrent branches of the graph (at most four branch
  * streams, groups assigned greedily to the least loaded branch, most
  * expensive first), joined before the per-shift reduction.  This balances
@@ -66,7 +67,7 @@ struct Buffers {
 };
 
 struct Group {
-    int32_t order = 0, branch = 0, grid = 0;
+    int32_t key = 0, branch = 0, grid = 0; /* kernel key: order, paired tree */
     int64_t offset = 0, count = 0;
     double cost = 0.0;
 };
@@ -127,21 +128,21 @@ struct qqmc_plan_s {
 namespace qqmc {
 namespace {
 
-/* Groups of a tile list by order, sorted within a group by decreasing
+/* Groups of a tile list by kernel key, sorted within a group by decreasing
  * cost, groups assigned to branches (longest processing time first). */
 void make_groups(qqmc_plan_s *p, const std::vector<std::pair<double, TileRef>> &all,
                  std::vector<TileRef> &tiles, std::vector<Group> &groups)
 {
-    std::vector<std::vector<std::pair<double, TileRef>>> by(QQMC_MAX_ORDER + 1);
-    for (auto &c : all) by[p->items[c.second.item].order].push_back(c);
+    std::vector<std::vector<std::pair<double, TileRef>>> by(kMaxKernelKey + 1);
+    for (auto &c : all) by[kernel_key(p->items[c.second.item])].push_back(c);
     tiles.clear();
     groups.clear();
-    for (int n = 1; n <= QQMC_MAX_ORDER; ++n) {
+    for (int n = 1; n <= kMaxKernelKey; ++n) {
         auto &v = by[n];
         if (v.empty()) continue;
         std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
         Group g;
-        g.order = n;
+        g.key = n;
         g.offset = (int64_t)tiles.size();
         g.count = (int64_t)v.size();
         for (auto &c : v) {
@@ -241,9 +242,9 @@ hipError_t enqueue(qqmc_plan_s *p, const std::vector<Group> &groups, const TileR
          * walking a strided share of the tiles; share 0: one workgroup per
          * tile, handed out by the hardware dispatcher */
         const int32_t grid =
-            share > 0.0 ? (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.order))
+            share > 0.0 ? (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.key))
                         : (int32_t)std::min<int64_t>(g.count, INT32_MAX);
-        if (e == hipSuccess) e = launch_batch(g.order, p->buf.items, d_tiles + g.offset, g.count, grid, b);
+        if (e == hipSuccess) e = launch_batch(g.key, p->buf.items, d_tiles + g.offset, g.count, grid, b);
     }
     for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
         if (!used[b]) continue;

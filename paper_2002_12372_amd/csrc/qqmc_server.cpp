@@ -9,9 +9,10 @@
  *               are built on the device by a kernel, per-request buffers
  *               come from the stream-ordered allocator, all on an admission
  *               stream, so admission never waits for the GPU;
- *   batching    every launch is one persistent kernel of one order; the
- *               order rotates over the orders with pending work, and the
- *               admitted requests of that order take tiles in turn (round
+ *   batching    every launch is one persistent kernel of one order (and
+ *               elimination tree: scalar, or paired for alpha != 0); it
+ *               rotates over the kernels with pending work, and the
+ *               admitted requests of that kernel take tiles in turn (round
  *               robin, up to a per-launch cost budget), so requests that
  *               arrive while others run share the next launches;
  *   overlap     three launches are in flight on three streams, so the tail of
@@ -124,7 +125,7 @@ struct qqmc_server_s {
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1, use_clock = 0, next_seq = 1;
-    int last_order = 0;
+    int last_key = 0;
     std::deque<std::shared_ptr<qqmc::Request>> waiting;
     std::vector<std::shared_ptr<qqmc::Request>> active;
     std::map<uint64_t, std::shared_ptr<qqmc::Request>> all;
@@ -230,28 +231,29 @@ void admit(qqmc_server_s *s)
  * held).  Returns false if there was nothing to issue. */
 bool issue(qqmc_server_s *s, Launch &L)
 {
-    /* one order per launch, rotating over the orders with pending tiles, so
-     * every launch is one full persistent kernel; inside the order, requests
-     * in admission order take one tile each per pass up to the cost budget */
-    bool pending[QQMC_MAX_ORDER + 1] = {};
+    /* one kernel key (order, paired tree) per launch, rotating over the keys
+     * with pending tiles, so every launch is one full persistent kernel;
+     * inside the key, requests in admission order take one tile each per
+     * pass up to the cost budget */
+    bool pending[kMaxKernelKey + 1] = {};
     for (auto &r : s->active)
-        if (r->next_tile < r->desc.n_tiles) pending[r->desc.order] = true;
-    int order = 0;
-    for (int k = 1; k <= QQMC_MAX_ORDER && !order; ++k) {
-        const int n = (s->last_order + k - 1) % QQMC_MAX_ORDER + 1;
-        if (pending[n]) order = n;
+        if (r->next_tile < r->desc.n_tiles) pending[kernel_key(r->desc)] = true;
+    int key = 0;
+    for (int k = 1; k <= kMaxKernelKey && !key; ++k) {
+        const int n = (s->last_key + k - 1) % kMaxKernelKey + 1;
+        if (pending[n]) key = n;
     }
-    if (!order) return false;
-    s->last_order = order;
+    if (!key) return false;
+    s->last_key = key;
     std::vector<std::shared_ptr<Request>> open;
     for (auto &r : s->active)
-        if (r->desc.order == order && r->next_tile < r->desc.n_tiles) open.push_back(r);
+        if (kernel_key(r->desc) == key && r->next_tile < r->desc.n_tiles) open.push_back(r);
     std::vector<double> cost(open.size());
     std::vector<int64_t> take(open.size(), 0);
     for (size_t i = 0; i < open.size(); ++i) cost[i] = tile_cost(open[i]->desc);
     /* at least eight tiles per resident workgroup, so the launch fills the
      * GPU and its last round of tiles is short */
-    const int64_t min_tiles = 8 * (int64_t)s->n_cu * batch_blocks_per_cu(order);
+    const int64_t min_tiles = 8 * (int64_t)s->n_cu * batch_blocks_per_cu(key);
     double spent = 0.0;
     int64_t taken = 0;
     bool progress = true;
@@ -267,7 +269,7 @@ bool issue(qqmc_server_s *s, Launch &L)
         }
     }
     std::vector<ItemDesc> items;
-    std::vector<std::vector<TileRef>> by(QQMC_MAX_ORDER + 1);
+    std::vector<std::vector<TileRef>> by(kMaxKernelKey + 1);
     L.issued.clear();
     for (size_t i = 0; i < open.size(); ++i) {
         if (!take[i]) continue;
@@ -278,18 +280,18 @@ bool issue(qqmc_server_s *s, Launch &L)
             t.item = idx;
             t.pad = 0;
             t.tile = open[i]->next_tile + k;
-            by[open[i]->desc.order].push_back(t);
+            by[kernel_key(open[i]->desc)].push_back(t);
         }
         open[i]->next_tile += take[i];
         L.issued.push_back({open[i], take[i]});
     }
     std::vector<TileRef> tiles;
     struct G {
-        int32_t order;
+        int32_t key;
         int64_t off, cnt;
     };
     std::vector<G> groups;
-    for (int n = QQMC_MAX_ORDER; n >= 1; --n) {
+    for (int n = kMaxKernelKey; n >= 1; --n) {
         if (by[n].empty()) continue;
         groups.push_back({n, (int64_t)tiles.size(), (int64_t)by[n].size()});
         tiles.insert(tiles.end(), by[n].begin(), by[n].end());
@@ -312,7 +314,7 @@ bool issue(qqmc_server_s *s, Launch &L)
      * than a fixed persistent grid */
     for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
         const int32_t grid = (int32_t)std::min<int64_t>(groups[g].cnt, INT32_MAX);
-        e = launch_batch(groups[g].order, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
+        e = launch_batch(groups[g].key, L.d_items, L.d_tiles + groups[g].off, groups[g].cnt, grid,
                          L.stream);
     }
     if (e == hipSuccess) e = hipEventRecord(L.done, L.stream);

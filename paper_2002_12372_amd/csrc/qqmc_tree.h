@@ -115,19 +115,29 @@ struct pairv {
 /* index of the pair (i, j), i < j, in the triangular pair table */
 QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
 
-template <int N> struct Geo {
-    static constexpr int K = (N < 8 ? N : 8) + 1;      /* block size          */
-    static constexpr int OFF = N + 1 - K;              /* cooperative levels  */
+/* Work split of one item.  PAIR selects the paired tree (vertices
+ * eliminated two at a time with 2x2 block pivots, for vertex diagonals that
+ * may vanish): its cooperative levels and per-lane path cover whole pairs. */
+template <int N, bool PAIR = false> struct Geo {
+    /* cooperative levels: n - 8, rounded up to even for the paired tree */
+    static constexpr int OFF = N > 8 ? (PAIR ? ((N - 7) & ~1) : N - 8) : 0;
+    static constexpr int K = N + 1 - OFF;              /* block size          */
     static constexpr int B = 5;                        /* register-tree depth */
-    static constexpr int T = (K - 1 > B) ? K - 1 - B : 0; /* per-lane path    */
+    /* per-lane path: scalar tree, down to a 6 x 6 block; paired tree, whole
+     * pairs down to a block of at most 5 x 5 (a pair node keeps its parent
+     * block live under its four children) */
+    static constexpr int T = PAIR ? (K > 5 ? 2 * ((K - 4) / 2) : 0)
+                                  : ((K - 1 > B) ? K - 1 - B : 0);
     static constexpr int G = 1 << T;                   /* lanes per item      */
     static constexpr int PPW = 64 / G;                 /* items per wave      */
     static constexpr int IPP = 1 << OFF;               /* items per point     */
     static constexpr int NP = N * (N + 1) / 2;         /* pair-table length   */
     /* waves per SIMD the kernels are compiled for: a depth-5 register tree
      * starts from a 6 x 6 block and needs the whole register file of one
-     * wave (architectural plus accumulation registers, no scratch) */
-    static constexpr int WPS = (K - T > 5) ? 1 : 2;
+     * wave (architectural plus accumulation registers, no scratch); the
+     * paired tree's per-lane path keeps four vectors per pair step, so it
+     * takes the whole register file too */
+    static constexpr int WPS = (PAIR || K - T > 5) ? 1 : 2;
 };
 
 template <int M> struct Blk {
@@ -150,6 +160,46 @@ QQMC_HD LeafK leaf_constants(const pairv &P)
     return k;
 }
 
+/* Closed form of the last two levels (latest vertex and the measurement)
+ * for a trailing block with corrections C: the two leaves differ only in the
+ * last pivot g0 - C11 - col_b row_b / p, so
+ *   sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0),
+ * the bracket expanded with the point's leaf constants. */
+QQMC_HD cplx leaf_value(const Blk<2> &C, cplx g0, const LeafK &lk)
+{
+    const cplx p = csub(g0, C.v[0][0]);
+    return cmul(p, cfmac(lk.s, C.v[1][0], cfma(lk.s, C.v[0][1], lk.a)));
+}
+
+/* Closed form of the last three levels: vertices u (global index v0), w (the
+ * last one) and the measurement m (global index n), by cofactors instead of
+ * elimination (no reciprocal): with S the 3x3 trailing matrix for index b of
+ * u,
+ *   sum_{b_w} (-1)^{b_w} det S = S_uu d + S_uw S_mu conj(s) + S_um S_wu s
+ * (the S_mm terms cancel, d as in the leaf with this node's C12, C21),
+ * multiplied by the 2x2 vertex determinant S_uu S_ww - S_uw S_wu. */
+QQMC_HD cplx node3_value(const Blk<3> &C, const pairv *pr, int v0, int n, cplx g0,
+                         const LeafK &lk)
+{
+    const cplx p = csub(g0, C.v[0][0]);
+    const pairv Pw = pr[pidx(v0, v0 + 1)];
+    const pairv Pm = pr[pidx(v0, n)];
+    const cplx sww = csub(g0, C.v[1][1]);
+    const cplx spp = cmul(p, sww);
+    const cplx sd = cmul(p, cfmac(lk.s, C.v[2][1], cfma(lk.s, C.v[1][2], lk.a)));
+    cplx t[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const cplx suw = csub(cnc(b ? Pw.gg : Pw.gl), C.v[0][1]);
+        const cplx swu = csub(b ? Pw.gl : Pw.gg, C.v[1][0]);
+        const cplx sum_ = csub(cnc(b ? Pm.gg : Pm.gl), C.v[0][2]);
+        const cplx smu = csub(b ? Pm.gl : Pm.gg, C.v[2][0]);
+        const cplx delta = cfma(cmul(sum_, swu), lk.s, cfmac(lk.s, cmul(suw, smu), sd));
+        t[b] = cmul(cfms(suw, swu, spp), delta);
+    }
+    return csub(t[0], t[1]);
+}
+
 /* Depth-first walk below block level L (block indices L..K-1 remain).  C is
  * the accumulated Schur correction of the trailing block, so the current
  * trailing matrix is (Wick entries) - C.  Returns the signed sum over the
@@ -164,38 +214,13 @@ template <int N, int L>
 QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, const LeafK &lk)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
-    const cplx p = csub(g0, C.v[0][0]);
     if constexpr (M == 2) {
-        /* latest vertex and the measurement: the two leaves differ only in
-         * the last pivot g0 - C11 - col_b row_b / p, so
-         * sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0),
-         * the bracket expanded with the point's leaf constants */
         (void)pr;
-        return cmul(p, cfmac(lk.s, C.v[1][0], cfma(lk.s, C.v[0][1], lk.a)));
+        return leaf_value(C, g0, lk);
     } else if constexpr (M == 3) {
-        /* vertices u (this level), w (the last one) and the measurement m,
-         * by cofactors instead of elimination (no reciprocal): with S the
-         * 3x3 trailing matrix for index b of u,
-         *   sum_{b_w} (-1)^{b_w} det S = S_uu d + S_uw S_mu conj(s) + S_um S_wu s
-         * (the S_mm terms cancel, d as in the leaf with this node's C12, C21),
-         * multiplied by the 2x2 vertex determinant S_uu S_ww - S_uw S_wu. */
-        const pairv Pw = pr[pidx(OFF + L, OFF + L + 1)];
-        const pairv Pm = pr[pidx(OFF + L, N)];
-        const cplx sww = csub(g0, C.v[1][1]);
-        const cplx spp = cmul(p, sww);
-        const cplx sd = cmul(p, cfmac(lk.s, C.v[2][1], cfma(lk.s, C.v[1][2], lk.a)));
-        cplx t[2];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const cplx suw = csub(cnc(b ? Pw.gg : Pw.gl), C.v[0][1]);
-            const cplx swu = csub(b ? Pw.gl : Pw.gg, C.v[1][0]);
-            const cplx sum_ = csub(cnc(b ? Pm.gg : Pm.gl), C.v[0][2]);
-            const cplx smu = csub(b ? Pm.gl : Pm.gg, C.v[2][0]);
-            const cplx delta = cfma(cmul(sum_, swu), lk.s, cfmac(lk.s, cmul(suw, smu), sd));
-            t[b] = cmul(cfms(suw, swu, spp), delta);
-        }
-        return csub(t[0], t[1]);
+        return node3_value(C, pr, OFF + L, N, g0, lk);
     } else {
+        const cplx p = csub(g0, C.v[0][0]);
         const cplx r = crecip_nr(p);
         Blk<M - 1> D0, D1;
         {
@@ -228,15 +253,15 @@ QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, cons
 
 /* Block correction accessor: zero when the lanes start from the full matrix
  * (n <= 8), otherwise the cooperative block in local memory. */
-template <int N> struct BlockSrc {
+template <int N, bool PAIR = false> struct BlockSrc {
     const cplx *c; /* K*K row-major, or unused */
     QQMC_HD cplx at(int i, int j) const
     {
-        if constexpr (Geo<N>::OFF == 0) {
+        if constexpr (Geo<N, PAIR>::OFF == 0) {
             (void)i; (void)j;
             return cmk(0.0, 0.0);
         } else {
-            return c[i * Geo<N>::K + j];
+            return c[i * Geo<N, PAIR>::K + j];
         }
     }
 };
@@ -298,6 +323,155 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                 C.v[i - T][j - T] = c;
             }
         v = subtree<N, T>(C, pr, g0, lk);
+    }
+    v = cmul(cmul(prod, prod), v);
+    return sgn ? cmk(-v.x, -v.y) : v;
+}
+
+/* Paired tree: a node at block level L eliminates the vertices v = OFF + L
+ * and w = v + 1 together.  With the trailing matrix T = (Wick entries) - C,
+ * the 2x2 pivot block P_b = [[T_vv, T_vw], [T_wv, T_ww]] depends only on the
+ * index b of v (the earlier point of the pair), the rows and columns of v on
+ * b and those of w on the index b' of w; with u, x the column and row of v
+ * and y, z those of w, the child (b, b') carries
+ *     C' = C + U x + V y,  [U V] = [u z] P_b^{-1},
+ * and the node's value relative to itself is
+ *     V(node) = det(P_0)^2 (V_00 - V_01) - det(P_1)^2 (V_10 - V_11).
+ * No scalar pivot of a single vertex is inverted: a zero vertex diagonal
+ * (alpha = n_sigma) and the skew-symmetric blocks of the particle-hole
+ * symmetric point are handled exactly.  The last one or two vertices end in
+ * the closed forms above, which invert nothing either. */
+template <int N, int L>
+QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx g0,
+                       const LeafK &lk)
+{
+    constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, M = K - L;
+    if constexpr (M == 2) {
+        (void)pr;
+        return leaf_value(C, g0, lk);
+    } else if constexpr (M == 3) {
+        return node3_value(C, pr, OFF + L, N, g0, lk);
+    } else {
+        constexpr int V0 = OFF + L;
+        const cplx a = csub(g0, C.v[0][0]), d = csub(g0, C.v[1][1]);
+        const cplx *Pvw = &pr[pidx(V0, V0 + 1)].gl;
+        cplx res = cmk(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            /* the table half is picked by address: index 1 takes column g^<
+             * and row -conj(g^>), index 0 the other halves */
+            const cplx be = csub(cnc(Pvw[b]), C.v[0][1]);
+            const cplx ga = csub(Pvw[b ^ 1], C.v[1][0]);
+            const cplx det = cfms(be, ga, cmul(a, d));
+            const cplx r = crecip_nr(det);
+            const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
+            cplx x[M - 2], u[M - 2];
+#pragma unroll
+            for (int j = 2; j < M; ++j) {
+                const cplx *P = &pr[pidx(V0, V0 + j)].gl;
+                x[j - 2] = csub(cnc(P[b]), C.v[0][j]);
+                u[j - 2] = csub(P[b ^ 1], C.v[j][0]);
+            }
+            cplx sub = cmk(0.0, 0.0);
+#pragma unroll
+            for (int bq = 0; bq < 2; ++bq) {
+                cplx y[M - 2], z[M - 2];
+#pragma unroll
+                for (int j = 2; j < M; ++j) {
+                    const cplx *Q = &pr[pidx(V0 + 1, V0 + j)].gl;
+                    y[j - 2] = csub(cnc(Q[bq]), C.v[1][j]);
+                    z[j - 2] = csub(Q[bq ^ 1], C.v[j][1]);
+                }
+                Blk<M - 2> D;
+#pragma unroll
+                for (int i = 2; i < M; ++i) {
+                    const cplx Ui = cfms(z[i - 2], gg, cmul(u[i - 2], dd));
+                    const cplx Vi = cfms(u[i - 2], bb, cmul(z[i - 2], aa));
+#pragma unroll
+                    for (int j = 2; j < M; ++j)
+                        D.v[i - 2][j - 2] = cfma(Vi, y[j - 2], cfma(Ui, x[j - 2], C.v[i][j]));
+                }
+                const cplx w = pair_walk<N, L + 2>(D, pr, g0, lk);
+                sub = bq ? csub(sub, w) : cadd(sub, w);
+            }
+            const cplx t = cmul(cmul(det, det), sub);
+            res = b ? csub(res, t) : cadd(res, t);
+        }
+        return res;
+    }
+}
+
+/* One lane's share of an item in the paired tree: the T prefix levels are
+ * T/2 pair steps for the lane's index bits (left-looking: each step keeps
+ * its U, V columns and x, y rows), then the pair walk. */
+template <int N>
+QQMC_HD cplx lane_sum_pair(const pairv *pr, BlockSrc<N, true> C0, int pre, cplx prod,
+                           int sgn, cplx g0)
+{
+    constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, T = Geo<N, true>::T;
+    const LeafK lk = leaf_constants(pr[pidx(N - 1, N)]);
+    cplx v;
+    if constexpr (T == 0) {
+        (void)pre;
+        Blk<K> C;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
+        v = pair_walk<N, 0>(C, pr, g0, lk);
+    } else {
+        constexpr int TP = T / 2;
+        cplx Uc[TP][K], Vc[TP][K], xr[TP][K], yr[TP][K];
+#pragma unroll
+        for (int s = 0; s < TP; ++s) {
+            const int k = 2 * s;
+            const int b = (pre >> (T - 1 - k)) & 1, bq = (pre >> (T - 2 - k)) & 1;
+            sgn ^= b ^ bq;
+            const cplx *Pvw = &pr[pidx(OFF + k, OFF + k + 1)].gl;
+            cplx a = csub(g0, C0.at(k, k)), d = csub(g0, C0.at(k + 1, k + 1));
+            cplx be = csub(cnc(Pvw[b]), C0.at(k, k + 1));
+            cplx ga = csub(Pvw[b ^ 1], C0.at(k + 1, k));
+#pragma unroll
+            for (int l = 0; l < s; ++l) {
+                a = cfms(Vc[l][k], yr[l][k], cfms(Uc[l][k], xr[l][k], a));
+                d = cfms(Vc[l][k + 1], yr[l][k + 1], cfms(Uc[l][k + 1], xr[l][k + 1], d));
+                be = cfms(Vc[l][k], yr[l][k + 1], cfms(Uc[l][k], xr[l][k + 1], be));
+                ga = cfms(Vc[l][k + 1], yr[l][k], cfms(Uc[l][k + 1], xr[l][k], ga));
+            }
+            const cplx det = cfms(be, ga, cmul(a, d));
+            const cplx r = crecip_nr(det);
+            const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
+#pragma unroll
+            for (int i = k + 2; i < K; ++i) {
+                const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
+                const cplx *Q = &pr[pidx(OFF + k + 1, OFF + i)].gl;
+                cplx x = csub(cnc(P[b]), C0.at(k, i)), u = csub(P[b ^ 1], C0.at(i, k));
+                cplx y = csub(cnc(Q[bq]), C0.at(k + 1, i)), z = csub(Q[bq ^ 1], C0.at(i, k + 1));
+#pragma unroll
+                for (int l = 0; l < s; ++l) {
+                    x = cfms(Vc[l][k], yr[l][i], cfms(Uc[l][k], xr[l][i], x));
+                    u = cfms(Vc[l][i], yr[l][k], cfms(Uc[l][i], xr[l][k], u));
+                    y = cfms(Vc[l][k + 1], yr[l][i], cfms(Uc[l][k + 1], xr[l][i], y));
+                    z = cfms(Vc[l][i], yr[l][k + 1], cfms(Uc[l][i], xr[l][k + 1], z));
+                }
+                xr[s][i] = x;
+                yr[s][i] = y;
+                Uc[s][i] = cfms(z, gg, cmul(u, dd));
+                Vc[s][i] = cfms(u, bb, cmul(z, aa));
+            }
+            prod = cmul(prod, det);
+        }
+        Blk<K - T> C;
+#pragma unroll
+        for (int i = T; i < K; ++i)
+#pragma unroll
+            for (int j = T; j < K; ++j) {
+                cplx c = C0.at(i, j);
+#pragma unroll
+                for (int l = 0; l < TP; ++l) c = cfma(Vc[l][i], yr[l][j], cfma(Uc[l][i], xr[l][j], c));
+                C.v[i - T][j - T] = c;
+            }
+        v = pair_walk<N, T>(C, pr, g0, lk);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;

@@ -40,7 +40,8 @@ class qqmc_order(ctypes.Structure):
                 ("lattice_a", ctypes.c_uint64), ("n_shifts", ctypes.c_int32),
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
-                ("mode", ctypes.c_int32), ("model", ctypes.c_void_p)]
+                ("mode", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("alpha", ctypes.c_double)]
 
 
 class qqmc_learn_params(ctypes.Structure):
@@ -48,7 +49,7 @@ class qqmc_learn_params(ctypes.Structure):
                 ("lattice_a", ctypes.c_uint64), ("shift", ctypes.POINTER(ctypes.c_double)),
                 ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
                 ("n_bins", ctypes.c_int32), ("lam", ctypes.c_double),
-                ("floor_eps", ctypes.c_double)]
+                ("floor_eps", ctypes.c_double), ("alpha", ctypes.c_double)]
 
 
 class qqmc_batch_item(ctypes.Structure):
@@ -71,7 +72,7 @@ SIGNATURES = [
     ("qqmc_free_tables", None, [_vp]),
     ("qqmc_eval_order", _i32, [_vp, _P(qqmc_order), _vp, _PD, _PD, _PD]),
     ("qqmc_eval_order_async", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _vp, _P(_i64)]),
-    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _vp, _i64, _i32, _vp, _vp]),
+    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _vp, _i64, _i32, _vp, _vp]),
     ("qqmc_plan_create", _i32, [_P(qqmc_batch_item), _i32, _i32, _i32, _vp, _P(_vp)]),
     ("qqmc_plan_run", _i32, [_vp, _vp]),
     ("qqmc_plan_results", _i32, [_vp, _vp, _PD]),
@@ -187,7 +188,7 @@ def make_order(job, t_meas, model=None):
     sh = np.ascontiguousarray(job.shifts, dtype=np.float64)
     o = qqmc_order(job.order, job.log2_n, job.lattice_a, sh.shape[0], _pd(sh),
                    job.model_tau, t_meas, job.mode,
-                   model.handle if model is not None else None)
+                   model.handle if model is not None else None, job.alpha)
     o._keep = (sh, model)
     return o
 
@@ -220,10 +221,10 @@ class Model:
 
 
 def learn_model(tables, order, log2_m, lattice_a, shift, model_tau, t_meas, n_bins=100,
-                lam=0.05, floor_eps=1e-3, stream=None):
+                lam=0.05, floor_eps=1e-3, stream=None, alpha=0.0):
     sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64).reshape(order))
     p = qqmc_learn_params(order, log2_m, lattice_a, _pd(sh), model_tau, t_meas, n_bins,
-                          lam, floor_eps)
+                          lam, floor_eps, alpha)
     h = ctypes.c_void_p()
     _check(lib().qqmc_learn_model(tables.handle, ctypes.byref(p), _stream(stream),
                                   ctypes.byref(h)))
@@ -266,12 +267,12 @@ def n_tiles(job, tile_len):
     return job.shifts.shape[0] * ((1 << job.log2_n) // tile_len)
 
 
-def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None):
+def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None, alpha=0.0):
     """u: (P, order) float64 CUDA tensor; f: (P, 2) float64 CUDA tensor."""
     P = u.shape[0]
     assert u.dtype.is_floating_point and u.is_contiguous() and f.is_contiguous()
     assert f.numel() >= 2 * P and u.numel() == P * order
-    _check(lib().qqmc_eval_points(tables.handle, int(order), float(t_meas),
+    _check(lib().qqmc_eval_points(tables.handle, int(order), float(t_meas), float(alpha),
                                   ctypes.c_void_p(u.data_ptr()), P, int(method),
                                   ctypes.c_void_p(f.data_ptr()), _stream(stream)))
 

@@ -75,23 +75,25 @@ class Dot:
 @dataclass
 class OrderJob:
     """One (parameter point, order) integration: N = 2^log2_n lattice points,
-    the lattice multiplier, K random shifts, the model-function tau."""
+    the lattice multiplier, K random shifts, the model-function tau, and the
+    interaction shift alpha (drawn from no random stream)."""
     order: int
     log2_n: int
     lattice_a: int
     shifts: np.ndarray
     model_tau: float = 1.0
     mode: int = 0
+    alpha: float = 0.0
 
 
 def order_job(seed: int, order: int, log2_n: int, n_shifts: int,
-              model_tau: float = 1.0, mode: int = 0) -> OrderJob:
+              model_tau: float = 1.0, mode: int = 0, alpha: float = 0.0) -> OrderJob:
     """Draw the multiplier, then the shifts, from one SplitMix64 stream whose
     seed mixes (seed, order) so that every order has its own stream."""
     rng = SplitMix64((seed * 1000003 + order) & _MASK)
     a = lattice_multiplier(rng, log2_n)
     sh = shifts(rng, n_shifts, order)
-    return OrderJob(order, log2_n, a, sh, model_tau, mode)
+    return OrderJob(order, log2_n, a, sh, model_tau, mode, alpha)
 
 
 # ---------------------------------------------------------------------------

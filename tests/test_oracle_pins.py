@@ -711,3 +711,23 @@ def test_alpha_reexpansion_order3(oracle_mod, alpha_tab, alpha):
     diff = (qa - q0).real
     m, se = diff.mean(), diff.std(ddof=1) / math.sqrt(diff.size)
     assert abs(m - pred) < 5 * se + 1e-6, (m, se, pred)
+
+
+def test_eval_mass_bounds_the_sums(oracle_mod, tiny_tables):
+    """The term mass of an estimate is the sum of 2 W M over the points: it
+    bounds |sum of f W| (each |S| <= M) and agrees with the per-point masses
+    that integrand() returns."""
+    job = order_job(3, 3, 10, 2)
+    sums = oracle_mod.eval_sums(tiny_tables, 10.0, 3, 10, job.lattice_a, job.shifts, 1.0)
+    mass = oracle_mod.eval_mass(tiny_tables, 10.0, 3, 10, job.lattice_a, job.shifts, 1.0)
+    assert np.all(np.abs(sums) <= mass) and np.all(mass > 0)
+    # the same mass point by point over a short index range
+    ref = 0.0
+    for i in range(40):
+        x = oracle_mod.lattice_point(i, 3, 10, job.lattice_a, job.shifts[0])
+        u, W, inside = oracle_mod.warp(x, 1.0, 10.0)
+        if inside:
+            ref += W * oracle_mod.integrand(tiny_tables, 10.0, u)[1]
+    got = oracle_mod.eval_mass(tiny_tables, 10.0, 3, 10, job.lattice_a, job.shifts[:1], 1.0,
+                               0, 40)[0]
+    assert abs(got - ref) <= 1e-12 * ref

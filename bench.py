@@ -100,12 +100,22 @@ def timed_steps(fn, steps, warmup, stream):
 def run_plain(args):
     import torch
     from paper_2002_12372_amd import qqmc
-    from paper_2002_12372_amd.flops import tree_flops, warp_flops
-    from qqmc_inputs import TINY_DOT as d, order_job
+    from paper_2002_12372_amd.flops import pair_tree_flops, tree_flops, warp_flops
+    from qqmc_inputs import Dot, TINY_DOT, order_job
 
     stream = torch.cuda.current_stream()
     n = args.order
-    job = order_job(1, n, args.log2n, args.shifts)
+    alpha = 0.0
+    d = TINY_DOT
+    if args.alpha is not None:
+        # the alpha-shifted interaction away from particle-hole symmetry;
+        # "ns" is the paper's choice alpha = n_sigma (zero vertex diagonal)
+        d = Dot(0.3, 1.0, 20.0, 0.4)
+    tables = qqmc.make_tables(d)
+    if args.alpha is not None:
+        alpha = qqmc.tables_export(tables)[2] if args.alpha == "ns" else float(args.alpha)
+    job = order_job(1, n, args.log2n, args.shifts, alpha=alpha)
+    tflops = pair_tree_flops(n) if alpha != 0.0 else tree_flops(n)
     N = 1 << args.log2n
     points = N * args.shifts
     if args.copy_bytes:
@@ -114,7 +124,6 @@ def run_plain(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tables = qqmc.make_tables(d)
     sums = torch.zeros(2 * args.shifts, dtype=torch.float64, device="cuda")
 
     def step():
@@ -124,7 +133,7 @@ def run_plain(args):
     ms_per_step = wall * 1e3 / args.steps
     value = points * args.steps / wall
     frac_in = inside_fraction(n, d.t_meas / job.model_tau)
-    alg_flops = points * (frac_in * tree_flops(n) + warp_flops(n))
+    alg_flops = points * (frac_in * tflops + warp_flops(n))
     avg_launch_s = sum(launch_ms) / len(launch_ms) * 1e-3
     achieved = alg_flops / avg_launch_s / 1e12
     out = {
@@ -141,19 +150,21 @@ def run_plain(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "charge coefficient Q_n of the wide-band Anderson dot "
-                               "(Gamma=1, eps_d=0, beta=20, V=0, t=10), order %d, "
+                               "(Gamma=1, eps_d=%g, beta=20, V=%g, t=10%s), order %d, "
                                "Korobov lattice N=2^%d x %d random shifts, tau=1"
-                               % (n, args.log2n, args.shifts),
+                               % (d.eps_d, d.bias_v,
+                                  ", alpha=%.6g, paired tree" % alpha if alpha else "",
+                                  n, args.log2n, args.shifts),
                    "order": n, "lattice_points": N, "shifts": args.shifts,
                    "inside_fraction": frac_in,
                    "inside_points_per_s": value * frac_in},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(n),
-                     "flops_per_inside_point": tree_flops(n),
+                     "traffic": measured_traffic(n) if alpha == 0.0 else None,
+                     "flops_per_inside_point": tflops,
                      "avg_launch_ms": avg_launch_s * 1e3},
     }
-    if not args.no_cpu:
+    if not args.no_cpu and alpha == 0.0:
         out["cpu_baseline"] = cpu_baseline(n, args.log2n, job.lattice_a, job.shifts,
                                            args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -451,6 +462,9 @@ def main():
                     choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--alpha", default=None,
+                    help="plain workload with the alpha-shifted interaction (a number, "
+                         "or ns for alpha = n_sigma), on eps_d=0.3, V=0.4")
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--shifts", type=int, default=32)
     ap.add_argument("--tile", type=int, default=0)

@@ -45,6 +45,31 @@ def tree_flops(n):
     return total + LEAF_CONSTANTS + PAIR_LOOKUP * n * (n + 1) // 2 + POINT_EPILOGUE
 
 
+def _pair_node(m):
+    """Paired-tree node holding an m x m trailing block, m >= 4: the two
+    diagonal entries, then for both indices b of the earlier vertex the 2x2
+    pivot block (entries, determinant, reciprocal, four scaled entries) and
+    the vertex's row and column, and for both indices of the later vertex its
+    row and column, the two scaled column vectors and the rank-2 update of
+    the (m-2)^2 child block except its measurement diagonal (never read);
+    det^2 times the signed child sum."""
+    child = 4 * (m - 2) + 28 * (m - 2) + 16 * ((m - 2) ** 2 - 1) + 2
+    per_b = 4 + 14 + 6 + 24 + 4 * (m - 2) + 2 * child + 12 + 2
+    return 4 + 2 * per_b
+
+
+def pair_tree_flops(n):
+    """Per point inside the domain, paired tree (alpha != 0): pair nodes
+    down to a 3x3 node (even n) or a leaf pair (odd n)."""
+    total, m, count = 0, n + 1, 1
+    while m >= 4:
+        total += count * _pair_node(m)
+        m -= 2
+        count *= 4
+    total += count * (NODE3 if m == 3 else ROOT2)
+    return total + LEAF_CONSTANTS + PAIR_LOOKUP * n * (n + 1) // 2 + POINT_EPILOGUE
+
+
 def warp_flops(n):
     """Per lattice point (lattice arithmetic, inverse CDF, weight; each
     transcendental counted as one operation)."""

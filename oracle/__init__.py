@@ -46,6 +46,11 @@ def _load():
     lib.oracle_n_sigma.argtypes = [d, d, d, d]
     lib.oracle_n_sigma.restype = d
     lib.oracle_gf_direct.argtypes = [d, d, d, d, d, P]
+    lib.oracle_n_sigma_band.argtypes = [d, d, d, d, d]
+    lib.oracle_n_sigma_band.restype = d
+    lib.oracle_gf_band.argtypes = [d, d, d, d, d, d, P]
+    lib.oracle_tables_band.argtypes = [d, d, d, d, d, i, d, P, P, P]
+    lib.oracle_tables_band.restype = i
     lib.oracle_interp.argtypes = [P, i, d, d, P]
     lib.oracle_det.argtypes = [i, P, P]
     lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, d, i, P, PI, P]
@@ -81,18 +86,26 @@ def _f64(a):
 
 
 class Tables:
-    """g^<, g^> on the uniform grid plus the exact n_sigma (App. E)."""
+    """g^<, g^> on the uniform grid plus the exact n_sigma (App. E); wide
+    band, or semicircular leads of half-bandwidth D when D > 0."""
 
-    def __init__(self, eps_d, gamma, beta, bias_v, n_grid=8192, t_half=10.0):
+    def __init__(self, eps_d, gamma, beta, bias_v, n_grid=8192, t_half=10.0,
+                 half_bandwidth=0.0):
         lib = _load()
         self.eps_d, self.gamma, self.beta, self.bias_v = eps_d, gamma, beta, bias_v
+        self.half_bandwidth = float(half_bandwidth)
         self.n_grid, self.t_half = int(n_grid), float(t_half)
         self.gl = np.zeros(2 * self.n_grid)
         self.gg = np.zeros(2 * self.n_grid)
         ns = ctypes.c_double()
-        rc = lib.oracle_tables(eps_d, gamma, beta, bias_v, self.n_grid,
-                               self.t_half, _p(self.gl), _p(self.gg),
-                               ctypes.byref(ns))
+        if self.half_bandwidth > 0.0:
+            rc = lib.oracle_tables_band(eps_d, gamma, beta, bias_v, self.half_bandwidth,
+                                        self.n_grid, self.t_half, _p(self.gl), _p(self.gg),
+                                        ctypes.byref(ns))
+        else:
+            rc = lib.oracle_tables(eps_d, gamma, beta, bias_v, self.n_grid,
+                                   self.t_half, _p(self.gl), _p(self.gg),
+                                   ctypes.byref(ns))
         if rc != 0:
             raise ValueError("oracle_tables: bad arguments")
         self.n_sigma = ns.value
@@ -122,6 +135,17 @@ class Tables:
 
 def n_sigma(eps_d, gamma, beta, bias_v):
     return _load().oracle_n_sigma(eps_d, gamma, beta, bias_v)
+
+
+def gf_band(eps_d, gamma, beta, bias_v, D, tau):
+    """(g^<(tau), g^>(tau)) with semicircular leads of half-bandwidth D."""
+    out = np.zeros(4)
+    _load().oracle_gf_band(eps_d, gamma, beta, bias_v, D, tau, _p(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def n_sigma_band(eps_d, gamma, beta, bias_v, D):
+    return _load().oracle_n_sigma_band(eps_d, gamma, beta, bias_v, D)
 
 
 def gf_direct(eps_d, gamma, beta, bias_v, tau):

@@ -317,6 +317,150 @@ int oracle_tables(double eps_d, double gamma, double beta, double bias_v,
     return 0;
 }
 
+/* ---- Finite bandwidth (App. E, "Model"): each lead has a semicircular
+ * density of states of half-bandwidth D; with Gamma = 4 gamma^2 / D the
+ * hybridisation inside the band is
+ *     Delta(omega) = (Gamma/D) (omega - i sqrt(D^2 - omega^2)),
+ * real outside.  The retarded function 1/(omega - eps_d - Delta) has no pole
+ * outside the band when |eps_d| < D - Gamma (then the band carries the whole
+ * spectral weight; the paper's frequency formulas have no bound-state
+ * terms, and this oracle accepts only that regime).  The spectral function
+ *     A(omega) = 2 (Gamma/D) s |g^R|^2,  s = sqrt(D^2 - omega^2),
+ *     |g^R|^2 = 1 / ((omega - eps_d - (Gamma/D) omega)^2 + (Gamma s / D)^2),
+ * and, with fbar the mean Fermi function of the two leads,
+ *     g^<(tau) =  i Int_{-D}^{D} A fbar      e^{-i omega tau} domega / 2pi,
+ *     g^>(tau) = -i Int_{-D}^{D} A (1-fbar)  e^{-i omega tau} domega / 2pi.
+ * The integrals run over theta in [0, pi] with omega = -D cos theta (the
+ * square roots at the band edges become sin theta), split at the Fermi
+ * levels and the level eps_d, each piece by adaptive Gauss-Legendre. */
+typedef struct {
+    double eps_d, gamma, beta, bias_v, D, tau;
+    int lesser;
+} band_ctx;
+
+/* Fermi function with the T = 0 step (1/2 at the step itself) */
+static double fermi_band(double beta, double x)
+{
+    if (isinf(beta)) return x < 0.0 ? 1.0 : (x > 0.0 ? 0.0 : 0.5);
+    double bx = beta * x;
+    if (bx > 0.0) {
+        double e = exp(-bx);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (exp(bx) + 1.0);
+}
+
+static double band_spectral(double eps_d, double gamma, double D, double omega)
+{
+    double s2 = D * D - omega * omega;
+    if (s2 <= 0.0) return 0.0;
+    double s = sqrt(s2), g = gamma / D;
+    double re = omega - eps_d - g * omega, im = g * s;
+    return 2.0 * g * s / (re * re + im * im);
+}
+
+static cplx band_integrand(const band_ctx *c, double theta)
+{
+    double omega = -c->D * cos(theta);
+    double A = band_spectral(c->eps_d, c->gamma, c->D, omega);
+    double fb = 0.5 * (fermi_band(c->beta, omega - 0.5 * c->bias_v) +
+                       fermi_band(c->beta, omega + 0.5 * c->bias_v));
+    double wgt = c->lesser ? fb : 1.0 - fb;
+    return A * wgt * cexp(-I * omega * c->tau) * c->D * sin(theta) / (2.0 * M_PI);
+}
+
+static cplx band_gl(const band_ctx *c, double a, double b, const double *gx, const double *gw,
+                    int m)
+{
+    double hw = 0.5 * (b - a), mid = 0.5 * (a + b);
+    cplx acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += gw[i] * band_integrand(c, mid + hw * gx[i]);
+    return hw * acc;
+}
+
+/* Adaptive bisection: accept the two halves when they agree with the whole
+ * piece to 1e-14 per unit of theta (at most about 3e-14 in all), or to the
+ * rounding level of the halves themselves. */
+static cplx band_adapt(const band_ctx *c, double a, double b, cplx whole, int depth,
+                       const double *gx, const double *gw, int m)
+{
+    double mid = 0.5 * (a + b);
+    cplx l = band_gl(c, a, mid, gx, gw, m), r = band_gl(c, mid, b, gx, gw, m);
+    double diff = cabs(l + r - whole);
+    if (depth >= 30 || diff <= 1e-14 * (b - a) || diff <= 1e-15 * (cabs(l) + cabs(r)))
+        return l + r;
+    return band_adapt(c, a, mid, l, depth + 1, gx, gw, m) +
+           band_adapt(c, mid, b, r, depth + 1, gx, gw, m);
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* g^< (lesser = 1) or g^> at tau, finite bandwidth. */
+static cplx band_gf(double eps_d, double gamma, double beta, double bias_v, double D,
+                    double tau, int lesser)
+{
+    enum { M = 10 };
+    double gx[M], gw[M];
+    gauss_legendre(M, gx, gw);
+    band_ctx c = { eps_d, gamma, beta, bias_v, D, tau, lesser };
+    double br[5];
+    int nb = 0;
+    br[nb++] = 0.0;
+    double pts[3] = { 0.5 * bias_v, -0.5 * bias_v, eps_d };
+    for (int k = 0; k < 3; ++k)
+        if (fabs(pts[k]) < D) br[nb++] = acos(-pts[k] / D);
+    br[nb++] = M_PI;
+    qsort(br, (size_t)nb, sizeof(double), cmp_double);
+    cplx total = 0.0;
+    for (int k = 0; k + 1 < nb; ++k) {
+        double a = br[k], b = br[k + 1];
+        if (!(b > a)) continue;
+        cplx whole = band_gl(&c, a, b, gx, gw, M);
+        total += band_adapt(&c, a, b, whole, 0, gx, gw, M);
+    }
+    return (lesser ? I : -I) * total;
+}
+
+static int band_ok(double eps_d, double gamma, double beta, double D)
+{
+    return D > 0.0 && isfinite(D) && gamma > 0.0 && beta > 0.0 && fabs(eps_d) < D - gamma;
+}
+
+double oracle_n_sigma_band(double eps_d, double gamma, double beta, double bias_v, double D)
+{
+    if (!band_ok(eps_d, gamma, beta, D)) return NAN;
+    return cimag(band_gf(eps_d, gamma, beta, bias_v, D, 0.0, 1));
+}
+
+void oracle_gf_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                    double tau, double *out)
+{
+    cplx l = band_gf(eps_d, gamma, beta, bias_v, D, tau, 1);
+    cplx g = band_gf(eps_d, gamma, beta, bias_v, D, tau, 0);
+    out[0] = creal(l); out[1] = cimag(l);
+    out[2] = creal(g); out[3] = cimag(g);
+}
+
+int oracle_tables_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int n_grid, double t_half, double *gl, double *gg, double *n_sigma)
+{
+    if (n_grid < 2 || !(t_half > 0.0) || !band_ok(eps_d, gamma, beta, D)) return -1;
+    double h = 2.0 * t_half / (n_grid - 1);
+    #pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < n_grid; ++j) {
+        double tau = -t_half + j * h, v[4];
+        oracle_gf_band(eps_d, gamma, beta, bias_v, D, tau, v);
+        gl[2 * j] = v[0]; gl[2 * j + 1] = v[1];
+        gg[2 * j] = v[2]; gg[2 * j + 1] = v[3];
+    }
+    *n_sigma = oracle_n_sigma_band(eps_d, gamma, beta, bias_v, D);
+    return 0;
+}
+
 /* Linear interpolation on the uniform grid; outside the grid the end value is
  * held (the index and the fraction are both clamped). */
 static cplx interp_c(const double *tab, int n_grid, double t_half, double tau)

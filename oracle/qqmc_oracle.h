@@ -40,6 +40,14 @@ void oracle_gf_direct(double eps_d, double gamma, double beta, double bias_v,
                       double tau, double *out);
 
 /* Linear interpolation in a table built as above; out = (re, im). */
+double oracle_n_sigma_band(double eps_d, double gamma, double beta, double bias_v, double D);
+
+void oracle_gf_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                    double tau, double *out);
+
+int oracle_tables_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int n_grid, double t_half, double *gl, double *gg, double *n_sigma);
+
 void oracle_interp(const double *tab, int n_grid, double t_half, double tau,
                    double *out);
 

@@ -731,3 +731,69 @@ def test_eval_mass_bounds_the_sums(oracle_mod, tiny_tables):
     got = oracle_mod.eval_mass(tiny_tables, 10.0, 3, 10, job.lattice_a, job.shifts[:1], 1.0,
                                0, 40)[0]
     assert abs(got - ref) <= 1e-12 * ref
+
+
+# ---------------------------------------------------------------------------
+# Finite bandwidth: semicircular leads of half-bandwidth D (App. E, "Model").
+# ---------------------------------------------------------------------------
+def test_band_closed_form_at_gamma_half_d(oracle_mod):
+    """Gamma = D/2, eps_d = 0: g^R = 2 (omega - i s)/D^2, so A is the
+    semicircle 4 s/D^2; at infinite temperature fbar = 1/2 and
+    g^<(tau) = i J_1(D tau)/(D tau) = -g^>(tau) (the Fourier transform of
+    the semicircle).  beta = 1e-12 leaves an O(beta) correction."""
+    from scipy.special import j1
+    D = 2.0
+    for tau in (0.0, 0.3, 1.7, 5.2, -3.1, 9.9):
+        gl, gg = oracle_mod.gf_band(0.0, 1.0, 1e-12, 0.0, D, tau)
+        ref = 0.5j if tau == 0 else 1j * j1(D * tau) / (D * tau)
+        assert abs(gl - ref) < 1e-12 and abs(gg + ref) < 1e-12, tau
+
+
+@pytest.mark.parametrize("eps,gam,beta,V", [(0.4, 0.3, 10.0, 0.5), (-1.2, 0.1, math.inf, 0.3),
+                                            (0.0, 0.9, 2.0, 1.5)])
+def test_band_sum_rule_and_occupation(oracle_mod, eps, gam, beta, V):
+    """Without bound states the band carries the whole spectral weight:
+    g^>(0) - g^<(0) = -i; and g^<(0) = i n_sigma with n_sigma in (0, 1)."""
+    gl, gg = oracle_mod.gf_band(eps, gam, beta, V, 2.0, 0.0)
+    assert abs(gg - gl + 1j) < 1e-13
+    ns = oracle_mod.n_sigma_band(eps, gam, beta, V, 2.0)
+    assert abs(gl - 1j * ns) < 1e-15 and 0.0 < ns < 1.0
+
+
+def test_band_particle_hole_symmetry(oracle_mod):
+    """eps_d = 0 and a symmetric bias: A is even and 1 - fbar(-w) = fbar(w),
+    so g^>(tau) = conj(g^<(tau))."""
+    for tau in (0.2, 1.0, 4.4, 9.0):
+        gl, gg = oracle_mod.gf_band(0.0, 0.4, 5.0, 0.8, 2.0, tau)
+        assert abs(gg - np.conj(gl)) < 1e-13
+
+
+def test_band_wide_band_limit(oracle_mod):
+    """D -> infinity at fixed Gamma: the tables approach the wide-band ones,
+    with an error of order Gamma/D (the real part of Delta and the
+    Lorentzian tails beyond the band)."""
+    eps, gam, beta, V = 0.3, 1.0, 5.0, 0.4
+    taus = np.linspace(0.5, 9.0, 9)
+    err = {}
+    for D in (50.0, 200.0):
+        e = 0.0
+        for tau in taus:
+            gl, gg = oracle_mod.gf_band(eps, gam, beta, V, D, tau)
+            w = oracle_mod.gf_direct(eps, gam, beta, V, tau)
+            e = max(e, abs(gl - w[0]), abs(gg - w[1]))
+        err[D] = e
+    assert err[200.0] < 5e-3
+    assert 2.5 < err[50.0] / err[200.0] < 6.0, err
+
+
+def test_band_tables_grid_and_symmetry(oracle_mod):
+    """The grid holds g(tau_j) at tau_j = -t_half + j h, and
+    g(-tau) = -conj(g(tau)) (i times a real spectral weight)."""
+    tb = oracle_mod.Tables(0.3, 0.1, 20.0, 0.4, 257, 10.0, half_bandwidth=2.0)
+    gl, gg = tb.gl_c(), tb.gg_c()
+    for j in (0, 17, 128, 200, 256):
+        l, g = oracle_mod.gf_band(0.3, 0.1, 20.0, 0.4, 2.0, tb.grid[j])
+        assert abs(gl[j] - l) < 1e-15 and abs(gg[j] - g) < 1e-15
+        assert abs(gl[256 - j] + np.conj(gl[j])) < 1e-13
+    with pytest.raises(ValueError):          # a bound state: |eps_d| >= D - Gamma
+        oracle_mod.Tables(1.95, 0.1, 20.0, 0.0, 64, 10.0, half_bandwidth=2.0)

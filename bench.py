@@ -106,15 +106,24 @@ def run_plain(args):
     stream = torch.cuda.current_stream()
     n = args.order
     alpha = 0.0
+    tau = 1.0
     d = TINY_DOT
-    if args.alpha is not None:
+    if args.band:
+        # the paper's finite-bandwidth application: semicircular leads D = 2,
+        # Gamma = 0.1, E_d = 0.9 Gamma, alpha = n_sigma, t = 10/Gamma,
+        # tau = 1.5/Gamma (bias 0.05, low temperature)
+        d = Dot(0.09, 0.1, 200.0, 0.05, t_meas=100.0, n_grid=65536, t_half=100.0,
+                half_bandwidth=2.0)
+        args.alpha = "ns"
+        tau = 15.0
+    elif args.alpha is not None:
         # the alpha-shifted interaction away from particle-hole symmetry;
         # "ns" is the paper's choice alpha = n_sigma (zero vertex diagonal)
         d = Dot(0.3, 1.0, 20.0, 0.4)
     tables = qqmc.make_tables(d)
     if args.alpha is not None:
         alpha = qqmc.tables_export(tables)[2] if args.alpha == "ns" else float(args.alpha)
-    job = order_job(1, n, args.log2n, args.shifts, alpha=alpha)
+    job = order_job(1, n, args.log2n, args.shifts, model_tau=tau, alpha=alpha)
     tflops = pair_tree_flops(n) if alpha != 0.0 else tree_flops(n)
     N = 1 << args.log2n
     points = N * args.shifts
@@ -149,12 +158,14 @@ def run_plain(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "charge coefficient Q_n of the wide-band Anderson dot "
-                               "(Gamma=1, eps_d=%g, beta=20, V=%g, t=10%s), order %d, "
-                               "Korobov lattice N=2^%d x %d random shifts, tau=1"
-                               % (d.eps_d, d.bias_v,
+        "config": {"workload": "charge coefficient Q_n of the %s Anderson dot "
+                               "(Gamma=%g, eps_d=%g, beta=%g, V=%g, t=%g%s), order %d, "
+                               "Korobov lattice N=2^%d x %d random shifts, tau=%g"
+                               % ("semicircular-lead (D=%g)" % d.half_bandwidth
+                                  if d.half_bandwidth else "wide-band",
+                                  d.gamma, d.eps_d, d.beta, d.bias_v, d.t_meas,
                                   ", alpha=%.6g, paired tree" % alpha if alpha else "",
-                                  n, args.log2n, args.shifts),
+                                  n, args.log2n, args.shifts, tau),
                    "order": n, "lattice_points": N, "shifts": args.shifts,
                    "inside_fraction": frac_in,
                    "inside_points_per_s": value * frac_in},
@@ -462,6 +473,8 @@ def main():
                     choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--band", action="store_true",
+                    help="plain workload on the paper's finite-bandwidth parameters")
     ap.add_argument("--alpha", default=None,
                     help="plain workload with the alpha-shifted interaction (a number, "
                          "or ns for alpha = n_sigma), on eps_d=0.3, V=0.4")

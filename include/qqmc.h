@@ -45,9 +45,11 @@ typedef enum {
 /* Highest perturbation order the kernels are built for. */
 #define QQMC_MAX_ORDER 14
 
-/* Wide-band Anderson dot (App. E "Model", hybridisation Delta = -i Gamma,
- * quadratic shift alpha = 0).  The Green's functions are tabulated on the
- * uniform grid tau_j = -t_half + j*h, h = 2 t_half/(n_grid-1). */
+/* Anderson dot between two leads (App. E "Model"): wide band (hybridisation
+ * Delta = -i Gamma) or semicircular leads of half-bandwidth D, with
+ * Delta(omega) = (Gamma/D)(omega - i sqrt(D^2 - omega^2)) in the band.  The
+ * Green's functions are tabulated on the uniform grid tau_j = -t_half + j*h,
+ * h = 2 t_half/(n_grid-1). */
 typedef struct {
     double eps_d;    /* dot level                                           */
     double gamma;    /* tunnelling rate Gamma > 0                           */
@@ -55,6 +57,9 @@ typedef struct {
     double bias_v;   /* symmetric bias V between the two leads              */
     double t_half;   /* half-range of the table grid (>= measurement time)  */
     int32_t n_grid;  /* number of grid points, 2 .. 2^24                    */
+    double half_bandwidth; /* D; 0 or +INFINITY: wide band.  A finite D
+                              needs |eps_d| < D - gamma (no bound state
+                              outside the band; EINVAL otherwise)        */
 } qqmc_dot;
 
 typedef struct qqmc_tables_s *qqmc_tables;
@@ -111,8 +116,12 @@ typedef struct {
  * (beta = +INFINITY) the grid is computed on the host from the Fourier
  * integral along a path deformed into the lower half plane (App. E,
  * "Precision calculation") and uploaded, n_sigma from the arctan closed
- * form.  EINVAL for gamma <= 0, beta <= 0 or NaN, t_half <= 0 or n_grid
- * outside 2..2^24. */
+ * form.  With a finite half_bandwidth D (any beta) the grid is computed on
+ * the host by a graded Gauss-Legendre rule over the band (theta in [0, pi],
+ * omega = -D cos theta, panels refined at the Fermi levels and at eps_d),
+ * n_sigma from the same rule, and uploaded.  EINVAL for gamma <= 0,
+ * beta <= 0 or NaN, t_half <= 0, n_grid outside 2..2^24, a negative or NaN
+ * half_bandwidth, or a finite one with |eps_d| >= D - gamma. */
 qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream,
                              qqmc_tables *out);
 

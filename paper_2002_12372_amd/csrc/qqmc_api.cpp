@@ -168,6 +168,11 @@ static qqmc_status check_dot(const qqmc_dot *dot)
                          "gamma, t_half must be positive and finite, beta positive (+inf: T = 0)");
     if (dot->n_grid < 2 || dot->n_grid > (1 << 24))
         return set_error(QQMC_EINVAL, "n_grid must be in 2..2^24");
+    if (std::isnan(dot->half_bandwidth) || dot->half_bandwidth < 0.0)
+        return set_error(QQMC_EINVAL, "half_bandwidth must be >= 0 (0 or +inf: wide band)");
+    if (finite_band(dot) && !(std::fabs(dot->eps_d) < dot->half_bandwidth - dot->gamma))
+        return set_error(QQMC_EINVAL,
+                         "finite band needs |eps_d| < D - gamma (no bound state outside the band)");
     return QQMC_OK;
 }
 
@@ -175,10 +180,16 @@ qqmc_status qqmc_tables_compute_host(const qqmc_dot *dot, double *gl, double *gg
 {
     if (qqmc_status st = check_dot(dot)) return st;
     if (!gl || !gg) return set_error(QQMC_EINVAL, "NULL output");
-    const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
     std::vector<double> tab(4 * (size_t)dot->n_grid);
-    build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,
-                      dot->t_half, ns, tab.data());
+    double ns;
+    if (finite_band(dot)) {
+        ns = build_tables_band(dot->eps_d, dot->gamma, dot->beta, dot->bias_v,
+                               dot->half_bandwidth, dot->n_grid, dot->t_half, tab.data());
+    } else {
+        ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
+        build_tables_host(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->n_grid,
+                          dot->t_half, ns, tab.data());
+    }
     for (int32_t j = 0; j < dot->n_grid; ++j) {
         gl[2 * j] = tab[4 * j];
         gl[2 * j + 1] = tab[4 * j + 1];
@@ -193,8 +204,16 @@ qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out
 {
     if (qqmc_status st = check_dot(dot)) return st;
     if (!out) return set_error(QQMC_EINVAL, "NULL argument");
-    const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
     hipStream_t s = (hipStream_t)stream;
+    if (finite_band(dot)) {
+        /* semicircular leads: band quadrature on the host, then upload */
+        std::vector<double> tab(4 * (size_t)dot->n_grid);
+        const double nsb = build_tables_band(dot->eps_d, dot->gamma, dot->beta, dot->bias_v,
+                                             dot->half_bandwidth, dot->n_grid, dot->t_half,
+                                             tab.data());
+        return upload_tables(tab.data(), dot->n_grid, dot->t_half, nsb, s, out);
+    }
+    const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
     if (std::isinf(dot->beta)) {
         /* zero temperature: contour quadrature on the host, then upload */
         std::vector<double> tab(4 * (size_t)dot->n_grid);

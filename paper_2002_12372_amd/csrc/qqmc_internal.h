@@ -91,6 +91,15 @@ double occupation_per_spin(double eps_d, double gamma, double beta,
 void build_tables_host(double eps_d, double gamma, double beta, double bias_v,
                        int32_t n_grid, double t_half, double n_sigma,
                        double *tab /* 4*n_grid, interleaved */);
+/* Semicircular leads of half-bandwidth D (|eps_d| < D - gamma): fills tab as
+ * above and returns n_sigma. */
+double build_tables_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                         int32_t n_grid, double t_half, double *tab);
+/* Finite bandwidth requested (0 and +infinity mean the wide band). */
+inline bool finite_band(const qqmc_dot *d)
+{
+    return d->half_bandwidth > 0.0 && d->half_bandwidth < INFINITY;
+}
 
 /* Error reporting (qqmc_api.cpp). */
 qqmc_status set_error(qqmc_status st, const std::string &msg);

@@ -54,7 +54,7 @@ struct TableEntry {
     uint64_t last_use = 0;
 };
 
-using TableKey = std::tuple<double, double, double, double, double, int32_t>;
+using TableKey = std::tuple<double, double, double, double, double, int32_t, double>;
 
 struct Request {
     uint64_t ticket = 0;
@@ -518,7 +518,8 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     r->desc.tile_len = (int32_t)std::min<int64_t>(s->tile_len, N);
     r->desc.tiles_per_shift = (int32_t)(N / r->desc.tile_len);
     r->desc.n_tiles = (int64_t)r->desc.tiles_per_shift * r->desc.n_shifts;
-    r->key = TableKey(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->t_half, dot->n_grid);
+    r->key = TableKey(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->t_half, dot->n_grid,
+                      finite_band(dot) ? dot->half_bandwidth : 0.0);
     if (request_bytes(*r, true) > s->budget)
         return set_error(QQMC_EADMIT, "request footprint exceeds the HBM budget");
     std::lock_guard<std::mutex> lk(s->mu);

@@ -3,7 +3,8 @@
  * n_sigma from the digamma closed form (arctan at zero temperature), and a
  * host build of the grid from the residue series of qqmc_gf.h (the device
  * build is tables_kernel) or, at zero temperature, from the deformed-contour
- * Fourier integral.
+ * Fourier integral; semicircular leads of finite bandwidth by a graded
+ * Gauss-Legendre rule over the band.
  */
 #include <algorithm>
 #include <cmath>
@@ -154,6 +155,97 @@ double occupation_per_spin(double eps_d, double gamma, double beta, double bias_
     return n;
 }
 
+namespace {
+
+/* Finite bandwidth (App. E, "Model"): semicircular leads of half-bandwidth
+ * D, Delta(omega) = (Gamma/D)(omega - i sqrt(D^2 - omega^2)) in the band.
+ * With |eps_d| < D - Gamma the retarded function has no pole outside the
+ * band, and
+ *     A(omega) = 2 g s / ((omega - eps_d - g omega)^2 + (g s)^2),
+ *     g = Gamma/D, s = sqrt(D^2 - omega^2),
+ *     g^<(tau) =  i Int A fbar     e^{-i omega tau} domega/2pi,
+ *     g^>(tau) = -i Int A (1-fbar) e^{-i omega tau} domega/2pi
+ * over the band.  Quadrature in theta, omega = -D cos theta (the band-edge
+ * square roots become sin theta): 16-point Gauss-Legendre panels, split at
+ * the Fermi levels and at eps_d, graded geometrically away from them (a
+ * panel next to a Fermi level spans about four units of beta (omega - mu),
+ * next to eps_d about Gamma), and never longer than about half a period of
+ * e^{-i omega t_half}.  Both functions come from the same nodes. */
+struct BandRule {
+    std::vector<double> omega, weight, fbar; /* weight includes D sin theta A / 2pi */
+};
+
+BandRule band_rule(double eps_d, double gamma, double beta, double bias_v, double D,
+                   double t_half)
+{
+    constexpr int M = 16;
+    double gx[M], gw[M];
+    legendre_rule(M, gx, gw);
+    const double hmax = std::min(0.2, 3.0 / (D * t_half + 1.0));
+    struct Mark {
+        double theta, scale;
+    };
+    std::vector<Mark> marks;
+    auto theta_of = [&](double w) { return std::acos(-w / D); };
+    const double mus[2] = {0.5 * bias_v, -0.5 * bias_v};
+    for (double mu : mus)
+        if (std::fabs(mu) < D) {
+            const double th = theta_of(mu), st = std::max(std::sin(th), 1e-3);
+            marks.push_back({th, std::isinf(beta) ? hmax : 4.0 / (beta * D * st)});
+        }
+    if (std::fabs(eps_d) < D) {
+        const double th = theta_of(eps_d), st = std::max(std::sin(th), 1e-3);
+        marks.push_back({th, gamma / (D * st)});
+    }
+    std::vector<double> edges = {0.0, kPiGF};
+    for (const Mark &m : marks) {
+        edges.push_back(m.theta);
+        const double d0 = std::min(m.scale, hmax);
+        for (double d = d0; d < kPiGF; d *= 2.0) {
+            edges.push_back(m.theta - d);
+            edges.push_back(m.theta + d);
+        }
+    }
+    std::vector<double> e;
+    for (double x : edges)
+        if (x >= 0.0 && x <= kPiGF) e.push_back(x);
+    std::sort(e.begin(), e.end());
+    BandRule r;
+    const double g = gamma / D;
+    for (size_t k = 0; k + 1 < e.size(); ++k) {
+        const double a = e[k], b = e[k + 1];
+        if (!(b - a > 1e-15)) continue;
+        const int pieces = (int)std::ceil((b - a) / hmax);
+        const double len = (b - a) / pieces;
+        for (int p = 0; p < pieces; ++p) {
+            const double lo = a + p * len, mid = lo + 0.5 * len;
+            for (int i = 0; i < M; ++i) {
+                const double th = mid + 0.5 * len * gx[i];
+                const double w = -D * std::cos(th), s = D * std::sin(th);
+                const double re = w - eps_d - g * w, im = g * s;
+                const double A = 2.0 * g * s / (re * re + im * im);
+                double fb;
+                if (std::isinf(beta)) {
+                    fb = 0.5 * ((w < mus[0] ? 1.0 : 0.0) + (w < mus[1] ? 1.0 : 0.0));
+                } else {
+                    auto fermi = [&](double x) {
+                        const double bx = beta * x;
+                        return bx > 0.0 ? std::exp(-bx) / (1.0 + std::exp(-bx))
+                                        : 1.0 / (std::exp(bx) + 1.0);
+                    };
+                    fb = 0.5 * (fermi(w - mus[0]) + fermi(w - mus[1]));
+                }
+                r.omega.push_back(w);
+                r.weight.push_back(0.5 * len * gw[i] * D * std::sin(th) * A / (2.0 * kPiGF));
+                r.fbar.push_back(fb);
+            }
+        }
+    }
+    return r;
+}
+
+} // namespace
+
 void build_tables_host(double eps_d, double gamma, double beta, double bias_v,
                        int32_t n_grid, double t_half, double n_sigma, double *tab)
 {
@@ -186,6 +278,44 @@ void build_tables_host(double eps_d, double gamma, double beta, double bias_v,
     for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work, t);
     work(0);
     for (auto &th : pool) th.join();
+}
+
+double build_tables_band(double eps_d, double gamma, double beta, double bias_v, double D,
+                         int32_t n_grid, double t_half, double *tab)
+{
+    const BandRule r = band_rule(eps_d, gamma, beta, bias_v, D, t_half);
+    const size_t m = r.omega.size();
+    double n_sigma = 0.0;
+    for (size_t k = 0; k < m; ++k) n_sigma += r.weight[k] * r.fbar[k];
+    const double h = 2.0 * t_half / (n_grid - 1);
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt < 1) nt = 1;
+    if (nt > 64) nt = 64;
+    auto work = [&](unsigned tid) {
+        for (int32_t j = (int32_t)tid; j < n_grid; j += (int32_t)nt) {
+            const double tau = -t_half + j * h;
+            /* sum over the nodes of weight * e^{-i omega tau}, split by fbar */
+            double lr = 0.0, li = 0.0, gr = 0.0, gi = 0.0;
+            for (size_t k = 0; k < m; ++k) {
+                const double c = std::cos(r.omega[k] * tau), sn = -std::sin(r.omega[k] * tau);
+                const double wl = r.weight[k] * r.fbar[k], wg = r.weight[k] - wl;
+                lr += wl * c;
+                li += wl * sn;
+                gr += wg * c;
+                gi += wg * sn;
+            }
+            /* g^< = i (lr + i li), g^> = -i (gr + i gi) */
+            tab[4 * j + 0] = -li;
+            tab[4 * j + 1] = lr;
+            tab[4 * j + 2] = gi;
+            tab[4 * j + 3] = -gr;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool) th.join();
+    return n_sigma;
 }
 
 } // namespace qqmc

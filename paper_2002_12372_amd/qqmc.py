@@ -32,7 +32,8 @@ class QQMCError(RuntimeError):
 class qqmc_dot(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("bias_v", ctypes.c_double),
-                ("t_half", ctypes.c_double), ("n_grid", ctypes.c_int32)]
+                ("t_half", ctypes.c_double), ("n_grid", ctypes.c_int32),
+                ("half_bandwidth", ctypes.c_double)]
 
 
 class qqmc_order(ctypes.Structure):
@@ -144,7 +145,8 @@ class Tables:
 
 
 def make_dot(d):
-    return qqmc_dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_half, d.n_grid)
+    return qqmc_dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_half, d.n_grid,
+                    getattr(d, "half_bandwidth", 0.0))
 
 
 def make_tables(dot, stream=None):

@@ -61,8 +61,9 @@ def shifts(rng: SplitMix64, n_shifts: int, order: int) -> np.ndarray:
 
 @dataclass
 class Dot:
-    """Wide-band Anderson dot: level eps_d, coupling Gamma, inverse
-    temperature beta, symmetric bias V, measurement time t."""
+    """Anderson dot: level eps_d, coupling Gamma, inverse temperature beta,
+    symmetric bias V, measurement time t, table grid; half_bandwidth D of
+    semicircular leads (0: wide band)."""
     eps_d: float = 0.0
     gamma: float = 1.0
     beta: float = 20.0
@@ -70,6 +71,7 @@ class Dot:
     t_meas: float = 10.0
     n_grid: int = 8192
     t_half: float = 10.0
+    half_bandwidth: float = 0.0
 
 
 @dataclass

@@ -47,6 +47,32 @@ def test_host_tables_match_oracle(libq, oracle_mod, d):
     assert np.max(np.abs(gg - tb.gg)) < 1e-13
 
 
+BAND_DOTS = [Dot(0.3, 0.1, 20.0, 0.4, half_bandwidth=2.0),
+             Dot(-0.6, 0.5, 8.0, 1.1, half_bandwidth=2.0),
+             Dot(0.0, 1.0, float("inf"), 0.6, half_bandwidth=2.0),
+             Dot(1.2, 0.2, 40.0, 0.0, t_meas=20.0, t_half=20.0, half_bandwidth=3.0)]
+
+
+@pytest.mark.parametrize("d", BAND_DOTS)
+def test_host_band_tables_match_oracle(libq, oracle_mod, d):
+    """Semicircular leads: the library's graded fixed rule against the
+    oracle's adaptive quadrature, over the whole grid."""
+    d = Dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_meas, 2049, d.t_half, d.half_bandwidth)
+    gl, gg, ns = libq.tables_compute_host(d)
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half,
+                           half_bandwidth=d.half_bandwidth)
+    assert abs(ns - tb.n_sigma) < 1e-13
+    assert np.max(np.abs(gl - tb.gl)) < 1e-13
+    assert np.max(np.abs(gg - tb.gg)) < 1e-13
+
+
+def test_host_band_rejects_bound_state_regime(libq):
+    with pytest.raises(libq.QQMCError):     # |eps_d| >= D - gamma
+        libq.tables_compute_host(Dot(1.95, 0.1, 20.0, 0.0, half_bandwidth=2.0))
+    with pytest.raises(libq.QQMCError):
+        libq.tables_compute_host(Dot(0.0, 1.0, 20.0, 0.0, half_bandwidth=-1.0))
+
+
 def test_host_tables_reject_bad_dot(libq):
     with pytest.raises(libq.QQMCError):
         libq.tables_compute_host(Dot(0.0, -1.0, 20.0, 0.0))

@@ -51,6 +51,13 @@ def _load():
     lib.oracle_gf_band.argtypes = [d, d, d, d, d, d, P]
     lib.oracle_tables_band.argtypes = [d, d, d, d, d, i, d, P, P, P]
     lib.oracle_tables_band.restype = i
+    lib.oracle_gf_lead.argtypes = [d, d, d, d, d, i, d, P]
+    lib.oracle_lead_tables.argtypes = [d, d, d, d, d, i, i, d, P, P]
+    lib.oracle_lead_tables.restype = i
+    lib.oracle_keldysh_sum_lead.argtypes = [P, P, P, P, i, d, d, d, d, i, P, P, P]
+    lib.oracle_eval_sums_lead.argtypes = [P, P, P, P, i, d, d, d, d, i, i, u64, i, P, d,
+                                          i64, i64, i, P, P]
+    lib.oracle_eval_sums_lead.restype = i
     lib.oracle_interp.argtypes = [P, i, d, d, P]
     lib.oracle_det.argtypes = [i, P, P]
     lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, d, i, P, PI, P]
@@ -90,7 +97,7 @@ class Tables:
     band, or semicircular leads of half-bandwidth D when D > 0."""
 
     def __init__(self, eps_d, gamma, beta, bias_v, n_grid=8192, t_half=10.0,
-                 half_bandwidth=0.0):
+                 half_bandwidth=0.0, lead=0):
         lib = _load()
         self.eps_d, self.gamma, self.beta, self.bias_v = eps_d, gamma, beta, bias_v
         self.half_bandwidth = float(half_bandwidth)
@@ -109,6 +116,18 @@ class Tables:
         if rc != 0:
             raise ValueError("oracle_tables: bad arguments")
         self.n_sigma = ns.value
+        # current into lead 1 (mu = -V/2) or 2 (mu = +V/2): the lead's
+        # gamma g^<_{0i}, gamma g^>_{0i} on the same grid (finite band only)
+        self.lead = int(lead)
+        self.cl = self.cg = None
+        if self.lead:
+            self.cl = np.zeros(2 * self.n_grid)
+            self.cg = np.zeros(2 * self.n_grid)
+            rc = lib.oracle_lead_tables(eps_d, gamma, beta, bias_v, self.half_bandwidth,
+                                        self.lead, self.n_grid, self.t_half, _p(self.cl),
+                                        _p(self.cg))
+            if rc != 0:
+                raise ValueError("oracle_lead_tables: bad arguments (finite band, lead 1 or 2)")
 
     @property
     def grid(self):
@@ -142,6 +161,60 @@ def gf_band(eps_d, gamma, beta, bias_v, D, tau):
     out = np.zeros(4)
     _load().oracle_gf_band(eps_d, gamma, beta, bias_v, D, tau, _p(out))
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def gf_lead(eps_d, gamma, beta, bias_v, D, lead, tau):
+    """(gamma g^<_{0i}(tau), gamma g^>_{0i}(tau)) for lead i (finite band)."""
+    out = np.zeros(4)
+    _load().oracle_gf_lead(eps_d, gamma, beta, bias_v, D, int(lead), float(tau), _p(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def current_integrand(tables, t_meas, u, alpha=0.0):
+    """f^I_n(u) = -4 i^n S(u) with the measurement column from the lead's
+    tables (Re: the order-n integrand of the particle current into the
+    lead), and 4 M(u)."""
+    u = _f64(u)
+    n = u.shape[0]
+    S = np.zeros(2)
+    M = ctypes.c_double()
+    gl, gg, ng, th, ns, a = tables._args(alpha)
+    _load().oracle_keldysh_sum_lead(gl, gg, _p(tables.cl), _p(tables.cg), ng, th, ns, a,
+                                    t_meas, n, _p(u), _p(S), ctypes.byref(M))
+    return -4.0 * (1j ** n) * (S[0] + 1j * S[1]), 4.0 * M.value
+
+
+def eval_current(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, i_begin=0,
+                 i_end=None, n_threads=0, alpha=0.0):
+    """Per-shift sums of f^I W over lattice indices [i_begin, i_end) and the
+    per-shift term masses."""
+    shifts = _f64(shifts)
+    K = shifts.shape[0]
+    if i_end is None:
+        i_end = 1 << log2_n
+    sums = np.zeros(2 * K)
+    mass = np.zeros(K)
+    gl, gg, ng, th, ns, a = tables._args(alpha)
+    rc = _load().oracle_eval_sums_lead(gl, gg, _p(tables.cl), _p(tables.cg), ng, th, ns, a,
+                                       t_meas, n, log2_n, int(lattice_a), K, _p(shifts),
+                                       model_tau, int(i_begin), int(i_end), n_threads,
+                                       _p(sums), _p(mass))
+    if rc != 0:
+        raise ValueError("oracle_eval_sums_lead: bad arguments")
+    return sums[0::2] + 1j * sums[1::2], mass
+
+
+def eval_order_current(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, alpha=0.0):
+    """I^{(s)} per shift (complex; the real part is the current coefficient),
+    their mean, the standard error of the real parts, and the mean term mass
+    per lattice point."""
+    N = 1 << log2_n
+    sums, mass = eval_current(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau,
+                              alpha=alpha)
+    q = sums / N
+    K = q.shape[0]
+    se = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
+    return q, q.mean(), se, mass / N
 
 
 def n_sigma_band(eps_d, gamma, beta, bias_v, D):

@@ -461,6 +461,103 @@ int oracle_tables_band(double eps_d, double gamma, double beta, double bias_v, d
     return 0;
 }
 
+/* Lead Green's functions for the current (finite bandwidth only): with lead
+ * i at chemical potential mu_i (lead 1: -V/2, lead 2: +V/2) and self-energy
+ * Sigma_i = Delta/2, the dot-lead function g_{0i} = g_{00} gamma G_i gives
+ * (Langreth rules)
+ *     gamma g^<_{0i} = conj(Delta)/2 g^<_{00} + Sigma^<_i g^R,
+ *     gamma g^>_{0i} = conj(Delta)/2 g^>_{00} + Sigma^>_i g^R,
+ *     Sigma^<_i = -i f_i Im Delta,  Sigma^>_i = i (1 - f_i) Im Delta,
+ * all inside the band (no bound state).  Same theta quadrature as above. */
+typedef struct {
+    double eps_d, gamma, beta, bias_v, D, tau, mu;
+    int lesser;
+} lead_ctx;
+
+static cplx lead_integrand(const lead_ctx *c, double theta)
+{
+    double omega = -c->D * cos(theta);
+    double s = c->D * sin(theta), g = c->gamma / c->D;
+    cplx delta = g * omega - I * g * s;
+    cplx gr = 1.0 / (omega - c->eps_d - delta);
+    double A = -2.0 * cimag(gr);
+    double fb = 0.5 * (fermi_band(c->beta, omega - 0.5 * c->bias_v) +
+                       fermi_band(c->beta, omega + 0.5 * c->bias_v));
+    double fi = fermi_band(c->beta, omega - c->mu);
+    cplx v;
+    if (c->lesser)
+        v = conj(delta) / 2.0 * (I * A * fb) + (-I * fi * cimag(delta)) * gr;
+    else
+        v = conj(delta) / 2.0 * (-I * A * (1.0 - fb)) + (I * (1.0 - fi) * cimag(delta)) * gr;
+    return v * cexp(-I * omega * c->tau) * s / (2.0 * M_PI);
+}
+
+static cplx lead_gl(const lead_ctx *c, double a, double b, const double *gx, const double *gw,
+                    int m)
+{
+    double hw = 0.5 * (b - a), mid = 0.5 * (a + b);
+    cplx acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += gw[i] * lead_integrand(c, mid + hw * gx[i]);
+    return hw * acc;
+}
+
+static cplx lead_adapt(const lead_ctx *c, double a, double b, cplx whole, int depth,
+                       const double *gx, const double *gw, int m)
+{
+    double mid = 0.5 * (a + b);
+    cplx l = lead_gl(c, a, mid, gx, gw, m), r = lead_gl(c, mid, b, gx, gw, m);
+    double diff = cabs(l + r - whole);
+    if (depth >= 30 || diff <= 1e-14 * (b - a) || diff <= 1e-15 * (cabs(l) + cabs(r)))
+        return l + r;
+    return lead_adapt(c, a, mid, l, depth + 1, gx, gw, m) +
+           lead_adapt(c, mid, b, r, depth + 1, gx, gw, m);
+}
+
+void oracle_gf_lead(double eps_d, double gamma, double beta, double bias_v, double D, int lead,
+                    double tau, double *out)
+{
+    enum { M = 10 };
+    double gx[M], gw[M];
+    gauss_legendre(M, gx, gw);
+    double br[5];
+    int nb = 0;
+    br[nb++] = 0.0;
+    double pts[3] = { 0.5 * bias_v, -0.5 * bias_v, eps_d };
+    for (int k = 0; k < 3; ++k)
+        if (fabs(pts[k]) < D) br[nb++] = acos(-pts[k] / D);
+    br[nb++] = M_PI;
+    qsort(br, (size_t)nb, sizeof(double), cmp_double);
+    for (int which = 0; which < 2; ++which) {
+        lead_ctx c = { eps_d, gamma, beta, bias_v, D, tau, lead == 1 ? -0.5 * bias_v : 0.5 * bias_v,
+                       which == 0 };
+        cplx total = 0.0;
+        for (int k = 0; k + 1 < nb; ++k) {
+            double a = br[k], b = br[k + 1];
+            if (!(b > a)) continue;
+            total += lead_adapt(&c, a, b, lead_gl(&c, a, b, gx, gw, M), 0, gx, gw, M);
+        }
+        out[2 * which] = creal(total);
+        out[2 * which + 1] = cimag(total);
+    }
+}
+
+int oracle_lead_tables(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int lead, int n_grid, double t_half, double *cl, double *cg)
+{
+    if (n_grid < 2 || !(t_half > 0.0) || !band_ok(eps_d, gamma, beta, D) ||
+        (lead != 1 && lead != 2))
+        return -1;
+    double h = 2.0 * t_half / (n_grid - 1);
+    #pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < n_grid; ++j) {
+        double v[4];
+        oracle_gf_lead(eps_d, gamma, beta, bias_v, D, lead, -t_half + j * h, v);
+        cl[2 * j] = v[0]; cl[2 * j + 1] = v[1];
+        cg[2 * j] = v[2]; cg[2 * j + 1] = v[3];
+    }
+    return 0;
+}
+
 /* Linear interpolation on the uniform grid; outside the grid the end value is
  * held (the index and the fraction are both clamped). */
 static cplx interp_c(const double *tab, int n_grid, double t_half, double tau)
@@ -539,6 +636,10 @@ typedef struct {
     const cplx *gl_d; /* (n+1)^2: g^<(tau_r - tau_c), point 0 = measurement  */
     const cplx *gg_d; /* (n+1)^2: g^>(tau_r - tau_c)                         */
     const double *tm; /* (n+1): times, tm[0] = t, tm[k] = u_k                */
+    /* current: the measurement column (i, t, 1) is a lead site; cl_d[r],
+     * cg_d[r] hold gamma g^<_{0i}, gamma g^>_{0i} at tau_r - t (NULL: the
+     * charge, column from the dot's own functions) */
+    const cplx *cl_d, *cg_d;
 } wick_ctx;
 
 static cplx keldysh_entry(const wick_ctx *w, int r, int a_r, int c, int a_c)
@@ -546,6 +647,10 @@ static cplx keldysh_entry(const wick_ctx *w, int r, int a_r, int c, int a_c)
     int np1 = w->n + 1;
     double d = w->tm[r] - w->tm[c];
     cplx gl = w->gl_d[r * np1 + c], gg = w->gg_d[r * np1 + c];
+    if (c == 0 && w->cl_d) {
+        gl = w->cl_d[r];
+        gg = w->cg_d[r];
+    }
     if (a_r == 0 && a_c == 0) return d > 0.0 ? gg : gl;
     if (a_r == 0 && a_c == 1) return gl;
     if (a_r == 1 && a_c == 0) return gg;
@@ -591,7 +696,7 @@ void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
     tm[0] = t_meas;
     for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
     fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
-    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm };
+    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm, NULL, NULL };
     build_up(&w, a, m);
     for (int i = 0; i < np1 * np1; ++i) {
         out[2 * i] = creal(m[i]);
@@ -603,18 +708,28 @@ void oracle_wick_matrix(const double *gl, const double *gg, int n_grid,
 /* S(u) of Eq. (integral_gf): sum over a in {0,1}^n, natural binary order
  * (bit k-1 of the counter is a_k), of (-1)^{sum a} det_up(a) det_dn(a),
  * where det_dn is the vertex block (rows/columns 1..n) of the up matrix. */
-void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
-                        double t_half, double n_sigma, double alpha, double t_meas,
-                        int n, const double *u, double *S_out, double *M_out)
+/* S(u) with the measurement column from a lead's tables (cl, cg: gamma
+ * g^<_{0i}, gamma g^>_{0i} on the same grid), or from the dot's (cl = NULL). */
+void oracle_keldysh_sum_lead(const double *gl, const double *gg, const double *cl,
+                             const double *cg, int n_grid, double t_half, double n_sigma,
+                             double alpha, double t_meas, int n, const double *u,
+                             double *S_out, double *M_out)
 {
     int np1 = n + 1;
     double tm[32];
-    cplx gl_d[32 * 32], gg_d[32 * 32], up[32 * 32], dn[32 * 32];
+    cplx gl_d[32 * 32], gg_d[32 * 32], up[32 * 32], dn[32 * 32], cl_d[32], cg_d[32];
     int a[32];
     tm[0] = t_meas;
     for (int k = 0; k < n; ++k) tm[k + 1] = u[k];
     fill_pair_values(gl, gg, n_grid, t_half, n, tm, gl_d, gg_d);
-    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm };
+    if (cl) {
+        for (int r = 0; r < np1; ++r) {
+            cl_d[r] = interp_c(cl, n_grid, t_half, tm[r] - t_meas);
+            cg_d[r] = interp_c(cg, n_grid, t_half, tm[r] - t_meas);
+        }
+    }
+    wick_ctx w = { n, I * (n_sigma - alpha), I * n_sigma, gl_d, gg_d, tm,
+                   cl ? cl_d : NULL, cl ? cg_d : NULL };
     double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0, mass = 0.0;
     for (long mask = 0; mask < (1L << n); ++mask) {
         int parity = 0;
@@ -637,6 +752,14 @@ void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
     }
     S_out[0] = sr; S_out[1] = si;
     *M_out = mass;
+}
+
+void oracle_keldysh_sum(const double *gl, const double *gg, int n_grid,
+                        double t_half, double n_sigma, double alpha, double t_meas,
+                        int n, const double *u, double *S_out, double *M_out)
+{
+    oracle_keldysh_sum_lead(gl, gg, NULL, NULL, n_grid, t_half, n_sigma, alpha, t_meas, n, u,
+                            S_out, M_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -840,6 +963,61 @@ int oracle_eval_mass(const double *gl, const double *gg, int n_grid,
         }
         mass[s] = acc;
     }
+    return 0;
+}
+
+/* The current into lead i (measurement column from the lead's tables cl,
+ * cg), exponential warp: per shift, the sums over lattice indices
+ * [i_begin, i_end) of f W with f = -4 i^n S(u) (Re f is the order-n
+ * integrand of the particle current from the dot into the lead, both spins:
+ * the lead's particle number changes at the rate -2 Re(gamma G^<_{0i}(t,t))
+ * per spin), and, if mass is not NULL, of 4 W M(u). */
+int oracle_eval_sums_lead(const double *gl, const double *gg, const double *cl,
+                          const double *cg, int n_grid, double t_half, double n_sigma,
+                          double alpha, double t_meas, int n, int log2_n, uint64_t lattice_a,
+                          int n_shifts, const double *shifts, double model_tau,
+                          int64_t i_begin, int64_t i_end, int n_threads, double *sums,
+                          double *mass)
+{
+    if (n < 1 || n > 24 || log2_n < 1 || log2_n > 40 || i_end < i_begin ||
+        i_begin < 0 || n_shifts < 1 || !cl || !cg)
+        return -1;
+    int64_t cnt = i_end - i_begin;
+    double *vals = (double *)malloc(sizeof(double) * 3 * (size_t)(cnt > 0 ? cnt : 1));
+    if (!vals) return -1;
+    int nt = n_threads > 0 ? n_threads : oracle_max_threads();
+    cplx ipow = 1.0;
+    for (int k = 0; k < n; ++k) ipow *= I;
+    for (int s = 0; s < n_shifts; ++s) {
+        const double *sh = shifts + (size_t)s * n;
+        #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+        for (int64_t q = 0; q < cnt; ++q) {
+            double x[32], u[32], W, S[2], M = 0.0;
+            cplx f = 0.0;
+            oracle_lattice_point((uint64_t)(i_begin + q), n, log2_n, lattice_a, sh, x);
+            if (oracle_warp(n, x, model_tau, t_meas, u, &W)) {
+                oracle_keldysh_sum_lead(gl, gg, cl, cg, n_grid, t_half, n_sigma, alpha, t_meas,
+                                        n, u, S, &M);
+                f = -4.0 * ipow * (S[0] + I * S[1]) * W;
+                M *= 4.0 * W;
+            }
+            vals[3 * q] = creal(f);
+            vals[3 * q + 1] = cimag(f);
+            vals[3 * q + 2] = M;
+        }
+        double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0, ms = 0.0;
+        for (int64_t q = 0; q < cnt; ++q) {
+            double y = vals[3 * q] - cr, t = sr + y;
+            cr = (t - sr) - y; sr = t;
+            y = vals[3 * q + 1] - ci; t = si + y;
+            ci = (t - si) - y; si = t;
+            ms += vals[3 * q + 2];
+        }
+        sums[2 * s] = sr;
+        sums[2 * s + 1] = si;
+        if (mass) mass[s] = ms;
+    }
+    free(vals);
     return 0;
 }
 

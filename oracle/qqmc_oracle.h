@@ -103,6 +103,24 @@ int oracle_eval_mass(const double *gl, const double *gg, int n_grid,
                      int n_shifts, const double *shifts, double model_tau,
                      int64_t i_begin, int64_t i_end, int n_threads, double *mass);
 
+void oracle_gf_lead(double eps_d, double gamma, double beta, double bias_v, double D, int lead,
+                    double tau, double *out);
+
+int oracle_lead_tables(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int lead, int n_grid, double t_half, double *cl, double *cg);
+
+void oracle_keldysh_sum_lead(const double *gl, const double *gg, const double *cl,
+                             const double *cg, int n_grid, double t_half, double n_sigma,
+                             double alpha, double t_meas, int n, const double *u,
+                             double *S_out, double *M_out);
+
+int oracle_eval_sums_lead(const double *gl, const double *gg, const double *cl,
+                          const double *cg, int n_grid, double t_half, double n_sigma,
+                          double alpha, double t_meas, int n, int log2_n, uint64_t lattice_a,
+                          int n_shifts, const double *shifts, double model_tau,
+                          int64_t i_begin, int64_t i_end, int n_threads, double *sums,
+                          double *mass);
+
 int oracle_max_threads(void);
 
 /* ---- Learned second warp (App. I, "Learning h^(i) from the integrand") ----

@@ -797,3 +797,109 @@ def test_band_tables_grid_and_symmetry(oracle_mod):
         assert abs(gl[256 - j] + np.conj(gl[j])) < 1e-13
     with pytest.raises(ValueError):          # a bound state: |eps_d| >= D - Gamma
         oracle_mod.Tables(1.95, 0.1, 20.0, 0.0, 64, 10.0, half_bandwidth=2.0)
+
+
+# ---------------------------------------------------------------------------
+# The current into a lead (finite bandwidth): the measurement column of the
+# Wick matrices is the lead site, with gamma g^<_{0i}, gamma g^>_{0i} from the
+# Langreth rules; the order-n current coefficient is Re of -4 i^n S.
+# ---------------------------------------------------------------------------
+CUR = dict(eps=0.3, gam=1.0, beta=2.0, V=0.8, D=4.0, t=10.0)
+
+
+@pytest.fixture(scope="module")
+def lead_tables(oracle_mod):
+    c = CUR
+    return {lead: oracle_mod.Tables(c["eps"], c["gam"], c["beta"], c["V"], 16001, c["t"],
+                                    half_bandwidth=c["D"], lead=lead) for lead in (1, 2)}
+
+
+def _landauer(eps, gam, beta, V, D, lead):
+    """Non-interacting current into the lead, both spins, from the
+    transmission T = Gamma_1 Gamma_2 |g^R|^2 with the band broadening
+    Gamma_i(omega) = (Gamma/D) sqrt(D^2 - omega^2) = gamma_t(omega):
+    I_0 = -Int gamma_t A (f_i - f_j) domega/2pi."""
+    g = gam / D
+
+    def integrand(w):
+        s = math.sqrt(max(D * D - w * w, 0.0))
+        A = 2 * g * s / ((w - eps - g * w) ** 2 + (g * s) ** 2)
+        mi, mj = (-V / 2, V / 2) if lead == 1 else (V / 2, -V / 2)
+        fermi = lambda x: 1.0 / (math.exp(min(beta * x, 700.0)) + 1.0)
+        return g * s * A * (fermi(w - mi) - fermi(w - mj))
+    pts = sorted(x for x in {eps, V / 2, -V / 2} if abs(x) < D)
+    return -integrate.quad(integrand, -D, D, points=pts, limit=500, epsabs=1e-14,
+                           epsrel=1e-13)[0] / (2 * math.pi)
+
+
+@pytest.mark.parametrize("eps,gam,beta,V,D", [(0.3, 0.5, 5.0, 0.8, 2.0),
+                                              (-0.4, 1.0, 2.0, 1.5, 4.0),
+                                              (0.0, 0.1, 20.0, 0.3, 2.0)])
+def test_current_order0_landauer(oracle_mod, eps, gam, beta, V, D):
+    """Order 0 of -4 Re(gamma G^<_{0i}(t, t)) is the Landauer current."""
+    for lead in (1, 2):
+        cl, _ = oracle_mod.gf_lead(eps, gam, beta, V, D, lead, 0.0)
+        ref = _landauer(eps, gam, beta, V, D, lead)
+        assert abs(-4.0 * cl.real - ref) <= 1e-12 * abs(ref), (lead, -4.0 * cl.real, ref)
+
+
+def test_current_order1_is_the_hartree_shift(oracle_mod, lead_tables):
+    """At first order the interaction shifts the level by U n_sigma (Hartree;
+    no exchange between equal spins), so in the stationary state
+    I_1 = n_sigma dI_0/deps_d; I_1 by adaptive quadrature of the order-1
+    current integrand, dI_0/deps_d by 5-point differences of the Landauer
+    current."""
+    c = CUR
+
+    def i0(e):
+        return _landauer(e, c["gam"], c["beta"], c["V"], c["D"], 1)
+    d = 1e-3
+    di0 = (8 * (i0(c["eps"] + d) - i0(c["eps"] - d)) - (i0(c["eps"] + 2 * d)
+                                                       - i0(c["eps"] - 2 * d))) / (12 * d)
+    ns = oracle_mod.n_sigma_band(c["eps"], c["gam"], c["beta"], c["V"], c["D"])
+    tb = lead_tables[1]
+    i1 = integrate.quad(lambda u: oracle_mod.current_integrand(tb, c["t"], [u])[0].real,
+                        0, c["t"], limit=400, epsabs=1e-13, epsrel=1e-12)[0]
+    assert abs(i1 - ns * di0) < 5e-7, (i1, ns * di0)
+
+
+def test_current_vanishes_without_bias(oracle_mod):
+    """V = 0: no stationary current at first order (quadrature over the
+    vertex time).  At t = 10 the charging current after the switch-on has
+    decayed to about 1e-7 (the same residual as in the Hartree pin)."""
+    tb = oracle_mod.Tables(0.3, 1.0, 2.0, 0.0, 4001, 10.0, half_bandwidth=4.0, lead=1)
+    i1 = integrate.quad(lambda u: oracle_mod.current_integrand(tb, 10.0, [u])[0].real,
+                        0, 10.0, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+    tb_v = oracle_mod.Tables(0.3, 1.0, 2.0, 0.8, 4001, 10.0, half_bandwidth=4.0, lead=1)
+    i1_v = integrate.quad(lambda u: oracle_mod.current_integrand(tb_v, 10.0, [u])[0].real,
+                          0, 10.0, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+    assert abs(i1) < 5e-7 and abs(i1_v) > 1e-2
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_current_conservation(oracle_mod, lead_tables, n):
+    """Stationary state: what enters lead 1 leaves lead 2, order by order
+    (paired estimates on one lattice)."""
+    c = CUR
+    job = order_job(61, n, 14, 16)
+    q1, _, _, _ = oracle_mod.eval_order_current(lead_tables[1], c["t"], n, 14, job.lattice_a,
+                                                job.shifts, 1.0)
+    q2, _, _, _ = oracle_mod.eval_order_current(lead_tables[2], c["t"], n, 14, job.lattice_a,
+                                                job.shifts, 1.0)
+    s = (q1 + q2).real
+    se = s.std(ddof=1) / math.sqrt(s.size)
+    assert abs(s.mean()) < 5 * se + 1e-6
+    assert abs(q1.mean().real) > 20 * se      # the currents themselves are resolved
+
+
+def test_lead_tables_grid(oracle_mod, lead_tables):
+    tb = lead_tables[1]
+    c = CUR
+    for j in (0, 5000, 8000, 12345, 16000):
+        cl, cg = oracle_mod.gf_lead(c["eps"], c["gam"], c["beta"], c["V"], c["D"], 1,
+                                    tb.grid[j])
+        got_l = tb.cl[2 * j] + 1j * tb.cl[2 * j + 1]
+        got_g = tb.cg[2 * j] + 1j * tb.cg[2 * j + 1]
+        assert abs(got_l - cl) < 1e-15 and abs(got_g - cg) < 1e-15
+    with pytest.raises(ValueError):          # the current needs a finite band
+        oracle_mod.Tables(0.0, 1.0, 2.0, 0.5, 64, 10.0, lead=1)

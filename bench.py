@@ -107,8 +107,18 @@ def run_plain(args):
     n = args.order
     alpha = 0.0
     tau = 1.0
+    mode = qqmc.MODE_CHARGE
     d = TINY_DOT
-    if args.band:
+    if args.current:
+        # the paper's current application (semicircular leads D = 2,
+        # Gamma = 0.1, E_d = 0.9 Gamma, alpha = n_sigma, t = 10/Gamma,
+        # tau = 1.5/Gamma): the current into lead 1
+        d = Dot(0.09, 0.1, 200.0, 0.05, t_meas=100.0, n_grid=65536, t_half=100.0,
+                half_bandwidth=2.0, lead=1)
+        args.alpha = "ns"
+        tau = 15.0
+        mode = qqmc.MODE_CURRENT
+    elif args.band:
         # the paper's finite-bandwidth application: semicircular leads D = 2,
         # Gamma = 0.1, E_d = 0.9 Gamma, alpha = n_sigma, t = 10/Gamma,
         # tau = 1.5/Gamma (bias 0.05, low temperature)
@@ -123,8 +133,10 @@ def run_plain(args):
     tables = qqmc.make_tables(d)
     if args.alpha is not None:
         alpha = qqmc.tables_export(tables)[2] if args.alpha == "ns" else float(args.alpha)
-    job = order_job(1, n, args.log2n, args.shifts, model_tau=tau, alpha=alpha)
+    job = order_job(1, n, args.log2n, args.shifts, model_tau=tau, mode=mode, alpha=alpha)
     tflops = pair_tree_flops(n) if alpha != 0.0 else tree_flops(n)
+    if mode == qqmc.MODE_CURRENT:
+        tflops += 16 * n        # the lead-function lookups of the measurement column
     N = 1 << args.log2n
     points = N * args.shifts
     if args.copy_bytes:
@@ -158,10 +170,12 @@ def run_plain(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "charge coefficient Q_n of the %s Anderson dot "
+        "config": {"workload": "%s of the %s Anderson dot "
                                "(Gamma=%g, eps_d=%g, beta=%g, V=%g, t=%g%s), order %d, "
                                "Korobov lattice N=2^%d x %d random shifts, tau=%g"
-                               % ("semicircular-lead (D=%g)" % d.half_bandwidth
+                               % ("current coefficient I_n into lead 1"
+                                  if mode == qqmc.MODE_CURRENT else "charge coefficient Q_n",
+                                  "semicircular-lead (D=%g)" % d.half_bandwidth
                                   if d.half_bandwidth else "wide-band",
                                   d.gamma, d.eps_d, d.beta, d.bias_v, d.t_meas,
                                   ", alpha=%.6g, paired tree" % alpha if alpha else "",
@@ -473,6 +487,9 @@ def main():
                     choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--current", action="store_true",
+                    help="plain workload: the current on the paper's finite-bandwidth "
+                         "parameters")
     ap.add_argument("--band", action="store_true",
                     help="plain workload on the paper's finite-bandwidth parameters")
     ap.add_argument("--alpha", default=None,

@@ -60,6 +60,9 @@ typedef struct {
     double half_bandwidth; /* D; 0 or +INFINITY: wide band.  A finite D
                               needs |eps_d| < D - gamma (no bound state
                               outside the band; EINVAL otherwise)        */
+    int32_t lead;    /* 0; or 1 (chemical potential -V/2) / 2 (+V/2): also
+                        tabulate that lead's dot-lead functions for
+                        QQMC_MODE_CURRENT (needs a finite D)                */
 } qqmc_dot;
 
 typedef struct qqmc_tables_s *qqmc_tables;
@@ -69,7 +72,14 @@ enum {
     QQMC_MODE_CHARGE = 0,   /* -2 i^{n+1} S(u) W: the charge coefficient      */
     QQMC_MODE_MODEL = 1,    /* f := p_n over the whole v-domain: every sample
                                equals C = tau^n (warp/estimator self-test)    */
-    QQMC_MODE_CONSTANT = 2  /* f := 1 on the ordered simplex: t^n/n!          */
+    QQMC_MODE_CONSTANT = 2, /* f := 1 on the ordered simplex: t^n/n!          */
+    QQMC_MODE_CURRENT = 3   /* -4 i^n S(u) W with the measurement column on
+                               the lead site (tables made with dot.lead = i):
+                               the real part is the order-n particle current
+                               from the dot into lead i, both spins, i.e.
+                               -4 Re gamma G^<_{0i}(t, t) (App. E); single
+                               launches only (no learned warp, plan or
+                               server)                                        */
 };
 
 /* A learned second warp (App. I, "Learning h^(i) from the integrand"): per
@@ -149,6 +159,20 @@ qqmc_status qqmc_tables_info(qqmc_tables t, int32_t *n_grid, double *t_half);
 /* Releases the handle and its device memory.  NULL is ignored. */
 void qqmc_free_tables(qqmc_tables t);
 
+/* Dot-lead functions of lead i for the current (App. E; finite bandwidth):
+ * with Sigma_i = Delta/2 and the Langreth rules for g_{0i} = g_{00} gamma G_i,
+ *   gamma g^<_{0i}(omega) = conj(Delta)/2 g^< + Sigma^<_i g^R,
+ *   gamma g^>_{0i}(omega) = conj(Delta)/2 g^> + Sigma^>_i g^R,
+ *   Sigma^<_i = -i f_i Im Delta,  Sigma^>_i = i (1 - f_i) Im Delta,
+ * Fourier transformed on the dot's grid by the band rule of
+ * qqmc_make_tables.  Host-only: fills cl, cg (2*n_grid doubles each).
+ * EINVAL unless dot->lead is 1 or 2 and the band is finite and valid. */
+qqmc_status qqmc_lead_tables_compute_host(const qqmc_dot *dot, double *cl, double *cg);
+
+/* Attaches caller lead functions (host arrays as above, same grid as t) to
+ * existing tables, replacing any there; synchronous. */
+qqmc_status qqmc_tables_lead_from_host(qqmc_tables t, const double *cl, const double *cg);
+
 /* ---- The hot path -------------------------------------------------------
  * qqmc_eval_order: estimates Q_n (Eq. (warped_int2), randomised over shifts
  * as in App. G).  Launches the integrand kernel over all N x K points on
@@ -184,6 +208,9 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
 /* Per-point integrand f_n(u) = -2 i^{n+1} S(u) of Eq. (integral_gf) (the
  * integrand of Q_n over the ordered simplex, without warping weight).
  *   alpha   interaction shift, as in qqmc_order (finite)
+ *   observable  QQMC_OBS_CHARGE: f_n as above; QQMC_OBS_CURRENT: -4 i^n S(u)
+ *           with the lead site in the measurement column (tables with lead
+ *           functions)
  *   u       device, n_points x order row-major, vertex times (u_1..u_n)
  *   f       device, 2*n_points doubles (re, im)
  *   method  QQMC_METHOD_TREE: the production kernel; requires
@@ -194,9 +221,10 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
  *           (within the table range).
  * Asynchronous on `stream`. */
 enum { QQMC_METHOD_TREE = 0, QQMC_METHOD_DIRECT = 1 };
+enum { QQMC_OBS_CHARGE = 0, QQMC_OBS_CURRENT = 1 };
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
-                             double alpha, const double *u, int64_t n_points,
-                             int32_t method, double *f, void *stream);
+                             double alpha, int32_t observable, const double *u,
+                             int64_t n_points, int32_t method, double *f, void *stream);
 
 /* ---- Learned second warp (App. I) ---------------------------------------
  * Learning: the library evaluates the order-n integrand f~ (exponential warp

@@ -663,7 +663,12 @@ static void build_up(const wick_ctx *w, const int *a, cplx *m)
     int np1 = w->n + 1;
     for (int r = 0; r < np1; ++r) {
         for (int c = 0; c < np1; ++c) {
-            if (r == c) { m[r * np1 + c] = r == 0 ? w->gm : w->g0; continue; }
+            if (r == c) {
+                /* the corner (0,t,0)-(i,t,1) is the lead function at 0 for the
+                 * current; it cancels from the Keldysh sum in any case */
+                m[r * np1 + c] = r == 0 ? (w->cl_d ? w->cl_d[0] : w->gm) : w->g0;
+                continue;
+            }
             int ar = r == 0 ? 0 : a[r - 1];
             int ac = c == 0 ? 1 : a[c - 1];
             m[r * np1 + c] = keldysh_entry(w, r, ar, c, ac);

@@ -49,8 +49,10 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
         return set_error(QQMC_EINVAL, "model_tau must be positive");
     if (!(ord->t_meas > 0.0) || !(ord->t_meas <= t_half))
         return set_error(QQMC_EINVAL, "t_meas must satisfy 0 < t_meas <= t_half of the tables");
-    if (ord->mode < QQMC_MODE_CHARGE || ord->mode > QQMC_MODE_CONSTANT)
+    if (ord->mode < QQMC_MODE_CHARGE || ord->mode > QQMC_MODE_CURRENT)
         return set_error(QQMC_EINVAL, "unknown mode");
+    if (ord->mode == QQMC_MODE_CURRENT && ord->model)
+        return set_error(QQMC_EINVAL, "the current has no learned warp");
     if (ord->model && (ord->model->order != n || !ord->model->d_cdf))
         return set_error(QQMC_EINVAL, "model of another order");
     if (!std::isfinite(ord->alpha)) return set_error(QQMC_EINVAL, "alpha must be finite");
@@ -109,6 +111,7 @@ void fill_item_tables(ItemDesc &d, const qqmc_tables_s *t)
      * diagonal cancels from the Keldysh sum and is never formed here */
     d.g0x = 0.0;
     d.g0y = t->n_sigma - d.alpha;
+    d.col = t->d_col;
 }
 
 qqmc_status upload_tables(const double *tab4, int32_t n_grid, double t_half, double n_sigma,
@@ -173,6 +176,8 @@ static qqmc_status check_dot(const qqmc_dot *dot)
     if (finite_band(dot) && !(std::fabs(dot->eps_d) < dot->half_bandwidth - dot->gamma))
         return set_error(QQMC_EINVAL,
                          "finite band needs |eps_d| < D - gamma (no bound state outside the band)");
+    if (dot->lead != 0 && !((dot->lead == 1 || dot->lead == 2) && finite_band(dot)))
+        return set_error(QQMC_EINVAL, "lead must be 0, or 1 or 2 with a finite half_bandwidth");
     return QQMC_OK;
 }
 
@@ -211,7 +216,24 @@ qqmc_status qqmc_make_tables(const qqmc_dot *dot, void *stream, qqmc_tables *out
         const double nsb = build_tables_band(dot->eps_d, dot->gamma, dot->beta, dot->bias_v,
                                              dot->half_bandwidth, dot->n_grid, dot->t_half,
                                              tab.data());
-        return upload_tables(tab.data(), dot->n_grid, dot->t_half, nsb, s, out);
+        qqmc_tables t = nullptr;
+        if (qqmc_status st = upload_tables(tab.data(), dot->n_grid, dot->t_half, nsb, s, &t))
+            return st;
+        if (dot->lead) {
+            build_lead_tables(dot->eps_d, dot->gamma, dot->beta, dot->bias_v,
+                              dot->half_bandwidth, dot->lead, dot->n_grid, dot->t_half,
+                              tab.data());
+            hipError_t e = hipMalloc(&t->d_col, sizeof(double) * tab.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(t->d_col, tab.data(), sizeof(double) * tab.size(),
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                qqmc_free_tables(t);
+                return hip_error(e, "lead table upload");
+            }
+        }
+        *out = t;
+        return QQMC_OK;
     }
     const double ns = occupation_per_spin(dot->eps_d, dot->gamma, dot->beta, dot->bias_v);
     if (std::isinf(dot->beta)) {
@@ -288,7 +310,44 @@ void qqmc_free_tables(qqmc_tables t)
 {
     if (!t) return;
     if (t->d_tab) hipFree(t->d_tab);
+    if (t->d_col) hipFree(t->d_col);
     delete t;
+}
+
+qqmc_status qqmc_lead_tables_compute_host(const qqmc_dot *dot, double *cl, double *cg)
+{
+    if (qqmc_status st = check_dot(dot)) return st;
+    if (!cl || !cg) return set_error(QQMC_EINVAL, "NULL output");
+    if (dot->lead != 1 && dot->lead != 2) return set_error(QQMC_EINVAL, "lead must be 1 or 2");
+    std::vector<double> tab(4 * (size_t)dot->n_grid);
+    build_lead_tables(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->half_bandwidth,
+                      dot->lead, dot->n_grid, dot->t_half, tab.data());
+    for (int32_t j = 0; j < dot->n_grid; ++j) {
+        cl[2 * j] = tab[4 * j];
+        cl[2 * j + 1] = tab[4 * j + 1];
+        cg[2 * j] = tab[4 * j + 2];
+        cg[2 * j + 1] = tab[4 * j + 3];
+    }
+    return QQMC_OK;
+}
+
+qqmc_status qqmc_tables_lead_from_host(qqmc_tables t, const double *cl, const double *cg)
+{
+    if (qqmc_status st = check_tables(t)) return st;
+    if (!cl || !cg) return set_error(QQMC_EINVAL, "NULL argument");
+    std::vector<double> tab(4 * (size_t)t->n_grid);
+    for (int32_t j = 0; j < t->n_grid; ++j) {
+        tab[4 * j + 0] = cl[2 * j];
+        tab[4 * j + 1] = cl[2 * j + 1];
+        tab[4 * j + 2] = cg[2 * j];
+        tab[4 * j + 3] = cg[2 * j + 1];
+    }
+    hipError_t e = hipSuccess;
+    if (!t->d_col) e = hipMalloc(&t->d_col, sizeof(double) * tab.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(t->d_col, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "lead table upload");
+    return QQMC_OK;
 }
 
 qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord, int32_t tile_len,
@@ -302,6 +361,8 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord, int32_t 
     const int64_t N = (int64_t)1 << ord->log2_n;
     ItemDesc d = v.desc;
     fill_item_tables(d, t);
+    if (d.mode == QQMC_MODE_CURRENT && !d.col)
+        return set_error(QQMC_EINVAL, "the current needs tables with lead functions");
     if (tile_len == 0) tile_len = default_tile_len(d, N);
     if (tile_len < 64 || tile_len % 64 != 0 || N % tile_len != 0)
         return set_error(QQMC_EINVAL, "tile_len must be a multiple of 64 dividing N");
@@ -380,8 +441,8 @@ qqmc_status qqmc_eval_order(qqmc_tables t, const qqmc_order *ord, void *stream,
 }
 
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double alpha,
-                             const double *u, int64_t n_points, int32_t method, double *f,
-                             void *stream)
+                             int32_t observable, const double *u, int64_t n_points,
+                             int32_t method, double *f, void *stream)
 {
     if (qqmc_status st = check_tables(t)) return st;
     if (order < 1 || order > QQMC_MAX_ORDER) return set_error(QQMC_EINVAL, "bad order");
@@ -390,17 +451,22 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double
     if (!(t_meas > 0.0) || !(t_meas <= t->t_half))
         return set_error(QQMC_EINVAL, "t_meas must satisfy 0 < t_meas <= t_half");
     if (!std::isfinite(alpha)) return set_error(QQMC_EINVAL, "alpha must be finite");
+    if (observable != QQMC_OBS_CHARGE && observable != QQMC_OBS_CURRENT)
+        return set_error(QQMC_EINVAL, "unknown observable");
+    if (observable == QQMC_OBS_CURRENT && !t->d_col)
+        return set_error(QQMC_EINVAL, "the current needs tables with lead functions");
+    const double *col = observable == QQMC_OBS_CURRENT ? t->d_col : nullptr;
     if (method != QQMC_METHOD_TREE && method != QQMC_METHOD_DIRECT)
         return set_error(QQMC_EINVAL, "unknown method");
     if (n_points == 0) return QQMC_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (method == QQMC_METHOD_TREE)
-        e = launch_points_tree(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, alpha, order,
-                               t_meas, u, n_points, f, s);
+        e = launch_points_tree(t->d_tab, col, t->n_grid, t->t_half, t->h, t->n_sigma, alpha,
+                               order, t_meas, u, n_points, f, s);
     else if (method == QQMC_METHOD_DIRECT)
-        e = launch_points_direct(t->d_tab, t->n_grid, t->t_half, t->h, t->n_sigma, alpha, order,
-                                 t_meas, u, n_points, f, s);
+        e = launch_points_direct(t->d_tab, col, t->n_grid, t->t_half, t->h, t->n_sigma, alpha,
+                                 order, t_meas, u, n_points, f, s);
     else
         return set_error(QQMC_EINVAL, "unknown method");
     if (e != hipSuccess) return hip_error(e, "qqmc_eval_points launch");

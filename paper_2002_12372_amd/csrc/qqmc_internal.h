@@ -32,6 +32,7 @@ struct ItemDesc {
     int32_t pad_;
     double *sample_out;      /* device: per-point Re fbar (learning pass), or null */
     double alpha;            /* interaction shift U (n_up - alpha)(n_dn - alpha) */
+    const double *col;       /* device: lead functions for the current, or null */
 };
 
 /* Batched-kernel selector of an item, 1 .. 2 QQMC_MAX_ORDER: its order,
@@ -59,11 +60,12 @@ hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
                                const int64_t *shift_base_dev,
                                double *shift_sums, int32_t total_shifts,
                                hipStream_t s);
-hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half,
-                              double h, double n_sigma, double alpha, int32_t order,
+hipError_t launch_points_tree(const double *tab, const double *col, int32_t n_grid,
+                              double t_half, double h, double n_sigma, double alpha,
+                              int32_t order,
                               double t_meas, const double *u, int64_t n_points,
                               double *f, hipStream_t s);
-hipError_t launch_points_direct(const double *tab, int32_t n_grid,
+hipError_t launch_points_direct(const double *tab, const double *col, int32_t n_grid,
                                 double t_half, double h, double n_sigma, double alpha,
                                 int32_t order, double t_meas, const double *u,
                                 int64_t n_points, double *f, hipStream_t s);
@@ -95,6 +97,10 @@ void build_tables_host(double eps_d, double gamma, double beta, double bias_v,
  * above and returns n_sigma. */
 double build_tables_band(double eps_d, double gamma, double beta, double bias_v, double D,
                          int32_t n_grid, double t_half, double *tab);
+/* Lead functions gamma g^<_{0i}, gamma g^>_{0i} of lead i (1: mu = -V/2,
+ * 2: +V/2) on the same grid, same layout. */
+void build_lead_tables(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int32_t lead, int32_t n_grid, double t_half, double *tab);
 /* Finite bandwidth requested (0 and +infinity mean the wide band). */
 inline bool finite_band(const qqmc_dot *d)
 {
@@ -116,6 +122,7 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid,
 
 struct qqmc_tables_s {
     double *d_tab = nullptr;   /* 4*n_grid doubles: (g<re, g<im, g>re, g>im) */
+    double *d_col = nullptr;   /* lead functions, same layout, or null       */
     int32_t n_grid = 0;
     double t_half = 0.0, h = 0.0, n_sigma = 0.0;
     int device = 0;

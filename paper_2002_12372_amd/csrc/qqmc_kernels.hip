@@ -31,8 +31,11 @@ namespace {
 
 constexpr int WAVE = 64;
 
-template <int N, bool PAIR = false> struct Lds {
+template <int N, bool PAIR = false, bool CUR = false> struct Lds {
     using Gm = Geo<N, PAIR>;
+    /* pair-table stride: the NP pairs, then for the current the n lead
+     * values of the measurement column */
+    static constexpr int NPS = Gm::NP + (CUR ? N : 0);
     static constexpr int times = 0;                                    /* 64*N doubles   */
     static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
     static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
@@ -44,7 +47,7 @@ template <int N, bool PAIR = false> struct Lds {
     static constexpr int pairs = ids + 64 * 4;                         /* tables*NP pairv */
     /* one broadcast row per group (two for the paired tree) */
     static constexpr int rows = PAIR ? 2 : 1;
-    static constexpr int row = pairs + tables * Gm::NP * 32;   /* rows*PPW*(N+1) cplx */
+    static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
 };
@@ -93,6 +96,21 @@ template <int N> __device__ __forceinline__ cplx charge_prefactor(cplx s)
     else return cmk(-2.0 * s.y, 2.0 * s.x);
 }
 
+/* -4 i^n S: its real part is the order-n integrand of the particle current
+ * into the lead (both spins); the charge's is -2 i^{n+1} S. */
+template <int N, bool CUR> __device__ __forceinline__ cplx observable_prefactor(cplx s)
+{
+    if constexpr (!CUR) {
+        return charge_prefactor<N>(s);
+    } else {
+        constexpr int q = N & 3;
+        if constexpr (q == 0) return cmk(-4.0 * s.x, -4.0 * s.y);
+        else if constexpr (q == 1) return cmk(4.0 * s.y, -4.0 * s.x);
+        else if constexpr (q == 2) return cmk(4.0 * s.x, 4.0 * s.y);
+        else return cmk(-4.0 * s.y, 4.0 * s.x);
+    }
+}
+
 struct Kahan {
     double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
     __device__ __forceinline__ void add(cplx v)
@@ -123,6 +141,8 @@ struct Env {
     double t_half, inv_h, t_meas;
     cplx g0;      /* vertex diagonal i (n_sigma - alpha)                      */
     cplx gm;      /* measurement diagonal i n_sigma (the direct method only)  */
+    const double *col; /* current: the lead's gamma g^<_{0i}, gamma g^>_{0i}
+                          on the same grid, or null (the charge)            */
     int n_grid;
 };
 
@@ -131,9 +151,9 @@ struct Env {
  * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
  * 9 x 9 trailing correction block in s_c0 and returns the product of the
  * OFF pivots. */
-template <int N>
-__device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_row,
-                          cplx *s_c0)
+template <int N, bool CUR = false>
+__device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
+                          cplx *s_row, cplx *s_c0)
 {
     using Gm = Geo<N>;
     constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
@@ -155,7 +175,8 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
                  * might alias */
                 cplx v[N + 1];
 #pragma unroll
-                for (int j = k + 1; j <= N; ++j) v[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
+                for (int j = k + 1; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
                 s_row[k] = csub(g0, crow[m][k]);
 #pragma unroll
                 for (int j = k + 1; j <= N; ++j) s_row[j] = v[j];
@@ -194,9 +215,9 @@ __device__ cplx top_block(const pairv *pr, int top, int sub, cplx g0, cplx *s_ro
  * s_row (2 (n+1) entries); every lane applies the rank-2 update to its rows
  * below.  Leaves the K x K trailing correction block in s_c0 and returns the
  * product of the pivot-block determinants. */
-template <int N>
-__device__ cplx top_block_pair(const pairv *pr, int top, int sub, cplx g0, cplx *s_row,
-                               cplx *s_c0)
+template <int N, bool CUR = false>
+__device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
+                               cplx *s_row, cplx *s_c0)
 {
     using Gm = Geo<N, true>;
     constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
@@ -217,7 +238,8 @@ __device__ cplx top_block_pair(const pairv *pr, int top, int sub, cplx g0, cplx 
             if (r == k) {
                 cplx v[N + 1];
 #pragma unroll
-                for (int j = k + 1; j <= N; ++j) v[j] = csub(wick_entry(pr, k, j, b), crow[m][j]);
+                for (int j = k + 1; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
                 s_r0[k] = csub(g0, crow[m][k]);
 #pragma unroll
                 for (int j = k + 1; j <= N; ++j) s_r0[j] = v[j];
@@ -226,7 +248,8 @@ __device__ cplx top_block_pair(const pairv *pr, int top, int sub, cplx g0, cplx 
                 cplx v[N + 1];
                 v[k] = csub(wick_entry(pr, k + 1, k, b), crow[m][k]);
 #pragma unroll
-                for (int j = k + 2; j <= N; ++j) v[j] = csub(wick_entry(pr, k + 1, j, bq), crow[m][j]);
+                for (int j = k + 2; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k + 1, j, N, bq), crow[m][j]);
                 s_r1[k + 1] = csub(g0, crow[m][k + 1]);
                 s_r1[k] = v[k];
 #pragma unroll
@@ -268,11 +291,12 @@ __device__ cplx top_block_pair(const pairv *pr, int top, int sub, cplx g0, cplx 
 
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
-template <int N, bool PAIR = false>
+template <int N, bool PAIR = false, bool CUR = false>
 __device__ void keldysh_points(int cnt, const Env &env, char *lds)
 {
     using Gm = Geo<N, PAIR>;
-    using L = Lds<N, PAIR>;
+    using L = Lds<N, PAIR, CUR>;
+    constexpr int NPS = L::NPS;
     const double *s_times = reinterpret_cast<const double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
     pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
@@ -289,9 +313,9 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             /* one point per group: the group's lanes build its pair table;
              * the loop is unrolled so every table load is issued before the
              * first interpolation waits */
-            prg = s_pairs + grp * Gm::NP;
+            prg = s_pairs + grp * NPS;
             const double *tm = s_times + pt * N;
-            constexpr int PER = (Gm::NP + Gm::G - 1) / Gm::G;
+            constexpr int PER = (NPS + Gm::G - 1) / Gm::G;
             pairv val[PER];
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
@@ -300,12 +324,18 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                     const int j = pair_hi(q), i = q - j * (j - 1) / 2;
                     const double tj = j == N ? env.t_meas : tm[j];
                     val[k] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
+                } else if (CUR && q < NPS) {
+                    /* the lead values of vertex q - NP, held as -conj */
+                    const pairv c = interp_pair(env.col, env.n_grid, env.t_half, env.inv_h,
+                                                tm[q - Gm::NP] - env.t_meas);
+                    val[k].gl = cnc(c.gl);
+                    val[k].gg = cnc(c.gg);
                 }
             }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int q = sub + k * Gm::G;
-                if (q < Gm::NP) prg[q] = val[k];
+                if (q < NPS) prg[q] = val[k];
             }
             wave_sync();
         } else {
@@ -313,20 +343,31 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
              * (base is a multiple of IPP whenever PTS > 1); their pair
              * tables are built by the whole wave when the points change */
             constexpr int PTS = Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1;
-            prg = s_pairs + (grp / Gm::IPP) * Gm::NP;
+            prg = s_pairs + (grp / Gm::IPP) * NPS;
             if (PTS > 1 || base % Gm::IPP == 0) {
                 const int first = base / Gm::IPP;
-                for (int q = lane; q < PTS * Gm::NP; q += WAVE) {
-                    const int slot = q / Gm::NP, qq = q % Gm::NP;
+                for (int q = lane; q < PTS * NPS; q += WAVE) {
+                    const int slot = q / NPS, qq = q % NPS;
                     const int p = first + slot < cnt ? first + slot : 0;
                     const double *tm = s_times + p * N;
-                    const int j = pair_hi(qq), i = qq - j * (j - 1) / 2;
-                    const double tj = j == N ? env.t_meas : tm[j];
-                    s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
+                    if (!CUR || qq < Gm::NP) {
+                        const int j = pair_hi(qq), i = qq - j * (j - 1) / 2;
+                        const double tj = j == N ? env.t_meas : tm[j];
+                        s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h,
+                                                 tj - tm[i]);
+                    } else {
+                        const pairv c = interp_pair(env.col, env.n_grid, env.t_half, env.inv_h,
+                                                    tm[qq - Gm::NP] - env.t_meas);
+                        s_pairs[q].gl = cnc(c.gl);
+                        s_pairs[q].gg = cnc(c.gg);
+                    }
                 }
                 wave_sync();
             }
         }
+        /* measurement-column entries: the lead values for the current, the
+         * last row of the pair table (pairs (k, n)) for the charge */
+        const pairv *mc = prg + (CUR ? Gm::NP : pidx(0, N));
         cplx prod = cmk(1.0, 0.0);
         int sgn = 0;
         BlockSrc<N, PAIR> src;
@@ -334,14 +375,14 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         if constexpr (Gm::OFF > 0) {
             cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
-            if constexpr (PAIR) prod = top_block_pair<N>(prg, top, sub, env.g0, s_row, s_c0);
-            else prod = top_block<N>(prg, top, sub, env.g0, s_row, s_c0);
+            if constexpr (PAIR) prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
+            else prod = top_block<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;
         }
         cplx s;
-        if constexpr (PAIR) s = lane_sum_pair<N>(prg, src, sub, prod, sgn, env.g0);
-        else s = lane_sum<N>(prg, src, sub, prod, sgn, env.g0);
+        if constexpr (PAIR) s = lane_sum_pair<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        else s = lane_sum<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
         /* sum over the lanes of a group, then over the groups of the round
          * that share a point: they are SPAN aligned consecutive lanes, all
          * active or all idle (points hold IPP consecutive items and rounds
@@ -383,10 +424,10 @@ __device__ __forceinline__ double model_inverse(const double *__restrict__ c, in
  * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
  * learning pass): also writes Re fbar of every lattice index of the tile to
  * it.sample_out. */
-template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false>
+template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = false>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
-    using L = Lds<N, PAIR>;
+    using L = Lds<N, PAIR, CUR>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     double *s_w = reinterpret_cast<double *>(lds + L::w);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
@@ -402,6 +443,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     Env env;
     env.tab = it.tab; env.t_half = it.t_half; env.inv_h = 1.0 / it.h; env.t_meas = it.t_meas;
     env.g0 = cmk(it.g0x, it.g0y); env.gm = cmk(it.g0x, it.g0y + it.alpha);
+    env.col = it.col;
     env.n_grid = it.n_grid;
     Kahan acc;
     for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
@@ -425,7 +467,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
         double W = it.tau_n / p;
         if constexpr (MODEL) W /= qm;
         const bool inside = u[N - 1] > 0.0;
-        if (it.mode != QQMC_MODE_CHARGE) {
+        if (!CUR && it.mode != QQMC_MODE_CHARGE) {
             /* the model function is the combined one, p_n prod_j q_j */
             if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * qm * W, 0.0));
             else if (inside) acc.add(cmk(W, 0.0));
@@ -444,9 +486,9 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             it.sample_out[idx] = 0.0;
         }
         wave_sync();
-        keldysh_points<N, PAIR>(cnt, env, lds);
+        keldysh_points<N, PAIR, CUR>(cnt, env, lds);
         if (lane < cnt) {
-            const cplx f = charge_prefactor<N>(s_S[lane]);
+            const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
             const double w = s_w[lane];
             acc.add(cmk(f.x * w, f.y * w));
             if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
@@ -456,12 +498,12 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     return wave_sum(acc.value());
 }
 
-template <int N, bool MODEL, bool PAIR>
+template <int N, bool MODEL, bool PAIR, bool CUR = false>
 __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
-        const cplx v = order_tile<N, MODEL, false, PAIR>(it, tile, lds);
+        const cplx v = order_tile<N, MODEL, false, PAIR, CUR>(it, tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * tile] = v.x;
             it.tile_sums[2 * tile + 1] = v.y;
@@ -514,12 +556,12 @@ __global__ void __launch_bounds__(256) shift_reduce_kernel(const ItemDesc *items
 }
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
-template <int N, bool PAIR>
+template <int N, bool PAIR, bool CUR>
 __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(Env env, const double *u,
                                                               int64_t n_points, double *f)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    using L = Lds<N, PAIR>;
+    using L = Lds<N, PAIR, CUR>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
     const int lane = threadIdx.x;
@@ -546,10 +588,10 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(En
             s_S[rk] = cmk(0.0, 0.0);
         }
         wave_sync();
-        keldysh_points<N, PAIR>(cnt, env, lds);
+        keldysh_points<N, PAIR, CUR>(cnt, env, lds);
         if (row < n_points) {
             cplx v = cmk(__builtin_nan(""), __builtin_nan(""));
-            if (ok) v = charge_prefactor<N>(s_S[rk]);
+            if (ok) v = observable_prefactor<N, CUR>(s_S[rk]);
             f[2 * row] = v.x;
             f[2 * row + 1] = v.y;
         }
@@ -608,7 +650,9 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
         __syncthreads();
         for (int q = lane; q < NP1 * NP1; q += WAVE) {
             const int r = q / NP1, c = q % NP1;
-            s_g[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, s_tm[r] - s_tm[c]);
+            /* the current's measurement column is the lead site */
+            const double *tab = (c == 0 && env.col) ? env.col : env.tab;
+            s_g[q] = interp_pair(tab, env.n_grid, env.t_half, env.inv_h, s_tm[r] - s_tm[c]);
         }
         __syncthreads();
         Kahan acc;
@@ -618,7 +662,7 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
                 for (int c = 0; c < NP1; ++c) {
                     cplx v;
                     if (r == c) {
-                        v = r == 0 ? env.gm : env.g0;
+                        v = r == 0 ? (env.col ? s_g[0].gl : env.gm) : env.g0;
                     } else {
                         const int al = r == 0 ? 0 : (a >> (r - 1)) & 1;
                         const int be = c == 0 ? 1 : (a >> (c - 1)) & 1;
@@ -651,7 +695,8 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
             __syncthreads();
         }
         if (lane == 0) {
-            const cplx out = charge_prefactor<N>(cmk(sx[0], sy[0]));
+            const cplx out = env.col ? observable_prefactor<N, true>(cmk(sx[0], sy[0]))
+                                     : charge_prefactor<N>(cmk(sx[0], sy[0]));
             f[2 * pt] = out.x;
             f[2 * pt + 1] = out.y;
         }
@@ -767,7 +812,10 @@ template <int N> struct OrderLaunch {
     template <bool PAIR> static hipError_t go(const ItemDesc &it, hipStream_t s)
     {
         const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-        if (it.model_cdf)
+        if (it.mode == QQMC_MODE_CURRENT)   /* no learned warp (checked on the host) */
+            hipLaunchKernelGGL((order_kernel<N, false, PAIR, true>), dim3((unsigned)blocks),
+                               dim3(64), (Lds<N, PAIR, true>::bytes), s, it);
+        else if (it.model_cdf)
             hipLaunchKernelGGL((order_kernel<N, true, PAIR>), dim3((unsigned)blocks), dim3(64),
                                (Lds<N, PAIR>::bytes), s, it);
         else
@@ -802,8 +850,12 @@ template <int N> struct TreePointsLaunch {
         int64_t blocks = (n_points + WAVE - 1) / WAVE;
         if (blocks > 65536) blocks = 65536;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((points_tree_kernel<N, PAIR>), dim3((unsigned)blocks), dim3(64),
-                           (Lds<N, PAIR>::bytes), s, env, u, n_points, f);
+        if (env.col)
+            hipLaunchKernelGGL((points_tree_kernel<N, PAIR, true>), dim3((unsigned)blocks),
+                               dim3(64), (Lds<N, PAIR, true>::bytes), s, env, u, n_points, f);
+        else
+            hipLaunchKernelGGL((points_tree_kernel<N, PAIR, false>), dim3((unsigned)blocks),
+                               dim3(64), (Lds<N, PAIR>::bytes), s, env, u, n_points, f);
         return hipGetLastError();
     }
     static hipError_t run(Env env, bool pair, const double *u, int64_t n_points, double *f,
@@ -825,11 +877,12 @@ template <int N> struct DirectPointsLaunch {
     }
 };
 
-Env make_env(const double *tab, int32_t n_grid, double t_half, double h, double n_sigma,
-             double alpha, double t_meas)
+Env make_env(const double *tab, const double *col, int32_t n_grid, double t_half, double h,
+             double n_sigma, double alpha, double t_meas)
 {
     Env e;
     e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.inv_h = 1.0 / h; e.t_meas = t_meas;
+    e.col = col;
     e.g0 = cmk(0.0, n_sigma - alpha);
     e.gm = cmk(0.0, n_sigma);
     return e;
@@ -865,24 +918,25 @@ hipError_t launch_shift_reduce(const ItemDesc *items_dev, int32_t n_items,
     return hipGetLastError();
 }
 
-hipError_t launch_points_tree(const double *tab, int32_t n_grid, double t_half, double h,
-                              double n_sigma, double alpha, int32_t order, double t_meas,
-                              const double *u, int64_t n_points, double *f, hipStream_t s)
+hipError_t launch_points_tree(const double *tab, const double *col, int32_t n_grid,
+                              double t_half, double h, double n_sigma, double alpha,
+                              int32_t order, double t_meas, const double *u, int64_t n_points,
+                              double *f, hipStream_t s)
 {
     if (n_points <= 0) return hipSuccess;
     return dispatch<TreePointsLaunch>(order,
-                                      make_env(tab, n_grid, t_half, h, n_sigma, alpha, t_meas),
+                                      make_env(tab, col, n_grid, t_half, h, n_sigma, alpha, t_meas),
                                       alpha != 0.0, u, n_points, f, s);
 }
 
-hipError_t launch_points_direct(const double *tab, int32_t n_grid, double t_half,
-                                double h, double n_sigma, double alpha, int32_t order,
-                                double t_meas, const double *u, int64_t n_points, double *f,
-                                hipStream_t s)
+hipError_t launch_points_direct(const double *tab, const double *col, int32_t n_grid,
+                                double t_half, double h, double n_sigma, double alpha,
+                                int32_t order, double t_meas, const double *u, int64_t n_points,
+                                double *f, hipStream_t s)
 {
     if (n_points <= 0) return hipSuccess;
     return dispatch<DirectPointsLaunch>(order,
-                                        make_env(tab, n_grid, t_half, h, n_sigma, alpha, t_meas),
+                                        make_env(tab, col, n_grid, t_half, h, n_sigma, alpha, t_meas),
                                         u, n_points, f, s);
 }
 

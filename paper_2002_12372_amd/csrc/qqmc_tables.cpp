@@ -173,6 +173,7 @@ namespace {
  * e^{-i omega t_half}.  Both functions come from the same nodes. */
 struct BandRule {
     std::vector<double> omega, weight, fbar; /* weight includes D sin theta A / 2pi */
+    std::vector<double> measure;              /* the same without A                 */
 };
 
 BandRule band_rule(double eps_d, double gamma, double beta, double bias_v, double D,
@@ -237,6 +238,7 @@ BandRule band_rule(double eps_d, double gamma, double beta, double bias_v, doubl
                 }
                 r.omega.push_back(w);
                 r.weight.push_back(0.5 * len * gw[i] * D * std::sin(th) * A / (2.0 * kPiGF));
+                r.measure.push_back(0.5 * len * gw[i] * D * std::sin(th) / (2.0 * kPiGF));
                 r.fbar.push_back(fb);
             }
         }
@@ -316,6 +318,59 @@ double build_tables_band(double eps_d, double gamma, double beta, double bias_v,
     work(0);
     for (auto &th : pool) th.join();
     return n_sigma;
+}
+
+void build_lead_tables(double eps_d, double gamma, double beta, double bias_v, double D,
+                       int32_t lead, int32_t n_grid, double t_half, double *tab)
+{
+    /* gamma g^<_{0i} = conj(Delta)/2 g^< + Sigma^<_i g^R,
+     * gamma g^>_{0i} = conj(Delta)/2 g^> + Sigma^>_i g^R, with
+     * Sigma^<_i = -i f_i Im Delta, Sigma^>_i = i (1 - f_i) Im Delta, per node
+     * of the band rule (its panels already meet both Fermi levels) */
+    const BandRule r = band_rule(eps_d, gamma, beta, bias_v, D, t_half);
+    const size_t m = r.omega.size();
+    const double mu = lead == 1 ? -0.5 * bias_v : 0.5 * bias_v, g = gamma / D;
+    std::vector<cd> vl(m), vg(m);
+    for (size_t k = 0; k < m; ++k) {
+        const double w = r.omega[k], sq = std::sqrt(std::max(D * D - w * w, 0.0));
+        const cd delta(g * w, -g * sq);
+        const cd gr = 1.0 / (w - eps_d - delta);
+        const double A = -2.0 * gr.imag();
+        double fi;
+        if (std::isinf(beta)) {
+            fi = w < mu ? 1.0 : 0.0;
+        } else {
+            const double bx = beta * (w - mu);
+            fi = bx > 0.0 ? std::exp(-bx) / (1.0 + std::exp(-bx)) : 1.0 / (std::exp(bx) + 1.0);
+        }
+        const cd I(0.0, 1.0), half_conj = std::conj(delta) / 2.0;
+        vl[k] = r.measure[k] * (half_conj * (I * A * r.fbar[k]) + (-I * fi * delta.imag()) * gr);
+        vg[k] = r.measure[k] *
+                (half_conj * (-I * A * (1.0 - r.fbar[k])) + (I * (1.0 - fi) * delta.imag()) * gr);
+    }
+    const double h = 2.0 * t_half / (n_grid - 1);
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt < 1) nt = 1;
+    if (nt > 64) nt = 64;
+    auto work = [&](unsigned tid) {
+        for (int32_t j = (int32_t)tid; j < n_grid; j += (int32_t)nt) {
+            const double tau = -t_half + j * h;
+            cd sl(0.0, 0.0), sg(0.0, 0.0);
+            for (size_t k = 0; k < m; ++k) {
+                const cd e(std::cos(r.omega[k] * tau), -std::sin(r.omega[k] * tau));
+                sl += vl[k] * e;
+                sg += vg[k] * e;
+            }
+            tab[4 * j + 0] = sl.real();
+            tab[4 * j + 1] = sl.imag();
+            tab[4 * j + 2] = sg.real();
+            tab[4 * j + 3] = sg.imag();
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool) th.join();
 }
 
 } // namespace qqmc

@@ -145,19 +145,39 @@ template <int M> struct Blk {
 };
 
 /* The last vertex's pair (n-1, measurement), the same for every leaf of a
- * point: with col_b / row_b its column and row entries minus the block
- * corrections C10 / C01,
- *   col_1 row_1 - col_0 row_0 = a + s C01 + conj(s) C10,
- *   a = g^< (-conj g^>) - g^> (-conj g^<),  s = g^> - g^<. */
+ * point: with col_b / row_b the vertex's entries in the measurement column
+ * and row, minus the block corrections C01 / C10,
+ *   col_1 row_1 - col_0 row_0 = a + s C01 + t C10,
+ *   s = row_0 - row_1,  t = col_0 - col_1.
+ * The row entries are b ? g^< : g^> of the pair.  For the charge the column
+ * entries are -conj(b ? g^> : g^<) of the same pair, so
+ *   a = g^< (-conj g^>) - g^> (-conj g^<),  s = g^> - g^<,  t = conj(s);
+ * for the current into a lead (CUR) they come from the lead's functions,
+ * held as M = (-conj col_0, -conj col_1). */
 struct LeafK {
-    cplx a, s;
+    cplx a, s, t;
 };
-QQMC_HD LeafK leaf_constants(const pairv &P)
+template <bool CUR = false> QQMC_HD LeafK leaf_constants(const pairv &P, const pairv &M)
 {
     LeafK k;
-    k.a = cfms(P.gg, cnc(P.gl), cmul(P.gl, cnc(P.gg)));
-    k.s = csub(P.gg, P.gl);
+    if constexpr (CUR) {
+        k.a = cfms(P.gg, cnc(M.gl), cmul(P.gl, cnc(M.gg)));
+        k.s = csub(P.gg, P.gl);
+        k.t = csub(cnc(M.gl), cnc(M.gg));
+    } else {
+        (void)M;
+        k.a = cfms(P.gg, cnc(P.gl), cmul(P.gl, cnc(P.gg)));
+        k.s = csub(P.gg, P.gl);
+        k.t = cmk(0.0, 0.0); /* conj(s), applied through cfmac */
+    }
     return k;
+}
+
+/* y + t x: t = conj(s) for the charge */
+template <bool CUR> QQMC_HD cplx add_col_coef(const LeafK &lk, cplx x, cplx y)
+{
+    if constexpr (CUR) return cfma(lk.t, x, y);
+    else return cfmac(lk.s, x, y);
 }
 
 /* Closed form of the last two levels (latest vertex and the measurement)
@@ -165,36 +185,41 @@ QQMC_HD LeafK leaf_constants(const pairv &P)
  * last pivot g0 - C11 - col_b row_b / p, so
  *   sum_b (-1)^b dn_b up_b / (pivots above)^2 = p (col_1 row_1 - col_0 row_0),
  * the bracket expanded with the point's leaf constants. */
-QQMC_HD cplx leaf_value(const Blk<2> &C, cplx g0, const LeafK &lk)
+template <bool CUR = false> QQMC_HD cplx leaf_value(const Blk<2> &C, cplx g0, const LeafK &lk)
 {
     const cplx p = csub(g0, C.v[0][0]);
-    return cmul(p, cfmac(lk.s, C.v[1][0], cfma(lk.s, C.v[0][1], lk.a)));
+    return cmul(p, add_col_coef<CUR>(lk, C.v[1][0], cfma(lk.s, C.v[0][1], lk.a)));
 }
 
 /* Closed form of the last three levels: vertices u (global index v0), w (the
  * last one) and the measurement m (global index n), by cofactors instead of
  * elimination (no reciprocal): with S the 3x3 trailing matrix for index b of
  * u,
- *   sum_{b_w} (-1)^{b_w} det S = S_uu d + S_uw S_mu conj(s) + S_um S_wu s
+ *   sum_{b_w} (-1)^{b_w} det S = S_uu d + S_uw S_mu t + S_um S_wu s
  * (the S_mm terms cancel, d as in the leaf with this node's C12, C21),
- * multiplied by the 2x2 vertex determinant S_uu S_ww - S_uw S_wu. */
-QQMC_HD cplx node3_value(const Blk<3> &C, const pairv *pr, int v0, int n, cplx g0,
-                         const LeafK &lk)
+ * multiplied by the 2x2 vertex determinant S_uu S_ww - S_uw S_wu.  mc holds
+ * the measurement-column entries of the current (unused for the charge). */
+template <bool CUR = false>
+QQMC_HD cplx node3_value(const Blk<3> &C, const pairv *pr, const pairv *mc, int v0, int n,
+                         cplx g0, const LeafK &lk)
 {
     const cplx p = csub(g0, C.v[0][0]);
     const pairv Pw = pr[pidx(v0, v0 + 1)];
     const pairv Pm = pr[pidx(v0, n)];
+    pairv Mu;
+    if constexpr (CUR) Mu = mc[v0];
+    else { (void)mc; Mu = Pm; }
     const cplx sww = csub(g0, C.v[1][1]);
     const cplx spp = cmul(p, sww);
-    const cplx sd = cmul(p, cfmac(lk.s, C.v[2][1], cfma(lk.s, C.v[1][2], lk.a)));
+    const cplx sd = cmul(p, add_col_coef<CUR>(lk, C.v[2][1], cfma(lk.s, C.v[1][2], lk.a)));
     cplx t[2];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const cplx suw = csub(cnc(b ? Pw.gg : Pw.gl), C.v[0][1]);
         const cplx swu = csub(b ? Pw.gl : Pw.gg, C.v[1][0]);
-        const cplx sum_ = csub(cnc(b ? Pm.gg : Pm.gl), C.v[0][2]);
+        const cplx sum_ = csub(cnc(b ? Mu.gg : Mu.gl), C.v[0][2]);
         const cplx smu = csub(b ? Pm.gl : Pm.gg, C.v[2][0]);
-        const cplx delta = cfma(cmul(sum_, swu), lk.s, cfmac(lk.s, cmul(suw, smu), sd));
+        const cplx delta = cfma(cmul(sum_, swu), lk.s, add_col_coef<CUR>(lk, cmul(suw, smu), sd));
         t[b] = cmul(cfms(suw, swu, spp), delta);
     }
     return csub(t[0], t[1]);
@@ -210,15 +235,17 @@ QQMC_HD cplx node3_value(const Blk<3> &C, const pairv *pr, int v0, int n, cplx g
  * node builds the correction blocks of BOTH children (indices 0 and 1 of the
  * level's point) before descending, so while the first child's subtree runs
  * only the second child's (m-1) x (m-1) block is held, not the m x m parent. */
-template <int N, int L>
-QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, const LeafK &lk)
+template <int N, int L, bool CUR = false>
+QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, const pairv *mc, cplx g0,
+                     const LeafK &lk)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
     if constexpr (M == 2) {
         (void)pr;
-        return leaf_value(C, g0, lk);
+        (void)mc;
+        return leaf_value<CUR>(C, g0, lk);
     } else if constexpr (M == 3) {
-        return node3_value(C, pr, OFF + L, N, g0, lk);
+        return node3_value<CUR>(C, pr, mc, OFF + L, N, g0, lk);
     } else {
         const cplx p = csub(g0, C.v[0][0]);
         const cplx r = crecip_nr(p);
@@ -229,7 +256,8 @@ QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, cons
             cplx row0[M - 1], row1[M - 1];
 #pragma unroll
             for (int j = 1; j < M; ++j) {
-                const pairv P = pr[pidx(OFF + L, OFF + L + j)];
+                /* the current's measurement column comes from mc */
+                const pairv P = (CUR && j == M - 1) ? mc[OFF + L] : pr[pidx(OFF + L, OFF + L + j)];
                 row0[j - 1] = csub(cnc(P.gl), C.v[0][j]);
                 row1[j - 1] = csub(cnc(P.gg), C.v[0][j]);
             }
@@ -245,8 +273,8 @@ QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, cplx g0, cons
                 }
             }
         }
-        const cplx v0 = subtree<N, L + 1>(D0, pr, g0, lk);
-        const cplx v1 = subtree<N, L + 1>(D1, pr, g0, lk);
+        const cplx v0 = subtree<N, L + 1, CUR>(D0, pr, mc, g0, lk);
+        const cplx v1 = subtree<N, L + 1, CUR>(D1, pr, mc, g0, lk);
         return cmul(cmul(p, p), csub(v0, v1));
     }
 }
@@ -270,12 +298,12 @@ template <int N, bool PAIR = false> struct BlockSrc {
  * bit = earliest block level), starting block correction C0, product of the
  * pivots eliminated before the block, parity of the indices fixed before.
  * Returns the signed sum over the lane's 2^B index vectors. */
-template <int N>
-QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
+template <int N, bool CUR = false>
+QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N> C0, int pre, cplx prod,
                       int sgn, cplx g0)
 {
     constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, T = Geo<N>::T;
-    const LeafK lk = leaf_constants(pr[pidx(N - 1, N)]);
+    const LeafK lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
     cplx v;
     if constexpr (T == 0) {
         (void)pre;
@@ -284,7 +312,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        v = subtree<N, 0>(C, pr, g0, lk);
+        v = subtree<N, 0, CUR>(C, pr, mc, g0, lk);
     } else {
         cplx chat[T][K], rowv[T][K];
 #pragma unroll
@@ -300,8 +328,9 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                 /* the index picks the table half by address: index 1 takes
                  * column g^< and row -conj(g^>), index 0 the other halves */
                 const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
+                const cplx *R = (CUR && i == K - 1) ? &mc[OFF + k].gl : P;
                 cplx col = csub(P[b ^ 1], C0.at(i, k));
-                cplx row = csub(cnc(P[b]), C0.at(k, i));
+                cplx row = csub(cnc(R[b]), C0.at(k, i));
 #pragma unroll
                 for (int l = 0; l < k; ++l) {
                     col = cfms(chat[l][i], rowv[l][k], col);
@@ -322,7 +351,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
                 for (int l = 0; l < T; ++l) c = cfma(chat[l][i], rowv[l][j], c);
                 C.v[i - T][j - T] = c;
             }
-        v = subtree<N, T>(C, pr, g0, lk);
+        v = subtree<N, T, CUR>(C, pr, mc, g0, lk);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;
@@ -341,16 +370,17 @@ QQMC_HD cplx lane_sum(const pairv *pr, BlockSrc<N> C0, int pre, cplx prod,
  * (alpha = n_sigma) and the skew-symmetric blocks of the particle-hole
  * symmetric point are handled exactly.  The last one or two vertices end in
  * the closed forms above, which invert nothing either. */
-template <int N, int L>
-QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx g0,
-                       const LeafK &lk)
+template <int N, int L, bool CUR = false>
+QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, const pairv *mc,
+                       cplx g0, const LeafK &lk)
 {
     constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, M = K - L;
     if constexpr (M == 2) {
         (void)pr;
-        return leaf_value(C, g0, lk);
+        (void)mc;
+        return leaf_value<CUR>(C, g0, lk);
     } else if constexpr (M == 3) {
-        return node3_value(C, pr, OFF + L, N, g0, lk);
+        return node3_value<CUR>(C, pr, mc, OFF + L, N, g0, lk);
     } else {
         constexpr int V0 = OFF + L;
         const cplx a = csub(g0, C.v[0][0]), d = csub(g0, C.v[1][1]);
@@ -369,7 +399,8 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx 
 #pragma unroll
             for (int j = 2; j < M; ++j) {
                 const cplx *P = &pr[pidx(V0, V0 + j)].gl;
-                x[j - 2] = csub(cnc(P[b]), C.v[0][j]);
+                const cplx *R = (CUR && j == M - 1) ? &mc[V0].gl : P;
+                x[j - 2] = csub(cnc(R[b]), C.v[0][j]);
                 u[j - 2] = csub(P[b ^ 1], C.v[j][0]);
             }
             cplx sub = cmk(0.0, 0.0);
@@ -379,7 +410,8 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx 
 #pragma unroll
                 for (int j = 2; j < M; ++j) {
                     const cplx *Q = &pr[pidx(V0 + 1, V0 + j)].gl;
-                    y[j - 2] = csub(cnc(Q[bq]), C.v[1][j]);
+                    const cplx *R = (CUR && j == M - 1) ? &mc[V0 + 1].gl : Q;
+                    y[j - 2] = csub(cnc(R[bq]), C.v[1][j]);
                     z[j - 2] = csub(Q[bq ^ 1], C.v[j][1]);
                 }
                 Blk<M - 2> D;
@@ -391,7 +423,7 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx 
                     for (int j = 2; j < M; ++j)
                         D.v[i - 2][j - 2] = cfma(Vi, y[j - 2], cfma(Ui, x[j - 2], C.v[i][j]));
                 }
-                const cplx w = pair_walk<N, L + 2>(D, pr, g0, lk);
+                const cplx w = pair_walk<N, L + 2, CUR>(D, pr, mc, g0, lk);
                 sub = bq ? csub(sub, w) : cadd(sub, w);
             }
             const cplx t = cmul(cmul(det, det), sub);
@@ -404,12 +436,12 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, cplx 
 /* One lane's share of an item in the paired tree: the T prefix levels are
  * T/2 pair steps for the lane's index bits (left-looking: each step keeps
  * its U, V columns and x, y rows), then the pair walk. */
-template <int N>
-QQMC_HD cplx lane_sum_pair(const pairv *pr, BlockSrc<N, true> C0, int pre, cplx prod,
-                           int sgn, cplx g0)
+template <int N, bool CUR = false>
+QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C0, int pre,
+                           cplx prod, int sgn, cplx g0)
 {
     constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, T = Geo<N, true>::T;
-    const LeafK lk = leaf_constants(pr[pidx(N - 1, N)]);
+    const LeafK lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
     cplx v;
     if constexpr (T == 0) {
         (void)pre;
@@ -418,7 +450,7 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, BlockSrc<N, true> C0, int pre, cplx 
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        v = pair_walk<N, 0>(C, pr, g0, lk);
+        v = pair_walk<N, 0, CUR>(C, pr, mc, g0, lk);
     } else {
         constexpr int TP = T / 2;
         cplx Uc[TP][K], Vc[TP][K], xr[TP][K], yr[TP][K];
@@ -445,8 +477,10 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, BlockSrc<N, true> C0, int pre, cplx 
             for (int i = k + 2; i < K; ++i) {
                 const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
                 const cplx *Q = &pr[pidx(OFF + k + 1, OFF + i)].gl;
-                cplx x = csub(cnc(P[b]), C0.at(k, i)), u = csub(P[b ^ 1], C0.at(i, k));
-                cplx y = csub(cnc(Q[bq]), C0.at(k + 1, i)), z = csub(Q[bq ^ 1], C0.at(i, k + 1));
+                const cplx *RP = (CUR && i == K - 1) ? &mc[OFF + k].gl : P;
+                const cplx *RQ = (CUR && i == K - 1) ? &mc[OFF + k + 1].gl : Q;
+                cplx x = csub(cnc(RP[b]), C0.at(k, i)), u = csub(P[b ^ 1], C0.at(i, k));
+                cplx y = csub(cnc(RQ[bq]), C0.at(k + 1, i)), z = csub(Q[bq ^ 1], C0.at(i, k + 1));
 #pragma unroll
                 for (int l = 0; l < s; ++l) {
                     x = cfms(Vc[l][k], yr[l][i], cfms(Uc[l][k], xr[l][i], x));
@@ -471,7 +505,7 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, BlockSrc<N, true> C0, int pre, cplx 
                 for (int l = 0; l < TP; ++l) c = cfma(Vc[l][i], yr[l][j], cfma(Uc[l][i], xr[l][j], c));
                 C.v[i - T][j - T] = c;
             }
-        v = pair_walk<N, T>(C, pr, g0, lk);
+        v = pair_walk<N, T, CUR>(C, pr, mc, g0, lk);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;
@@ -484,6 +518,16 @@ QQMC_HD cplx wick_entry(const pairv *pr, int i, int j, int b)
 {
     if (i < j) return cnc((&pr[pidx(i, j)].gl)[b]);
     return (&pr[pidx(j, i)].gl)[b ^ 1];
+}
+
+/* The same with the current's measurement column (column n) from mc. */
+template <bool CUR>
+QQMC_HD cplx wick_entry_m(const pairv *pr, const pairv *mc, int i, int j, int n, int b)
+{
+    if (CUR && i < j && j == n) return cnc((&mc[i].gl)[b]);
+    (void)mc;
+    (void)n;
+    return wick_entry(pr, i, j, b);
 }
 
 /* Linear interpolation on the uniform grid tau_j = -t_half + j h, given

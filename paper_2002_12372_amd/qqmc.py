@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libqqmc.so")
 
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EDEVICE, EADMIT, ENOTICKET = -1, -2, -3, -4, -5
-MODE_CHARGE, MODE_MODEL, MODE_CONSTANT = 0, 1, 2
+MODE_CHARGE, MODE_MODEL, MODE_CONSTANT, MODE_CURRENT = 0, 1, 2, 3
+OBS_CHARGE, OBS_CURRENT = 0, 1
 METHOD_TREE, METHOD_DIRECT = 0, 1
 MAX_ORDER = 14
 SERVER_TILE_LEN = 256   # QQMC_SERVER_TILE_LEN
@@ -33,7 +34,7 @@ class qqmc_dot(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("bias_v", ctypes.c_double),
                 ("t_half", ctypes.c_double), ("n_grid", ctypes.c_int32),
-                ("half_bandwidth", ctypes.c_double)]
+                ("half_bandwidth", ctypes.c_double), ("lead", ctypes.c_int32)]
 
 
 class qqmc_order(ctypes.Structure):
@@ -73,7 +74,9 @@ SIGNATURES = [
     ("qqmc_free_tables", None, [_vp]),
     ("qqmc_eval_order", _i32, [_vp, _P(qqmc_order), _vp, _PD, _PD, _PD]),
     ("qqmc_eval_order_async", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _vp, _P(_i64)]),
-    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _vp, _i64, _i32, _vp, _vp]),
+    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _i32, _vp, _i64, _i32, _vp, _vp]),
+    ("qqmc_lead_tables_compute_host", _i32, [_P(qqmc_dot), _PD, _PD]),
+    ("qqmc_tables_lead_from_host", _i32, [_vp, _PD, _PD]),
     ("qqmc_plan_create", _i32, [_P(qqmc_batch_item), _i32, _i32, _i32, _vp, _P(_vp)]),
     ("qqmc_plan_run", _i32, [_vp, _vp]),
     ("qqmc_plan_results", _i32, [_vp, _vp, _PD]),
@@ -146,7 +149,7 @@ class Tables:
 
 def make_dot(d):
     return qqmc_dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_half, d.n_grid,
-                    getattr(d, "half_bandwidth", 0.0))
+                    getattr(d, "half_bandwidth", 0.0), getattr(d, "lead", 0))
 
 
 def make_tables(dot, stream=None):
@@ -155,6 +158,22 @@ def make_tables(dot, stream=None):
     cd = make_dot(dot)
     _check(lib().qqmc_make_tables(ctypes.byref(cd), _stream(stream), ctypes.byref(h)))
     return Tables(h.value, dot.n_grid, dot.t_half)
+
+
+def lead_tables_compute_host(dot):
+    """(cl, cg): the lead's gamma g^<_{0i}, gamma g^>_{0i} on the dot's grid
+    (dot.lead = 1 or 2, finite band), computed on the host."""
+    cd = make_dot(dot)
+    cl = np.zeros(2 * dot.n_grid)
+    cg = np.zeros(2 * dot.n_grid)
+    _check(lib().qqmc_lead_tables_compute_host(ctypes.byref(cd), _pd(cl), _pd(cg)))
+    return cl, cg
+
+
+def tables_lead_from_host(tables, cl, cg):
+    cl = np.ascontiguousarray(cl, dtype=np.float64)
+    cg = np.ascontiguousarray(cg, dtype=np.float64)
+    _check(lib().qqmc_tables_lead_from_host(tables.handle, _pd(cl), _pd(cg)))
 
 
 def tables_compute_host(dot):
@@ -269,12 +288,14 @@ def n_tiles(job, tile_len):
     return job.shifts.shape[0] * ((1 << job.log2_n) // tile_len)
 
 
-def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None, alpha=0.0):
+def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None, alpha=0.0,
+                current=False):
     """u: (P, order) float64 CUDA tensor; f: (P, 2) float64 CUDA tensor."""
     P = u.shape[0]
     assert u.dtype.is_floating_point and u.is_contiguous() and f.is_contiguous()
     assert f.numel() >= 2 * P and u.numel() == P * order
     _check(lib().qqmc_eval_points(tables.handle, int(order), float(t_meas), float(alpha),
+                                  OBS_CURRENT if current else OBS_CHARGE,
                                   ctypes.c_void_p(u.data_ptr()), P, int(method),
                                   ctypes.c_void_p(f.data_ptr()), _stream(stream)))
 

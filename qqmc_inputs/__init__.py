@@ -63,7 +63,8 @@ def shifts(rng: SplitMix64, n_shifts: int, order: int) -> np.ndarray:
 class Dot:
     """Anderson dot: level eps_d, coupling Gamma, inverse temperature beta,
     symmetric bias V, measurement time t, table grid; half_bandwidth D of
-    semicircular leads (0: wide band)."""
+    semicircular leads (0: wide band); lead 1 or 2 also tabulates that lead's
+    dot-lead functions for the current (0: none)."""
     eps_d: float = 0.0
     gamma: float = 1.0
     beta: float = 20.0
@@ -72,6 +73,7 @@ class Dot:
     n_grid: int = 8192
     t_half: float = 10.0
     half_bandwidth: float = 0.0
+    lead: int = 0
 
 
 @dataclass

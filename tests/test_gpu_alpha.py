@@ -12,8 +12,9 @@ the term mass; per estimate and tile sum 1e-9 relative.  At alpha = n_sigma
 the paired tree's 2x2 pivot block of two consecutive vertices far apart in
 time is nearly singular (its off-diagonal Green's functions have decayed),
 and elimination without pivoting loses digits there: measured up to 2e-13 of
-the term mass per point.  Those cases are held to 1e-12 of the term mass
-(per point, and per estimate or tile with the oracle's summed term mass).
+the term mass per point here (5e-12 on a faster-decaying dot).  Points at
+alpha = n_sigma are held to 1e-10 of their term mass; estimates and tiles to
+1e-12 of the oracle's summed term mass.
 """
 import math
 import time
@@ -90,7 +91,7 @@ def test_points_tree_alpha(q, oracle_mod, n, alpha):
     f = _eval_points(q, gt, n, u, q.METHOD_TREE, alpha)
     _check_values(f, [oracle_mod.integrand(tb, T_MEAS, row, alpha) for row in u],
                   "tree n=%d alpha=%g" % (n, alpha),
-                  1e-12 if alpha == tb.n_sigma else 1e-13)
+                  1e-10 if alpha == tb.n_sigma else 1e-13)
 
 
 @pytest.mark.parametrize("alpha", [0.7, "ns"])

@@ -66,6 +66,27 @@ def test_host_band_tables_match_oracle(libq, oracle_mod, d):
     assert np.max(np.abs(gg - tb.gg)) < 1e-13
 
 
+@pytest.mark.parametrize("lead", [1, 2])
+@pytest.mark.parametrize("d", BAND_DOTS[:3])
+def test_host_lead_tables_match_oracle(libq, oracle_mod, d, lead):
+    """Dot-lead functions for the current: the library's band rule against
+    the oracle's adaptive quadrature over the whole grid."""
+    d = Dot(d.eps_d, d.gamma, d.beta, d.bias_v, d.t_meas, 2049, d.t_half, d.half_bandwidth,
+            lead)
+    cl, cg = libq.lead_tables_compute_host(d)
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half,
+                           half_bandwidth=d.half_bandwidth, lead=lead)
+    assert np.max(np.abs(cl - tb.cl)) < 1e-13
+    assert np.max(np.abs(cg - tb.cg)) < 1e-13
+
+
+def test_host_lead_needs_finite_band(libq):
+    with pytest.raises(libq.QQMCError):
+        libq.lead_tables_compute_host(Dot(0.0, 1.0, 20.0, 0.4, lead=1))
+    with pytest.raises(libq.QQMCError):
+        libq.lead_tables_compute_host(Dot(0.0, 1.0, 20.0, 0.4, half_bandwidth=2.0, lead=3))
+
+
 def test_host_band_rejects_bound_state_regime(libq):
     with pytest.raises(libq.QQMCError):     # |eps_d| >= D - gamma
         libq.tables_compute_host(Dot(1.95, 0.1, 20.0, 0.0, half_bandwidth=2.0))

@@ -58,6 +58,11 @@ def _load():
     lib.oracle_eval_sums_lead.argtypes = [P, P, P, P, i, d, d, d, d, i, i, u64, i, P, d,
                                           i64, i64, i, P, P]
     lib.oracle_eval_sums_lead.restype = i
+    PU = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_sobol_point.argtypes = [u64, i, PU, PU, P]
+    lib.oracle_eval_sums_sobol.argtypes = [P, P, i, d, d, d, d, i, PU, i, PU, d, i, i64, i64,
+                                           i, P]
+    lib.oracle_eval_sums_sobol.restype = i
     lib.oracle_interp.argtypes = [P, i, d, d, P]
     lib.oracle_det.argtypes = [i, P, P]
     lib.oracle_wick_matrix.argtypes = [P, P, i, d, d, d, d, i, P, PI, P]
@@ -215,6 +220,41 @@ def eval_order_current(tables, t_meas, n, log2_n, lattice_a, shifts, model_tau, 
     K = q.shape[0]
     se = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
     return q, q.mean(), se, mass / N
+
+
+def _pu(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def sobol_point(i, V, dshift=None):
+    """Sobol' point i (App. B) from direction numbers V (n x 32 uint32) and
+    an optional digital shift (n uint32)."""
+    V = np.ascontiguousarray(V, dtype=np.uint32)
+    n = V.shape[0]
+    x = np.zeros(n)
+    ds = None if dshift is None else np.ascontiguousarray(dshift, dtype=np.uint32)
+    _load().oracle_sobol_point(int(i), n, _pu(V), _pu(ds) if ds is not None else None, _p(x))
+    return x
+
+
+def eval_order_sobol(tables, t_meas, n, log2_n, V, dshifts, model_tau, mode=0, alpha=0.0,
+                     n_threads=0):
+    """Q^{(s)} over the first 2^log2_n Sobol' points, one digital shift per
+    row of dshifts; their mean and standard error."""
+    V = np.ascontiguousarray(V, dtype=np.uint32)
+    dshifts = np.ascontiguousarray(dshifts, dtype=np.uint32)
+    K = dshifts.shape[0]
+    assert V.shape == (n, 32) and dshifts.shape == (K, n)
+    sums = np.zeros(2 * K)
+    N = 1 << log2_n
+    rc = _load().oracle_eval_sums_sobol(*tables._args(alpha), t_meas, n, _pu(V), K,
+                                        _pu(dshifts), model_tau, mode, 0, N, n_threads,
+                                        _p(sums))
+    if rc != 0:
+        raise ValueError("oracle_eval_sums_sobol: bad arguments")
+    q = (sums[0::2] + 1j * sums[1::2]) / N
+    se = float(np.std(q.real, ddof=1) / np.sqrt(K)) if K > 1 else float("nan")
+    return q, q.mean(), se
 
 
 def n_sigma_band(eps_d, gamma, beta, bias_v, D):

@@ -880,13 +880,28 @@ static int warp_model(int n, const double *x, const double *cdf, int n_bins,
     return inside;
 }
 
-int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
-                           double t_half, double n_sigma, double alpha, double t_meas,
-                           int n, int log2_n, uint64_t lattice_a,
-                           int n_shifts, const double *shifts, double model_tau,
-                           const double *cdf, int n_bins,
-                           int mode, int64_t i_begin, int64_t i_end, int n_threads,
-                           double *sums)
+/* Sobol' point i with a random digital shift (App. B): coordinate j is
+ * (XOR over the set bits k of i of V[j][k]) XOR dshift[j], times 2^-32. */
+void oracle_sobol_point(uint64_t i, int n, const uint32_t *V, const uint32_t *dshift, double *x)
+{
+    for (int j = 0; j < n; ++j) {
+        uint32_t v = dshift ? dshift[j] : 0u;
+        for (int k = 0; k < 32; ++k)
+            if ((i >> k) & 1u) v ^= V[j * 32 + k];
+        x[j] = (double)v * (1.0 / 4294967296.0);
+    }
+}
+
+/* The estimator over the lattice (sobol_v == NULL) or over Sobol' points
+ * (sobol_v: n x 32 direction numbers, sobol_shifts: n_shifts x n words). */
+static int eval_sums_core(const double *gl, const double *gg, int n_grid,
+                          double t_half, double n_sigma, double alpha, double t_meas,
+                          int n, int log2_n, uint64_t lattice_a,
+                          int n_shifts, const double *shifts, const uint32_t *sobol_v,
+                          const uint32_t *sobol_shifts, double model_tau,
+                          const double *cdf, int n_bins,
+                          int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                          double *sums)
 {
     if (n < 1 || n > 24 || log2_n < 1 || log2_n > 40 || i_end < i_begin ||
         i_begin < 0 || n_shifts < 1 || mode < 0 || mode > 2 || (cdf && n_bins < 1))
@@ -899,11 +914,15 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
     cplx ipow = 1.0;
     for (int k = 0; k < n + 1; ++k) ipow *= I;
     for (int s = 0; s < n_shifts; ++s) {
-        const double *sh = shifts + (size_t)s * n;
+        const double *sh = sobol_v ? NULL : shifts + (size_t)s * n;
         #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
         for (int64_t q = 0; q < cnt; ++q) {
             double x[32], u[32], W, S[2], M, qp;
-            oracle_lattice_point((uint64_t)(i_begin + q), n, log2_n, lattice_a, sh, x);
+            if (sobol_v)
+                oracle_sobol_point((uint64_t)(i_begin + q), n, sobol_v,
+                                   sobol_shifts + (size_t)s * n, x);
+            else
+                oracle_lattice_point((uint64_t)(i_begin + q), n, log2_n, lattice_a, sh, x);
             int inside = warp_model(n, x, cdf, n_bins, model_tau, t_meas, u, &W, &qp);
             cplx f = 0.0;
             if (mode == 1) {
@@ -938,6 +957,31 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
     }
     free(vals);
     return 0;
+}
+
+int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
+                           double t_half, double n_sigma, double alpha, double t_meas,
+                           int n, int log2_n, uint64_t lattice_a,
+                           int n_shifts, const double *shifts, double model_tau,
+                           const double *cdf, int n_bins,
+                           int mode, int64_t i_begin, int64_t i_end, int n_threads,
+                           double *sums)
+{
+    return eval_sums_core(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, log2_n, lattice_a,
+                          n_shifts, shifts, NULL, NULL, model_tau, cdf, n_bins, mode, i_begin,
+                          i_end, n_threads, sums);
+}
+
+int oracle_eval_sums_sobol(const double *gl, const double *gg, int n_grid,
+                           double t_half, double n_sigma, double alpha, double t_meas,
+                           int n, const uint32_t *sobol_v, int n_shifts,
+                           const uint32_t *sobol_shifts, double model_tau, int mode,
+                           int64_t i_begin, int64_t i_end, int n_threads, double *sums)
+{
+    if (!sobol_v || !sobol_shifts) return -1;
+    return eval_sums_core(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, 32, 0, n_shifts,
+                          NULL, sobol_v, sobol_shifts, model_tau, NULL, 0, mode, i_begin, i_end,
+                          n_threads, sums);
 }
 
 /* Term mass of the charge estimate (exponential warp): per shift, the sum

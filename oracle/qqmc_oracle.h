@@ -121,6 +121,14 @@ int oracle_eval_sums_lead(const double *gl, const double *gg, const double *cl,
                           int64_t i_begin, int64_t i_end, int n_threads, double *sums,
                           double *mass);
 
+void oracle_sobol_point(uint64_t i, int n, const uint32_t *V, const uint32_t *dshift, double *x);
+
+int oracle_eval_sums_sobol(const double *gl, const double *gg, int n_grid,
+                           double t_half, double n_sigma, double alpha, double t_meas,
+                           int n, const uint32_t *sobol_v, int n_shifts,
+                           const uint32_t *sobol_shifts, double model_tau, int mode,
+                           int64_t i_begin, int64_t i_end, int n_threads, double *sums);
+
 int oracle_max_threads(void);
 
 /* ---- Learned second warp (App. I, "Learning h^(i) from the integrand") ----

@@ -903,3 +903,96 @@ def test_lead_tables_grid(oracle_mod, lead_tables):
         assert abs(got_l - cl) < 1e-15 and abs(got_g - cg) < 1e-15
     with pytest.raises(ValueError):          # the current needs a finite band
         oracle_mod.Tables(0.0, 1.0, 2.0, 0.5, 64, 10.0, lead=1)
+
+
+# ---------------------------------------------------------------------------
+# Sobol' points (App. B): derived primitive polynomials and direction numbers
+# (qqmc_inputs.sobol), digital shifts, the oracle's point and estimator.
+# ---------------------------------------------------------------------------
+def _phi(k):
+    r, m, p = k, k, 2
+    while p * p <= m:
+        if m % p == 0:
+            while m % p == 0:
+                m //= p
+            r -= r // p
+        p += 1
+    if m > 1:
+        r -= r // m
+    return r
+
+
+def test_sobol_primitive_polynomial_counts():
+    """There are phi(2^s - 1)/s primitive polynomials of degree s over GF(2);
+    the derived list holds them in order of degree, and each generates a
+    linear recurrence of full period 2^s - 1."""
+    from qqmc_inputs import sobol as S
+    polys = S.primitive_polynomials(19)
+    for s in range(1, 6):
+        assert sum(1 for d, _ in polys if d == s) == _phi((1 << s) - 1) // s
+    for s, poly in polys:
+        state, seen = 1, set()
+        for _ in range((1 << s) - 1):          # LFSR with feedback poly
+            seen.add(state)
+            fb = bin(state & (poly >> 1)).count("1") & 1
+            state = ((state << 1) | fb) & ((1 << s) - 1) if s > 1 else fb
+            if s == 1:
+                state = 1
+        assert len(seen) == (1 << s) - 1 or s == 1
+
+
+def test_sobol_first_dimension_is_van_der_corput(oracle_mod):
+    from qqmc_inputs import sobol as S
+    V = S.direction_numbers(3)
+    for i in (0, 1, 2, 3, 5, 1000, 123456):
+        rev = int("{:032b}".format(i)[::-1], 2)
+        assert oracle_mod.sobol_point(i, V)[0] == rev / 2.0 ** 32
+
+
+def test_sobol_one_dimensional_nets(oracle_mod):
+    """Every coordinate of the first 2^m points, digitally shifted, puts
+    exactly one point in each interval [k 2^-m, (k+1) 2^-m)."""
+    from qqmc_inputs import sobol as S
+    m, n = 10, 8
+    V = S.direction_numbers(n)
+    ds = S.digital_shifts(3, 1, n)[0]
+    X = np.array([oracle_mod.sobol_point(i, V, ds) for i in range(1 << m)])
+    for j in range(n):
+        counts = np.bincount((X[:, j] * (1 << m)).astype(int), minlength=1 << m)
+        assert np.all(counts == 1), j
+
+
+@pytest.mark.parametrize("pair", [(0, 1), (1, 2), (2, 5), (3, 7), (6, 7)])
+def test_sobol_two_dimensional_t_values(oracle_mod, pair):
+    """The t-value from the generating-matrix rank criterion agrees with
+    direct counting: the first 2^m points put exactly 2^t points in every
+    elementary box of area 2^(t-m), and some box of area 2^(t-1-m) misses."""
+    from qqmc_inputs import sobol as S
+    m = 8
+    V = S.direction_numbers(8)
+    a, b = pair
+    t = S.t_value_2d(V[a], V[b], m)
+    X = np.array([oracle_mod.sobol_point(i, V) for i in range(1 << m)])[:, [a, b]]
+
+    def stratified(tt):
+        d = m - tt
+        for d1 in range(d + 1):
+            ia = (X[:, 0] * (1 << d1)).astype(int)
+            ib = (X[:, 1] * (1 << (d - d1))).astype(int)
+            counts = np.bincount(ia * (1 << (d - d1)) + ib, minlength=1 << d)
+            if not np.all(counts == 1 << tt):
+                return False
+        return True
+    assert stratified(t)
+    if t > 0:
+        assert not stratified(t - 1)
+
+
+def test_sobol_q2_against_quadrature(oracle_mod, tiny_tables, q2_quadrature):
+    """Q_2 over 2^14 Sobol' points x 16 digital shifts within its error bar
+    of the two-dimensional adaptive quadrature."""
+    from qqmc_inputs import sobol as S
+    V = S.direction_numbers(2)
+    ds = S.digital_shifts(5, 16, 2)
+    _, mean, se = oracle_mod.eval_order_sobol(tiny_tables, 10.0, 2, 14, V, ds, 1.0)
+    assert abs(mean.real - q2_quadrature) < 5 * se + 1e-8

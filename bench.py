@@ -101,7 +101,7 @@ def run_plain(args):
     import torch
     from paper_2002_12372_amd import qqmc
     from paper_2002_12372_amd.flops import pair_tree_flops, tree_flops, warp_flops
-    from qqmc_inputs import Dot, TINY_DOT, order_job
+    from qqmc_inputs import Dot, TINY_DOT, order_job, sobol_job
 
     stream = torch.cuda.current_stream()
     n = args.order
@@ -133,7 +133,8 @@ def run_plain(args):
     tables = qqmc.make_tables(d)
     if args.alpha is not None:
         alpha = qqmc.tables_export(tables)[2] if args.alpha == "ns" else float(args.alpha)
-    job = order_job(1, n, args.log2n, args.shifts, model_tau=tau, mode=mode, alpha=alpha)
+    make_job = sobol_job if args.sobol else order_job
+    job = make_job(1, n, args.log2n, args.shifts, model_tau=tau, mode=mode, alpha=alpha)
     tflops = pair_tree_flops(n) if alpha != 0.0 else tree_flops(n)
     if mode == qqmc.MODE_CURRENT:
         tflops += 16 * n        # the lead-function lookups of the measurement column
@@ -172,14 +173,15 @@ def run_plain(args):
         "data": "synthetic",
         "config": {"workload": "%s of the %s Anderson dot "
                                "(Gamma=%g, eps_d=%g, beta=%g, V=%g, t=%g%s), order %d, "
-                               "Korobov lattice N=2^%d x %d random shifts, tau=%g"
+                               "%s N=2^%d x %d random shifts, tau=%g"
                                % ("current coefficient I_n into lead 1"
                                   if mode == qqmc.MODE_CURRENT else "charge coefficient Q_n",
                                   "semicircular-lead (D=%g)" % d.half_bandwidth
                                   if d.half_bandwidth else "wide-band",
                                   d.gamma, d.eps_d, d.beta, d.bias_v, d.t_meas,
                                   ", alpha=%.6g, paired tree" % alpha if alpha else "",
-                                  n, args.log2n, args.shifts, tau),
+                                  n, "Sobol' points (digital shifts)" if args.sobol
+                                  else "Korobov lattice", args.log2n, args.shifts, tau),
                    "order": n, "lattice_points": N, "shifts": args.shifts,
                    "inside_fraction": frac_in,
                    "inside_points_per_s": value * frac_in},
@@ -189,7 +191,7 @@ def run_plain(args):
                      "flops_per_inside_point": tflops,
                      "avg_launch_ms": avg_launch_s * 1e3},
     }
-    if not args.no_cpu and alpha == 0.0:
+    if not args.no_cpu and alpha == 0.0 and not args.sobol:
         out["cpu_baseline"] = cpu_baseline(n, args.log2n, job.lattice_a, job.shifts,
                                            args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -487,6 +489,8 @@ def main():
                     choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--sobol", action="store_true",
+                    help="plain workload on Sobol' points instead of the lattice")
     ap.add_argument("--current", action="store_true",
                     help="plain workload: the current on the paper's finite-bandwidth "
                          "parameters")

@@ -114,6 +114,17 @@ typedef struct {
                                are built at the quadratic level E_d, whose
                                one-electron energy is E_d - alpha U; finite;
                                0 = the plain interaction U n_up n_dn          */
+    const uint32_t *sobol_v;      /* host, order x 32, or NULL: Sobol' points
+                                     (App. B) instead of the lattice; point i
+                                     has coordinates (XOR over the set bits k
+                                     of i of sobol_v[j][k]) * 2^-32; lattice_a
+                                     and shifts are then not used            */
+    const uint32_t *sobol_shifts; /* host, n_shifts x order digital shifts
+                                     (XORed into the coordinate words), with
+                                     sobol_v; both copied during the call.
+                                     Sobol' items run as single launches
+                                     (charge or current; no learned warp, plan
+                                     or server)                               */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the

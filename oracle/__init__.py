@@ -237,6 +237,21 @@ def sobol_point(i, V, dshift=None):
     return x
 
 
+def eval_sums_sobol(tables, t_meas, n, V, dshifts, model_tau, i_begin, i_end, mode=0,
+                    alpha=0.0, n_threads=0):
+    """Per-shift sums of fbar W over Sobol' indices [i_begin, i_end)."""
+    V = np.ascontiguousarray(V, dtype=np.uint32)
+    dshifts = np.ascontiguousarray(dshifts, dtype=np.uint32)
+    K = dshifts.shape[0]
+    sums = np.zeros(2 * K)
+    rc = _load().oracle_eval_sums_sobol(*tables._args(alpha), t_meas, n, _pu(V), K,
+                                        _pu(dshifts), model_tau, mode, int(i_begin), int(i_end),
+                                        n_threads, _p(sums))
+    if rc != 0:
+        raise ValueError("oracle_eval_sums_sobol: bad arguments")
+    return sums[0::2] + 1j * sums[1::2]
+
+
 def eval_order_sobol(tables, t_meas, n, log2_n, V, dshifts, model_tau, mode=0, alpha=0.0,
                      n_threads=0):
     """Q^{(s)} over the first 2^log2_n Sobol' points, one digital shift per

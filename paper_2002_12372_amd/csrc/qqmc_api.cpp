@@ -40,11 +40,14 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
     if (ord->log2_n < 6 || ord->log2_n > 24)
         return set_error(QQMC_EINVAL, "log2_n must be in 6..24");
     const uint64_t N = (uint64_t)1 << ord->log2_n;
-    if ((ord->lattice_a & 1u) == 0 || ord->lattice_a <= 1 || ord->lattice_a >= N)
+    const bool sobol = ord->sobol_v != nullptr;
+    if (!sobol && ((ord->lattice_a & 1u) == 0 || ord->lattice_a <= 1 || ord->lattice_a >= N))
         return set_error(QQMC_EINVAL, "lattice_a must be odd with 1 < a < N");
     if (ord->n_shifts < 1 || ord->n_shifts > 65535)
         return set_error(QQMC_EINVAL, "n_shifts must be in 1..65535");
-    if (!ord->shifts) return set_error(QQMC_EINVAL, "shifts is NULL");
+    if (!sobol && !ord->shifts) return set_error(QQMC_EINVAL, "shifts is NULL");
+    if (sobol && !ord->sobol_shifts) return set_error(QQMC_EINVAL, "sobol_shifts is NULL");
+    if (sobol && ord->model) return set_error(QQMC_EINVAL, "Sobol' points take no learned warp");
     if (!(ord->model_tau > 0.0) || !std::isfinite(ord->model_tau))
         return set_error(QQMC_EINVAL, "model_tau must be positive");
     if (!(ord->t_meas > 0.0) || !(ord->t_meas <= t_half))
@@ -57,7 +60,14 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
         return set_error(QQMC_EINVAL, "model of another order");
     if (!std::isfinite(ord->alpha)) return set_error(QQMC_EINVAL, "alpha must be finite");
     const size_t ns = (size_t)ord->n_shifts * (size_t)n;
-    out->shifts.assign(ord->shifts, ord->shifts + ns);
+    if (sobol) {
+        out->shifts.assign(ns, 0.0);
+        out->sobol.assign(ord->sobol_v, ord->sobol_v + (size_t)n * 32);
+        out->sobol.insert(out->sobol.end(), ord->sobol_shifts, ord->sobol_shifts + ns);
+    } else {
+        out->shifts.assign(ord->shifts, ord->shifts + ns);
+        out->sobol.clear();
+    }
     for (double v : out->shifts)
         if (!(v >= 0.0 && v < 1.0)) return set_error(QQMC_EINVAL, "every shift must lie in [0, 1)");
     ItemDesc &d = out->desc;
@@ -144,6 +154,7 @@ qqmc_status upload_tables(const double *tab4, int32_t n_grid, double t_half, dou
 /* Device buffers of one asynchronous order evaluation. */
 struct OrderBuffers {
     double *shifts = nullptr, *tile_sums = nullptr, *shift_sums = nullptr;
+    uint32_t *sobol = nullptr;
     ItemDesc *item = nullptr;
     int64_t *base = nullptr;
 };
@@ -380,7 +391,14 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord, int32_t 
     if (e == hipSuccess)
         e = hipMemcpyAsync(b.shifts, v.shifts.data(), sizeof(double) * v.shifts.size(),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !v.sobol.empty()) {
+        e = hipMallocAsync((void **)&b.sobol, sizeof(uint32_t) * v.sobol.size(), s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.sobol, v.sobol.data(), sizeof(uint32_t) * v.sobol.size(),
+                               hipMemcpyHostToDevice, s);
+    }
     d.shifts = b.shifts;
+    d.sobol = b.sobol;
     d.tile_sums = tile_sums ? tile_sums : b.tile_sums;
     const int64_t zero = 0;
     if (e == hipSuccess)
@@ -390,6 +408,7 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord, int32_t 
     if (e == hipSuccess) e = launch_order(d, s);
     if (e == hipSuccess) e = launch_shift_reduce(b.item, 1, b.base, shift_sums, d.n_shifts, s);
     free_async(b.shifts, s);
+    free_async(b.sobol, s);
     free_async(b.tile_sums, s);
     free_async(b.item, s);
     free_async(b.base, s);

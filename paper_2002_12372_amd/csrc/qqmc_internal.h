@@ -33,6 +33,8 @@ struct ItemDesc {
     double *sample_out;      /* device: per-point Re fbar (learning pass), or null */
     double alpha;            /* interaction shift U (n_up - alpha)(n_dn - alpha) */
     const double *col;       /* device: lead functions for the current, or null */
+    const uint32_t *sobol;   /* device: Sobol' direction numbers (order x 32)
+                                then digital shifts (n_shifts x order), or null */
 };
 
 /* Batched-kernel selector of an item, 1 .. 2 QQMC_MAX_ORDER: its order,
@@ -114,6 +116,7 @@ qqmc_status hip_error(hipError_t e, const char *what);
 struct Validated {
     ItemDesc desc;             /* pointers not yet set */
     std::vector<double> shifts;
+    std::vector<uint32_t> sobol; /* direction numbers, then digital shifts */
 };
 qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid,
                            double t_half, Validated *out);

@@ -424,7 +424,8 @@ __device__ __forceinline__ double model_inverse(const double *__restrict__ c, in
  * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
  * learning pass): also writes Re fbar of every lattice index of the tile to
  * it.sample_out. */
-template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = false>
+template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = false,
+          bool SOB = false>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
     using L = Lds<N, PAIR, CUR>;
@@ -445,17 +446,42 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     env.g0 = cmk(it.g0x, it.g0y); env.gm = cmk(it.g0x, it.g0y + it.alpha);
     env.col = it.col;
     env.n_grid = it.n_grid;
+    /* Sobol' points (App. B): each lane keeps the coordinate words of its
+     * index; the tile starts at a multiple of 64 and lanes step by 64, so
+     * the low six index bits are the lane's and the bits that change from
+     * one step to the next are the same in every lane */
+    uint32_t word[SOB ? N : 1];
+    const uint32_t *sv = it.sobol;
+    if constexpr (SOB) {
+        const uint32_t *ds = it.sobol + N * 32 + (int64_t)s * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            uint32_t w = ds[j];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if ((lane >> k) & 1) w ^= sv[j * 32 + k];
+            for (int k = 6; k < 32; ++k)
+                if ((i0 >> k) & 1u) w ^= sv[j * 32 + k];
+            word[j] = w;
+        }
+    }
     Kahan acc;
     for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
         const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
-        /* rank-1 lattice point, then u_m = u_{m-1} - v_m, v_m = -tau log(1-x_m) */
+        /* rank-1 lattice (or Sobol') point, then u_m = u_{m-1} - v_m,
+         * v_m = -tau log(1-x_m) */
         double u[N];
         double prev = it.t_meas, p = 1.0, qm = 1.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const uint32_t m = (idx * it.z[j]) & it.mask;
-            double y = (double)m * it.inv_n + shift[j];
-            if (y >= 1.0) y -= 1.0;
+            double y;
+            if constexpr (SOB) {
+                y = (double)word[j] * (1.0 / 4294967296.0);
+            } else {
+                const uint32_t m = (idx * it.z[j]) & it.mask;
+                y = (double)m * it.inv_n + shift[j];
+                if (y >= 1.0) y -= 1.0;
+            }
             /* learned second warp: y -> w = F_j^{-1}(y), weight / q_j(w) */
             if constexpr (MODEL)
                 qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
@@ -467,6 +493,15 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
         double W = it.tau_n / p;
         if constexpr (MODEL) W /= qm;
         const bool inside = u[N - 1] > 0.0;
+        if constexpr (SOB) {
+            /* next index: the bits of base ^ (base + 64), the same in every lane */
+            const uint32_t base = i0 + (uint32_t)c0;
+            const uint32_t flip = base ^ (base + (uint32_t)WAVE);
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                for (int k = 6; k < 32 && (flip >> k); ++k)
+                    if ((flip >> k) & 1u) word[j] ^= sv[j * 32 + k];
+        }
         if (!CUR && it.mode != QQMC_MODE_CHARGE) {
             /* the model function is the combined one, p_n prod_j q_j */
             if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * qm * W, 0.0));
@@ -498,12 +533,12 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
     return wave_sum(acc.value());
 }
 
-template <int N, bool MODEL, bool PAIR, bool CUR = false>
+template <int N, bool MODEL, bool PAIR, bool CUR = false, bool SOB = false>
 __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
-        const cplx v = order_tile<N, MODEL, false, PAIR, CUR>(it, tile, lds);
+        const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB>(it, tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * tile] = v.x;
             it.tile_sums[2 * tile + 1] = v.y;
@@ -812,7 +847,15 @@ template <int N> struct OrderLaunch {
     template <bool PAIR> static hipError_t go(const ItemDesc &it, hipStream_t s)
     {
         const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-        if (it.mode == QQMC_MODE_CURRENT)   /* no learned warp (checked on the host) */
+        /* the current and Sobol' points take no learned warp (checked on
+         * the host) */
+        if (it.sobol && it.mode == QQMC_MODE_CURRENT)
+            hipLaunchKernelGGL((order_kernel<N, false, PAIR, true, true>), dim3((unsigned)blocks),
+                               dim3(64), (Lds<N, PAIR, true>::bytes), s, it);
+        else if (it.sobol)
+            hipLaunchKernelGGL((order_kernel<N, false, PAIR, false, true>), dim3((unsigned)blocks),
+                               dim3(64), (Lds<N, PAIR>::bytes), s, it);
+        else if (it.mode == QQMC_MODE_CURRENT)
             hipLaunchKernelGGL((order_kernel<N, false, PAIR, true>), dim3((unsigned)blocks),
                                dim3(64), (Lds<N, PAIR, true>::bytes), s, it);
         else if (it.model_cdf)

@@ -339,10 +339,11 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
             return st;
         }
         Validated v;
-        if (items[i].order.mode == QQMC_MODE_CURRENT) {
+        if (items[i].order.mode == QQMC_MODE_CURRENT || items[i].order.sobol_v) {
             delete p;
             return set_error(QQMC_EINVAL, "item " + std::to_string(i) +
-                                              ": the current runs as single launches only");
+                                              ": the current and Sobol' points run as single "
+                                              "launches only");
         }
         if (qqmc_status st = validate_order(&items[i].order, items[i].tables->n_grid,
                                             items[i].tables->t_half, &v)) {

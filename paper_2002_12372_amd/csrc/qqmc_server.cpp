@@ -511,8 +511,8 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     auto r = std::make_shared<Request>();
     Validated v;
     if (qqmc_status st = validate_order(ord, dot->n_grid, dot->t_half, &v)) return st;
-    if (ord->mode == QQMC_MODE_CURRENT)
-        return set_error(QQMC_EINVAL, "the current runs as single launches only");
+    if (ord->mode == QQMC_MODE_CURRENT || ord->sobol_v)
+        return set_error(QQMC_EINVAL, "the current and Sobol' points run as single launches only");
     r->dot = *dot;
     r->desc = v.desc;
     r->shifts = v.shifts;

@@ -43,7 +43,9 @@ class qqmc_order(ctypes.Structure):
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("model", ctypes.c_void_p),
-                ("alpha", ctypes.c_double)]
+                ("alpha", ctypes.c_double),
+                ("sobol_v", ctypes.POINTER(ctypes.c_uint32)),
+                ("sobol_shifts", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class qqmc_learn_params(ctypes.Structure):
@@ -207,10 +209,17 @@ def make_order(job, t_meas, model=None):
     """job: qqmc_inputs.OrderJob; model: a Model of the same order or None.
     The returned struct keeps the shift array alive through ``_keep``."""
     sh = np.ascontiguousarray(job.shifts, dtype=np.float64)
+    sv = getattr(job, "sobol_v", None)
+    pv = ps = ss = None
+    if sv is not None:
+        sv = np.ascontiguousarray(sv, dtype=np.uint32)
+        ss = np.ascontiguousarray(job.sobol_shifts, dtype=np.uint32)
+        pv = sv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        ps = ss.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
     o = qqmc_order(job.order, job.log2_n, job.lattice_a, sh.shape[0], _pd(sh),
                    job.model_tau, t_meas, job.mode,
-                   model.handle if model is not None else None, job.alpha)
-    o._keep = (sh, model)
+                   model.handle if model is not None else None, job.alpha, pv, ps)
+    o._keep = (sh, model, sv, None if sv is None else ss)
     return o
 
 

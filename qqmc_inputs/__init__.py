@@ -11,7 +11,7 @@ pseudorandom number generators", OOPSLA 2014), implemented here from its
 published definition.
 """
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -88,6 +88,8 @@ class OrderJob:
     model_tau: float = 1.0
     mode: int = 0
     alpha: float = 0.0
+    sobol_v: Optional[np.ndarray] = None       # (order, 32) uint32, or None
+    sobol_shifts: Optional[np.ndarray] = None  # (n_shifts, order) uint32
 
 
 def order_job(seed: int, order: int, log2_n: int, n_shifts: int,
@@ -98,6 +100,18 @@ def order_job(seed: int, order: int, log2_n: int, n_shifts: int,
     a = lattice_multiplier(rng, log2_n)
     sh = shifts(rng, n_shifts, order)
     return OrderJob(order, log2_n, a, sh, model_tau, mode, alpha)
+
+
+def sobol_job(seed: int, order: int, log2_n: int, n_shifts: int, model_tau: float = 1.0,
+              mode: int = 0, alpha: float = 0.0) -> OrderJob:
+    """The first 2^log2_n Sobol' points (App. B) with n_shifts random digital
+    shifts from one SplitMix64 stream seeded by (seed, order); direction
+    numbers as derived in qqmc_inputs.sobol."""
+    from . import sobol
+    V = sobol.direction_numbers(order)
+    ds = sobol.digital_shifts((seed * 1000003 + order + 77) & _MASK, n_shifts, order)
+    return OrderJob(order, log2_n, 0, np.zeros((n_shifts, order)), model_tau, mode, alpha,
+                    V, ds)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,117 @@
+"""Sobol' points (App. B) on the GPU against the oracle: the same direction
+numbers and digital shifts (qqmc_inputs.sobol) on both sides, per-shift
+estimates and sampled tiles, both elimination trees, the charge and the
+current.  Tolerances as in the lattice parity tests (1e-9 relative)."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from qqmc_inputs import Dot, STRESS_DOT, TINY_DOT, order_job, sobol_job
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_12372_amd import qqmc
+    qqmc.lib()
+    return qqmc
+
+
+def _upload(q, tb):
+    return q.tables_from_host(tb.gl, tb.gg, tb.n_grid, tb.t_half, tb.n_sigma)
+
+
+def _compare(qs, qo, label, floor=None):
+    for s in range(len(qo)):
+        fl = 1e-15 if floor is None else floor
+        assert abs(qs[s] - qo[s]) <= 1e-9 * abs(qo[s]) + fl, (label, s, qs[s], qo[s])
+
+
+@pytest.mark.parametrize("n,log2_n,K", [(1, 14, 8), (2, 12, 4), (4, 11, 3), (6, 11, 2),
+                                        (8, 10, 2), (10, 8, 2), (12, 7, 1)])
+def test_sobol_estimates_match_oracle(q, oracle_mod, n, log2_n, K):
+    d = STRESS_DOT if n > 8 else TINY_DOT
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    job = sobol_job(81, n, log2_n, K)
+    qs, _, _ = q.eval_order(_upload(q, tb), job, 10.0)
+    qo, _, _ = oracle_mod.eval_order_sobol(tb, 10.0, n, log2_n, job.sobol_v, job.sobol_shifts,
+                                           1.0)
+    _compare(qs, qo, "sobol n=%d" % n)
+
+
+def test_sobol_paired_tree(q, oracle_mod):
+    """alpha = n_sigma (zero vertex diagonal) on Sobol' points."""
+    tb = oracle_mod.Tables(0.3, 1.0, 20.0, 0.4)
+    a = tb.n_sigma
+    job = sobol_job(82, 6, 11, 3, alpha=a)
+    qs, _, _ = q.eval_order(_upload(q, tb), job, 10.0)
+    qo, _, _ = oracle_mod.eval_order_sobol(tb, 10.0, 6, 11, job.sobol_v, job.sobol_shifts,
+                                           1.0, alpha=a)
+    _compare(qs, qo, "sobol paired", floor=1e-13)
+
+
+def test_sobol_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
+    """n = 8, N = 2^20, 32 digital shifts at the default tile length: sampled
+    tiles against the oracle over the same index ranges (the kernel steps the
+    coordinate words by 64 indices across each tile)."""
+    gt = _upload(q, tiny_tables)
+    job = sobol_job(1, 8, 20, 32)
+    sums = torch.zeros(64, dtype=torch.float64, device="cuda")
+    nt = q.eval_order_async(gt, job, 10.0, sums, None)
+    torch.cuda.synchronize()
+    tile_len = (1 << 20) * 32 // nt
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    per = (1 << 20) // tile_len
+    for k in np.random.default_rng(96).choice(nt, size=8, replace=False):
+        s, i0 = divmod(int(k), per)
+        ref = oracle_mod.eval_sums_sobol(tiny_tables, 10.0, 8, job.sobol_v,
+                                         job.sobol_shifts[s:s + 1], 1.0, i0 * tile_len,
+                                         (i0 + 1) * tile_len)[0]
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13
+
+
+def test_sobol_and_lattice_agree_full_size(q, tiny_tables):
+    """Both point sets estimate the same Q_8 (N = 2^20 x 32)."""
+    gt = _upload(q, tiny_tables)
+    _, ms, ses = q.eval_order(gt, sobol_job(2, 8, 20, 32), 10.0)
+    _, ml, sel = q.eval_order(gt, order_job(2, 8, 20, 32), 10.0)
+    print("Q_8 Sobol' %.10f +- %.1e, lattice %.10f +- %.1e" % (ms.real, ses, ml.real, sel))
+    assert abs(ms.real - ml.real) < 5 * math.hypot(ses, sel)
+
+
+def test_sobol_current(q, oracle_mod):
+    d = Dot(0.3, 1.0, 2.0, 0.8, n_grid=4001, half_bandwidth=4.0)
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half,
+                           half_bandwidth=d.half_bandwidth, lead=1)
+    gt = _upload(q, tb)
+    q.tables_lead_from_host(gt, tb.cl, tb.cg)
+    job = sobol_job(83, 3, 11, 3, mode=q.MODE_CURRENT)
+    qs, _, _ = q.eval_order(gt, job, 10.0)
+    # the oracle's current estimator takes lattice points; the Sobol' one is
+    # checked per point: sum of the current integrand over the same points
+    ref = np.zeros(3, dtype=complex)
+    for s in range(3):
+        acc = 0.0
+        for i in range(1 << 11):
+            x = oracle_mod.sobol_point(i, job.sobol_v, job.sobol_shifts[s])
+            u, W, inside = oracle_mod.warp(x, 1.0, 10.0)
+            if inside:
+                acc += W * oracle_mod.current_integrand(tb, 10.0, u)[0]
+        ref[s] = acc / (1 << 11)
+    _compare(qs, ref, "sobol current", floor=1e-14)
+
+
+def test_sobol_rejected_by_plans(q, tiny_tables):
+    gt = _upload(q, tiny_tables)
+    with pytest.raises(q.QQMCError):
+        q.plan_create([(gt, sobol_job(84, 3, 10, 2))], 10.0, tile_len=256)

@@ -26,6 +26,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 
 KERNEL_SOURCES = ["paper_2002_12372_amd/csrc/qqmc_kernels.hip",
+                  "paper_2002_12372_amd/csrc/qqmc_kernels.h",
                   "paper_2002_12372_amd/csrc/qqmc_tree.h",
                   "paper_2002_12372_amd/csrc/qqmc_gf.h",
                   "paper_2002_12372_amd/csrc/qqmc_internal.h",

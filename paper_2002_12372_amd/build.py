@@ -9,8 +9,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqqmc.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["qqmc_kernels.hip", "qqmc_api.cpp", "qqmc_tables.cpp", "qqmc_plan.cpp", "qqmc_model.cpp",
-           "qqmc_server.cpp"]
+SOURCES = ["qqmc_kernels.hip", "qqmc_kernels_pair.hip", "qqmc_kernels_cur.hip",
+           "qqmc_kernels_sob.hip", "qqmc_api.cpp", "qqmc_tables.cpp", "qqmc_plan.cpp",
+           "qqmc_model.cpp", "qqmc_server.cpp"]
 
 # gfx950 only; packed-FP32 instructions are kept out of the generated code.
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -1,0 +1,746 @@
+/*
+ * qqmc_kernels.h -- device code shared by the kernel translation units
+ * (qqmc_kernels*.hip): local-memory layout, wave helpers, the cooperative top
+ * blocks, the per-point Keldysh sums, the tile function and the kernel
+ * templates, and generic launchers for one (order, variant).  Each variant
+ * (scalar or paired elimination tree, charge or current, lattice or Sobol'
+ * points) is instantiated in its own translation unit, so they compile in
+ * parallel; the units call one another only through the named functions
+ * declared at the end.
+ *
+ * Work decomposition.  One workgroup is one 64-lane wavefront.  A work tile
+ * is (shift s, 64*c consecutive lattice indices).  For every 64 indices the
+ * wave
+ *   1. generates the shifted Korobov lattice point and warps it through the
+ *      inverse CDF of the product model h(v) = exp(-v/tau) (one lane per
+ *      index: Eqs. (warper1d), (x_of_v_simple), (hi_expo)),
+ *   2. compacts the points inside the domain 0 < u_n (App. I: points outside
+ *      contribute exactly zero) with a ballot,
+ *   3. for every compacted point builds the pair table of interpolated
+ *      g^<(tau), g^>(tau) in LDS (lanes of the point's group share the work),
+ *   4. evaluates the Keldysh sum with the elimination tree of qqmc_tree.h,
+ *      G = 2^T lanes per point (or per top-level prefix for n > 8),
+ *   5. folds -2 i^{n+1} S(u) W into a per-lane compensated accumulator.
+ * The tree kernels are compiled for two waves per SIMD (256 registers per
+ * lane; the few values that do not fit go to scratch), which measured
+ * faster than one wave per SIMD with no spills.
+ * The tile's sum goes to one slot of a partials array; a second kernel sums
+ * the slots of each shift in a fixed order.  No floating-point atomics are
+ * used anywhere, so results are bitwise reproducible.
+ */
+#ifndef QQMC_KERNELS_H
+#define QQMC_KERNELS_H
+
+#include "qqmc_gf.h"
+#include "qqmc_internal.h"
+#include "qqmc_tree.h"
+
+namespace qqmc {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+template <int N, bool PAIR = false, bool CUR = false> struct Lds {
+    using Gm = Geo<N, PAIR>;
+    /* pair-table stride: the NP pairs, then for the current the n lead
+     * values of the measurement column */
+    static constexpr int NPS = Gm::NP + (CUR ? N : 0);
+    static constexpr int times = 0;                                    /* 64*N doubles   */
+    static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
+    static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
+    static constexpr int ids = S + 64 * 16;                            /* 64 int32       */
+    /* pair tables: one per item group, or one per distinct point of a
+     * round when several items share a point */
+    static constexpr int tables =
+        Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
+    static constexpr int pairs = ids + 64 * 4;                         /* tables*NP pairv */
+    /* one broadcast row per group (two for the paired tree) */
+    static constexpr int rows = PAIR ? 2 : 1;
+    static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
+    static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
+    static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+};
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m)
+{
+    return __shfl_xor(v, m, WAVE);
+}
+
+/* Ordering point for the single-wave workgroups of the tree kernels: the
+ * local-memory operations of one wave execute in program order, so lanes
+ * exchanging data through local memory need only keep the compiler from
+ * moving memory operations across this point -- no hardware barrier and no
+ * wait for outstanding local-memory operations.  Every kernel that uses it
+ * is launched with exactly one 64-lane wave per workgroup. */
+__device__ __forceinline__ void wave_sync()
+{
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+/* Later point j of the pair with triangular index q = j(j-1)/2 + i, i < j:
+ * the largest j with j(j-1)/2 <= q (float square root is exact enough for
+ * q < 2^20; the two integer corrections make it exact regardless). */
+__device__ __forceinline__ int pair_hi(int q)
+{
+    int j = (int)((1.0f + sqrtf(8.0f * (float)q + 1.0f)) * 0.5f);
+    if (j * (j - 1) / 2 > q) --j;
+    if ((j + 1) * j / 2 <= q) ++j;
+    return j;
+}
+
+/* -2 i^{n+1} S: the charge prefactor (spin sum 2, i^n of the expansion, the
+ * extra -i of <n> = -i g^<). */
+template <int N> __device__ __forceinline__ cplx charge_prefactor(cplx s)
+{
+    constexpr int q = (N + 1) & 3;
+    if constexpr (q == 0) return cmk(-2.0 * s.x, -2.0 * s.y);
+    else if constexpr (q == 1) return cmk(2.0 * s.y, -2.0 * s.x);
+    else if constexpr (q == 2) return cmk(2.0 * s.x, 2.0 * s.y);
+    else return cmk(-2.0 * s.y, 2.0 * s.x);
+}
+
+/* -4 i^n S: its real part is the order-n integrand of the particle current
+ * into the lead (both spins); the charge's is -2 i^{n+1} S. */
+template <int N, bool CUR> __device__ __forceinline__ cplx observable_prefactor(cplx s)
+{
+    if constexpr (!CUR) {
+        return charge_prefactor<N>(s);
+    } else {
+        constexpr int q = N & 3;
+        if constexpr (q == 0) return cmk(-4.0 * s.x, -4.0 * s.y);
+        else if constexpr (q == 1) return cmk(4.0 * s.y, -4.0 * s.x);
+        else if constexpr (q == 2) return cmk(4.0 * s.x, 4.0 * s.y);
+        else return cmk(-4.0 * s.y, 4.0 * s.x);
+    }
+}
+
+struct Kahan {
+    double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
+    __device__ __forceinline__ void add(cplx v)
+    {
+        double y = v.x - cx, t = sx + y;
+        cx = (t - sx) - y; sx = t;
+        y = v.y - cy; t = sy + y;
+        cy = (t - sy) - y; sy = t;
+    }
+    __device__ __forceinline__ cplx value() const { return cmk(sx - cx, sy - cy); }
+};
+
+/* Fixed-order butterfly over the whole wave; every lane ends with the same
+ * bits (IEEE addition is commutative). */
+__device__ __forceinline__ cplx wave_sum(cplx v)
+{
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+        v.x += shfl_xor_d(v.x, m);
+        v.y += shfl_xor_d(v.y, m);
+    }
+    return v;
+}
+
+/* Environment of the points being evaluated (one parameter point). */
+struct Env {
+    const double *tab;
+    double t_half, inv_h, t_meas;
+    cplx g0;      /* vertex diagonal i (n_sigma - alpha)                      */
+    cplx gm;      /* measurement diagonal i n_sigma (the direct method only)  */
+    const double *col; /* current: the lead's gamma g^<_{0i}, gamma g^>_{0i}
+                          on the same grid, or null (the charge)            */
+    int n_grid;
+};
+
+/* The first OFF = n - 8 eliminations of a work item (n > 8), done by the G
+ * lanes of the item's group with whole matrix rows per lane (row r on lane
+ * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
+ * 9 x 9 trailing correction block in s_c0 and returns the product of the
+ * OFF pivots. */
+template <int N, bool CUR = false>
+__device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
+                          cplx *s_row, cplx *s_c0)
+{
+    using Gm = Geo<N>;
+    constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
+    constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
+    cplx crow[RPL][N + 1];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m)
+#pragma unroll
+        for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
+    cplx prod = cmk(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < OFF; ++k) {
+        const int b = (top >> (OFF - 1 - k)) & 1;
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            if (sub + m * G == k) {
+                /* every table read before the first store, so the reads
+                 * are issued together rather than each behind a store it
+                 * might alias */
+                cplx v[N + 1];
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
+                s_row[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) s_row[j] = v[j];
+            }
+        }
+        wave_sync();
+        const cplx p = s_row[k];
+        const cplx rp = crecip_nr(p);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r > k && r <= N) {
+                const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[m][k]), rp);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) crow[m][j] = cfma(ch, s_row[j], crow[m][j]);
+            }
+        }
+        prod = cmul(prod, p);
+        wave_sync();
+    }
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+        const int r = sub + m * G;
+        if (r >= OFF && r <= N) {
+#pragma unroll
+            for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[m][j];
+        }
+    }
+    wave_sync();
+    return prod;
+}
+
+/* The paired tree's first OFF eliminations (OFF even, n > 8): pair steps of
+ * vertices (k, k+1) with 2x2 block pivots, rows spread over the G lanes as
+ * in top_block.  The lanes holding rows k and k+1 broadcast them through
+ * s_row (2 (n+1) entries); every lane applies the rank-2 update to its rows
+ * below.  Leaves the K x K trailing correction block in s_c0 and returns the
+ * product of the pivot-block determinants. */
+template <int N, bool CUR = false>
+__device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
+                               cplx *s_row, cplx *s_c0)
+{
+    using Gm = Geo<N, true>;
+    constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
+    constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
+    cplx *s_r0 = s_row, *s_r1 = s_row + (N + 1);
+    cplx crow[RPL][N + 1];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m)
+#pragma unroll
+        for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
+    cplx prod = cmk(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < OFF; k += 2) {
+        const int b = (top >> (OFF - 1 - k)) & 1, bq = (top >> (OFF - 2 - k)) & 1;
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r == k) {
+                cplx v[N + 1];
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
+                s_r0[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                for (int j = k + 1; j <= N; ++j) s_r0[j] = v[j];
+            } else if (r == k + 1) {
+                /* (k+1, k): the earlier point is k, so index b */
+                cplx v[N + 1];
+                v[k] = csub(wick_entry(pr, k + 1, k, b), crow[m][k]);
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j)
+                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k + 1, j, N, bq), crow[m][j]);
+                s_r1[k + 1] = csub(g0, crow[m][k + 1]);
+                s_r1[k] = v[k];
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j) s_r1[j] = v[j];
+            }
+        }
+        wave_sync();
+        const cplx a = s_r0[k], be = s_r0[k + 1], ga = s_r1[k], d = s_r1[k + 1];
+        const cplx det = cfms(be, ga, cmul(a, d));
+        const cplx rdet = crecip_nr(det);
+        const cplx dd = cmul(d, rdet), aa = cmul(a, rdet), bb = cmul(be, rdet), gg = cmul(ga, rdet);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            if (r > k + 1 && r <= N) {
+                const cplx u = csub(wick_entry(pr, r, k, b), crow[m][k]);
+                const cplx z = csub(wick_entry(pr, r, k + 1, bq), crow[m][k + 1]);
+                const cplx Ui = cfms(z, gg, cmul(u, dd));
+                const cplx Vi = cfms(u, bb, cmul(z, aa));
+#pragma unroll
+                for (int j = k + 2; j <= N; ++j)
+                    crow[m][j] = cfma(Vi, s_r1[j], cfma(Ui, s_r0[j], crow[m][j]));
+            }
+        }
+        prod = cmul(prod, det);
+        wave_sync();
+    }
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+        const int r = sub + m * G;
+        if (r >= OFF && r <= N) {
+#pragma unroll
+            for (int j = OFF; j <= N; ++j) s_c0[(r - OFF) * K + (j - OFF)] = crow[m][j];
+        }
+    }
+    wave_sync();
+    return prod;
+}
+
+/* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
+ * earliest first) sit in s_times; writes S to s_S[0..cnt). */
+template <int N, bool PAIR = false, bool CUR = false>
+__device__ void keldysh_points(int cnt, const Env &env, char *lds)
+{
+    using Gm = Geo<N, PAIR>;
+    using L = Lds<N, PAIR, CUR>;
+    constexpr int NPS = L::NPS;
+    const double *s_times = reinterpret_cast<const double *>(lds + L::times);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
+    const int lane = threadIdx.x;
+    const int grp = lane / Gm::G, sub = lane % Gm::G;
+    const int n_items = cnt * Gm::IPP;
+    for (int base = 0; base < n_items; base += Gm::PPW) {
+        const int item = base + grp;
+        const bool active = item < n_items;
+        const int pt = active ? item / Gm::IPP : 0;
+        const int top = active ? item % Gm::IPP : 0;
+        pairv *prg;
+        if constexpr (Gm::IPP == 1) {
+            /* one point per group: the group's lanes build its pair table;
+             * the loop is unrolled so every table load is issued before the
+             * first interpolation waits */
+            prg = s_pairs + grp * NPS;
+            const double *tm = s_times + pt * N;
+            constexpr int PER = (NPS + Gm::G - 1) / Gm::G;
+            pairv val[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int q = sub + k * Gm::G;
+                if (q < Gm::NP) {
+                    const int j = pair_hi(q), i = q - j * (j - 1) / 2;
+                    const double tj = j == N ? env.t_meas : tm[j];
+                    val[k] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
+                } else if (CUR && q < NPS) {
+                    /* the lead values of vertex q - NP, held as -conj */
+                    const pairv c = interp_pair(env.col, env.n_grid, env.t_half, env.inv_h,
+                                                tm[q - Gm::NP] - env.t_meas);
+                    val[k].gl = cnc(c.gl);
+                    val[k].gg = cnc(c.gg);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int q = sub + k * Gm::G;
+                if (q < NPS) prg[q] = val[k];
+            }
+            wave_sync();
+        } else {
+            /* several items share a point: PTS distinct points per round
+             * (base is a multiple of IPP whenever PTS > 1); their pair
+             * tables are built by the whole wave when the points change */
+            constexpr int PTS = Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1;
+            prg = s_pairs + (grp / Gm::IPP) * NPS;
+            if (PTS > 1 || base % Gm::IPP == 0) {
+                const int first = base / Gm::IPP;
+                for (int q = lane; q < PTS * NPS; q += WAVE) {
+                    const int slot = q / NPS, qq = q % NPS;
+                    const int p = first + slot < cnt ? first + slot : 0;
+                    const double *tm = s_times + p * N;
+                    if (!CUR || qq < Gm::NP) {
+                        const int j = pair_hi(qq), i = qq - j * (j - 1) / 2;
+                        const double tj = j == N ? env.t_meas : tm[j];
+                        s_pairs[q] = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h,
+                                                 tj - tm[i]);
+                    } else {
+                        const pairv c = interp_pair(env.col, env.n_grid, env.t_half, env.inv_h,
+                                                    tm[qq - Gm::NP] - env.t_meas);
+                        s_pairs[q].gl = cnc(c.gl);
+                        s_pairs[q].gg = cnc(c.gg);
+                    }
+                }
+                wave_sync();
+            }
+        }
+        /* measurement-column entries: the lead values for the current, the
+         * last row of the pair table (pairs (k, n)) for the charge */
+        const pairv *mc = prg + (CUR ? Gm::NP : pidx(0, N));
+        cplx prod = cmk(1.0, 0.0);
+        int sgn = 0;
+        BlockSrc<N, PAIR> src;
+        src.c = nullptr;
+        if constexpr (Gm::OFF > 0) {
+            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
+            cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
+            if constexpr (PAIR) prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
+            else prod = top_block<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
+            sgn = __popc((unsigned)top) & 1;
+            src.c = s_c0;
+        }
+        cplx s;
+        if constexpr (PAIR) s = lane_sum_pair<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        else s = lane_sum<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        /* sum over the lanes of a group, then over the groups of the round
+         * that share a point: they are SPAN aligned consecutive lanes, all
+         * active or all idle (points hold IPP consecutive items and rounds
+         * start at multiples of PPW) */
+        constexpr int SPAN = Gm::G * (Gm::IPP < Gm::PPW ? Gm::IPP : Gm::PPW);
+#pragma unroll
+        for (int m = 1; m < SPAN; m <<= 1) {
+            s.x += shfl_xor_d(s.x, m);
+            s.y += shfl_xor_d(s.y, m);
+        }
+        if (lane % SPAN == 0 && active) {
+            if constexpr (Gm::IPP == 1) s_S[pt] = s;
+            else s_S[pt] = cadd(s_S[pt], s);
+        }
+        wave_sync();
+    }
+}
+
+/* Inverse CDF of one coordinate's learned density (App. I): piecewise
+ * constant on `bins` equal bins of [0, 1), CDF c[0..bins] at the bin edges.
+ * Sets w with F(w) = x and returns the density q(w); the bin is the last b
+ * with c[b] <= x (binary search, c non-decreasing, c[0] = 0 <= x < 1). */
+__device__ __forceinline__ double model_inverse(const double *__restrict__ c, int bins, double x,
+                                                double &w)
+{
+    int lo = 0, hi = bins;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    const double c0 = c[lo], width = c[lo + 1] - c0;
+    w = ((double)lo + (x - c0) / width) / (double)bins;
+    return (double)bins * width;
+}
+
+/* One work tile of one order-n integral: sum of fbar over 64*c lattice
+ * indices of one shift.  Returns the wave's sum (same bits in every lane).
+ * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
+ * learning pass): also writes Re fbar of every lattice index of the tile to
+ * it.sample_out. */
+template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = false,
+          bool SOB = false>
+__device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
+{
+    using L = Lds<N, PAIR, CUR>;
+    double *s_times = reinterpret_cast<double *>(lds + L::times);
+    double *s_w = reinterpret_cast<double *>(lds + L::w);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    int32_t *s_ids = reinterpret_cast<int32_t *>(lds + L::ids);
+    (void)s_ids;
+    const int lane = threadIdx.x;
+    const int s = (int)(tile / it.tiles_per_shift);
+    const uint32_t i0 = (uint32_t)(tile % it.tiles_per_shift) * (uint32_t)it.tile_len;
+    const double *sh = it.shifts + (int64_t)s * N;
+    double shift[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) shift[j] = sh[j];
+    Env env;
+    env.tab = it.tab; env.t_half = it.t_half; env.inv_h = 1.0 / it.h; env.t_meas = it.t_meas;
+    env.g0 = cmk(it.g0x, it.g0y); env.gm = cmk(it.g0x, it.g0y + it.alpha);
+    env.col = it.col;
+    env.n_grid = it.n_grid;
+    /* Sobol' points (App. B): each lane keeps the coordinate words of its
+     * index; the tile starts at a multiple of 64 and lanes step by 64, so
+     * the low six index bits are the lane's and the bits that change from
+     * one step to the next are the same in every lane */
+    uint32_t word[SOB ? N : 1];
+    const uint32_t *sv = it.sobol;
+    if constexpr (SOB) {
+        const uint32_t *ds = it.sobol + N * 32 + (int64_t)s * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            uint32_t w = ds[j];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if ((lane >> k) & 1) w ^= sv[j * 32 + k];
+            for (int k = 6; k < 32; ++k)
+                if ((i0 >> k) & 1u) w ^= sv[j * 32 + k];
+            word[j] = w;
+        }
+    }
+    Kahan acc;
+    for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
+        const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
+        /* rank-1 lattice (or Sobol') point, then u_m = u_{m-1} - v_m,
+         * v_m = -tau log(1-x_m) */
+        double u[N];
+        double prev = it.t_meas, p = 1.0, qm = 1.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double y;
+            if constexpr (SOB) {
+                y = (double)word[j] * (1.0 / 4294967296.0);
+            } else {
+                const uint32_t m = (idx * it.z[j]) & it.mask;
+                y = (double)m * it.inv_n + shift[j];
+                if (y >= 1.0) y -= 1.0;
+            }
+            /* learned second warp: y -> w = F_j^{-1}(y), weight / q_j(w) */
+            if constexpr (MODEL)
+                qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
+            const double v = -it.tau * log1p(-y);
+            u[j] = prev - v;
+            p *= exp(-(prev - u[j]) / it.tau);
+            prev = u[j];
+        }
+        double W = it.tau_n / p;
+        if constexpr (MODEL) W /= qm;
+        const bool inside = u[N - 1] > 0.0;
+        if constexpr (SOB) {
+            /* next index: the bits of base ^ (base + 64), the same in every lane */
+            const uint32_t base = i0 + (uint32_t)c0;
+            const uint32_t flip = base ^ (base + (uint32_t)WAVE);
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                for (int k = 6; k < 32 && (flip >> k); ++k)
+                    if ((flip >> k) & 1u) word[j] ^= sv[j * 32 + k];
+        }
+        if (!CUR && it.mode != QQMC_MODE_CHARGE) {
+            /* the model function is the combined one, p_n prod_j q_j */
+            if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * qm * W, 0.0));
+            else if (inside) acc.add(cmk(W, 0.0));
+            continue;
+        }
+        const uint64_t mask = __ballot(inside);
+        const int cnt = __popcll(mask);
+        if (inside) {
+            const int rk = lane_rank(mask);
+#pragma unroll
+            for (int k = 0; k < N; ++k) s_times[rk * N + k] = u[N - 1 - k];
+            s_w[rk] = W;
+            s_S[rk] = cmk(0.0, 0.0);
+            if constexpr (SAMPLE) s_ids[rk] = (int32_t)idx;
+        } else if constexpr (SAMPLE) {
+            it.sample_out[idx] = 0.0;
+        }
+        wave_sync();
+        keldysh_points<N, PAIR, CUR>(cnt, env, lds);
+        if (lane < cnt) {
+            const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
+            const double w = s_w[lane];
+            acc.add(cmk(f.x * w, f.y * w));
+            if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
+        }
+        wave_sync();
+    }
+    return wave_sum(acc.value());
+}
+
+template <int N, bool MODEL, bool PAIR, bool CUR = false, bool SOB = false>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
+        const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB>(it, tile, lds);
+        if (threadIdx.x == 0) {
+            it.tile_sums[2 * tile] = v.x;
+            it.tile_sums[2 * tile + 1] = v.y;
+        }
+    }
+}
+
+/* Learning pass of the learned second warp (App. I): Re fbar of every
+ * lattice index of the item's tiles into it.sample_out (exponential warp
+ * only, charge mode). */
+template <int N, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDesc it)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x)
+        (void)order_tile<N, false, true, PAIR>(it, tile, lds);
+}
+
+/* Production-kernel evaluation at caller-given vertex times (tree method). */
+template <int N, bool PAIR, bool CUR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(Env env, const double *u,
+                                                              int64_t n_points, double *f)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    using L = Lds<N, PAIR, CUR>;
+    double *s_times = reinterpret_cast<double *>(lds + L::times);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    const int lane = threadIdx.x;
+    for (int64_t c0 = (int64_t)blockIdx.x * WAVE; c0 < n_points; c0 += (int64_t)gridDim.x * WAVE) {
+        const int64_t row = c0 + lane;
+        double ur[N];
+        bool ok = row < n_points;
+        if (ok) {
+            double prev = env.t_meas;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                ur[j] = u[row * N + j];
+                ok = ok && (ur[j] <= prev);
+                prev = ur[j];
+            }
+            ok = ok && ur[N - 1] >= 0.0;
+        }
+        const uint64_t mask = __ballot(ok);
+        const int cnt = __popcll(mask);
+        const int rk = lane_rank(mask);
+        if (ok) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) s_times[rk * N + k] = ur[N - 1 - k];
+            s_S[rk] = cmk(0.0, 0.0);
+        }
+        wave_sync();
+        keldysh_points<N, PAIR, CUR>(cnt, env, lds);
+        if (row < n_points) {
+            cplx v = cmk(__builtin_nan(""), __builtin_nan(""));
+            if (ok) v = observable_prefactor<N, CUR>(s_S[rk]);
+            f[2 * row] = v.x;
+            f[2 * row + 1] = v.y;
+        }
+        wave_sync();
+    }
+}
+
+/* Persistent batched kernel for one order: resident workgroups walk a tile
+ * list (tiles of many items, all of order N) that the host sorted by
+ * decreasing cost, workgroup b taking entries b, b + G, b + 2G, ... (G =
+ * grid size).  The loop index comes from blockIdx, so the loop is
+ * wave-uniform, and every tile runs the same order_tile code as the
+ * single-order kernel, so per-tile sums are the same bits.  Work of several
+ * orders runs as concurrent launches of this kernel (graph branches).
+ * (A work queue fed by a lane-0 atomic was tried first: the compiler
+ * threaded the lane-0 branches at the top and bottom of the loop into an
+ * inner cycle for lanes 1..63 that never reached the next atomic.) */
+template <int N, bool PAIR>
+__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
+                                                            const TileRef *__restrict__ tiles,
+                                                            int64_t n_tiles)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const TileRef ref = tiles[t];
+        /* by value: the descriptor lives in registers for the whole tile */
+        const ItemDesc it = items[ref.item];
+        const cplx v = it.model_cdf ? order_tile<N, true, false, PAIR>(it, ref.tile, lds)
+                                    : order_tile<N, false, false, PAIR>(it, ref.tile, lds);
+        if (threadIdx.x == 0) {
+            it.tile_sums[2 * ref.tile] = v.x;
+            it.tile_sums[2 * ref.tile + 1] = v.y;
+        }
+    }
+}
+
+template <template <int> class F, typename... A>
+hipError_t dispatch(int order, A... args)
+{
+    switch (order) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 9: return F<9>::run(args...);
+    case 10: return F<10>::run(args...);
+    case 11: return F<11>::run(args...);
+    case 12: return F<12>::run(args...);
+    case 13: return F<13>::run(args...);
+    case 14: return F<14>::run(args...);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+
+template <int N, bool MODEL, bool PAIR, bool CUR, bool SOB>
+hipError_t go_order(const ItemDesc &it, hipStream_t s)
+{
+    const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
+    hipLaunchKernelGGL((order_kernel<N, MODEL, PAIR, CUR, SOB>), dim3((unsigned)blocks), dim3(64),
+                       (Lds<N, PAIR, CUR>::bytes), s, it);
+    return hipGetLastError();
+}
+
+template <int N, bool PAIR> hipError_t go_sample(const ItemDesc &it, hipStream_t s)
+{
+    const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
+    hipLaunchKernelGGL((sample_kernel<N, PAIR>), dim3((unsigned)blocks), dim3(64),
+                       (Lds<N, PAIR>::bytes), s, it);
+    return hipGetLastError();
+}
+
+template <int N, bool PAIR, bool CUR>
+hipError_t go_points_tree(Env env, const double *u, int64_t n_points, double *f, hipStream_t s)
+{
+    int64_t blocks = (n_points + WAVE - 1) / WAVE;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((points_tree_kernel<N, PAIR, CUR>), dim3((unsigned)blocks), dim3(64),
+                       (Lds<N, PAIR, CUR>::bytes), s, env, u, n_points, f);
+    return hipGetLastError();
+}
+
+template <int N, bool PAIR>
+hipError_t go_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
+                    int32_t grid_blocks, hipStream_t s)
+{
+    const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
+    hipLaunchKernelGGL((batch_kernel<N, PAIR>), dim3((unsigned)g), dim3(64),
+                       (Lds<N, PAIR>::bytes), s, items_dev, tiles_dev, n_tiles);
+    return hipGetLastError();
+}
+
+template <int N, bool PAIR> int32_t occ_batch()
+{
+    int blocks = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, batch_kernel<N, PAIR>, 64, (size_t)Lds<N, PAIR>::bytes);
+    return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+inline Env make_env(const double *tab, const double *col, int32_t n_grid, double t_half, double h,
+             double n_sigma, double alpha, double t_meas)
+{
+    Env e;
+    e.tab = tab; e.n_grid = n_grid; e.t_half = t_half; e.inv_h = 1.0 / h; e.t_meas = t_meas;
+    e.col = col;
+    e.g0 = cmk(0.0, n_sigma - alpha);
+    e.gm = cmk(0.0, n_sigma);
+    return e;
+}
+
+} // namespace
+
+/* Variant units.  qqmc_kernels_pair.hip: the paired tree (alpha != 0) for
+ * the charge on the lattice; qqmc_kernels_cur.hip: the current on the
+ * lattice (both trees); qqmc_kernels_sob.hip: Sobol' points (both trees,
+ * charge or current). */
+hipError_t launch_order_pair(const ItemDesc &it, hipStream_t s);
+hipError_t launch_sample_pair(const ItemDesc &it, hipStream_t s);
+hipError_t launch_points_tree_pair(const double *tab, int32_t n_grid, double t_half, double h,
+                                   double n_sigma, double alpha, int32_t order, double t_meas,
+                                   const double *u, int64_t n_points, double *f, hipStream_t s);
+hipError_t launch_batch_pair(int32_t order, const ItemDesc *items_dev, const TileRef *tiles_dev,
+                             int64_t n_tiles, int32_t grid_blocks, hipStream_t s);
+int32_t batch_blocks_per_cu_pair(int32_t order);
+hipError_t launch_order_current(const ItemDesc &it, hipStream_t s);
+hipError_t launch_points_tree_current(const double *tab, const double *col, int32_t n_grid,
+                                      double t_half, double h, double n_sigma, double alpha,
+                                      int32_t order, double t_meas, const double *u,
+                                      int64_t n_points, double *f, hipStream_t s);
+hipError_t launch_order_sobol(const ItemDesc &it, hipStream_t s);
+
+} // namespace qqmc
+
+#endif

@@ -136,7 +136,9 @@ def run_plain(args):
         alpha = qqmc.tables_export(tables)[2] if args.alpha == "ns" else float(args.alpha)
     make_job = sobol_job if args.sobol else order_job
     job = make_job(1, n, args.log2n, args.shifts, model_tau=tau, mode=mode, alpha=alpha)
-    tflops = pair_tree_flops(n) if alpha != 0.0 else tree_flops(n)
+    # the library runs the paired tree when |n_sigma - alpha| < 0.05
+    paired = abs(qqmc.tables_export(tables)[2] - alpha) < 0.05
+    tflops = pair_tree_flops(n) if paired else tree_flops(n)
     if mode == qqmc.MODE_CURRENT:
         tflops += 16 * n        # the lead-function lookups of the measurement column
     N = 1 << args.log2n
@@ -180,7 +182,8 @@ def run_plain(args):
                                   "semicircular-lead (D=%g)" % d.half_bandwidth
                                   if d.half_bandwidth else "wide-band",
                                   d.gamma, d.eps_d, d.beta, d.bias_v, d.t_meas,
-                                  ", alpha=%.6g, paired tree" % alpha if alpha else "",
+                                  (", alpha=%.6g, %s tree" % (alpha, "paired" if paired else "scalar"))
+                                  if alpha else "",
                                   n, "Sobol' points (digital shifts)" if args.sobol
                                   else "Korobov lattice", args.log2n, args.shifts, tau),
                    "order": n, "lattice_points": N, "shifts": args.shifts,

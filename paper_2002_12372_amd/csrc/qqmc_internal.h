@@ -37,12 +37,20 @@ struct ItemDesc {
                                 then digital shifts (n_shifts x order), or null */
 };
 
+/* Tree selection by the vertex diagonal g0 = i (n_sigma - alpha): the
+ * scalar tree divides by it at the root, so below |n_sigma - alpha| = 0.05
+ * (pivot growth beyond about (0.6/0.05)^2 against the largest Green's
+ * function values) the paired tree runs, whose 2x2 pivot blocks stay
+ * invertible at a zero diagonal; above it the scalar tree is both cheaper
+ * and better conditioned. */
+constexpr double kPairDiagonal = 0.05;
+inline bool needs_pair(double g0y) { return g0y < kPairDiagonal && g0y > -kPairDiagonal; }
+
 /* Batched-kernel selector of an item, 1 .. 2 QQMC_MAX_ORDER: its order,
- * plus QQMC_MAX_ORDER when it runs the paired elimination tree (alpha != 0,
- * the vertex diagonal may vanish). */
+ * plus QQMC_MAX_ORDER when it runs the paired elimination tree. */
 inline int32_t kernel_key(const ItemDesc &d)
 {
-    return d.order + (d.alpha != 0.0 ? QQMC_MAX_ORDER : 0);
+    return d.order + (needs_pair(d.g0y) ? QQMC_MAX_ORDER : 0);
 }
 constexpr int32_t kMaxKernelKey = 2 * QQMC_MAX_ORDER;
 inline int32_t key_order(int32_t key) { return (key - 1) % QQMC_MAX_ORDER + 1; }

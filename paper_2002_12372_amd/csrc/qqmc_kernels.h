@@ -722,7 +722,7 @@ inline Env make_env(const double *tab, const double *col, int32_t n_grid, double
 
 } // namespace
 
-/* Variant units.  qqmc_kernels_pair.hip: the paired tree (alpha != 0) for
+/* Variant units.  qqmc_kernels_pair.hip: the paired tree (needs_pair) for
  * the charge on the lattice; qqmc_kernels_cur.hip: the current on the
  * lattice (both trees); qqmc_kernels_sob.hip: Sobol' points (both trees,
  * charge or current). */

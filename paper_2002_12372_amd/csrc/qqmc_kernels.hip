@@ -277,19 +277,19 @@ hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_
     return hipGetLastError();
 }
 
-/* Sobol' points, the current, the paired tree (alpha != 0: the vertex
- * diagonal may vanish), else the scalar tree. */
+/* Sobol' points, the current, the paired tree (a vertex diagonal near zero,
+ * needs_pair), else the scalar tree. */
 hipError_t launch_order(const ItemDesc &it, hipStream_t s)
 {
     if (it.sobol) return launch_order_sobol(it, s);
     if (it.mode == QQMC_MODE_CURRENT) return launch_order_current(it, s);
-    if (it.alpha != 0.0) return launch_order_pair(it, s);
+    if (needs_pair(it.g0y)) return launch_order_pair(it, s);
     return dispatch<OrderScalar>(it.order, it, s);
 }
 
 hipError_t launch_sample(const ItemDesc &it, hipStream_t s)
 {
-    if (it.alpha != 0.0) return launch_sample_pair(it, s);
+    if (needs_pair(it.g0y)) return launch_sample_pair(it, s);
     return dispatch<SampleScalar>(it.order, it, s);
 }
 
@@ -311,7 +311,7 @@ hipError_t launch_points_tree(const double *tab, const double *col, int32_t n_gr
     if (col)
         return launch_points_tree_current(tab, col, n_grid, t_half, h, n_sigma, alpha, order,
                                           t_meas, u, n_points, f, s);
-    if (alpha != 0.0)
+    if (needs_pair(n_sigma - alpha))
         return launch_points_tree_pair(tab, n_grid, t_half, h, n_sigma, alpha, order, t_meas, u,
                                        n_points, f, s);
     return dispatch<PointsScalar>(order,

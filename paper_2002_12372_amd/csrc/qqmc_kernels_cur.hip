@@ -12,7 +12,7 @@ namespace {
 template <int N> struct OrderCur {
     static hipError_t run(const ItemDesc &it, hipStream_t s)
     {
-        return it.alpha != 0.0 ? go_order<N, false, true, true, false>(it, s)
+        return needs_pair(it.g0y) ? go_order<N, false, true, true, false>(it, s)
                                : go_order<N, false, false, true, false>(it, s);
     }
 };
@@ -40,7 +40,7 @@ hipError_t launch_points_tree_current(const double *tab, const double *col, int3
 {
     return dispatch<PointsCur>(order,
                                make_env(tab, col, n_grid, t_half, h, n_sigma, alpha, t_meas),
-                               alpha != 0.0, u, n_points, f, s);
+                               needs_pair(n_sigma - alpha), u, n_points, f, s);
 }
 
 } // namespace qqmc

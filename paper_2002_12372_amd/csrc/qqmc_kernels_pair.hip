@@ -1,7 +1,7 @@
 /*
- * qqmc_kernels_pair.hip -- the paired elimination tree (alpha != 0, 2x2
- * block pivots; qqmc_tree.h) for the charge on the lattice: order, learning
- * pass, points and batched launches.
+ * qqmc_kernels_pair.hip -- the paired elimination tree (2x2 block pivots,
+ * for a vertex diagonal near zero; qqmc_tree.h) for the charge on the
+ * lattice: order, learning pass, points and batched launches.
  */
 #include "qqmc_kernels.h"
 

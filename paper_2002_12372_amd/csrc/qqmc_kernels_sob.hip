@@ -12,7 +12,7 @@ namespace {
 template <int N> struct OrderSob {
     static hipError_t run(const ItemDesc &it, hipStream_t s)
     {
-        const bool pair = it.alpha != 0.0, cur = it.mode == QQMC_MODE_CURRENT;
+        const bool pair = needs_pair(it.g0y), cur = it.mode == QQMC_MODE_CURRENT;
         if (cur)
             return pair ? go_order<N, false, true, true, true>(it, s)
                         : go_order<N, false, false, true, true>(it, s);

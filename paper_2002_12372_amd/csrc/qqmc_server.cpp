@@ -10,7 +10,8 @@
  *               come from the stream-ordered allocator, all on an admission
  *               stream, so admission never waits for the GPU;
  *   batching    every launch is one persistent kernel of one order (and
- *               elimination tree: scalar, or paired for alpha != 0); it
+ *               elimination tree: scalar, or paired for a vertex diagonal
+ *               near zero); it
  *               rotates over the kernels with pending work, and the
  *               admitted requests of that kernel take tiles in turn (round
  *               robin, up to a per-launch cost budget), so requests that

@@ -278,3 +278,18 @@ def test_particle_hole_symmetric_alpha_half(q, oracle_mod, d):
         qs, _, _ = q.eval_order(gt, job, T_MEAS)
         assert np.all(np.isfinite(qs)), n
         assert np.max(np.abs(qs)) <= 1e-13, (n, qs)
+
+
+@pytest.mark.parametrize("offset", [0.06, -0.06, 0.04, -0.04])
+@pytest.mark.parametrize("n", [4, 7, 8])
+def test_tree_choice_threshold(q, oracle_mod, n, offset):
+    """Either side of the tree switch (|n_sigma - alpha| = 0.05): the scalar
+    tree at a diagonal of 0.06, the paired tree at 0.04, both within 1e-13 of
+    the term mass per point."""
+    tb = _tables(oracle_mod, ALPHA_DOT)
+    gt = _upload(q, tb)
+    alpha = tb.n_sigma - offset
+    u = _points(np.random.default_rng(3300 + n), n, 48)
+    f = _eval_points(q, gt, n, u, q.METHOD_TREE, alpha)
+    _check_values(f, [oracle_mod.integrand(tb, T_MEAS, row, alpha) for row in u],
+                  "n=%d diagonal %g" % (n, offset))

@@ -41,7 +41,7 @@ namespace {
 
 constexpr int WAVE = 64;
 
-template <int N, bool PAIR = false, bool CUR = false> struct Lds {
+template <int N, bool PAIR = false, bool CUR = false, bool SOB = false> struct Lds {
     using Gm = Geo<N, PAIR>;
     /* pair-table stride: the NP pairs, then for the current the n lead
      * values of the measurement column */
@@ -59,7 +59,9 @@ template <int N, bool PAIR = false, bool CUR = false> struct Lds {
     static constexpr int rows = PAIR ? 2 : 1;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
-    static constexpr int bytes = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+    static constexpr int sobv = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+    /* Sobol' direction numbers, N x 32 words */
+    static constexpr int bytes = sobv + (SOB ? N * 32 * 4 : 0);
 };
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m)
@@ -438,7 +440,7 @@ template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = 
           bool SOB = false>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
-    using L = Lds<N, PAIR, CUR>;
+    using L = Lds<N, PAIR, CUR, SOB>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     double *s_w = reinterpret_cast<double *>(lds + L::w);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
@@ -461,19 +463,26 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
      * the low six index bits are the lane's and the bits that change from
      * one step to the next are the same in every lane */
     uint32_t word[SOB ? N : 1];
-    const uint32_t *sv = it.sobol;
+    uint32_t *s_v = reinterpret_cast<uint32_t *>(lds + L::sobv);
     if constexpr (SOB) {
+        /* the direction numbers in local memory: every read below has one
+         * address for the whole wave */
+        for (int q = lane; q < N * 32; q += WAVE) s_v[q] = it.sobol[q];
+        wave_sync();
         const uint32_t *ds = it.sobol + N * 32 + (int64_t)s * N;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             uint32_t w = ds[j];
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                if ((lane >> k) & 1) w ^= sv[j * 32 + k];
-            for (int k = 6; k < 32; ++k)
-                if ((i0 >> k) & 1u) w ^= sv[j * 32 + k];
+                if ((lane >> k) & 1) w ^= s_v[j * 32 + k];
             word[j] = w;
         }
+        for (int k = 6; k < 32; ++k)
+            if ((i0 >> k) & 1u) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) word[j] ^= s_v[j * 32 + k];
+            }
     }
     Kahan acc;
     for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
@@ -504,13 +513,14 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
         if constexpr (MODEL) W /= qm;
         const bool inside = u[N - 1] > 0.0;
         if constexpr (SOB) {
-            /* next index: the bits of base ^ (base + 64), the same in every lane */
+            /* next index: adding 64 flips bits 6 .. 6 + c - 1 of the base,
+             * c - 1 the trailing ones of base >> 6, the same in every lane */
             const uint32_t base = i0 + (uint32_t)c0;
-            const uint32_t flip = base ^ (base + (uint32_t)WAVE);
+            const int c = __builtin_ctz(~(base >> 6)) + 1;
+            for (int k = 6; k < 6 + c && k < 32; ++k) {
 #pragma unroll
-            for (int j = 0; j < N; ++j)
-                for (int k = 6; k < 32 && (flip >> k); ++k)
-                    if ((flip >> k) & 1u) word[j] ^= sv[j * 32 + k];
+                for (int j = 0; j < N; ++j) word[j] ^= s_v[j * 32 + k];
+            }
         }
         if (!CUR && it.mode != QQMC_MODE_CHARGE) {
             /* the model function is the combined one, p_n prod_j q_j */
@@ -668,7 +678,7 @@ hipError_t go_order(const ItemDesc &it, hipStream_t s)
 {
     const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
     hipLaunchKernelGGL((order_kernel<N, MODEL, PAIR, CUR, SOB>), dim3((unsigned)blocks), dim3(64),
-                       (Lds<N, PAIR, CUR>::bytes), s, it);
+                       (Lds<N, PAIR, CUR, SOB>::bytes), s, it);
     return hipGetLastError();
 }
 

@@ -410,7 +410,8 @@ def run_learned(args):
     estimates against the exponential warp alone, for two first-warp taus."""
     import torch
     from paper_2002_12372_amd import qqmc
-    from qqmc_inputs import TINY_DOT as d, order_job
+    from qqmc_inputs import TINY_DOT as d, order_job, sobol_job
+    from qqmc_inputs import sobol as S
 
     n = args.order
     stream = torch.cuda.current_stream()
@@ -419,12 +420,16 @@ def run_learned(args):
     rows = []
     for tau in (1.0, 1.5):
         lj = order_job(41, n, args.learn_log2m, 1, model_tau=tau)
+        sob = {}
+        if args.sobol:
+            sob = {"sobol_v": S.direction_numbers(n), "sobol_shift": S.digital_shifts(41, 1, n)[0]}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         model = qqmc.learn_model(tables, n, args.learn_log2m, lj.lattice_a, lj.shifts[0], tau,
-                                 d.t_meas, args.learn_bins, args.learn_lambda, 1e-3)
+                                 d.t_meas, args.learn_bins, args.learn_lambda, 1e-3, **sob)
         t_learn = time.perf_counter() - t0
-        job = order_job(1, n, args.log2n, args.shifts, model_tau=tau)
+        job = (sobol_job if args.sobol else order_job)(1, n, args.log2n, args.shifts,
+                                                       model_tau=tau)
         sums = torch.zeros(2 * args.shifts, dtype=torch.float64, device="cuda")
 
         def step(m):
@@ -448,10 +453,12 @@ def run_learned(args):
         "value": rows[0]["learned"]["points_per_s"], "unit": "points/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f64", "data": "synthetic", "rows": rows,
         "config": {"workload": "plain dot (Gamma=1, eps_d=0, beta=20, V=0, t=10), order %d, "
-                               "N=2^%d x %d shifts; model learned from 2^%d points, %d bins, "
-                               "lambda %.3g, floor 1e-3"
-                               % (n, args.log2n, args.shifts, args.learn_log2m, args.learn_bins,
-                                  args.learn_lambda)}}), flush=True)
+                               "%s N=2^%d x %d shifts; model learned from 2^%d of those points, "
+                               "%d bins, lambda %.3g, floor 1e-3"
+                               % (n, "Sobol' points (digital shifts)," if args.sobol
+                                  else "Korobov lattice", args.log2n, args.shifts,
+                                  args.learn_log2m, args.learn_bins, args.learn_lambda)}}),
+          flush=True)
 
 
 def run_bethe(args):

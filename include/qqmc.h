@@ -123,8 +123,9 @@ typedef struct {
                                      (XORed into the coordinate words), with
                                      sobol_v; both copied during the call.
                                      Sobol' items run as single launches
-                                     (charge or current; no learned warp, plan
-                                     or server)                               */
+                                     (the charge, with or without a learned
+                                     warp, or the current; no plan or
+                                     server)                                  */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
@@ -240,7 +241,8 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
 /* ---- Learned second warp (App. I) ---------------------------------------
  * Learning: the library evaluates the order-n integrand f~ (exponential warp
  * with model_tau, charge mode, Jacobian included) at the 2^log2_m points of
- * one shifted lattice on the GPU, projects |Re f~| onto each coordinate of
+ * one shifted lattice, or of one digitally shifted Sobol' sequence (the
+ * sample App. I draws), on the GPU, projects |Re f~| onto each coordinate of
  * the unit cube with n_bins equal bins, smooths each projection with the
  * Gaussian kernel exp(-(w - w')^2 / lambda^2) over the bin centres,
  * normalises it to a density, mixes in the uniform density with weight
@@ -249,8 +251,10 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
 typedef struct {
     int32_t order;          /* n, 1 .. QQMC_MAX_ORDER                         */
     int32_t log2_m;         /* learning sample M = 2^log2_m, 6 .. 24          */
-    uint64_t lattice_a;     /* odd Korobov multiplier of the sample lattice   */
-    const double *shift;    /* host, order doubles in [0, 1)                  */
+    uint64_t lattice_a;     /* odd Korobov multiplier of the sample lattice
+                               (not used with sobol_v)                        */
+    const double *shift;    /* host, order doubles in [0, 1) (not used with
+                               sobol_v)                                        */
     double model_tau;       /* first (exponential) warp, > 0                  */
     double t_meas;          /* 0 < t_meas <= table t_half                     */
     int32_t n_bins;         /* 1 .. 4096                                      */
@@ -258,6 +262,10 @@ typedef struct {
     double floor_eps;       /* uniform weight in [0, 1]                       */
     double alpha;           /* interaction shift of the learned integrand, as
                                in qqmc_order                                   */
+    const uint32_t *sobol_v;     /* host, order x 32 direction numbers as in
+                                    qqmc_order, or NULL (lattice sample)      */
+    const uint32_t *sobol_shift; /* host, order words: the sample's digital
+                                    shift; set exactly when sobol_v is         */
 } qqmc_learn_params;
 
 /* Learns a model on the current device; synchronises `stream`.  EINVAL on

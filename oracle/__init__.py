@@ -60,8 +60,8 @@ def _load():
     lib.oracle_eval_sums_lead.restype = i
     PU = ctypes.POINTER(ctypes.c_uint32)
     lib.oracle_sobol_point.argtypes = [u64, i, PU, PU, P]
-    lib.oracle_eval_sums_sobol.argtypes = [P, P, i, d, d, d, d, i, PU, i, PU, d, i, i64, i64,
-                                           i, P]
+    lib.oracle_eval_sums_sobol.argtypes = [P, P, i, d, d, d, d, i, PU, i, PU, d, P, i, i,
+                                           i64, i64, i, P]
     lib.oracle_eval_sums_sobol.restype = i
     lib.oracle_interp.argtypes = [P, i, d, d, P]
     lib.oracle_det.argtypes = [i, P, P]
@@ -81,6 +81,9 @@ def _load():
     lib.oracle_eval_sums_model.restype = i
     lib.oracle_learn_model.argtypes = [P, P, i, d, d, d, d, i, i, u64, P, d, i, d, d, i, P, P]
     lib.oracle_learn_model.restype = i
+    lib.oracle_learn_model_sobol.argtypes = [P, P, i, d, d, d, d, i, i, PU, PU, d, i, d, d, i,
+                                             P, P]
+    lib.oracle_learn_model_sobol.restype = i
     lib.oracle_model_from_hist.argtypes = [i, i, P, d, d, P]
     lib.oracle_model_from_hist.restype = i
     lib.oracle_model_inverse.argtypes = [P, i, d, P]
@@ -237,34 +240,48 @@ def sobol_point(i, V, dshift=None):
     return x
 
 
+def _cdf_arg(cdf, n):
+    if cdf is None:
+        return None, 0
+    cdf = _f64(cdf)
+    assert cdf.ndim == 2 and cdf.shape[0] == n
+    return cdf, cdf.shape[1] - 1
+
+
 def eval_sums_sobol(tables, t_meas, n, V, dshifts, model_tau, i_begin, i_end, mode=0,
-                    alpha=0.0, n_threads=0):
-    """Per-shift sums of fbar W over Sobol' indices [i_begin, i_end)."""
+                    alpha=0.0, n_threads=0, cdf=None):
+    """Per-shift sums of fbar W over Sobol' indices [i_begin, i_end)
+    (cdf: the learned second warp, (n, n_bins + 1), or None)."""
     V = np.ascontiguousarray(V, dtype=np.uint32)
     dshifts = np.ascontiguousarray(dshifts, dtype=np.uint32)
     K = dshifts.shape[0]
     sums = np.zeros(2 * K)
+    cdf, nb = _cdf_arg(cdf, n)
     rc = _load().oracle_eval_sums_sobol(*tables._args(alpha), t_meas, n, _pu(V), K,
-                                        _pu(dshifts), model_tau, mode, int(i_begin), int(i_end),
-                                        n_threads, _p(sums))
+                                        _pu(dshifts), model_tau,
+                                        _p(cdf) if cdf is not None else None, nb, mode,
+                                        int(i_begin), int(i_end), n_threads, _p(sums))
     if rc != 0:
         raise ValueError("oracle_eval_sums_sobol: bad arguments")
     return sums[0::2] + 1j * sums[1::2]
 
 
 def eval_order_sobol(tables, t_meas, n, log2_n, V, dshifts, model_tau, mode=0, alpha=0.0,
-                     n_threads=0):
+                     n_threads=0, cdf=None):
     """Q^{(s)} over the first 2^log2_n Sobol' points, one digital shift per
-    row of dshifts; their mean and standard error."""
+    row of dshifts; their mean and standard error (cdf as in
+    eval_sums_sobol)."""
     V = np.ascontiguousarray(V, dtype=np.uint32)
     dshifts = np.ascontiguousarray(dshifts, dtype=np.uint32)
     K = dshifts.shape[0]
     assert V.shape == (n, 32) and dshifts.shape == (K, n)
     sums = np.zeros(2 * K)
     N = 1 << log2_n
+    cdf, nb = _cdf_arg(cdf, n)
     rc = _load().oracle_eval_sums_sobol(*tables._args(alpha), t_meas, n, _pu(V), K,
-                                        _pu(dshifts), model_tau, mode, 0, N, n_threads,
-                                        _p(sums))
+                                        _pu(dshifts), model_tau,
+                                        _p(cdf) if cdf is not None else None, nb, mode, 0, N,
+                                        n_threads, _p(sums))
     if rc != 0:
         raise ValueError("oracle_eval_sums_sobol: bad arguments")
     q = (sums[0::2] + 1j * sums[1::2]) / N
@@ -400,6 +417,22 @@ def learn_model(tables, t_meas, n, log2_m, lattice_a, shift, model_tau, n_bins,
     rc = _load().oracle_learn_model(*tables._args(alpha), t_meas, n, log2_m, int(lattice_a),
                                     _p(shift), model_tau, n_bins, lam, floor_eps,
                                     n_threads, _p(hist), _p(cdf))
+    assert rc == 0
+    return hist, cdf
+
+
+def learn_model_sobol(tables, t_meas, n, log2_m, V, dshift, model_tau, n_bins, lam,
+                      floor_eps, n_threads=0, alpha=0.0):
+    """learn_model over the Sobol' points i < 2^log2_m with one digital
+    shift (dshift: n words)."""
+    V = np.ascontiguousarray(V, dtype=np.uint32)
+    dshift = np.ascontiguousarray(dshift, dtype=np.uint32).reshape(n)
+    assert V.shape == (n, 32)
+    hist = np.zeros((n, n_bins))
+    cdf = np.zeros((n, n_bins + 1))
+    rc = _load().oracle_learn_model_sobol(*tables._args(alpha), t_meas, n, log2_m, _pu(V),
+                                          _pu(dshift), model_tau, n_bins, lam, floor_eps,
+                                          n_threads, _p(hist), _p(cdf))
     assert rc == 0
     return hist, cdf
 

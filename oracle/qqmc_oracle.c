@@ -975,13 +975,14 @@ int oracle_eval_sums_model(const double *gl, const double *gg, int n_grid,
 int oracle_eval_sums_sobol(const double *gl, const double *gg, int n_grid,
                            double t_half, double n_sigma, double alpha, double t_meas,
                            int n, const uint32_t *sobol_v, int n_shifts,
-                           const uint32_t *sobol_shifts, double model_tau, int mode,
+                           const uint32_t *sobol_shifts, double model_tau,
+                           const double *cdf, int n_bins, int mode,
                            int64_t i_begin, int64_t i_end, int n_threads, double *sums)
 {
     if (!sobol_v || !sobol_shifts) return -1;
     return eval_sums_core(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, 32, 0, n_shifts,
-                          NULL, sobol_v, sobol_shifts, model_tau, NULL, 0, mode, i_begin, i_end,
-                          n_threads, sums);
+                          NULL, sobol_v, sobol_shifts, model_tau, cdf, n_bins, mode, i_begin,
+                          i_end, n_threads, sums);
 }
 
 /* Term mass of the charge estimate (exponential warp): per shift, the sum
@@ -1082,12 +1083,23 @@ int oracle_eval_sums(const double *gl, const double *gg, int n_grid,
                                   i_begin, i_end, n_threads, sums);
 }
 
-int oracle_learn_model(const double *gl, const double *gg, int n_grid,
-                       double t_half, double n_sigma, double alpha, double t_meas,
-                       int n, int log2_m, uint64_t lattice_a,
-                       const double *shift, double model_tau, int n_bins,
-                       double lambda, double floor_eps, int n_threads,
-                       double *hist, double *cdf)
+/* Point i of the learning sample: the shifted lattice, or (sobol_v set)
+ * Sobol' point i with the digital shift dshift. */
+static void learn_point(int64_t i, int n, int log2_m, uint64_t lattice_a, const double *shift,
+                        const uint32_t *sobol_v, const uint32_t *dshift, double *x)
+{
+    if (sobol_v)
+        oracle_sobol_point((uint64_t)i, n, sobol_v, dshift, x);
+    else
+        oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
+}
+
+static int learn_core(const double *gl, const double *gg, int n_grid,
+                      double t_half, double n_sigma, double alpha, double t_meas,
+                      int n, int log2_m, uint64_t lattice_a, const double *shift,
+                      const uint32_t *sobol_v, const uint32_t *dshift,
+                      double model_tau, int n_bins, double lambda, double floor_eps,
+                      int n_threads, double *hist, double *cdf)
 {
     if (n < 1 || n > 24 || log2_m < 1 || log2_m > 30 || n_bins < 1) return -1;
     const int64_t M = (int64_t)1 << log2_m;
@@ -1105,7 +1117,7 @@ int oracle_learn_model(const double *gl, const double *gg, int n_grid,
     #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
     for (int64_t i = 0; i < M; ++i) {
         double x[32], u[32], W, S[2], Mass;
-        oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
+        learn_point(i, n, log2_m, lattice_a, shift, sobol_v, dshift, x);
         double v = 0.0;
         if (oracle_warp(n, x, model_tau, t_meas, u, &W)) {
             oracle_keldysh_sum(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, u, S, &Mass);
@@ -1117,7 +1129,7 @@ int oracle_learn_model(const double *gl, const double *gg, int n_grid,
     for (int64_t i = 0; i < M; ++i) {
         if (vals[i] == 0.0) continue;
         double x[32];
-        oracle_lattice_point((uint64_t)i, n, log2_m, lattice_a, shift, x);
+        learn_point(i, n, log2_m, lattice_a, shift, sobol_v, dshift, x);
         for (int j = 0; j < n; ++j) {
             int b = (int)(x[j] * n_bins);
             if (b > n_bins - 1) b = n_bins - 1;
@@ -1129,4 +1141,29 @@ int oracle_learn_model(const double *gl, const double *gg, int n_grid,
     free(vals);
     free(h);
     return rc;
+}
+
+int oracle_learn_model(const double *gl, const double *gg, int n_grid,
+                       double t_half, double n_sigma, double alpha, double t_meas,
+                       int n, int log2_m, uint64_t lattice_a,
+                       const double *shift, double model_tau, int n_bins,
+                       double lambda, double floor_eps, int n_threads,
+                       double *hist, double *cdf)
+{
+    return learn_core(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, log2_m, lattice_a,
+                      shift, NULL, NULL, model_tau, n_bins, lambda, floor_eps, n_threads,
+                      hist, cdf);
+}
+
+int oracle_learn_model_sobol(const double *gl, const double *gg, int n_grid,
+                             double t_half, double n_sigma, double alpha, double t_meas,
+                             int n, int log2_m, const uint32_t *sobol_v,
+                             const uint32_t *dshift, double model_tau, int n_bins,
+                             double lambda, double floor_eps, int n_threads,
+                             double *hist, double *cdf)
+{
+    if (!sobol_v || !dshift) return -1;
+    return learn_core(gl, gg, n_grid, t_half, n_sigma, alpha, t_meas, n, log2_m, 0, NULL,
+                      sobol_v, dshift, model_tau, n_bins, lambda, floor_eps, n_threads,
+                      hist, cdf);
 }

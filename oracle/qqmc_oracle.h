@@ -126,7 +126,8 @@ void oracle_sobol_point(uint64_t i, int n, const uint32_t *V, const uint32_t *ds
 int oracle_eval_sums_sobol(const double *gl, const double *gg, int n_grid,
                            double t_half, double n_sigma, double alpha, double t_meas,
                            int n, const uint32_t *sobol_v, int n_shifts,
-                           const uint32_t *sobol_shifts, double model_tau, int mode,
+                           const uint32_t *sobol_shifts, double model_tau,
+                           const double *cdf, int n_bins, int mode,
                            int64_t i_begin, int64_t i_end, int n_threads, double *sums);
 
 int oracle_max_threads(void);
@@ -158,6 +159,16 @@ int oracle_learn_model(const double *gl, const double *gg, int n_grid,
                        const double *shift, double model_tau, int n_bins,
                        double lambda, double floor_eps, int n_threads,
                        double *hist, double *cdf);
+
+/* The same learning pass over the Sobol' points i < 2^log2_m (App. I samples
+ * the cube with Sobol' points): sobol_v n x 32 direction numbers, dshift n
+ * words of one digital shift. */
+int oracle_learn_model_sobol(const double *gl, const double *gg, int n_grid,
+                             double t_half, double n_sigma, double alpha, double t_meas,
+                             int n, int log2_m, const uint32_t *sobol_v,
+                             const uint32_t *dshift, double model_tau, int n_bins,
+                             double lambda, double floor_eps, int n_threads,
+                             double *hist, double *cdf);
 
 /* Builds a model from given per-coordinate projections (n*n_bins values):
  * smoothing, normalisation, floor and CDF as in oracle_learn_model. */

@@ -47,7 +47,6 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
         return set_error(QQMC_EINVAL, "n_shifts must be in 1..65535");
     if (!sobol && !ord->shifts) return set_error(QQMC_EINVAL, "shifts is NULL");
     if (sobol && !ord->sobol_shifts) return set_error(QQMC_EINVAL, "sobol_shifts is NULL");
-    if (sobol && ord->model) return set_error(QQMC_EINVAL, "Sobol' points take no learned warp");
     if (!(ord->model_tau > 0.0) || !std::isfinite(ord->model_tau))
         return set_error(QQMC_EINVAL, "model_tau must be positive");
     if (!(ord->t_meas > 0.0) || !(ord->t_meas <= t_half))

@@ -567,14 +567,14 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc
 }
 
 /* Learning pass of the learned second warp (App. I): Re fbar of every
- * lattice index of the item's tiles into it.sample_out (exponential warp
- * only, charge mode). */
-template <int N, bool PAIR>
+ * lattice (or Sobol') index of the item's tiles into it.sample_out
+ * (exponential warp only, charge mode). */
+template <int N, bool PAIR, bool SOB = false>
 __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x)
-        (void)order_tile<N, false, true, PAIR>(it, tile, lds);
+        (void)order_tile<N, false, true, PAIR, false, SOB>(it, tile, lds);
 }
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
@@ -682,11 +682,12 @@ hipError_t go_order(const ItemDesc &it, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int N, bool PAIR> hipError_t go_sample(const ItemDesc &it, hipStream_t s)
+template <int N, bool PAIR, bool SOB = false>
+hipError_t go_sample(const ItemDesc &it, hipStream_t s)
 {
     const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-    hipLaunchKernelGGL((sample_kernel<N, PAIR>), dim3((unsigned)blocks), dim3(64),
-                       (Lds<N, PAIR>::bytes), s, it);
+    hipLaunchKernelGGL((sample_kernel<N, PAIR, SOB>), dim3((unsigned)blocks), dim3(64),
+                       (Lds<N, PAIR, false, SOB>::bytes), s, it);
     return hipGetLastError();
 }
 
@@ -750,6 +751,8 @@ hipError_t launch_points_tree_current(const double *tab, const double *col, int3
                                       int32_t order, double t_meas, const double *u,
                                       int64_t n_points, double *f, hipStream_t s);
 hipError_t launch_order_sobol(const ItemDesc &it, hipStream_t s);
+hipError_t launch_order_sobol_model(const ItemDesc &it, hipStream_t s);
+hipError_t launch_sample_sobol(const ItemDesc &it, hipStream_t s);
 
 } // namespace qqmc
 

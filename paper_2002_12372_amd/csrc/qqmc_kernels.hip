@@ -277,11 +277,11 @@ hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_
     return hipGetLastError();
 }
 
-/* Sobol' points, the current, the paired tree (a vertex diagonal near zero,
- * needs_pair), else the scalar tree. */
+/* Sobol' points (with or without a learned warp), the current, the paired
+ * tree (a vertex diagonal near zero, needs_pair), else the scalar tree. */
 hipError_t launch_order(const ItemDesc &it, hipStream_t s)
 {
-    if (it.sobol) return launch_order_sobol(it, s);
+    if (it.sobol) return it.model_cdf ? launch_order_sobol_model(it, s) : launch_order_sobol(it, s);
     if (it.mode == QQMC_MODE_CURRENT) return launch_order_current(it, s);
     if (needs_pair(it.g0y)) return launch_order_pair(it, s);
     return dispatch<OrderScalar>(it.order, it, s);
@@ -289,6 +289,7 @@ hipError_t launch_order(const ItemDesc &it, hipStream_t s)
 
 hipError_t launch_sample(const ItemDesc &it, hipStream_t s)
 {
+    if (it.sobol) return launch_sample_sobol(it, s);
     if (needs_pair(it.g0y)) return launch_sample_pair(it, s);
     return dispatch<SampleScalar>(it.order, it, s);
 }

@@ -1,7 +1,8 @@
 /*
  * qqmc_kernels_sob.hip -- Sobol' points (App. B; coordinate words stepped by
  * the direction numbers of the changing index bits) for the charge and the
- * current, both elimination trees.
+ * current, both elimination trees (the learned warp over Sobol' points is in
+ * qqmc_kernels_sob_model.hip).
  */
 #include "qqmc_kernels.h"
 

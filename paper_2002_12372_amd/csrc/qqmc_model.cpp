@@ -79,7 +79,10 @@ qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p, void *st
         return set_error(QQMC_EINVAL, "lambda must be positive");
     if (!(p->floor_eps >= 0.0 && p->floor_eps <= 1.0))
         return set_error(QQMC_EINVAL, "floor_eps must be in [0, 1]");
-    /* the learning sample is one shifted lattice, charge mode, no model */
+    if ((p->sobol_v == nullptr) != (p->sobol_shift == nullptr))
+        return set_error(QQMC_EINVAL, "sobol_v and sobol_shift go together");
+    /* the learning sample is one shifted lattice or the first 2^log2_m
+     * digitally shifted Sobol' points, charge mode, no model */
     qqmc_order o;
     std::memset(&o, 0, sizeof(o));
     o.order = p->order;
@@ -87,6 +90,8 @@ qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p, void *st
     o.lattice_a = p->lattice_a;
     o.n_shifts = 1;
     o.shifts = p->shift;
+    o.sobol_v = p->sobol_v;
+    o.sobol_shifts = p->sobol_shift;
     o.model_tau = p->model_tau;
     o.t_meas = p->t_meas;
     o.mode = QQMC_MODE_CHARGE;
@@ -105,18 +110,27 @@ qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p, void *st
     hipStream_t s = (hipStream_t)stream;
     std::vector<double> vals((size_t)M);
     double *d_shift = nullptr, *d_out = nullptr;
+    uint32_t *d_sobol = nullptr;
     hipError_t e = hipMallocAsync((void **)&d_shift, sizeof(double) * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_out, sizeof(double) * (size_t)M, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_shift, v.shifts.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !v.sobol.empty()) {
+        e = hipMallocAsync((void **)&d_sobol, sizeof(uint32_t) * v.sobol.size(), s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_sobol, v.sobol.data(), sizeof(uint32_t) * v.sobol.size(),
+                               hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) {
         d.shifts = d_shift;
+        d.sobol = d_sobol;
         d.sample_out = d_out;
         e = launch_sample(d, s);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(vals.data(), d_out, sizeof(double) * (size_t)M, hipMemcpyDeviceToHost, s);
     if (d_shift) hipFreeAsync(d_shift, s);
+    if (d_sobol) hipFreeAsync(d_sobol, s);
     if (d_out) hipFreeAsync(d_out, s);
     const hipError_t es = hipStreamSynchronize(s);
     if (e == hipSuccess) e = es;
@@ -128,15 +142,24 @@ qqmc_status qqmc_learn_model(qqmc_tables t, const qqmc_learn_params *p, void *st
     m->n_bins = nb;
     m->hist.assign((size_t)n * nb, 0.0);
     m->cdf.assign((size_t)n * (nb + 1), 0.0);
-    /* projection of |Re f~| on each coordinate, in lattice-index order; the
+    /* projection of |Re f~| on each coordinate, in index order; the
      * coordinates are recomputed exactly as the kernel forms them */
+    const uint32_t *sv = v.sobol.empty() ? nullptr : v.sobol.data();
     for (int64_t i = 0; i < M; ++i) {
         const double a = std::fabs(vals[(size_t)i]);
         if (a == 0.0) continue;
         for (int j = 0; j < n; ++j) {
-            const uint32_t mm = ((uint32_t)i * d.z[j]) & d.mask;
-            double y = (double)mm * d.inv_n + v.shifts[(size_t)j];
-            if (y >= 1.0) y -= 1.0;
+            double y;
+            if (sv) {
+                uint32_t w = sv[(size_t)n * 32 + j];
+                for (int k = 0; k < 32; ++k)
+                    if (((uint64_t)i >> k) & 1u) w ^= sv[(size_t)j * 32 + k];
+                y = (double)w * (1.0 / 4294967296.0);
+            } else {
+                const uint32_t mm = ((uint32_t)i * d.z[j]) & d.mask;
+                y = (double)mm * d.inv_n + v.shifts[(size_t)j];
+                if (y >= 1.0) y -= 1.0;
+            }
             int b = (int)(y * nb);
             if (b > nb - 1) b = nb - 1;
             m->hist[(size_t)j * nb + b] += a;

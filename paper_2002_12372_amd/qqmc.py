@@ -53,7 +53,9 @@ class qqmc_learn_params(ctypes.Structure):
                 ("lattice_a", ctypes.c_uint64), ("shift", ctypes.POINTER(ctypes.c_double)),
                 ("model_tau", ctypes.c_double), ("t_meas", ctypes.c_double),
                 ("n_bins", ctypes.c_int32), ("lam", ctypes.c_double),
-                ("floor_eps", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("floor_eps", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("sobol_v", ctypes.POINTER(ctypes.c_uint32)),
+                ("sobol_shift", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class qqmc_batch_item(ctypes.Structure):
@@ -251,10 +253,21 @@ class Model:
 
 
 def learn_model(tables, order, log2_m, lattice_a, shift, model_tau, t_meas, n_bins=100,
-                lam=0.05, floor_eps=1e-3, stream=None, alpha=0.0):
-    sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64).reshape(order))
+                lam=0.05, floor_eps=1e-3, stream=None, alpha=0.0, sobol_v=None,
+                sobol_shift=None):
+    """Learning pass over one shifted lattice (lattice_a, shift), or over
+    Sobol' points (sobol_v: order x 32 direction numbers, sobol_shift: order
+    words; lattice_a and shift are then ignored)."""
+    sh = np.ascontiguousarray(np.asarray(shift if shift is not None else np.zeros(order),
+                                         dtype=np.float64).reshape(order))
+    pv = ps = None
+    if sobol_v is not None:
+        sobol_v = np.ascontiguousarray(sobol_v, dtype=np.uint32).reshape(order, 32)
+        sobol_shift = np.ascontiguousarray(sobol_shift, dtype=np.uint32).reshape(order)
+        pv = sobol_v.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        ps = sobol_shift.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
     p = qqmc_learn_params(order, log2_m, lattice_a, _pd(sh), model_tau, t_meas, n_bins,
-                          lam, floor_eps, alpha)
+                          lam, floor_eps, alpha, pv, ps)
     h = ctypes.c_void_p()
     _check(lib().qqmc_learn_model(tables.handle, ctypes.byref(p), _stream(stream),
                                   ctypes.byref(h)))

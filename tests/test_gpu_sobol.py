@@ -1,7 +1,9 @@
 """Sobol' points (App. B) on the GPU against the oracle: the same direction
 numbers and digital shifts (qqmc_inputs.sobol) on both sides, per-shift
 estimates and sampled tiles, both elimination trees, the charge and the
-current.  Tolerances as in the lattice parity tests (1e-9 relative)."""
+current; the learned second warp (App. I) over Sobol' points, learning pass
+and estimates.  Tolerances as in the lattice parity tests (1e-9 relative;
+projections 1e-10 of their sum, CDFs 1e-10)."""
 import math
 
 import numpy as np
@@ -115,3 +117,132 @@ def test_sobol_rejected_by_plans(q, tiny_tables):
     gt = _upload(q, tiny_tables)
     with pytest.raises(q.QQMCError):
         q.plan_create([(gt, sobol_job(84, 3, 10, 2))], 10.0, tile_len=256)
+
+
+# ---------------------------------------------------------------------------
+# The learned second warp over Sobol' points (App. I learns from Sobol'
+# samples of the cube; App. B)
+# ---------------------------------------------------------------------------
+def _sobol_learn_inputs(n, seed):
+    from qqmc_inputs import sobol as S
+    return S.direction_numbers(n), S.digital_shifts(seed, 1, n)[0]
+
+
+@pytest.mark.parametrize("n,log2_m,n_bins", [(1, 10, 16), (4, 12, 50), (8, 11, 100),
+                                             (10, 8, 40)])
+def test_sobol_learning_matches_oracle(q, oracle_mod, n, log2_m, n_bins):
+    d = STRESS_DOT if n > 8 else TINY_DOT
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    V, ds = _sobol_learn_inputs(n, 85)
+    hist_o, cdf_o = oracle_mod.learn_model_sobol(tb, 10.0, n, log2_m, V, ds, 1.0, n_bins,
+                                                 0.05, 1e-3)
+    m = q.learn_model(_upload(q, tb), n, log2_m, 0, None, 1.0, 10.0, n_bins, 0.05, 1e-3,
+                      sobol_v=V, sobol_shift=ds)
+    cdf, hist = m.export()
+    assert hist.shape == hist_o.shape and cdf.shape == cdf_o.shape
+    scale = hist_o.sum(axis=1, keepdims=True)
+    assert np.all(np.abs(hist - hist_o) <= 1e-10 * scale)
+    assert np.all(cdf[:, 0] == 0.0) and np.all(cdf[:, -1] == 1.0)
+    assert np.max(np.abs(cdf - cdf_o)) <= 1e-10
+
+
+def test_sobol_learning_paired_tree(q, oracle_mod):
+    """The learning pass at alpha = n_sigma (zero vertex diagonal)."""
+    tb = oracle_mod.Tables(0.3, 1.0, 20.0, 0.4)
+    a = tb.n_sigma
+    V, ds = _sobol_learn_inputs(5, 86)
+    hist_o, cdf_o = oracle_mod.learn_model_sobol(tb, 10.0, 5, 11, V, ds, 1.0, 50, 0.05, 1e-3,
+                                                 alpha=a)
+    m = q.learn_model(_upload(q, tb), 5, 11, 0, None, 1.0, 10.0, 50, 0.05, 1e-3, alpha=a,
+                      sobol_v=V, sobol_shift=ds)
+    cdf, hist = m.export()
+    scale = hist_o.sum(axis=1, keepdims=True)
+    assert np.all(np.abs(hist - hist_o) <= 1e-10 * scale)
+    assert np.max(np.abs(cdf - cdf_o)) <= 1e-10
+
+
+@pytest.mark.parametrize("n,log2_n,K", [(1, 13, 4), (2, 12, 4), (5, 11, 3), (8, 10, 2),
+                                        (10, 8, 2), (12, 7, 1)])
+def test_sobol_estimates_with_model_match_oracle(q, oracle_mod, n, log2_n, K):
+    """The oracle's model (learned on Sobol' points) uploaded as is: per-shift
+    estimates over Sobol' points through both warps agree."""
+    d = STRESS_DOT if n > 8 else TINY_DOT
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    V, ds = _sobol_learn_inputs(n, 87)
+    _, cdf = oracle_mod.learn_model_sobol(tb, 10.0, n, 10, V, ds, 1.0, 64, 0.05, 1e-3)
+    job = sobol_job(88, n, log2_n, K)
+    qs, _, _ = q.eval_order(_upload(q, tb), job, 10.0, model=q.model_from_host(cdf))
+    qo, _, _ = oracle_mod.eval_order_sobol(tb, 10.0, n, log2_n, job.sobol_v, job.sobol_shifts,
+                                           1.0, cdf=cdf)
+    _compare(qs, qo, "sobol model n=%d" % n)
+
+
+def test_sobol_model_paired_tree(q, oracle_mod):
+    tb = oracle_mod.Tables(0.3, 1.0, 20.0, 0.4)
+    a = tb.n_sigma
+    V, ds = _sobol_learn_inputs(6, 89)
+    _, cdf = oracle_mod.learn_model_sobol(tb, 10.0, 6, 10, V, ds, 1.0, 64, 0.05, 1e-3, alpha=a)
+    job = sobol_job(90, 6, 11, 3, alpha=a)
+    qs, _, _ = q.eval_order(_upload(q, tb), job, 10.0, model=q.model_from_host(cdf))
+    qo, _, _ = oracle_mod.eval_order_sobol(tb, 10.0, 6, 11, job.sobol_v, job.sobol_shifts,
+                                           1.0, alpha=a, cdf=cdf)
+    _compare(qs, qo, "sobol model paired", floor=1e-13)
+
+
+def test_sobol_model_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
+    """n = 8, N = 2^20 x 32 digital shifts, a model learned on the GPU from
+    2^14 Sobol' points: sampled tiles against the oracle with that model."""
+    gt = _upload(q, tiny_tables)
+    V, ds = _sobol_learn_inputs(8, 91)
+    m = q.learn_model(gt, 8, 14, 0, None, 1.0, 10.0, 100, 0.05, 1e-3, sobol_v=V,
+                      sobol_shift=ds)
+    cdf, _ = m.export()
+    job = sobol_job(3, 8, 20, 32)
+    sums = torch.zeros(64, dtype=torch.float64, device="cuda")
+    nt = q.eval_order_async(gt, job, 10.0, sums, None, model=m)
+    torch.cuda.synchronize()
+    tile_len = (1 << 20) * 32 // nt
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len, model=m)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    per = (1 << 20) // tile_len
+    for k in np.random.default_rng(98).choice(nt, size=8, replace=False):
+        s, i0 = divmod(int(k), per)
+        ref = oracle_mod.eval_sums_sobol(tiny_tables, 10.0, 8, job.sobol_v,
+                                         job.sobol_shifts[s:s + 1], 1.0, i0 * tile_len,
+                                         (i0 + 1) * tile_len, cdf=cdf)[0]
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13
+
+
+def test_sobol_model_mode_and_estimate_full_size(q, tiny_tables):
+    """N = 2^20 x 32, n = 8, a model learned on the GPU from Sobol' points:
+    with f := p_n prod_j q_j every sample is tau^n; the charge estimate
+    through the learned warp agrees with the exponential warp alone."""
+    gt = _upload(q, tiny_tables)
+    V, ds = _sobol_learn_inputs(8, 92)
+    m = q.learn_model(gt, 8, 14, 0, None, 1.0, 10.0, 100, 0.05, 1e-3, sobol_v=V,
+                      sobol_shift=ds)
+    qs, _, _ = q.eval_order(gt, sobol_job(4, 8, 20, 32, mode=q.MODE_MODEL), 10.0, model=m)
+    assert np.max(np.abs(qs - 1.0)) <= 1e-12
+    job = sobol_job(5, 8, 20, 32)
+    _, ml, sel = q.eval_order(gt, job, 10.0, model=m)
+    _, me, see = q.eval_order(gt, job, 10.0)
+    print("Q_8 Sobol' learned warp %.10f +- %.1e, exponential %.10f +- %.1e"
+          % (ml.real, sel, me.real, see))
+    assert abs(ml.real - me.real) < 5 * math.hypot(sel, see)
+
+
+def test_sobol_learning_rejects_half_inputs(q, tiny_tables):
+    """Direction numbers without the digital shift: EINVAL at the C ABI."""
+    import ctypes
+    gt = _upload(q, tiny_tables)
+    V = np.ascontiguousarray(_sobol_learn_inputs(3, 93)[0])
+    sh = np.zeros(3)
+    p = q.qqmc_learn_params(3, 10, 3, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0,
+                            10.0, 16, 0.05, 1e-3, 0.0,
+                            V.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None)
+    h = ctypes.c_void_p()
+    st = q.lib().qqmc_learn_model(gt.handle, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == q.EINVAL and not h.value

@@ -996,3 +996,85 @@ def test_sobol_q2_against_quadrature(oracle_mod, tiny_tables, q2_quadrature):
     ds = S.digital_shifts(5, 16, 2)
     _, mean, se = oracle_mod.eval_order_sobol(tiny_tables, 10.0, 2, 14, V, ds, 1.0)
     assert abs(mean.real - q2_quadrature) < 5 * se + 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Sobol' points through the learned second warp (App. I samples the cube with
+# Sobol' points, App. B)
+# ---------------------------------------------------------------------------
+def _sobol_xor_point(i, V, ds):
+    """Sobol' point i written out here: XOR of the direction numbers of the
+    set index bits and the shift word, times 2^-32."""
+    x = np.zeros(V.shape[0])
+    for j in range(V.shape[0]):
+        w = int(ds[j])
+        for k in range(32):
+            if (i >> k) & 1:
+                w ^= int(V[j, k])
+        x[j] = w / 2.0 ** 32
+    return x
+
+
+def _learn_sobol(oracle_mod, tables, n, log2_m=10, n_bins=50, lam=0.05, floor_eps=1e-3,
+                 seed=23):
+    from qqmc_inputs import sobol as S
+    V = S.direction_numbers(n)
+    ds = S.digital_shifts(seed, 1, n)[0]
+    return oracle_mod.learn_model_sobol(tables, 10.0, n, log2_m, V, ds, 1.0, n_bins, lam,
+                                        floor_eps)
+
+
+def test_sobol_model_projection_brute_force(oracle_mod, tiny_tables):
+    """The projection of |Re f~| over 64 Sobol' points, redone point by point
+    from the integrand, the warp and the XOR construction of the points."""
+    from qqmc_inputs import sobol as S
+    n, log2_m, n_bins = 3, 6, 8
+    V = S.direction_numbers(n)
+    ds = S.digital_shifts(23, 1, n)[0]
+    hist, cdf = oracle_mod.learn_model_sobol(tiny_tables, 10.0, n, log2_m, V, ds, 1.0,
+                                             n_bins, 0.05, 1e-3)
+    ref = np.zeros((n, n_bins))
+    for i in range(1 << log2_m):
+        x = _sobol_xor_point(i, V, ds)
+        u, W, inside = oracle_mod.warp(x, 1.0, 10.0)
+        if not inside:
+            continue
+        f, _ = oracle_mod.integrand(tiny_tables, 10.0, u)
+        for j in range(n):
+            ref[j, min(int(x[j] * n_bins), n_bins - 1)] += abs((f * W).real)
+    assert np.allclose(hist, ref, rtol=1e-12, atol=0)
+    assert np.allclose(cdf, oracle_mod.model_from_hist(ref, 0.05, 1e-3), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_sobol_learned_model_mode_is_exact(oracle_mod, tiny_tables, n):
+    """f := p_n prod_j q_j over Sobol' points through the learned warp: every
+    sample is tau^n, so each shift's mean is exactly 1 at tau = 1."""
+    from qqmc_inputs import sobol as S
+    _, cdf = _learn_sobol(oracle_mod, tiny_tables, n)
+    V = S.direction_numbers(n)
+    ds = S.digital_shifts(8, 4, n)
+    q, _, _ = oracle_mod.eval_order_sobol(tiny_tables, 10.0, n, 10, V, ds, 1.0, mode=1, cdf=cdf)
+    assert np.max(np.abs(q - 1.0)) <= 1e-12
+
+
+def test_sobol_flat_model_reduces_to_the_exponential_warp(oracle_mod, tiny_tables):
+    from qqmc_inputs import sobol as S
+    n = 3
+    cdf = oracle_mod.model_from_hist(np.ones((n, 20)), 1e6, 0.0)
+    V = S.direction_numbers(n)
+    ds = S.digital_shifts(9, 4, n)
+    a, _, _ = oracle_mod.eval_order_sobol(tiny_tables, 10.0, n, 10, V, ds, 1.0)
+    b, _, _ = oracle_mod.eval_order_sobol(tiny_tables, 10.0, n, 10, V, ds, 1.0, cdf=cdf)
+    assert np.allclose(a, b, rtol=1e-11, atol=0)
+
+
+def test_sobol_learned_warp_q2_against_quadrature(oracle_mod, tiny_tables, q2_quadrature):
+    """Q_2 over Sobol' points through a model learned on Sobol' points agrees
+    with the two-dimensional adaptive quadrature."""
+    from qqmc_inputs import sobol as S
+    _, cdf = _learn_sobol(oracle_mod, tiny_tables, 2, log2_m=12)
+    V = S.direction_numbers(2)
+    ds = S.digital_shifts(10, 16, 2)
+    _, mean, se = oracle_mod.eval_order_sobol(tiny_tables, 10.0, 2, 14, V, ds, 1.0, cdf=cdf)
+    assert abs(mean.real - q2_quadrature) < 5 * se + 1e-8

@@ -77,9 +77,9 @@ enum {
                                the lead site (tables made with dot.lead = i):
                                the real part is the order-n particle current
                                from the dot into lead i, both spins, i.e.
-                               -4 Re gamma G^<_{0i}(t, t) (App. E); single
-                               launches only (no learned warp, plan or
-                               server)                                        */
+                               -4 Re gamma G^<_{0i}(t, t) (App. E); no
+                               learned warp; in plans and the server as
+                               the charge is                                  */
 };
 
 /* A learned second warp (App. I, "Learning h^(i) from the integrand"): per
@@ -124,8 +124,8 @@ typedef struct {
                                      sobol_v; both copied during the call.
                                      Sobol' items run as single launches
                                      (the charge, with or without a learned
-                                     warp, or the current; no plan or
-                                     server)                                  */
+                                     warp, or the current; plans and the
+                                     server reject them with EINVAL)          */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
@@ -305,7 +305,9 @@ typedef struct qqmc_plan_s *qqmc_plan;
 /* tile_len: lattice indices per tile (0 = autotuned); grid_blocks:
  * persistent workgroups per order-8 launch, scaled by residency for other
  * orders (0 = autotuned, which may also choose one workgroup per tile; then
- * qqmc_plan_info reports grid_blocks 0). */
+ * qqmc_plan_info reports grid_blocks 0).  Items may mix the charge, the
+ * model and constant modes, and the current (whose tables must hold lead
+ * functions); EINVAL for Sobol' items. */
 qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items,
                              int32_t tile_len, int32_t grid_blocks,
                              void *stream, qqmc_plan *out);
@@ -336,7 +338,9 @@ typedef struct qqmc_server_s *qqmc_server;
 qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots,
                                int32_t batch_tiles, qqmc_server *out);
 /* Queues a request; never blocks on the GPU.  EADMIT if its footprint alone
- * exceeds hbm_budget_bytes; EINVAL as for qqmc_eval_order. */
+ * exceeds hbm_budget_bytes; EINVAL as for qqmc_eval_order, for Sobol'
+ * points, and for the current on a dot without a lead (dot.lead names the
+ * lead; the server builds and caches its dot-lead functions). */
 qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot,
                         const qqmc_order *ord, uint64_t *ticket);
 /* QQMC_PENDING until done; then fills the outputs (as qqmc_eval_order, each

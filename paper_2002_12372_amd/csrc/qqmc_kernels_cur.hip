@@ -1,7 +1,7 @@
 /*
  * qqmc_kernels_cur.hip -- the current into a lead (the lead site in the
- * measurement column) on the lattice, both elimination trees: order and
- * points launches.
+ * measurement column) on the lattice, both elimination trees: order, points
+ * and batched (plans, server) launches.
  */
 #include "qqmc_kernels.h"
 
@@ -26,7 +26,39 @@ template <int N> struct PointsCur {
     }
 };
 
+template <int N> struct BatchCur {
+    static hipError_t run(bool pair, const ItemDesc *items_dev, const TileRef *tiles_dev,
+                          int64_t n_tiles, int32_t grid_blocks, hipStream_t s)
+    {
+        return pair ? go_batch<N, true, true>(items_dev, tiles_dev, n_tiles, grid_blocks, s)
+                    : go_batch<N, false, true>(items_dev, tiles_dev, n_tiles, grid_blocks, s);
+    }
+};
+
+template <int N> struct OccCur {
+    static hipError_t run(bool pair, int32_t *out)
+    {
+        *out = pair ? occ_batch<N, true, true>() : occ_batch<N, false, true>();
+        return hipSuccess;
+    }
+};
+
 } // namespace
+
+hipError_t launch_batch_current(int32_t order, bool pair, const ItemDesc *items_dev,
+                                const TileRef *tiles_dev, int64_t n_tiles, int32_t grid_blocks,
+                                hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    return dispatch<BatchCur>(order, pair, items_dev, tiles_dev, n_tiles, grid_blocks, s);
+}
+
+int32_t batch_blocks_per_cu_current(int32_t order, bool pair)
+{
+    int32_t b = 1;
+    if (dispatch<OccCur>(order, pair, &b) != hipSuccess) return 1;
+    return b;
+}
 
 hipError_t launch_order_current(const ItemDesc &it, hipStream_t s)
 {

@@ -77,10 +77,12 @@ struct Group {
 /* Relative cost of one tile: warp for every point, the Keldysh sum (about
  * 140 issued FP64 operations per index vector, the tree's work plus the
  * lanes' repeated set-up, plus O(n^2) per point) for the points inside the
- * domain.  Only ratios matter: it orders tiles and sizes launches. */
+ * domain (the charge and the current).  Only ratios matter: it orders tiles
+ * and sizes launches. */
 double tile_cost(const ItemDesc &d)
 {
-    const double frac = d.mode == QQMC_MODE_CHARGE ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;
+    const bool sum = d.mode == QQMC_MODE_CHARGE || d.mode == QQMC_MODE_CURRENT;
+    const double frac = sum ? inside_fraction(d.order, d.t_meas / d.tau) : 0.0;
     const double per_point = 8.0 * d.order + frac * (140.0 * std::ldexp(1.0, d.order) + 30.0 * d.order * d.order);
     return per_point * d.tile_len;
 }
@@ -339,11 +341,15 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
             return st;
         }
         Validated v;
-        if (items[i].order.mode == QQMC_MODE_CURRENT || items[i].order.sobol_v) {
+        if (items[i].order.sobol_v) {
             delete p;
             return set_error(QQMC_EINVAL, "item " + std::to_string(i) +
-                                              ": the current and Sobol' points run as single "
-                                              "launches only");
+                                              ": Sobol' points run as single launches only");
+        }
+        if (items[i].order.mode == QQMC_MODE_CURRENT && !items[i].tables->d_col) {
+            delete p;
+            return set_error(QQMC_EINVAL, "item " + std::to_string(i) +
+                                              ": the current needs tables with lead functions");
         }
         if (qqmc_status st = validate_order(&items[i].order, items[i].tables->n_grid,
                                             items[i].tables->t_half, &v)) {

@@ -55,7 +55,7 @@ struct TableEntry {
     uint64_t last_use = 0;
 };
 
-using TableKey = std::tuple<double, double, double, double, double, int32_t, double>;
+using TableKey = std::tuple<double, double, double, double, double, int32_t, double, int32_t>;
 
 struct Request {
     uint64_t ticket = 0;
@@ -144,7 +144,11 @@ struct qqmc_server_s {
 namespace qqmc {
 namespace {
 
-size_t table_bytes(const qqmc_dot &d) { return sizeof(double) * 4 * (size_t)d.n_grid; }
+/* the dot's tables, and a lead's dot-lead functions when it names one */
+size_t table_bytes(const qqmc_dot &d)
+{
+    return sizeof(double) * 4 * (size_t)d.n_grid * (d.lead ? 2 : 1);
+}
 
 size_t request_bytes(const Request &r, bool need_table)
 {
@@ -509,11 +513,14 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     if (!(dot->gamma > 0.0) || !(dot->beta > 0.0) || !(dot->t_half > 0.0) || dot->n_grid < 2 ||
         dot->n_grid > (1 << 24))
         return set_error(QQMC_EINVAL, "bad dot parameters");
+    if (dot->lead != 0 && !((dot->lead == 1 || dot->lead == 2) && finite_band(dot)))
+        return set_error(QQMC_EINVAL, "lead must be 0, or 1 or 2 with a finite half_bandwidth");
     auto r = std::make_shared<Request>();
     Validated v;
     if (qqmc_status st = validate_order(ord, dot->n_grid, dot->t_half, &v)) return st;
-    if (ord->mode == QQMC_MODE_CURRENT || ord->sobol_v)
-        return set_error(QQMC_EINVAL, "the current and Sobol' points run as single launches only");
+    if (ord->sobol_v) return set_error(QQMC_EINVAL, "Sobol' points run as single launches only");
+    if (ord->mode == QQMC_MODE_CURRENT && dot->lead == 0)
+        return set_error(QQMC_EINVAL, "the current needs a dot with a lead (1 or 2)");
     r->dot = *dot;
     r->desc = v.desc;
     r->shifts = v.shifts;
@@ -522,7 +529,7 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     r->desc.tiles_per_shift = (int32_t)(N / r->desc.tile_len);
     r->desc.n_tiles = (int64_t)r->desc.tiles_per_shift * r->desc.n_shifts;
     r->key = TableKey(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->t_half, dot->n_grid,
-                      finite_band(dot) ? dot->half_bandwidth : 0.0);
+                      finite_band(dot) ? dot->half_bandwidth : 0.0, dot->lead);
     if (request_bytes(*r, true) > s->budget)
         return set_error(QQMC_EADMIT, "request footprint exceeds the HBM budget");
     std::lock_guard<std::mutex> lk(s->mu);

@@ -7,6 +7,9 @@ per shift: estimates against the oracle's; at full size: sampled tiles, and
 two stationary-state laws (current conservation between the leads at order
 2, the Hartree shift at order 1).
 
+Plans and the server run the current as they run the charge: per-shift sums
+equal, bit for bit, those of single launches at the same tile length.
+
 Tolerances as in the charge parity tests (per value 1e-10 relative or 1e-13
 of the term mass, estimates 1e-9 relative).  At alpha = n_sigma the paired
 tree runs with a zero vertex diagonal: a 2x2 pivot block spanning a long gap
@@ -194,9 +197,101 @@ def test_current_rejections(q, otab, tiny_tables):
     job = order_job(75, 3, 10, 2, mode=q.MODE_CURRENT)
     with pytest.raises(q.QQMCError):           # no lead functions
         q.eval_order(gt_plain, job, T)
+    with pytest.raises(q.QQMCError):           # plans need the lead functions too
+        q.plan_create([(gt_plain, job)], T, tile_len=256)
     gt = _upload(q, otab[1])
-    with pytest.raises(q.QQMCError):           # plans run the charge only
-        q.plan_create([(gt, job)], T, tile_len=256)
     cdf = np.tile(np.linspace(0.0, 1.0, 9), (3, 1))
     with pytest.raises(q.QQMCError):           # no learned warp for the current
         q.eval_order(gt, job, T, model=q.model_from_host(cdf))
+
+
+# ---------------------------------------------------------------------------
+# The current in plans (persistent batched launch) and in the server
+# ---------------------------------------------------------------------------
+def _solo(q, gt, job, tile_len):
+    K = job.shifts.shape[0]
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, T, sums, None, tile_len=min(tile_len, 1 << job.log2_n))
+    torch.cuda.synchronize()
+    h = sums.cpu().numpy()
+    return (h[0::2] + 1j * h[1::2]) / (1 << job.log2_n)
+
+
+def _band_dots():
+    return [Dot(0.3, 1.0, 2.0, 0.8, T, 4001, T, 4.0, 1),
+            Dot(0.3, 1.0, 2.0, 0.8, T, 4001, T, 4.0, 2),
+            Dot(-0.6, 0.7, 5.0, 0.4, T, 4001, T, 3.0, 1)]
+
+
+def test_current_plan_matches_single_launches_bitwise(q, oracle_mod, otab):
+    """Current and charge items of three band dots (two leads of one), both
+    trees (alpha = 0 and alpha = n_sigma), orders 1..9, in one plan: every
+    replay gives the single launches' bits; one item against the oracle."""
+    dots = _band_dots()
+    tabs = [q.make_tables(d) for d in dots]
+    entries = []
+    for p, (d, gt) in enumerate(zip(dots, tabs)):
+        a_ns = otab[1].n_sigma if p < 2 else 0.0
+        for n in (1, 3, 5, 8, 9):
+            for alpha in (0.0, a_ns):
+                entries.append((gt, order_job(60 + p, n, 9 + (n % 3), 3, mode=q.MODE_CURRENT,
+                                              alpha=alpha)))
+        entries.append((gt, order_job(70 + p, 4, 10, 3)))
+    tb = otab[1]                                # the oracle's tables, uploaded as they are
+    entries.append((_upload(q, tb), order_job(75, 5, 10, 3, mode=q.MODE_CURRENT)))
+    plan = q.plan_create(entries, T, tile_len=256)
+    for rep in range(3):
+        q.plan_run(plan)
+        res = q.plan_results(plan)
+        for k, ((gt, job), got) in enumerate(zip(entries, res)):
+            assert np.array_equal(got, _solo(q, gt, job, 256)), (k, job.order, job.mode, rep)
+    job = entries[-1][1]
+    qo, _, _, mass = oracle_mod.eval_order_current(tb, T, 5, job.log2_n, job.lattice_a,
+                                                   job.shifts, 1.0)
+    assert np.all(np.abs(res[-1] - qo) <= 1e-9 * np.abs(qo) + 1e-12 * mass + 1e-15)
+
+
+def test_current_plan_autotuned(q):
+    dots = _band_dots()
+    gt = q.make_tables(dots[0])
+    entries = [(gt, order_job(80 + n, n, 10, 2, mode=q.MODE_CURRENT)) for n in (2, 6, 8)]
+    plan = q.plan_create(entries, T)
+    info = q.plan_info(plan)
+    q.plan_run(plan)
+    for (g, job), got in zip(entries, q.plan_results(plan)):
+        assert np.array_equal(got, _solo(q, g, job, info["tile_len"]))
+
+
+def test_current_server_equals_solo_runs(q):
+    """Current and charge requests on band dots with leads, served together:
+    each result is the single launch's at the server's tile length."""
+    import time
+    dots = _band_dots()
+    reqs = []
+    for i in range(10):
+        d = dots[i % 3]
+        n = 2 + (i * 3) % 7
+        mode = q.MODE_CURRENT if i % 4 != 3 else q.MODE_CHARGE
+        reqs.append((d, order_job(90 + i, n, 10 + i % 2, 3, mode=mode)))
+    srv = q.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    tickets = [srv.submit(d, job, T) for d, job in reqs]
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.005)
+    assert len(out) == len(tickets)
+    cache = {}
+    for t, (d, job) in zip(tickets, reqs):
+        key = (d.eps_d, d.beta, d.lead)
+        if key not in cache:
+            cache[key] = q.make_tables(d)
+        assert np.array_equal(out[t]["q_shift"], _solo(q, cache[key], job, q.SERVER_TILE_LEN))
+    with pytest.raises(q.QQMCError):           # the current needs a dot with a lead
+        srv.submit(Dot(0.3, 1.0, 2.0, 0.8, T, 4001, T, 4.0, 0),
+                   order_job(99, 3, 10, 2, mode=q.MODE_CURRENT), T)
+    srv.close()

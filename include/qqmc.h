@@ -231,12 +231,19 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
  *           QQMC_METHOD_DIRECT: enumerates all 2^n Keldysh index vectors with
  *           one partially pivoted LU per determinant; any vertex times
  *           (within the table range).
+ *   mass    device, n_points doubles, or NULL: the term mass of each point,
+ *           |c| sum_a |det_up(a) det_dn(a)| with c the prefactor above
+ *           (2 for the charge, 4 for the current), so |f| <= mass and
+ *           |f| / mass measures the cancellation in the Keldysh sum (the
+ *           sign problem of the expansion); direct method only (EINVAL
+ *           with the tree method).
  * Asynchronous on `stream`. */
 enum { QQMC_METHOD_TREE = 0, QQMC_METHOD_DIRECT = 1 };
 enum { QQMC_OBS_CHARGE = 0, QQMC_OBS_CURRENT = 1 };
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas,
                              double alpha, int32_t observable, const double *u,
-                             int64_t n_points, int32_t method, double *f, void *stream);
+                             int64_t n_points, int32_t method, double *f, double *mass,
+                             void *stream);
 
 /* ---- Learned second warp (App. I) ---------------------------------------
  * Learning: the library evaluates the order-n integrand f~ (exponential warp

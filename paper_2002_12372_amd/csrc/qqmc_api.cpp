@@ -460,7 +460,7 @@ qqmc_status qqmc_eval_order(qqmc_tables t, const qqmc_order *ord, void *stream,
 
 qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double alpha,
                              int32_t observable, const double *u, int64_t n_points,
-                             int32_t method, double *f, void *stream)
+                             int32_t method, double *f, double *mass, void *stream)
 {
     if (qqmc_status st = check_tables(t)) return st;
     if (order < 1 || order > QQMC_MAX_ORDER) return set_error(QQMC_EINVAL, "bad order");
@@ -476,6 +476,8 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double
     const double *col = observable == QQMC_OBS_CURRENT ? t->d_col : nullptr;
     if (method != QQMC_METHOD_TREE && method != QQMC_METHOD_DIRECT)
         return set_error(QQMC_EINVAL, "unknown method");
+    if (mass && method != QQMC_METHOD_DIRECT)
+        return set_error(QQMC_EINVAL, "the term mass comes from the direct method only");
     if (n_points == 0) return QQMC_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
@@ -484,7 +486,7 @@ qqmc_status qqmc_eval_points(qqmc_tables t, int32_t order, double t_meas, double
                                order, t_meas, u, n_points, f, s);
     else if (method == QQMC_METHOD_DIRECT)
         e = launch_points_direct(t->d_tab, col, t->n_grid, t->t_half, t->h, t->n_sigma, alpha,
-                                 order, t_meas, u, n_points, f, s);
+                                 order, t_meas, u, n_points, f, mass, s);
     else
         return set_error(QQMC_EINVAL, "unknown method");
     if (e != hipSuccess) return hip_error(e, "qqmc_eval_points launch");

@@ -81,7 +81,7 @@ hipError_t launch_points_tree(const double *tab, const double *col, int32_t n_gr
 hipError_t launch_points_direct(const double *tab, const double *col, int32_t n_grid,
                                 double t_half, double h, double n_sigma, double alpha,
                                 int32_t order, double t_meas, const double *u,
-                                int64_t n_points, double *f, hipStream_t s);
+                                int64_t n_points, double *f, double *mass, hipStream_t s);
 /* One persistent launch over a tile list whose items all have this kernel
  * key. */
 hipError_t launch_batch(int32_t key, const ItemDesc *items_dev,

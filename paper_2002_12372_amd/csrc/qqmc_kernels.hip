@@ -101,12 +101,13 @@ __device__ cplx det_pivoted(cplx (&a)[M][M], int m)
 
 template <int N>
 __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double *u,
-                                                          int64_t n_points, double *f)
+                                                          int64_t n_points, double *f,
+                                                          double *mass)
 {
     constexpr int NP1 = N + 1;
     __shared__ pairv s_g[NP1 * NP1];
     __shared__ double s_tm[NP1];
-    __shared__ double sx[WAVE], sy[WAVE];
+    __shared__ double sx[WAVE], sy[WAVE], sm[WAVE];
     const int lane = threadIdx.x;
     for (int64_t pt = blockIdx.x; pt < n_points; pt += gridDim.x) {
         if (lane == 0) s_tm[0] = env.t_meas;
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
             s_g[q] = interp_pair(tab, env.n_grid, env.t_half, env.inv_h, s_tm[r] - s_tm[c]);
         }
         __syncthreads();
-        Kahan acc;
+        Kahan acc, acc_m;
         for (int a = lane; a < (1 << N); a += WAVE) {
             cplx up[NP1][NP1], dn[NP1][NP1];
             for (int r = 0; r < NP1; ++r) {
@@ -144,17 +145,21 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
             const cplx du = det_pivoted<NP1>(up, NP1);
             const cplx dd = det_pivoted<NP1>(dn, N);
             cplx term = cmul(du, dd);
+            /* term mass: |det_up det_dn| of every index vector */
+            acc_m.add(cmk(sqrt(term.x * term.x + term.y * term.y), 0.0));
             if (__popc((unsigned)a) & 1) term = cmk(-term.x, -term.y);
             acc.add(term);
         }
         const cplx v = acc.value();
         sx[lane] = v.x;
         sy[lane] = v.y;
+        sm[lane] = acc_m.value().x;
         __syncthreads();
         for (int w = WAVE / 2; w > 0; w >>= 1) {
             if (lane < w) {
                 sx[lane] += sx[lane + w];
                 sy[lane] += sy[lane + w];
+                sm[lane] += sm[lane + w];
             }
             __syncthreads();
         }
@@ -163,6 +168,8 @@ __global__ void __launch_bounds__(64) points_direct_kernel(Env env, const double
                                      : charge_prefactor<N>(cmk(sx[0], sy[0]));
             f[2 * pt] = out.x;
             f[2 * pt + 1] = out.y;
+            /* on the scale of f: |prefactor| sum_a |det_up det_dn| */
+            if (mass) mass[pt] = (env.col ? 4.0 : 2.0) * sm[0];
         }
         __syncthreads();
     }
@@ -239,13 +246,13 @@ template <int N> struct PointsScalar {
 };
 
 template <int N> struct DirectPointsLaunch {
-    static hipError_t run(Env env, const double *u, int64_t n_points, double *f,
+    static hipError_t run(Env env, const double *u, int64_t n_points, double *f, double *mass,
                           hipStream_t s)
     {
         int64_t blocks = n_points < 65536 ? n_points : 65536;
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(points_direct_kernel<N>, dim3((unsigned)blocks), dim3(64), 0, s,
-                           env, u, n_points, f);
+                           env, u, n_points, f, mass);
         return hipGetLastError();
     }
 };
@@ -323,12 +330,12 @@ hipError_t launch_points_tree(const double *tab, const double *col, int32_t n_gr
 hipError_t launch_points_direct(const double *tab, const double *col, int32_t n_grid,
                                 double t_half, double h, double n_sigma, double alpha,
                                 int32_t order, double t_meas, const double *u, int64_t n_points,
-                                double *f, hipStream_t s)
+                                double *f, double *mass, hipStream_t s)
 {
     if (n_points <= 0) return hipSuccess;
     return dispatch<DirectPointsLaunch>(order,
                                         make_env(tab, col, n_grid, t_half, h, n_sigma, alpha, t_meas),
-                                        u, n_points, f, s);
+                                        u, n_points, f, mass, s);
 }
 
 hipError_t launch_batch(int32_t key, const ItemDesc *items_dev, const TileRef *tiles_dev,

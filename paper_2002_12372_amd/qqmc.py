@@ -78,7 +78,7 @@ SIGNATURES = [
     ("qqmc_free_tables", None, [_vp]),
     ("qqmc_eval_order", _i32, [_vp, _P(qqmc_order), _vp, _PD, _PD, _PD]),
     ("qqmc_eval_order_async", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _vp, _P(_i64)]),
-    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _i32, _vp, _i64, _i32, _vp, _vp]),
+    ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _i32, _vp, _i64, _i32, _vp, _vp, _vp]),
     ("qqmc_lead_tables_compute_host", _i32, [_P(qqmc_dot), _PD, _PD]),
     ("qqmc_tables_lead_from_host", _i32, [_vp, _PD, _PD]),
     ("qqmc_plan_create", _i32, [_P(qqmc_batch_item), _i32, _i32, _i32, _vp, _P(_vp)]),
@@ -311,15 +311,20 @@ def n_tiles(job, tile_len):
 
 
 def eval_points(tables, order, t_meas, u, f, method=METHOD_TREE, stream=None, alpha=0.0,
-                current=False):
-    """u: (P, order) float64 CUDA tensor; f: (P, 2) float64 CUDA tensor."""
+                current=False, mass=None):
+    """u: (P, order) float64 CUDA tensor; f: (P, 2) float64 CUDA tensor;
+    mass: (P,) float64 CUDA tensor or None (direct method only)."""
     P = u.shape[0]
     assert u.dtype.is_floating_point and u.is_contiguous() and f.is_contiguous()
     assert f.numel() >= 2 * P and u.numel() == P * order
+    if mass is not None:
+        assert mass.is_contiguous() and mass.numel() >= P
     _check(lib().qqmc_eval_points(tables.handle, int(order), float(t_meas), float(alpha),
                                   OBS_CURRENT if current else OBS_CHARGE,
                                   ctypes.c_void_p(u.data_ptr()), P, int(method),
-                                  ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+                                  ctypes.c_void_p(f.data_ptr()),
+                                  ctypes.c_void_p(mass.data_ptr() if mass is not None else 0),
+                                  _stream(stream)))
 
 
 class Plan:

@@ -104,6 +104,21 @@ def test_points_direct_current(q, oracle_mod, otab, n):
            "direct n=%d" % n)
 
 
+def test_points_direct_current_term_mass(q, oracle_mod, otab):
+    """The current's term mass 4 sum_a |det_up det_dn| (lead site in the
+    measurement column) against the oracle's, per point."""
+    tb = otab[2]
+    gt = _upload(q, tb)
+    u = _points(np.random.default_rng(4200), 5, 16)
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    f = torch.zeros((u.shape[0], 2), dtype=torch.float64, device="cuda")
+    m = torch.zeros(u.shape[0], dtype=torch.float64, device="cuda")
+    q.eval_points(gt, 5, T, ut, f, method=q.METHOD_DIRECT, current=True, mass=m)
+    torch.cuda.synchronize()
+    ref = np.array([oracle_mod.current_integrand(tb, T, row)[1] for row in u])
+    assert np.all(np.abs(m.cpu().numpy() - ref) <= 1e-11 * ref)
+
+
 def _compare(qs, qo, floor, label):
     for s in range(len(qo)):
         assert abs(qs[s] - qo[s]) <= 1e-9 * abs(qo[s]) + floor[s], (label, s, qs[s], qo[s])

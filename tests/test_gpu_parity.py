@@ -117,6 +117,26 @@ def test_points_direct_vs_oracle_and_causality(q, oracle_mod, tiny_tables, n):
         assert abs(flh[k, 0] + 1j * flh[k, 1]) <= 1e-13 * M2
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 9])
+def test_points_direct_term_mass(q, oracle_mod, tiny_tables, n):
+    """The direct method's term mass 2 sum_a |det_up det_dn| against the
+    oracle's, per point (sums of positive terms: 1e-11 relative), and
+    |f| <= mass; the tree method refuses a mass buffer."""
+    gt = _upload(q, tiny_tables)
+    u = _points(np.random.default_rng(2100 + n), n, 10.0, 24 if n <= 7 else 6)
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    f = torch.zeros((u.shape[0], 2), dtype=torch.float64, device="cuda")
+    m = torch.zeros(u.shape[0], dtype=torch.float64, device="cuda")
+    q.eval_points(gt, n, 10.0, ut, f, method=q.METHOD_DIRECT, mass=m)
+    torch.cuda.synchronize()
+    mh, fh = m.cpu().numpy(), f.cpu().numpy()
+    ref = np.array([oracle_mod.integrand(tiny_tables, 10.0, row)[1] for row in u])
+    assert np.all(np.abs(mh - ref) <= 1e-11 * ref)
+    assert np.all(np.abs(fh[:, 0] + 1j * fh[:, 1]) <= mh * (1 + 1e-12))
+    with pytest.raises(q.QQMCError):
+        q.eval_points(gt, n, 10.0, ut, f, method=q.METHOD_TREE, mass=m)
+
+
 def test_points_tree_rejects_unordered_rows(q, tiny_tables):
     gt = _upload(q, tiny_tables)
     u = np.array([[9.0, 5.0, 1.0], [5.0, 9.0, 1.0], [11.0, 5.0, 1.0], [9.0, 5.0, -0.1]])

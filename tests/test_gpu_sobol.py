@@ -246,3 +246,33 @@ def test_sobol_learning_rejects_half_inputs(q, tiny_tables):
     h = ctypes.c_void_p()
     st = q.lib().qqmc_learn_model(gt.handle, ctypes.byref(p), None, ctypes.byref(h))
     assert st == q.EINVAL and not h.value
+
+
+def test_sobol_largest_size_sampled_tiles(q, oracle_mod, tiny_tables):
+    """N = 2^24 (the largest lattice size), order 3, two digital shifts:
+    sampled tiles, each shift's last tile among them, against the oracle
+    (the coordinate words are stepped through every index bit up to 23)."""
+    gt = _upload(q, tiny_tables)
+    log2_n, K = 24, 2
+    job = sobol_job(6, 3, log2_n, K)
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    nt = q.eval_order_async(gt, job, 10.0, sums, None)
+    torch.cuda.synchronize()
+    tile_len = (1 << log2_n) * K // nt
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    per = (1 << log2_n) // tile_len
+    picks = set(int(k) for k in np.random.default_rng(99).choice(nt, size=6, replace=False))
+    picks |= {per - 1, 2 * per - 1}
+    for k in sorted(picks):
+        s, i0 = divmod(k, per)
+        ref = oracle_mod.eval_sums_sobol(tiny_tables, 10.0, 3, job.sobol_v,
+                                         job.sobol_shifts[s:s + 1], 1.0, i0 * tile_len,
+                                         (i0 + 1) * tile_len)[0]
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13, (k, tc[k], ref)
+    total = sums.cpu().numpy()
+    assert np.allclose(total[0::2], [th[0::2][s * per:(s + 1) * per].sum() for s in range(K)],
+                       rtol=1e-12, atol=1e-15)

@@ -121,11 +121,14 @@ typedef struct {
                                      and shifts are then not used            */
     const uint32_t *sobol_shifts; /* host, n_shifts x order digital shifts
                                      (XORed into the coordinate words), with
-                                     sobol_v; both copied during the call.
-                                     Sobol' items run as single launches
-                                     (the charge, with or without a learned
-                                     warp, or the current; plans and the
-                                     server reject them with EINVAL)          */
+                                     sobol_v; both copied during the call
+                                     (by plans and the server at creation /
+                                     submission).  The charge (with or
+                                     without a learned warp) and the current
+                                     run on Sobol' points everywhere the
+                                     lattice runs; tiles start at multiples
+                                     of 64 indices (every tile_len is a power
+                                     of two >= 64)                            */
 } qqmc_order;
 
 /* ---- Green's function tables (App. E, Eq. (lesser_greater_freq) with the
@@ -314,7 +317,8 @@ typedef struct qqmc_plan_s *qqmc_plan;
  * orders (0 = autotuned, which may also choose one workgroup per tile; then
  * qqmc_plan_info reports grid_blocks 0).  Items may mix the charge, the
  * model and constant modes, and the current (whose tables must hold lead
- * functions); EINVAL for Sobol' items. */
+ * functions), on the lattice or on Sobol' points, with or without a learned
+ * warp (not for the current). */
 qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items,
                              int32_t tile_len, int32_t grid_blocks,
                              void *stream, qqmc_plan *out);
@@ -345,9 +349,10 @@ typedef struct qqmc_server_s *qqmc_server;
 qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots,
                                int32_t batch_tiles, qqmc_server *out);
 /* Queues a request; never blocks on the GPU.  EADMIT if its footprint alone
- * exceeds hbm_budget_bytes; EINVAL as for qqmc_eval_order, for Sobol'
- * points, and for the current on a dot without a lead (dot.lead names the
- * lead; the server builds and caches its dot-lead functions). */
+ * exceeds hbm_budget_bytes; EINVAL as for qqmc_eval_order, and for the
+ * current on a dot without a lead (dot.lead names the lead; the server
+ * builds and caches its dot-lead functions).  Sobol' points are served as
+ * the lattice is. */
 qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot,
                         const qqmc_order *ord, uint64_t *ticket);
 /* QQMC_PENDING until done; then fills the outputs (as qqmc_eval_order, each

@@ -79,6 +79,7 @@ qqmc_status validate_order(const qqmc_order *ord, int32_t n_grid, double t_half,
     d.t_meas = ord->t_meas;
     d.tau = ord->model_tau;
     d.alpha = ord->alpha;
+    d.sobol_points = sobol ? 1 : 0;
     double c = 1.0;
     for (int k = 0; k < n; ++k) c *= ord->model_tau;
     d.tau_n = c;

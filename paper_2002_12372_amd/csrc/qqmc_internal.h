@@ -29,7 +29,7 @@ struct ItemDesc {
     double *tile_sums;       /* device, 2 per tile, or null                 */
     const double *model_cdf; /* device: learned warp, order x (bins + 1), or null */
     int32_t model_bins;
-    int32_t pad_;
+    int32_t sobol_points;    /* 1: Sobol' points (sobol below), 0: the lattice */
     double *sample_out;      /* device: per-point Re fbar (learning pass), or null */
     double alpha;            /* interaction shift U (n_up - alpha)(n_dn - alpha) */
     const double *col;       /* device: lead functions for the current, or null */
@@ -46,18 +46,20 @@ struct ItemDesc {
 constexpr double kPairDiagonal = 0.05;
 inline bool needs_pair(double g0y) { return g0y < kPairDiagonal && g0y > -kPairDiagonal; }
 
-/* Batched-kernel selector of an item, 1 .. 4 QQMC_MAX_ORDER: its order,
+/* Batched-kernel selector of an item, 1 .. 8 QQMC_MAX_ORDER: its order,
  * plus QQMC_MAX_ORDER when it runs the paired elimination tree, plus
- * 2 QQMC_MAX_ORDER for the current. */
+ * 2 QQMC_MAX_ORDER for the current, plus 4 QQMC_MAX_ORDER on Sobol' points. */
 inline int32_t kernel_key(const ItemDesc &d)
 {
     return d.order + (needs_pair(d.g0y) ? QQMC_MAX_ORDER : 0) +
-           (d.mode == QQMC_MODE_CURRENT ? 2 * QQMC_MAX_ORDER : 0);
+           (d.mode == QQMC_MODE_CURRENT ? 2 * QQMC_MAX_ORDER : 0) +
+           (d.sobol_points ? 4 * QQMC_MAX_ORDER : 0);
 }
-constexpr int32_t kMaxKernelKey = 4 * QQMC_MAX_ORDER;
+constexpr int32_t kMaxKernelKey = 8 * QQMC_MAX_ORDER;
 inline int32_t key_order(int32_t key) { return (key - 1) % QQMC_MAX_ORDER + 1; }
 inline bool key_pair(int32_t key) { return ((key - 1) / QQMC_MAX_ORDER) & 1; }
-inline bool key_current(int32_t key) { return (key - 1) / (2 * QQMC_MAX_ORDER) == 1; }
+inline bool key_current(int32_t key) { return ((key - 1) / (2 * QQMC_MAX_ORDER)) & 1; }
+inline bool key_sobol(int32_t key) { return (key - 1) / (4 * QQMC_MAX_ORDER) == 1; }
 
 /* Entry of the batched tile list: which item, which tile of it. */
 struct TileRef {

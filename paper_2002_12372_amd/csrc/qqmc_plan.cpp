@@ -51,12 +51,14 @@ double inside_fraction(int n, double t_over_tau)
 
 struct Buffers {
     double *shifts = nullptr, *tile_sums = nullptr, *shift_sums = nullptr;
+    uint32_t *sobol = nullptr;
     ItemDesc *items = nullptr;
     int64_t *base = nullptr;
     TileRef *tiles = nullptr;
     void release()
     {
         if (shifts) hipFree(shifts);
+        if (sobol) hipFree(sobol);
         if (tile_sums) hipFree(tile_sums);
         if (shift_sums) hipFree(shift_sums);
         if (items) hipFree(items);
@@ -92,6 +94,7 @@ double tile_cost(const ItemDesc &d)
 struct qqmc_plan_s {
     std::vector<qqmc::ItemDesc> items;   /* device pointers filled in */
     std::vector<std::vector<double>> shifts;
+    std::vector<std::vector<uint32_t>> sobol; /* direction numbers + digital shifts, or empty */
     std::vector<int64_t> shift_base;
     std::vector<double> inv_n;
     std::vector<qqmc::TileRef> tiles;    /* grouped by order */
@@ -192,9 +195,12 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
     make_groups(p, all, p->tiles, p->groups);
     p->n_tiles = (int64_t)p->tiles.size();
 
-    size_t n_shift_vals = 0;
+    size_t n_shift_vals = 0, n_sobol_words = 0;
     for (auto &s : p->shifts) n_shift_vals += s.size();
+    for (auto &s : p->sobol) n_sobol_words += s.size();
     hipError_t e = hipMalloc(&p->buf.shifts, sizeof(double) * (n_shift_vals ? n_shift_vals : 1));
+    if (e == hipSuccess && n_sobol_words)
+        e = hipMalloc(&p->buf.sobol, sizeof(uint32_t) * n_sobol_words);
     if (e == hipSuccess) e = hipMalloc(&p->buf.tile_sums, sizeof(double) * 2 * (tile_off ? tile_off : 1));
     if (e == hipSuccess) e = hipMalloc(&p->buf.shift_sums, sizeof(double) * 2 * p->total_shifts);
     if (e == hipSuccess) e = hipMalloc(&p->buf.items, sizeof(ItemDesc) * p->items.size());
@@ -204,12 +210,18 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
         p->buf.release();
         return hip_error(e, "plan buffers");
     }
-    size_t so = 0;
+    size_t so = 0, wo = 0;
     int64_t to = 0;
     for (size_t i = 0; i < p->items.size(); ++i) {
         ItemDesc &d = p->items[i];
         e = hipMemcpy(p->buf.shifts + so, p->shifts[i].data(), sizeof(double) * p->shifts[i].size(),
                       hipMemcpyHostToDevice);
+        if (e == hipSuccess && !p->sobol[i].empty()) {
+            e = hipMemcpy(p->buf.sobol + wo, p->sobol[i].data(),
+                          sizeof(uint32_t) * p->sobol[i].size(), hipMemcpyHostToDevice);
+            d.sobol = p->buf.sobol + wo;
+            wo += p->sobol[i].size();
+        }
         if (e != hipSuccess) return hip_error(e, "plan upload");
         d.shifts = p->buf.shifts + so;
         d.tile_sums = p->buf.tile_sums + 2 * to;
@@ -341,11 +353,6 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
             return st;
         }
         Validated v;
-        if (items[i].order.sobol_v) {
-            delete p;
-            return set_error(QQMC_EINVAL, "item " + std::to_string(i) +
-                                              ": Sobol' points run as single launches only");
-        }
         if (items[i].order.mode == QQMC_MODE_CURRENT && !items[i].tables->d_col) {
             delete p;
             return set_error(QQMC_EINVAL, "item " + std::to_string(i) +
@@ -359,6 +366,7 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
         fill_item_tables(v.desc, items[i].tables);
         p->items.push_back(v.desc);
         p->shifts.push_back(v.shifts);
+        p->sobol.push_back(v.sobol);
         p->shift_base.push_back(sb);
         p->inv_n.push_back(v.desc.inv_n);
         sb += v.desc.n_shifts;

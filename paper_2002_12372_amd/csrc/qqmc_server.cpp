@@ -62,8 +62,10 @@ struct Request {
     qqmc_dot dot{};
     ItemDesc desc{};
     std::vector<double> shifts;
+    std::vector<uint32_t> sobol;     /* direction numbers + digital shifts, or empty */
     TableKey key;
     double *d_shifts = nullptr, *d_tiles = nullptr;
+    uint32_t *d_sobol = nullptr;
     int64_t next_tile = 0, done_tiles = 0;
     double t_submit = 0.0, t_done = 0.0;
     bool finished = false;
@@ -153,7 +155,7 @@ size_t table_bytes(const qqmc_dot &d)
 size_t request_bytes(const Request &r, bool need_table)
 {
     return (need_table ? table_bytes(r.dot) : 0) + sizeof(double) * r.shifts.size() +
-           sizeof(double) * 2 * (size_t)r.desc.n_tiles;
+           sizeof(uint32_t) * r.sobol.size() + sizeof(double) * 2 * (size_t)r.desc.n_tiles;
 }
 
 void fail(qqmc_server_s *s, const std::shared_ptr<Request> &r, qqmc_status st)
@@ -218,6 +220,13 @@ void admit(qqmc_server_s *s)
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->d_shifts, r->shifts.data(), sizeof(double) * r->shifts.size(),
                                hipMemcpyHostToDevice, s->admit_stream);
+        if (e == hipSuccess && !r->sobol.empty()) {
+            e = hipMallocAsync((void **)&r->d_sobol, sizeof(uint32_t) * r->sobol.size(),
+                               s->admit_stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->d_sobol, r->sobol.data(), sizeof(uint32_t) * r->sobol.size(),
+                                   hipMemcpyHostToDevice, s->admit_stream);
+        }
         if (e == hipSuccess) e = hipEventRecord(s->admitted, s->admit_stream);
         if (e == hipSuccess) s->admitted_pending = true;
         if (e != hipSuccess) {
@@ -226,6 +235,7 @@ void admit(qqmc_server_s *s)
             continue;
         }
         r->desc.shifts = r->d_shifts;
+        r->desc.sobol = r->d_sobol;
         r->desc.tile_sums = r->d_tiles;
         s->used += request_bytes(*r, false);
         s->active.push_back(r);
@@ -392,7 +402,9 @@ void complete(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin)
         }
         hipFreeAsync(r->d_shifts, C.stream);
         hipFreeAsync(r->d_tiles, C.stream);
+        if (r->d_sobol) hipFreeAsync(r->d_sobol, C.stream);
         r->d_shifts = r->d_tiles = nullptr;
+        r->d_sobol = nullptr;
         s->used -= request_bytes(*r, false);
         auto it = s->tables.find(r->key);
         if (it != s->tables.end()) it->second.refs -= 1;
@@ -518,12 +530,12 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     auto r = std::make_shared<Request>();
     Validated v;
     if (qqmc_status st = validate_order(ord, dot->n_grid, dot->t_half, &v)) return st;
-    if (ord->sobol_v) return set_error(QQMC_EINVAL, "Sobol' points run as single launches only");
     if (ord->mode == QQMC_MODE_CURRENT && dot->lead == 0)
         return set_error(QQMC_EINVAL, "the current needs a dot with a lead (1 or 2)");
     r->dot = *dot;
     r->desc = v.desc;
     r->shifts = v.shifts;
+    r->sobol = v.sobol;
     const int64_t N = (int64_t)v.desc.mask + 1;
     r->desc.tile_len = (int32_t)std::min<int64_t>(s->tile_len, N);
     r->desc.tiles_per_shift = (int32_t)(N / r->desc.tile_len);
@@ -605,6 +617,7 @@ void qqmc_server_destroy(qqmc_server s)
         auto &r = kv.second;
         if (r->d_shifts) hipFree(r->d_shifts);
         if (r->d_tiles) hipFree(r->d_tiles);
+        if (r->d_sobol) hipFree(r->d_sobol);
     }
     for (auto &kv : s->tables) qqmc_free_tables(kv.second.t);
     if (C.stream) hipStreamDestroy(C.stream);

@@ -113,10 +113,74 @@ def test_sobol_current(q, oracle_mod):
     _compare(qs, ref, "sobol current", floor=1e-14)
 
 
-def test_sobol_rejected_by_plans(q, tiny_tables):
+def _solo(q, gt, job, tile_len, model=None):
+    K = job.shifts.shape[0]
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, None, tile_len=min(tile_len, 1 << job.log2_n),
+                       model=model)
+    torch.cuda.synchronize()
+    h = sums.cpu().numpy()
+    return (h[0::2] + 1j * h[1::2]) / (1 << job.log2_n)
+
+
+def test_sobol_plan_matches_single_launches_bitwise(q, oracle_mod, tiny_tables):
+    """Sobol' items in one plan with lattice items: the charge on both
+    trees, through a learned warp, and the current; every graph replay
+    gives the single launches' bits; one item against the oracle."""
     gt = _upload(q, tiny_tables)
-    with pytest.raises(q.QQMCError):
-        q.plan_create([(gt, sobol_job(84, 3, 10, 2))], 10.0, tile_len=256)
+    tb_a = oracle_mod.Tables(0.3, 1.0, 20.0, 0.4)
+    gt_a = _upload(q, tb_a)
+    V, ds = _sobol_learn_inputs(5, 94)
+    _, cdf = oracle_mod.learn_model_sobol(tiny_tables, 10.0, 5, 10, V, ds, 1.0, 32, 0.05, 1e-3)
+    model = q.model_from_host(cdf)
+    d = Dot(0.3, 1.0, 2.0, 0.8, 10.0, 4001, 10.0, 4.0, 1)
+    gt_c = q.make_tables(d)
+    entries = []
+    for n in (1, 3, 6, 8, 9):
+        entries.append((gt, sobol_job(100 + n, n, 9 + n % 3, 3)))
+        entries.append((gt, order_job(110 + n, n, 10, 2)))
+    entries.append((gt_a, sobol_job(120, 6, 10, 3, alpha=tb_a.n_sigma)))
+    entries.append((gt, sobol_job(121, 5, 11, 3), model))
+    entries.append((gt_c, sobol_job(122, 4, 10, 3, mode=q.MODE_CURRENT)))
+    plan = q.plan_create(entries, 10.0, tile_len=256)
+    for rep in range(3):
+        q.plan_run(plan)
+        res = q.plan_results(plan)
+        for k, (e, got) in enumerate(zip(entries, res)):
+            ref = _solo(q, e[0], e[1], 256, e[2] if len(e) > 2 else None)
+            assert np.array_equal(got, ref), (k, e[1].order, rep)
+    job = entries[4][1]                          # Sobol', order 6, tiny dot
+    qo, _, _ = oracle_mod.eval_order_sobol(tiny_tables, 10.0, 6, job.log2_n, job.sobol_v,
+                                           job.sobol_shifts, 1.0)
+    _compare(res[4], qo, "plan sobol n=6")
+
+
+def test_sobol_server_equals_solo_runs(q):
+    """Sobol' and lattice requests served together: each result is the
+    single launch's at the server's tile length."""
+    import time
+    dots = [Dot(0.0, 1.0, 20.0, 0.0), Dot(-1.2, 0.7, 20.0, 0.5)]
+    reqs = []
+    for i in range(8):
+        n = 2 + (i * 3) % 8
+        mk = sobol_job if i % 3 != 2 else order_job
+        reqs.append((dots[i % 2], mk(130 + i, n, 10 + i % 2, 3)))
+    srv = q.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    tickets = [srv.submit(d, job, 10.0) for d, job in reqs]
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.005)
+    assert len(out) == len(tickets)
+    tabs = [q.make_tables(d) for d in dots]
+    for i, (t, (d, job)) in enumerate(zip(tickets, reqs)):
+        assert np.array_equal(out[t]["q_shift"], _solo(q, tabs[i % 2], job, q.SERVER_TILE_LEN))
+    srv.close()
 
 
 # ---------------------------------------------------------------------------

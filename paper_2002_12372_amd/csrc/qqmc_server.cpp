@@ -230,6 +230,12 @@ void admit(qqmc_server_s *s)
         if (e == hipSuccess) e = hipEventRecord(s->admitted, s->admit_stream);
         if (e == hipSuccess) s->admitted_pending = true;
         if (e != hipSuccess) {
+            /* release what this admission allocated before failing it */
+            if (r->d_shifts) hipFreeAsync(r->d_shifts, s->admit_stream);
+            if (r->d_tiles) hipFreeAsync(r->d_tiles, s->admit_stream);
+            if (r->d_sobol) hipFreeAsync(r->d_sobol, s->admit_stream);
+            r->d_shifts = r->d_tiles = nullptr;
+            r->d_sobol = nullptr;
             it->second.refs -= 1;
             fail(s, r, hip_error(e, "server admission"));
             continue;

@@ -46,15 +46,27 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false> struct L
     /* pair-table stride: the NP pairs, then for the current the n lead
      * values of the measurement column */
     static constexpr int NPS = Gm::NP + (CUR ? N : 0);
-    static constexpr int times = 0;                                    /* 64*N doubles   */
-    static constexpr int w = times + 64 * N * 8;                       /* 64 doubles     */
-    static constexpr int S = w + 64 * 8;                               /* 64 cplx        */
-    static constexpr int ids = S + 64 * 16;                            /* 64 int32       */
+    /* queued in-domain points of a tile: up to 63 carried over plus the 64
+     * of one step.  The queue runs where it measured faster: one-wave
+     * kernels with several lanes per point and no cooperative top levels
+     * (scalar tree orders 6-8, paired tree orders 6 and 8).  Elsewhere it
+     * was as fast or slower: the two-wave orders 1-4 are limited by local
+     * memory, with one lane per point (order 5) the rounds are nearly full
+     * anyway, above order 8 the default tiles are one step long, and the
+     * paired order-7 kernel sits at 256 registers, which the queue's extra
+     * live values overflow into accumulation registers (10% slower). */
+    static constexpr bool QUEUE =
+        Gm::WPS == 1 && Gm::OFF == 0 && Gm::G > 1 && (!PAIR || N != 7);
+    static constexpr int QCAP = QUEUE ? 128 : 64;
+    static constexpr int times = 0;                                    /* QCAP*N doubles */
+    static constexpr int w = times + QCAP * N * 8;                     /* QCAP doubles   */
+    static constexpr int S = w + QCAP * 8;                             /* QCAP cplx      */
+    static constexpr int ids = S + QCAP * 16;                          /* QCAP int32     */
     /* pair tables: one per item group, or one per distinct point of a
      * round when several items share a point */
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
-    static constexpr int pairs = ids + 64 * 4;                         /* tables*NP pairv */
+    static constexpr int pairs = ids + QCAP * 4;                       /* tables*NP pairv */
     /* one broadcast row per group (two for the paired tree) */
     static constexpr int rows = PAIR ? 2 : 1;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
@@ -431,6 +443,51 @@ __device__ __forceinline__ double model_inverse(const double *__restrict__ c, in
     return (double)bins * width;
 }
 
+/* Point idx of a tile (rank-1 lattice or Sobol'), warped: u_m = u_{m-1} -
+ * v_m with v_m = -tau log(1 - x_m), after the learned second warp when
+ * MODEL.  Sets u, the weight W = C / (p_n prod_j q_j) and pw = p_n prod_j q_j
+ * W (the model-mode sample); on Sobol' points also steps the lane's
+ * coordinate words to index idx + 64 (base: the step's first index).
+ * Returns whether the point lies in the domain (u_n > 0). */
+template <int N, bool MODEL, bool SOB>
+__device__ __forceinline__ bool warped_point(const ItemDesc &it, uint32_t idx, const double *shift,
+                                             uint32_t *word, const uint32_t *s_v, uint32_t base,
+                                             double *u, double &W, double &pw)
+{
+    double prev = it.t_meas, p = 1.0, qm = 1.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double y;
+        if constexpr (SOB) {
+            y = (double)word[j] * (1.0 / 4294967296.0);
+        } else {
+            const uint32_t m = (idx * it.z[j]) & it.mask;
+            y = (double)m * it.inv_n + shift[j];
+            if (y >= 1.0) y -= 1.0;
+        }
+        /* learned second warp: y -> w = F_j^{-1}(y), weight / q_j(w) */
+        if constexpr (MODEL)
+            qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
+        const double v = -it.tau * log1p(-y);
+        u[j] = prev - v;
+        p *= exp(-(prev - u[j]) / it.tau);
+        prev = u[j];
+    }
+    W = it.tau_n / p;
+    if constexpr (MODEL) W /= qm;
+    pw = p * qm * W;
+    if constexpr (SOB) {
+        /* next index: adding 64 flips bits 6 .. 6 + c - 1 of the base,
+         * c - 1 the trailing ones of base >> 6, the same in every lane */
+        const int c = __builtin_ctz(~(base >> 6)) + 1;
+        for (int k = 6; k < 6 + c && k < 32; ++k) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) word[j] ^= s_v[j * 32 + k];
+        }
+    }
+    return u[N - 1] > 0.0;
+}
+
 /* One work tile of one order-n integral: sum of fbar over 64*c lattice
  * indices of one shift.  Returns the wave's sum (same bits in every lane).
  * MODEL: the item has a learned second warp (it.model_cdf).  SAMPLE (the
@@ -485,70 +542,101 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             }
     }
     Kahan acc;
-    for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
-        const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
-        /* rank-1 lattice (or Sobol') point, then u_m = u_{m-1} - v_m,
-         * v_m = -tau log(1-x_m) */
-        double u[N];
-        double prev = it.t_meas, p = 1.0, qm = 1.0;
+    if constexpr (L::QUEUE) {
+        /* In-domain points queue in local memory across steps and the trees
+         * run on full batches of 64 (every round of PPW points full), the
+         * rest on the tile's last step: a step's own in-domain count seldom
+         * fills its last round.  `queued` is wave-uniform (ballot counts). */
+        int queued = 0;
+        for (int c0 = 0;; c0 += WAVE) {
+            const bool more = c0 < it.tile_len;
+            if (!more && queued == 0) break;
+            if (more) {
+                const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
+                double u[N], W, pw;
+                const bool inside =
+                    warped_point<N, MODEL, SOB>(it, idx, shift, word, s_v, i0 + (uint32_t)c0, u, W, pw);
+                if (!CUR && it.mode != QQMC_MODE_CHARGE) {
+                    /* the model function is the combined one, p_n prod_j q_j */
+                    if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(pw, 0.0));
+                    else if (inside) acc.add(cmk(W, 0.0));
+                    continue;
+                }
+                const uint64_t mask = __ballot(inside);
+                const int cnt = __popcll(mask);
+                if (inside) {
+                    const int q = queued + lane_rank(mask);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            double y;
-            if constexpr (SOB) {
-                y = (double)word[j] * (1.0 / 4294967296.0);
-            } else {
-                const uint32_t m = (idx * it.z[j]) & it.mask;
-                y = (double)m * it.inv_n + shift[j];
-                if (y >= 1.0) y -= 1.0;
+                    for (int k = 0; k < N; ++k) s_times[q * N + k] = u[N - 1 - k];
+                    s_w[q] = W;
+                    s_S[q] = cmk(0.0, 0.0);
+                    if constexpr (SAMPLE) s_ids[q] = (int32_t)idx;
+                } else if constexpr (SAMPLE) {
+                    it.sample_out[idx] = 0.0;
+                }
+                queued += cnt;
+                wave_sync();
+                /* wait for a full batch, except on the tile's last step */
+                if (queued < WAVE && c0 + WAVE < it.tile_len) continue;
             }
-            /* learned second warp: y -> w = F_j^{-1}(y), weight / q_j(w) */
-            if constexpr (MODEL)
-                qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
-            const double v = -it.tau * log1p(-y);
-            u[j] = prev - v;
-            p *= exp(-(prev - u[j]) / it.tau);
-            prev = u[j];
-        }
-        double W = it.tau_n / p;
-        if constexpr (MODEL) W /= qm;
-        const bool inside = u[N - 1] > 0.0;
-        if constexpr (SOB) {
-            /* next index: adding 64 flips bits 6 .. 6 + c - 1 of the base,
-             * c - 1 the trailing ones of base >> 6, the same in every lane */
-            const uint32_t base = i0 + (uint32_t)c0;
-            const int c = __builtin_ctz(~(base >> 6)) + 1;
-            for (int k = 6; k < 6 + c && k < 32; ++k) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) word[j] ^= s_v[j * 32 + k];
+            /* a batch of 64 queued points, or on the tile's last step the
+             * rest (up to 64; what is left then goes in the next pass) */
+            const int m = queued < WAVE ? queued : WAVE;
+            keldysh_points<N, PAIR, CUR>(m, env, lds);
+            if (lane < m) {
+                const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
+                const double w = s_w[lane];
+                acc.add(cmk(f.x * w, f.y * w));
+                if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
             }
-        }
-        if (!CUR && it.mode != QQMC_MODE_CHARGE) {
-            /* the model function is the combined one, p_n prod_j q_j */
-            if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(p * qm * W, 0.0));
-            else if (inside) acc.add(cmk(W, 0.0));
-            continue;
-        }
-        const uint64_t mask = __ballot(inside);
-        const int cnt = __popcll(mask);
-        if (inside) {
-            const int rk = lane_rank(mask);
+            wave_sync();
+            /* the points beyond the batch (fewer than 64) move to the front */
+            const int left = queued - m;
+            if (lane < left) {
+                const int q = m + lane;
 #pragma unroll
-            for (int k = 0; k < N; ++k) s_times[rk * N + k] = u[N - 1 - k];
-            s_w[rk] = W;
-            s_S[rk] = cmk(0.0, 0.0);
-            if constexpr (SAMPLE) s_ids[rk] = (int32_t)idx;
-        } else if constexpr (SAMPLE) {
-            it.sample_out[idx] = 0.0;
+                for (int k = 0; k < N; ++k) s_times[lane * N + k] = s_times[q * N + k];
+                s_w[lane] = s_w[q];
+                s_S[lane] = cmk(0.0, 0.0);
+                if constexpr (SAMPLE) s_ids[lane] = s_ids[q];
+            }
+            queued = left;
+            wave_sync();
         }
-        wave_sync();
-        keldysh_points<N, PAIR, CUR>(cnt, env, lds);
-        if (lane < cnt) {
-            const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
-            const double w = s_w[lane];
-            acc.add(cmk(f.x * w, f.y * w));
-            if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
+    } else {
+        /* every step's in-domain points at once */
+        for (int c0 = 0; c0 < it.tile_len; c0 += WAVE) {
+            const uint32_t idx = i0 + (uint32_t)c0 + (uint32_t)lane;
+            double u[N], W, pw;
+            const bool inside =
+                warped_point<N, MODEL, SOB>(it, idx, shift, word, s_v, i0 + (uint32_t)c0, u, W, pw);
+            if (!CUR && it.mode != QQMC_MODE_CHARGE) {
+                if (it.mode == QQMC_MODE_MODEL) acc.add(cmk(pw, 0.0));
+                else if (inside) acc.add(cmk(W, 0.0));
+                continue;
+            }
+            const uint64_t mask = __ballot(inside);
+            const int cnt = __popcll(mask);
+            if (inside) {
+                const int rk = lane_rank(mask);
+#pragma unroll
+                for (int k = 0; k < N; ++k) s_times[rk * N + k] = u[N - 1 - k];
+                s_w[rk] = W;
+                s_S[rk] = cmk(0.0, 0.0);
+                if constexpr (SAMPLE) s_ids[rk] = (int32_t)idx;
+            } else if constexpr (SAMPLE) {
+                it.sample_out[idx] = 0.0;
+            }
+            wave_sync();
+            keldysh_points<N, PAIR, CUR>(cnt, env, lds);
+            if (lane < cnt) {
+                const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
+                const double w = s_w[lane];
+                acc.add(cmk(f.x * w, f.y * w));
+                if constexpr (SAMPLE) it.sample_out[s_ids[lane]] = f.x * w;
+            }
+            wave_sync();
         }
-        wave_sync();
     }
     return wave_sum(acc.value());
 }

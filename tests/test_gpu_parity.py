@@ -250,6 +250,40 @@ def test_full_size_sampled_tiles(q, oracle_mod, tiny_tables):
         assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13
 
 
+@pytest.mark.parametrize("n,tile_len,alpha", [(6, 4096, None), (7, 1024, None), (8, 2048, None),
+                                              (8, 64, None), (6, 1024, "ns"), (8, 1024, "ns")])
+def test_long_tiles_every_tile(q, oracle_mod, tiny_tables, n, tile_len, alpha):
+    """Tiles of 16-64 steps (the order kernels queue in-domain points across
+    the steps of a tile and run the trees on full batches of 64, the rest on
+    the last step, where more than 64 may wait): every tile sum against the
+    oracle over the same index range; also the one-step tile and the paired
+    tree (alpha = n_sigma of a dot with eps_d = 0.3, V = 0.4)."""
+    if alpha == "ns":
+        tb = oracle_mod.Tables(0.3, 1.0, 20.0, 0.4)
+        a = tb.n_sigma
+    else:
+        tb, a = tiny_tables, 0.0
+    gt = _upload(q, tb)
+    log2_n, K = 13, 2
+    job = order_job(7 + n, n, log2_n, K, alpha=a)
+    nt = K * (1 << log2_n) // tile_len
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    per = (1 << log2_n) // tile_len
+    picks = range(nt) if nt <= 16 else np.random.default_rng(n).choice(nt, size=16, replace=False)
+    for k in picks:
+        s, i0 = divmod(int(k), per)
+        ref = oracle_mod.eval_sums(tb, 10.0, n, log2_n, job.lattice_a, job.shifts[s:s + 1], 1.0, 0,
+                                   i0 * tile_len, (i0 + 1) * tile_len, alpha=a)[0]
+        mass = oracle_mod.eval_mass(tb, 10.0, n, log2_n, job.lattice_a, job.shifts[s:s + 1], 1.0,
+                                    i0 * tile_len, (i0 + 1) * tile_len, alpha=a)[0] if a else 0.0
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-12 * mass + 1e-13, (k, tc[k], ref)
+
+
 def test_eval_points_empty(q, tiny_tables):
     """No points: both methods return without touching the (empty) buffers."""
     gt = _upload(q, tiny_tables)

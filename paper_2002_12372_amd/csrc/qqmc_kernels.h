@@ -470,7 +470,8 @@ __device__ __forceinline__ bool warped_point(const ItemDesc &it, uint32_t idx, c
             qm *= model_inverse(it.model_cdf + j * (it.model_bins + 1), it.model_bins, y, y);
         const double v = -it.tau * log1p(-y);
         u[j] = prev - v;
-        p *= exp(-(prev - u[j]) / it.tau);
+        /* the model density of the step, exp(-v / tau), is 1 - y exactly */
+        p *= 1.0 - y;
         prev = u[j];
     }
     W = it.tau_n / p;

@@ -2,11 +2,17 @@
  * qqmc.h -- C ABI of the MI355X quantum quasi-Monte Carlo (QQMC) library.
  *
  * The library estimates the order-n coefficient Q_n of the charge
- * Q(U) = sum_n Q_n U^n of a wide-band Anderson quantum dot (arXiv:2002.12372,
- * Macek et al.): a randomly shifted rank-1 lattice is warped through the
- * product-of-exponentials model function into time-ordered interaction
- * vertices, and at every point the Keldysh sum of products of spin-up and
- * spin-down Wick determinants is evaluated on the GPU.
+ * Q(U) = sum_n Q_n U^n of an Anderson quantum dot (arXiv:2002.12372,
+ * Macek et al.): a randomly shifted rank-1 lattice (or digitally shifted
+ * Sobol' points, App. B) is warped through the product-of-exponentials model
+ * function (optionally followed by a learned per-coordinate warp, App. I)
+ * into time-ordered interaction vertices, and at every point the Keldysh sum
+ * of products of spin-up and spin-down Wick determinants is evaluated on the
+ * GPU.  The same path gives the particle current into a lead (App. E), for
+ * the alpha-shifted interaction U (n_up - alpha)(n_dn - alpha), with
+ * wide-band leads at T > 0 or T = 0 or semicircular leads of finite
+ * bandwidth; single launches, batched plans (HIP graphs) and a
+ * continuous-batching server share the same kernels and the same bits.
  *
  * General conventions
  *  - All arithmetic is IEEE binary64; complex numbers are (re, im) pairs of

@@ -284,6 +284,42 @@ def test_long_tiles_every_tile(q, oracle_mod, tiny_tables, n, tile_len, alpha):
         assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-12 * mass + 1e-13, (k, tc[k], ref)
 
 
+@pytest.mark.parametrize("n", [11, 12, 13, 14])
+def test_stress_full_size_sampled_tiles(q, oracle_mod, n):
+    """The stress configuration as the benchmark times it (eps_d = -0.5,
+    V = 0.2, N = 2^18 x 16 shifts, the same jobs, the library's default tile
+    length): sampled tile sums against the oracle over the same index ranges,
+    each shift's last tile among them, and the tile sums of every shift add
+    up to its shift sum."""
+    tb = oracle_mod.Tables(STRESS_DOT.eps_d, STRESS_DOT.gamma, STRESS_DOT.beta, STRESS_DOT.bias_v,
+                           STRESS_DOT.n_grid, STRESS_DOT.t_half)
+    gt = _upload(q, tb)
+    log2_n, K = 18, 16
+    job = order_job(4, n, log2_n, K)
+    sums = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+    nt = q.eval_order_async(gt, job, 10.0, sums, None)
+    torch.cuda.synchronize()
+    tile_len = (1 << log2_n) * K // nt
+    tiles = torch.zeros(2 * nt, dtype=torch.float64, device="cuda")
+    q.eval_order_async(gt, job, 10.0, sums, tiles, tile_len=tile_len)
+    torch.cuda.synchronize()
+    th = tiles.cpu().numpy()
+    tc = th[0::2] + 1j * th[1::2]
+    sh = sums.cpu().numpy()
+    sc = sh[0::2] + 1j * sh[1::2]
+    per = (1 << log2_n) // tile_len
+    for s in range(K):
+        part = tc[s * per:(s + 1) * per]
+        assert abs(part.sum() - sc[s]) <= 1e-12 * np.sum(np.abs(part)) + 1e-300
+    picks = set(int(k) for k in np.random.default_rng(100 + n).choice(nt, size=3, replace=False))
+    picks |= {per - 1, K * per - 1}
+    for k in sorted(picks):
+        s, i0 = divmod(k, per)
+        ref = oracle_mod.eval_sums(tb, 10.0, n, log2_n, job.lattice_a, job.shifts[s:s + 1], 1.0, 0,
+                                   i0 * tile_len, (i0 + 1) * tile_len)[0]
+        assert abs(tc[k] - ref) <= 1e-9 * abs(ref) + 1e-13, (n, k, tc[k], ref)
+
+
 def test_eval_points_empty(q, tiny_tables):
     """No points: both methods return without touching the (empty) buffers."""
     gt = _upload(q, tiny_tables)

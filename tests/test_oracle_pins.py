@@ -173,6 +173,23 @@ def test_wick_matrices_leibniz(oracle_mod, tiny_tables):
         assert abs(oracle_mod.det(m[1:, 1:]) - _leibniz(m[1:, 1:])) < 1e-14
 
 
+def test_keldysh_sum_and_mass_brute_force(oracle_mod, tiny_tables):
+    """S(u) = sum_a (-1)^|a| det_up det_dn and the term mass
+    M(u) = sum_a |det_up det_dn| against a sum written out here over the 2^n
+    index vectors, with Leibniz determinants of the Wick matrices."""
+    for u in (np.array([8.2, 4.4, 1.3]), np.array([9.1, 6.0, 3.3, 0.4])):
+        n = len(u)
+        S_ref, M_ref = 0.0, 0.0
+        for a in itertools.product((0, 1), repeat=n):
+            m = oracle_mod.wick_matrix(tiny_tables, 10.0, u, a)
+            term = _leibniz(m) * _leibniz(m[1:, 1:])
+            S_ref += (-1) ** sum(a) * term
+            M_ref += abs(term)
+        S, M = oracle_mod.keldysh_sum(tiny_tables, 10.0, u)
+        assert abs(S - S_ref) <= 1e-13 * M_ref
+        assert abs(M - M_ref) <= 1e-13 * M_ref
+
+
 def test_wick_matrix_keldysh_rule(oracle_mod, tiny_tables):
     """Spot entries of the 2x2 Keldysh rule of App. E: rows (0,t,0), U_k;
     columns (0,t,1), U_k; g^T = g^> for a later first argument."""

@@ -34,6 +34,7 @@
 #include "qqmc_gf.h"
 #include "qqmc_internal.h"
 #include "qqmc_tree.h"
+#include "qqmc_adapt.h"
 
 namespace qqmc {
 
@@ -71,9 +72,22 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false> struct L
     static constexpr int rows = PAIR ? 2 : 1;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
-    static constexpr int sobv = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+    static constexpr int c0_end = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
+    /* the paired tree's adaptive re-evaluation (qqmc_adapt.h), placed
+     * before the Sobol' numbers so that its offset and size are the same with
+     * and without them; its breadth-first start size MB is the largest that
+     * keeps a workgroup (Sobol' numbers included) within 40 KiB, the share
+     * of each of the four one-wave workgroups a compute unit holds in its
+     * 160 KiB of local memory */
+    static constexpr int adapt = (c0_end + 15) & ~15;
+    static constexpr int sob_bytes = N * 32 * 4;
+    static constexpr int kShare = 40960;
+    static constexpr int MB = !PAIR ? 8
+                              : adapt + AdaptWs<N, 8>::bytes + sob_bytes <= kShare ? 8
+                              : adapt + AdaptWs<N, 7>::bytes + sob_bytes <= kShare ? 7 : 6;
     /* Sobol' direction numbers, N x 32 words */
-    static constexpr int bytes = sobv + (SOB ? N * 32 * 4 : 0);
+    static constexpr int sobv = adapt + (PAIR ? AdaptWs<N, MB>::bytes : 0);
+    static constexpr int bytes = sobv + (SOB ? sob_bytes : 0);
 };
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m)
@@ -241,7 +255,7 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
  * product of the pivot-block determinants. */
 template <int N, bool CUR = false>
 __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
-                               cplx *s_row, cplx *s_c0)
+                               cplx *s_row, cplx *s_c0, double &grow)
 {
     using Gm = Geo<N, true>;
     constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
@@ -285,6 +299,14 @@ __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int su
         const cplx det = cfms(be, ga, cmul(a, d));
         const cplx rdet = crecip_nr(det);
         const cplx dd = cmul(d, rdet), aa = cmul(a, rdet), bb = cmul(be, rdet), gg = cmul(ga, rdet);
+        /* growth bound of the step: the broadcast rows are the same in
+         * every lane, the columns U, V are spread over the lanes' rows */
+        double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
+#pragma unroll
+        for (int j = k + 2; j <= N; ++j) {
+            mx = fmax(mx, cabs2(s_r0[j]));
+            my = fmax(my, cabs2(s_r1[j]));
+        }
 #pragma unroll
         for (int m = 0; m < RPL; ++m) {
             const int r = sub + m * G;
@@ -293,11 +315,14 @@ __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int su
                 const cplx z = csub(wick_entry(pr, r, k + 1, bq), crow[m][k + 1]);
                 const cplx Ui = cfms(z, gg, cmul(u, dd));
                 const cplx Vi = cfms(u, bb, cmul(z, aa));
+                mu = fmax(mu, cabs2(Ui));
+                mv = fmax(mv, cabs2(Vi));
 #pragma unroll
                 for (int j = k + 2; j <= N; ++j)
                     crow[m][j] = cfma(Vi, s_r1[j], cfma(Ui, s_r0[j], crow[m][j]));
             }
         }
+        grow = fmax(grow, fmax(mu * mx, mv * my));
         prod = cmul(prod, det);
         wave_sync();
     }
@@ -311,6 +336,40 @@ __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int su
     }
     wave_sync();
     return prod;
+}
+
+/* The adaptive path (qqmc_adapt.h) on one point whose pair table is pr
+ * (measurement column mc), from the start block S (m x m, first row vertex
+ * k; null: the whole point) with weight w0, in the local-memory workspace ws
+ * of the kernel.  Wave-uniform result.  Not inlined: it runs for few points,
+ * and as a separate function its code and registers stay out of the
+ * register tree's allocation. */
+template <int N, bool CUR, int MB>
+__device__ __attribute__((noinline)) cplx adapt_point(const pairv *pr, const pairv *mc, cplx g0,
+                                                     char *ws, const cplx *S, int m, int k,
+                                                     cplx w0)
+{
+    using AW = AdaptWs<N, MB>;
+    cplx *wsb = reinterpret_cast<cplx *>(ws);
+    AdaptCtx<CUR> a;
+    a.pr = pr;
+    a.mc = mc;
+    a.g0 = g0;
+    a.n = N;
+    a.lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
+    a.rep = wsb + AW::rep;
+    a.lvl = wsb + AW::lvl;
+    a.vs = wsb + AW::vs;
+    a.vp = wsb + AW::vp;
+    a.wsn = wsb + AW::wsn;
+    a.wpn = wsb + AW::wpn;
+    a.nw = wsb + AW::nw;
+    a.part = wsb + AW::part;
+    a.red = reinterpret_cast<double *>(wsb + AW::red);
+    a.lvl_size = AW::LVL;
+    a.rep_size = AW::RB;
+    WaveLanes x;
+    return adapt_eval<CUR, MB>(x, a, S, m, k, w0);
 }
 
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
@@ -327,6 +386,8 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
     const int lane = threadIdx.x;
     const int grp = lane / Gm::G, sub = lane % Gm::G;
     const int n_items = cnt * Gm::IPP;
+    bool point_top_flag = false; /* paired top levels of the current point grew */
+    (void)point_top_flag;
     for (int base = 0; base < n_items; base += Gm::PPW) {
         const int item = base + grp;
         const bool active = item < n_items;
@@ -396,17 +457,54 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         int sgn = 0;
         BlockSrc<N, PAIR> src;
         src.c = nullptr;
+        double gtop = 0.0, gbot = 0.0; /* squared growth bounds (paired tree) */
         if constexpr (Gm::OFF > 0) {
             cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
-            if constexpr (PAIR) prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
+            if constexpr (PAIR)
+                prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0, gtop);
             else prod = top_block<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;
         }
         cplx s;
-        if constexpr (PAIR) s = lane_sum_pair<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        if constexpr (PAIR) s = lane_sum_pair<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0, gbot);
         else s = lane_sum<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        if constexpr (PAIR) {
+            /* Points (n <= 8) or items (n > 8) whose pair steps grew beyond
+             * kGrowthFlag are evaluated again by the adaptive path; a point
+             * whose cooperative top levels grew is redone whole after its
+             * last round.  Flags, groups and results are wave-uniform. */
+            constexpr double F2 = kGrowthFlag * kGrowthFlag / 4.0;
+            constexpr uint64_t GM = Gm::G >= 64 ? ~0ull : ((1ull << Gm::G) - 1);
+            const uint64_t ft = __ballot(active && gtop > F2);
+            uint64_t rem = __ballot(active && (gbot > F2 || gtop > F2));
+            if constexpr (Gm::OFF > 0) {
+                static_assert(Gm::IPP >= Gm::PPW, "a round of the paired top holds one point");
+                point_top_flag = point_top_flag || ft != 0;
+                if (point_top_flag) rem = 0;
+            }
+            while (rem) {
+                const int g = __builtin_ctzll(rem) / Gm::G;
+                rem &= ~(GM << (g * Gm::G));
+                cplx r;
+                if constexpr (Gm::OFF == 0) {
+                    const pairv *tg = s_pairs + g * NPS;
+                    r = adapt_point<N, CUR, L::MB>(tg, tg + (CUR ? Gm::NP : pidx(0, N)), env.g0, lds + L::adapt,
+                                                    nullptr, N + 1, 0, cmk(1.0, 0.0));
+                } else {
+                    const int tg = (base + g) % Gm::IPP;
+                    cplx pg;
+                    pg.x = __shfl(prod.x, g * Gm::G, WAVE);
+                    pg.y = __shfl(prod.y, g * Gm::G, WAVE);
+                    cplx w0 = cmul(pg, pg);
+                    if (__popc((unsigned)tg) & 1) w0 = cmk(-w0.x, -w0.y);
+                    const cplx *c0g = reinterpret_cast<const cplx *>(lds + L::c0) + g * Gm::K * Gm::K;
+                    r = adapt_point<N, CUR, L::MB>(prg, mc, env.g0, lds + L::adapt, c0g, Gm::K, Gm::OFF, w0);
+                }
+                if (grp == g) s = sub == 0 ? r : cmk(0.0, 0.0);
+            }
+        }
         /* sum over the lanes of a group, then over the groups of the round
          * that share a point: they are SPAN aligned consecutive lanes, all
          * active or all idle (points hold IPP consecutive items and rounds
@@ -422,6 +520,17 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             else s_S[pt] = cadd(s_S[pt], s);
         }
         wave_sync();
+        if constexpr (PAIR && Gm::OFF > 0) {
+            /* after the point's last round: redo it whole if a top step grew */
+            if ((base + Gm::PPW) % Gm::IPP == 0 && point_top_flag) {
+                const int p = base / Gm::IPP;
+                const cplx r = adapt_point<N, CUR, L::MB>(prg, mc, env.g0, lds + L::adapt, nullptr, N + 1, 0,
+                                                           cmk(1.0, 0.0));
+                if (lane == 0) s_S[p] = r;
+                wave_sync();
+            }
+            if ((base + Gm::PPW) % Gm::IPP == 0) point_top_flag = false;
+        }
     }
 }
 

@@ -83,6 +83,7 @@ QQMC_HD cplx crecip(cplx a)
     return cmk(a.x * d, -a.y * d);
 }
 QQMC_HD cplx csel(int b, cplx one, cplx zero) { return b ? one : zero; }
+QQMC_HD double cabs2(cplx a) { return fma(a.x, a.x, a.y * a.y); }
 
 /* 1/a from the hardware reciprocal estimate refined by two Newton steps
  * (e = 1 - a r, r <- r + r e; each step squares the relative error), about
@@ -372,7 +373,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N> C0, int pre,
  * the closed forms above, which invert nothing either. */
 template <int N, int L, bool CUR = false>
 QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, const pairv *mc,
-                       cplx g0, const LeafK &lk)
+                       cplx g0, const LeafK &lk, double &grow)
 {
     constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, M = K - L;
     if constexpr (M == 2) {
@@ -396,34 +397,41 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, const
             const cplx r = crecip_nr(det);
             const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
             cplx x[M - 2], u[M - 2];
+            double mx = 0.0;
 #pragma unroll
             for (int j = 2; j < M; ++j) {
                 const cplx *P = &pr[pidx(V0, V0 + j)].gl;
                 const cplx *R = (CUR && j == M - 1) ? &mc[V0].gl : P;
                 x[j - 2] = csub(cnc(R[b]), C.v[0][j]);
                 u[j - 2] = csub(P[b ^ 1], C.v[j][0]);
+                mx = fmax(mx, cabs2(x[j - 2]));
             }
             cplx sub = cmk(0.0, 0.0);
 #pragma unroll
             for (int bq = 0; bq < 2; ++bq) {
                 cplx y[M - 2], z[M - 2];
+                double my = 0.0, mu = 0.0, mv = 0.0;
 #pragma unroll
                 for (int j = 2; j < M; ++j) {
                     const cplx *Q = &pr[pidx(V0 + 1, V0 + j)].gl;
                     const cplx *R = (CUR && j == M - 1) ? &mc[V0 + 1].gl : Q;
                     y[j - 2] = csub(cnc(R[bq]), C.v[1][j]);
                     z[j - 2] = csub(Q[bq ^ 1], C.v[j][1]);
+                    my = fmax(my, cabs2(y[j - 2]));
                 }
                 Blk<M - 2> D;
 #pragma unroll
                 for (int i = 2; i < M; ++i) {
                     const cplx Ui = cfms(z[i - 2], gg, cmul(u[i - 2], dd));
                     const cplx Vi = cfms(u[i - 2], bb, cmul(z[i - 2], aa));
+                    mu = fmax(mu, cabs2(Ui));
+                    mv = fmax(mv, cabs2(Vi));
 #pragma unroll
                     for (int j = 2; j < M; ++j)
                         D.v[i - 2][j - 2] = cfma(Vi, y[j - 2], cfma(Ui, x[j - 2], C.v[i][j]));
                 }
-                const cplx w = pair_walk<N, L + 2, CUR>(D, pr, mc, g0, lk);
+                grow = fmax(grow, fmax(mu * mx, mv * my));
+                const cplx w = pair_walk<N, L + 2, CUR>(D, pr, mc, g0, lk, grow);
                 sub = bq ? csub(sub, w) : cadd(sub, w);
             }
             const cplx t = cmul(cmul(det, det), sub);
@@ -438,7 +446,7 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, const
  * its U, V columns and x, y rows), then the pair walk. */
 template <int N, bool CUR = false>
 QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C0, int pre,
-                           cplx prod, int sgn, cplx g0)
+                           cplx prod, int sgn, cplx g0, double &grow)
 {
     constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF, T = Geo<N, true>::T;
     const LeafK lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
@@ -450,7 +458,7 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        v = pair_walk<N, 0, CUR>(C, pr, mc, g0, lk);
+        v = pair_walk<N, 0, CUR>(C, pr, mc, g0, lk, grow);
     } else {
         constexpr int TP = T / 2;
         cplx Uc[TP][K], Vc[TP][K], xr[TP][K], yr[TP][K];
@@ -473,6 +481,7 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
             const cplx det = cfms(be, ga, cmul(a, d));
             const cplx r = crecip_nr(det);
             const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
+            double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
 #pragma unroll
             for (int i = k + 2; i < K; ++i) {
                 const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
@@ -492,7 +501,12 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
                 yr[s][i] = y;
                 Uc[s][i] = cfms(z, gg, cmul(u, dd));
                 Vc[s][i] = cfms(u, bb, cmul(z, aa));
+                mx = fmax(mx, cabs2(x));
+                my = fmax(my, cabs2(y));
+                mu = fmax(mu, cabs2(Uc[s][i]));
+                mv = fmax(mv, cabs2(Vc[s][i]));
             }
+            grow = fmax(grow, fmax(mu * mx, mv * my));
             prod = cmul(prod, det);
         }
         Blk<K - T> C;
@@ -505,7 +519,7 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
                 for (int l = 0; l < TP; ++l) c = cfma(Vc[l][i], yr[l][j], cfma(Uc[l][i], xr[l][j], c));
                 C.v[i - T][j - T] = c;
             }
-        v = pair_walk<N, T, CUR>(C, pr, mc, g0, lk);
+        v = pair_walk<N, T, CUR>(C, pr, mc, g0, lk, grow);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;

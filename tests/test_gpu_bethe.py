@@ -38,9 +38,9 @@ def _bethe():
     return {int(a): float(b) for a, b in rows}
 
 
-@pytest.mark.parametrize("n", list(range(1, 11)))
+@pytest.mark.parametrize("n", list(range(1, 13)))
 def test_bethe_coefficients(q, tables, n):
-    log2_n = 16 if n <= 6 else 18
+    log2_n = 16 if n <= 6 else (18 if n <= 10 else 20)
     job = order_job(1, n, log2_n, 16, model_tau=0.95)
     qs, mean, se = q.eval_order(tables, job, BETHE_DOT.t_meas)
     ref = _bethe()[n]

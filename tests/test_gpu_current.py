@@ -10,13 +10,13 @@ two stationary-state laws (current conservation between the leads at order
 Plans and the server run the current as they run the charge: per-shift sums
 equal, bit for bit, those of single launches at the same tile length.
 
-Tolerances as in the charge parity tests (per value 1e-10 relative or 1e-13
-of the term mass, estimates 1e-9 relative).  At alpha = n_sigma the paired
-tree runs with a zero vertex diagonal: a 2x2 pivot block spanning a long gap
-between consecutive vertices is nearly singular and the elimination loses
-digits (measured up to 5e-12 of the term mass per point on this fast-decaying
-dot), so points, estimates and tiles there are held to 1e-10 of their (summed)
-term mass.
+Tolerances as in the charge parity tests, alpha = n_sigma included (per value
+1e-10 relative or 1e-13 of the term mass, estimates and tiles 1e-9 relative
++1e-15).  At alpha = n_sigma the paired tree runs with a zero vertex
+diagonal; points whose pair steps grow (a 2x2 pivot block spanning a long
+gap) are evaluated again with data-chosen elimination blocks.  The one
+comparison between tables built by the library and by the oracle (which
+agree to 1e-13, not bit for bit) carries a floor of 1e-12 of the term mass.
 """
 import math
 
@@ -91,7 +91,7 @@ def test_points_tree_current(q, oracle_mod, otab, n, alpha):
     u = _points(np.random.default_rng(4000 + n), n, 48 if n <= 8 else (6 if n <= 10 else 2))
     f = _eval_points(q, gt, n, u, q.METHOD_TREE, a)
     _check(f, [oracle_mod.current_integrand(tb, T, row, a) for row in u],
-           1e-10 if a else 1e-13, "tree n=%d" % n)
+           1e-13, "tree n=%d" % n)
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 8])
@@ -120,6 +120,9 @@ def test_points_direct_current_term_mass(q, oracle_mod, otab):
 
 
 def _compare(qs, qo, floor, label):
+    floor = np.broadcast_to(np.asarray(floor, dtype=float), (len(qo),))
+    worst = max((abs(qs[s] - qo[s]) / abs(qo[s]) for s in range(len(qo)) if qo[s] != 0), default=0.0)
+    print("%s: worst relative error %.2e" % (label, worst))
     for s in range(len(qo)):
         assert abs(qs[s] - qo[s]) <= 1e-9 * abs(qo[s]) + floor[s], (label, s, qs[s], qo[s])
 
@@ -135,7 +138,7 @@ def test_eval_order_current(q, oracle_mod, otab, n, log2_n, K, alpha):
     qs, _, _ = q.eval_order(gt, job, T)
     qo, _, _, mass = oracle_mod.eval_order_current(tb, T, n, log2_n, job.lattice_a, job.shifts,
                                                    1.0, alpha=a)
-    _compare(qs, qo, (1e-10 if a else 1e-12) * mass + 1e-15, "n=%d alpha=%g" % (n, a))
+    _compare(qs, qo, 1e-15, "n=%d alpha=%g" % (n, a))
 
 
 def test_current_library_tables_end_to_end(q, oracle_mod, otab):
@@ -171,7 +174,7 @@ def test_current_full_size_sampled_tiles(q, oracle_mod, otab):
         s, i0 = divmod(int(k), per)
         ref, mass = oracle_mod.eval_current(tb, T, 8, 20, job.lattice_a, job.shifts[s:s + 1],
                                             1.0, i0 * tile_len, (i0 + 1) * tile_len)
-        assert abs(tc[k] - ref[0]) <= 1e-9 * abs(ref[0]) + 1e-13 * mass[0] + 1e-15
+        assert abs(tc[k] - ref[0]) <= 1e-9 * abs(ref[0]) + 1e-15
 
 
 def test_current_conservation_full_size(q, otab):
@@ -263,7 +266,7 @@ def test_current_plan_matches_single_launches_bitwise(q, oracle_mod, otab):
     job = entries[-1][1]
     qo, _, _, mass = oracle_mod.eval_order_current(tb, T, 5, job.log2_n, job.lattice_a,
                                                    job.shifts, 1.0)
-    assert np.all(np.abs(res[-1] - qo) <= 1e-9 * np.abs(qo) + 1e-12 * mass + 1e-15)
+    assert np.all(np.abs(res[-1] - qo) <= 1e-9 * np.abs(qo) + 1e-15)
 
 
 def test_current_plan_autotuned(q):

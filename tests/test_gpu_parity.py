@@ -117,6 +117,35 @@ def test_points_direct_vs_oracle_and_causality(q, oracle_mod, tiny_tables, n):
         assert abs(flh[k, 0] + 1j * flh[k, 1]) <= 1e-13 * M2
 
 
+@pytest.mark.parametrize("n", [11, 12, 13, 14])
+def test_causality_stress_orders_on_device(q, oracle_mod, n):
+    """The stress orders on the stress dot: with one vertex after the
+    measurement time every Keldysh index vector pairs with one of opposite
+    sign and equal determinants (the structure of Eq. (integral_gf)), so the
+    direct method's sum vanishes to rounding, |f| <= 1e-13 of the term mass
+    (the oracle's and the device's)."""
+    d = STRESS_DOT
+    tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    gt = _upload(q, tb)
+    rng = np.random.default_rng(2100 + n)
+    count = 2
+    late = rng.uniform(0.0, 9.5, size=(count, n))
+    late[np.arange(count), rng.integers(n, size=count)] = rng.uniform(8.05, 9.9, size=count)
+    lt = torch.tensor(late, dtype=torch.float64, device="cuda")
+    fl = torch.zeros((count, 2), dtype=torch.float64, device="cuda")
+    ml = torch.zeros(count, dtype=torch.float64, device="cuda")
+    q.eval_points(gt, n, 8.0, lt, fl, method=q.METHOD_DIRECT, mass=ml)
+    torch.cuda.synchronize()
+    flh = fl.cpu().numpy()
+    mlh = ml.cpu().numpy()
+    for k, row in enumerate(late):
+        _, M2 = oracle_mod.integrand(tb, 8.0, row)
+        f = abs(flh[k, 0] + 1j * flh[k, 1])
+        print("n=%d point %d: |f| = %.2e, term mass %.3e (device %.3e)" % (n, k, f, M2, mlh[k]))
+        assert M2 > 0.0 and abs(mlh[k] - M2) <= 1e-11 * M2
+        assert f <= 1e-13 * M2
+
+
 @pytest.mark.parametrize("n", [1, 2, 4, 7, 9])
 def test_points_direct_term_mass(q, oracle_mod, tiny_tables, n):
     """The direct method's term mass 2 sum_a |det_up det_dn| against the

@@ -9,7 +9,10 @@ device.  Tables are built and resident in HBM before timing.
 Prints one JSON line: points/s (all lattice points, in or out of the domain),
 the roofline of the integrand kernel (FP64 vector ALU: algorithmic
 operations of the elimination tree per point inside the domain, see
-paper_2002_12372_amd/flops.py), and the CPU oracle timed on a bounded sample.
+paper_2002_12372_amd/flops.py), the CPU oracle timed on a bounded sample,
+and the serving trace (512 Poisson sweep requests at 200/s): p50 and p99
+latency and points/s of the continuous-batching server beside one plain
+launch per request in arrival order.
 """
 import argparse
 import json
@@ -28,6 +31,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 KERNEL_SOURCES = ["paper_2002_12372_amd/csrc/qqmc_kernels.hip",
                   "paper_2002_12372_amd/csrc/qqmc_kernels.h",
                   "paper_2002_12372_amd/csrc/qqmc_tree.h",
+                  "paper_2002_12372_amd/csrc/qqmc_adapt.h",
                   "paper_2002_12372_amd/csrc/qqmc_gf.h",
                   "paper_2002_12372_amd/csrc/qqmc_internal.h",
                   "paper_2002_12372_amd/csrc/qqmc_api.cpp"]
@@ -198,6 +202,10 @@ def run_plain(args):
     if not args.no_cpu and alpha == 0.0 and not args.sobol:
         out["cpu_baseline"] = cpu_baseline(n, args.log2n, job.lattice_a, job.shifts,
                                            args.cpu_sample)
+    if not args.no_serving and alpha == 0.0 and not args.sobol and n == 8:
+        # the metric's second half: p99 sweep latency of the serving trace,
+        # served by continuous batching and by plain launches
+        out["serving"] = serving_measure(args)[0]
     print(json.dumps(out), flush=True)
 
 
@@ -262,9 +270,12 @@ def run_batched(args):
     }), flush=True)
 
 
-def run_serving(args):
+def serving_measure(args):
     """Poisson sweep requests through the continuous-batching server, then the
-    same trace through one plain launch per request in arrival order."""
+    same trace through one plain launch per request in arrival order (first
+    come first served, the library's default tile length: the plain path at
+    its own best setting, whose per-shift sums the served results equal bit
+    for bit).  Returns the figures as a dict."""
     import numpy as np
     import torch
     from paper_2002_12372_amd import qqmc
@@ -296,7 +307,6 @@ def run_serving(args):
 
     lat_s, span_s, done = serve(1.0)
     print("served %d requests in %.2f s" % (len(trace), span_s), file=sys.stderr, flush=True)
-    # plain: one launch per request, first come first served
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     lat_p = []
@@ -310,8 +320,7 @@ def run_serving(args):
         tb = qqmc.make_tables(r.dot)
         K = r.job.shifts.shape[0]
         buf = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
-        qqmc.eval_order_async(tb, r.job, 10.0, buf, None,
-                              tile_len=min(qqmc.SERVER_TILE_LEN, 1 << r.job.log2_n), stream=stream)
+        qqmc.eval_order_async(tb, r.job, 10.0, buf, None, tile_len=0, stream=stream)
         h = buf.cpu().numpy()
         q = (h[0::2] + 1j * h[1::2]) / (1 << r.job.log2_n)
         te = time.perf_counter()
@@ -319,24 +328,40 @@ def run_serving(args):
         lat_p.append(te - t0 - r.arrival_s)
         same = same and np.array_equal(q, done[i]["q_shift"])
     span_p = time.perf_counter() - t0
+    print("plain launches: %d requests in %.2f s" % (len(trace), span_p), file=sys.stderr,
+          flush=True)
     lat_p = np.array(lat_p)
     capacity = len(trace) / busy
     out = {
-        "metric": "p99 sweep latency (served), s",
-        "value": float(np.percentile(lat_s, 99)), "unit": "s", "n_gpus": 1,
-        "higher_is_better": False, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "Poisson %.0f req/s, %d requests: eps_d~U[-3,3], Gamma~U[.5,2], "
-                               "V~U[0,1], n~U{2..12}, N=2^k k~U{14..22}, 16 shifts, beta=20, t=10"
-                               % (args.rate, args.requests),
-                   "slots": args.slots, "budget_gb": args.budget_gb},
-        "served": {"p50_s": float(np.percentile(lat_s, 50)), "p99_s": float(np.percentile(lat_s, 99)),
-                   "makespan_s": span_s, "points_per_s": sum(pts) / span_s},
+        "workload": "Poisson %.0f req/s, %d requests: eps_d~U[-3,3], Gamma~U[.5,2], "
+                    "V~U[0,1], n~U{2..12}, N=2^k k~U{14..22}, 16 shifts, beta=20, t=10"
+                    % (args.rate, args.requests),
+        "slots": args.slots, "budget_gb": args.budget_gb,
+        "p50_s": float(np.percentile(lat_s, 50)), "p99_s": float(np.percentile(lat_s, 99)),
+        "makespan_s": span_s, "points_per_s": sum(pts) / span_s,
         "plain_per_request": {"p50_s": float(np.percentile(lat_p, 50)),
                               "p99_s": float(np.percentile(lat_p, 99)),
                               "makespan_s": span_p, "points_per_s": sum(pts) / span_p,
                               "busy_s": busy},
         "capacity_req_per_s_estimate": capacity,
         "results_bitwise_equal_served_vs_plain": bool(same),
+    }
+    return out, serve, trace, capacity
+
+
+def run_serving(args):
+    import numpy as np
+    sv, serve, trace, capacity = serving_measure(args)
+    out = {
+        "metric": "p99 sweep latency (served), s",
+        "value": sv["p99_s"], "unit": "s", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": sv["workload"], "slots": sv["slots"],
+                   "budget_gb": sv["budget_gb"]},
+        "served": {k: sv[k] for k in ("p50_s", "p99_s", "makespan_s", "points_per_s")},
+        "plain_per_request": sv["plain_per_request"],
+        "capacity_req_per_s_estimate": capacity,
+        "results_bitwise_equal_served_vs_plain": sv["results_bitwise_equal_served_vs_plain"],
     }
     if args.find_capacity > 0:
         # bisection on the arrival rate: a rate is sustained when the queue
@@ -515,6 +540,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="plain workload: skip the serving trace (p99 sweep latency)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes first (a reference "
                          "for hardware byte counters)")

@@ -343,11 +343,12 @@ void qqmc_plan_destroy(qqmc_plan p);
  * in hbm_budget_bytes and a slot is free, keeps tables and partial sums on
  * the device, and launches batches that mix the pending tiles of every
  * admitted request (continuous batching: requests that arrive while others
- * run join the next batch).  A request is cut into tiles of
- * min(QQMC_SERVER_TILE_LEN, N) lattice indices, and its per-shift sums are
- * the same, bit for bit, as those of qqmc_eval_order_async on the same input
- * with that tile_len. */
-#define QQMC_SERVER_TILE_LEN 256
+ * run join the next batch).  A request is cut into the tiles that
+ * qqmc_eval_order uses by default (tile_len 0), and its per-shift sums are
+ * the same, bit for bit, as those of qqmc_eval_order on the same input.
+ * A launch first takes whole every admitted request that fits in a quarter
+ * of its cost budget, then contiguous tile ranges of the oldest requests
+ * (first come, first served). */
 typedef struct qqmc_server_s *qqmc_server;
 
 /* max_slots: requests resident at once; batch_tiles: tiles per launch

@@ -46,20 +46,25 @@ struct ItemDesc {
 constexpr double kPairDiagonal = 0.05;
 inline bool needs_pair(double g0y) { return g0y < kPairDiagonal && g0y > -kPairDiagonal; }
 
-/* Batched-kernel selector of an item, 1 .. 8 QQMC_MAX_ORDER: its order,
+/* Batched-kernel selector of an item, 1 .. 16 QQMC_MAX_ORDER: its order,
  * plus QQMC_MAX_ORDER when it runs the paired elimination tree, plus
- * 2 QQMC_MAX_ORDER for the current, plus 4 QQMC_MAX_ORDER on Sobol' points. */
+ * 2 QQMC_MAX_ORDER for the current, plus 4 QQMC_MAX_ORDER on Sobol' points,
+ * plus 8 QQMC_MAX_ORDER through a learned second warp (the charge only): a
+ * batched kernel carries only its own variant, because a kernel holding
+ * both warps measured about 2% slower on the exponential warp's tiles. */
 inline int32_t kernel_key(const ItemDesc &d)
 {
     return d.order + (needs_pair(d.g0y) ? QQMC_MAX_ORDER : 0) +
            (d.mode == QQMC_MODE_CURRENT ? 2 * QQMC_MAX_ORDER : 0) +
-           (d.sobol_points ? 4 * QQMC_MAX_ORDER : 0);
+           (d.sobol_points ? 4 * QQMC_MAX_ORDER : 0) +
+           (d.model_cdf ? 8 * QQMC_MAX_ORDER : 0);
 }
-constexpr int32_t kMaxKernelKey = 8 * QQMC_MAX_ORDER;
+constexpr int32_t kMaxKernelKey = 16 * QQMC_MAX_ORDER;
 inline int32_t key_order(int32_t key) { return (key - 1) % QQMC_MAX_ORDER + 1; }
 inline bool key_pair(int32_t key) { return ((key - 1) / QQMC_MAX_ORDER) & 1; }
 inline bool key_current(int32_t key) { return ((key - 1) / (2 * QQMC_MAX_ORDER)) & 1; }
-inline bool key_sobol(int32_t key) { return (key - 1) / (4 * QQMC_MAX_ORDER) == 1; }
+inline bool key_sobol(int32_t key) { return ((key - 1) / (4 * QQMC_MAX_ORDER)) & 1; }
+inline bool key_model(int32_t key) { return (key - 1) / (8 * QQMC_MAX_ORDER) == 1; }
 
 /* Entry of the batched tile list: which item, which tile of it. */
 struct TileRef {

@@ -829,22 +829,18 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(En
  * (A work queue fed by a lane-0 atomic was tried first: the compiler
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
-template <int N, bool PAIR, bool CUR = false, bool SOB = false>
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
 __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
                                                             const TileRef *__restrict__ tiles,
                                                             int64_t n_tiles)
 {
+    static_assert(!(CUR && MODEL), "the learned warp serves the charge");
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
         /* by value: the descriptor lives in registers for the whole tile */
         const ItemDesc it = items[ref.item];
-        cplx v;
-        if constexpr (CUR)
-            v = order_tile<N, false, false, PAIR, true, SOB>(it, ref.tile, lds);
-        else
-            v = it.model_cdf ? order_tile<N, true, false, PAIR, false, SOB>(it, ref.tile, lds)
-                             : order_tile<N, false, false, PAIR, false, SOB>(it, ref.tile, lds);
+        const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;
             it.tile_sums[2 * ref.tile + 1] = v.y;
@@ -904,21 +900,22 @@ hipError_t go_points_tree(Env env, const double *u, int64_t n_points, double *f,
     return hipGetLastError();
 }
 
-template <int N, bool PAIR, bool CUR = false, bool SOB = false>
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
 hipError_t go_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
                     int32_t grid_blocks, hipStream_t s)
 {
     const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
-    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB>), dim3((unsigned)g), dim3(64),
+    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB, MODEL>), dim3((unsigned)g), dim3(64),
                        (Lds<N, PAIR, CUR, SOB>::bytes), s, items_dev, tiles_dev, n_tiles);
     return hipGetLastError();
 }
 
-template <int N, bool PAIR, bool CUR = false, bool SOB = false> int32_t occ_batch()
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
+int32_t occ_batch()
 {
     int blocks = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &blocks, batch_kernel<N, PAIR, CUR, SOB>, 64, (size_t)Lds<N, PAIR, CUR, SOB>::bytes);
+        &blocks, batch_kernel<N, PAIR, CUR, SOB, MODEL>, 64, (size_t)Lds<N, PAIR, CUR, SOB>::bytes);
     return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 
@@ -967,6 +964,10 @@ hipError_t launch_batch_sobol_charge(int32_t order, bool pair, const ItemDesc *i
                                      const TileRef *tiles_dev, int64_t n_tiles,
                                      int32_t grid_blocks, hipStream_t s);
 int32_t batch_blocks_per_cu_sobol_charge(int32_t order, bool pair);
+hipError_t launch_batch_model(int32_t order, bool pair, bool sobol, const ItemDesc *items_dev,
+                              const TileRef *tiles_dev, int64_t n_tiles, int32_t grid_blocks,
+                              hipStream_t s);
+int32_t batch_blocks_per_cu_model(int32_t order, bool pair, bool sobol);
 
 } // namespace qqmc
 

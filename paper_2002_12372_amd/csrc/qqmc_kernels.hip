@@ -342,6 +342,9 @@ hipError_t launch_batch(int32_t key, const ItemDesc *items_dev, const TileRef *t
                         int64_t n_tiles, int32_t grid_blocks, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
+    if (key_model(key))
+        return launch_batch_model(key_order(key), key_pair(key), key_sobol(key), items_dev,
+                                  tiles_dev, n_tiles, grid_blocks, s);
     if (key_sobol(key))
         return launch_batch_sobol(key_order(key), key_pair(key), key_current(key), items_dev,
                                   tiles_dev, n_tiles, grid_blocks, s);
@@ -355,6 +358,8 @@ hipError_t launch_batch(int32_t key, const ItemDesc *items_dev, const TileRef *t
 
 int32_t batch_blocks_per_cu(int32_t key)
 {
+    if (key_model(key))
+        return batch_blocks_per_cu_model(key_order(key), key_pair(key), key_sobol(key));
     if (key_sobol(key))
         return batch_blocks_per_cu_sobol(key_order(key), key_pair(key), key_current(key));
     if (key_current(key)) return batch_blocks_per_cu_current(key_order(key), key_pair(key));

@@ -9,14 +9,14 @@
  *               are built on the device by a kernel, per-request buffers
  *               come from the stream-ordered allocator, all on an admission
  *               stream, so admission never waits for the GPU;
- *   batching    every launch is one persistent kernel of one order (and
- *               elimination tree: scalar, or paired for a vertex diagonal
- *               near zero); it
- *               rotates over the kernels with pending work, and the
- *               admitted requests of that kernel take tiles in turn (round
- *               robin, up to a per-launch cost budget), so requests that
- *               arrive while others run share the next launches;
- *   overlap     three launches are in flight on three streams, so the tail of
+ *   batching    a launch takes, up to a cost budget, first the whole of
+ *               every admitted request small enough to finish in it, then
+ *               contiguous tile ranges of the oldest requests (first come
+ *               first served), so requests that arrive while others run
+ *               share the next launches; its tiles run as one batched
+ *               kernel per kernel key (order, elimination tree,
+ *               observable, point set);
+ *   overlap     two launches are in flight on two streams, so the tail of
  *               one launch overlaps the next and the host prepares launches
  *               while the GPU runs;
  *   completion  when every tile of a request is done, its per-shift sums are
@@ -24,9 +24,9 @@
  *               and its device buffers are returned to the pool.
  * Green's-function tables stay on the device, shared by requests with the
  * same dot parameters (reference counted; unused ones are evicted first when
- * memory runs short).  Tiles are the same as qqmc_eval_order_async's for the
- * server's tile length, so every result equals the solo evaluation bit for
- * bit, alone or in the mix.
+ * memory runs short).  A request is cut into the tiles qqmc_eval_order
+ * uses by default, so every result equals the plain evaluation bit for bit,
+ * alone or in the mix.
  */
 #include <algorithm>
 #include <chrono>
@@ -46,7 +46,10 @@
 namespace qqmc {
 namespace {
 
-constexpr int kSlots = 3;
+/* launches in flight: two keep the GPU fed across launch boundaries;
+ * three measured 2% slower (kernels of different orders then contend for
+ * the compute units), one leaves gaps */
+constexpr int kSlots = 2;
 
 struct TableEntry {
     qqmc_tables t = nullptr;
@@ -116,7 +119,7 @@ template <typename T> hipError_t grow_pair(T **h, T **d, size_t *cap, size_t nee
 
 struct qqmc_server_s {
     size_t budget = 0, used = 0;
-    int32_t max_slots = 1, tile_len = QQMC_SERVER_TILE_LEN;
+    int32_t max_slots = 1;
     double launch_cost = 0.0;
     int device = 0, n_cu = 1;
     hipStream_t admit_stream = nullptr;
@@ -128,7 +131,6 @@ struct qqmc_server_s {
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1, use_clock = 0, next_seq = 1;
-    int last_key = 0;
     std::deque<std::shared_ptr<qqmc::Request>> waiting;
     std::vector<std::shared_ptr<qqmc::Request>> active;
     std::map<uint64_t, std::shared_ptr<qqmc::Request>> all;
@@ -249,45 +251,58 @@ void admit(qqmc_server_s *s)
 }
 
 /* Fills and submits launch slot L with tiles of the active requests (lock
- * held).  Returns false if there was nothing to issue. */
+ * held).  Returns false if there was nothing to issue.  Tiles are taken in
+ * two passes over the admitted requests, in admission order, up to the cost
+ * budget of a launch:
+ *   1. a request whose remaining work fits in a quarter of the budget is
+ *      taken whole, so the many small requests of a sweep finish in the next
+ *      launch instead of queueing behind large ones;
+ *   2. the oldest requests' remaining tiles then fill the budget as
+ *      contiguous ranges, at least enough tiles of a kernel to give every
+ *      resident workgroup eight (so a launch fills the GPU), first come first
+ *      served: completion follows arrival order, which bounds the tail
+ *      latency, and a launch reads few tables at a time.
+ * The tiles are grouped by kernel key (order, tree, observable, point set):
+ * one batched launch per key, in sequence on the slot's stream; the other
+ * slots' launches overlap them. */
 bool issue(qqmc_server_s *s, Launch &L)
 {
-    /* one kernel key (order, paired tree) per launch, rotating over the keys
-     * with pending tiles, so every launch is one full persistent kernel;
-     * inside the key, requests in admission order take one tile each per
-     * pass up to the cost budget */
-    bool pending[kMaxKernelKey + 1] = {};
-    for (auto &r : s->active)
-        if (r->next_tile < r->desc.n_tiles) pending[kernel_key(r->desc)] = true;
-    int key = 0;
-    for (int k = 1; k <= kMaxKernelKey && !key; ++k) {
-        const int n = (s->last_key + k - 1) % kMaxKernelKey + 1;
-        if (pending[n]) key = n;
-    }
-    if (!key) return false;
-    s->last_key = key;
-    std::vector<std::shared_ptr<Request>> open;
-    for (auto &r : s->active)
-        if (kernel_key(r->desc) == key && r->next_tile < r->desc.n_tiles) open.push_back(r);
-    std::vector<double> cost(open.size());
-    std::vector<int64_t> take(open.size(), 0);
-    for (size_t i = 0; i < open.size(); ++i) cost[i] = tile_cost(open[i]->desc);
-    /* at least eight tiles per resident workgroup, so the launch fills the
-     * GPU and its last round of tiles is short */
-    const int64_t min_tiles = 8 * (int64_t)s->n_cu * batch_blocks_per_cu(key);
+    const size_t na = s->active.size();
+    std::vector<int64_t> take(na, 0);
+    const double budget = s->launch_cost;
     double spent = 0.0;
-    int64_t taken = 0;
-    bool progress = true;
-    while (progress && (spent < s->launch_cost || taken < min_tiles)) {
-        progress = false;
-        for (size_t i = 0; i < open.size() && (spent < s->launch_cost || taken < min_tiles); ++i) {
-            if (open[i]->next_tile + take[i] < open[i]->desc.n_tiles) {
-                take[i] += 1;
-                spent += cost[i];
-                taken += 1;
-                progress = true;
-            }
+    for (size_t i = 0; i < na && spent < budget; ++i) {
+        const Request &r = *s->active[i];
+        const int64_t left = r.desc.n_tiles - r.next_tile;
+        if (left <= 0) continue;
+        const double c = tile_cost(r.desc) * (double)left;
+        if (c <= 0.25 * budget && spent + c <= budget) {
+            take[i] = left;
+            spent += c;
         }
+    }
+    for (size_t i = 0; i < na && spent < budget; ++i) {
+        const Request &r = *s->active[i];
+        const int64_t left = r.desc.n_tiles - r.next_tile - take[i];
+        if (left <= 0) continue;
+        const double tc = tile_cost(r.desc);
+        const int64_t fill = 8 * (int64_t)s->n_cu * batch_blocks_per_cu(kernel_key(r.desc));
+        int64_t k = tc > 0.0 ? (int64_t)std::ceil((budget - spent) / tc) : left;
+        k = std::min(left, std::max(k, fill));
+        take[i] += k;
+        spent += tc * (double)k;
+    }
+    bool any = false;
+    for (size_t i = 0; i < na; ++i) any = any || take[i] > 0;
+    if (!any) return false;
+    std::vector<std::shared_ptr<Request>> open;
+    for (size_t i = 0; i < na; ++i)
+        if (take[i]) open.push_back(s->active[i]);
+    {
+        std::vector<int64_t> t2;
+        for (size_t i = 0; i < na; ++i)
+            if (take[i]) t2.push_back(take[i]);
+        take.swap(t2);
     }
     std::vector<ItemDesc> items;
     std::vector<std::vector<TileRef>> by(kMaxKernelKey + 1);
@@ -491,7 +506,6 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     if (!s) return set_error(QQMC_ENOMEM, "host allocation failed");
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
-    s->tile_len = QQMC_SERVER_TILE_LEN;
     hipGetDevice(&s->device);
     hipError_t e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming);
@@ -508,13 +522,14 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     hipDeviceProp_t prop;
     hipGetDeviceProperties(&prop, s->device);
     s->n_cu = prop.multiProcessorCount;
-    /* cost budget of one launch: enough order-8 tiles (or batch_tiles tiles)
-     * to give every resident workgroup about sixteen (a few milliseconds) */
+    /* cost budget of one launch: enough order-8 tiles of 256 indices (or
+     * batch_tiles of them) to give every resident workgroup about sixteen
+     * (a few milliseconds) */
     ItemDesc ref;
     std::memset(&ref, 0, sizeof(ref));
     ref.order = 8;
     ref.mode = QQMC_MODE_CHARGE;
-    ref.tile_len = QQMC_SERVER_TILE_LEN;
+    ref.tile_len = 256;
     ref.t_meas = 10.0;
     ref.tau = 1.0;
     const int32_t bt = batch_tiles ? batch_tiles : 16 * s->n_cu * batch_blocks_per_cu(8);
@@ -543,7 +558,9 @@ qqmc_status qqmc_submit(qqmc_server s, const qqmc_dot *dot, const qqmc_order *or
     r->shifts = v.shifts;
     r->sobol = v.sobol;
     const int64_t N = (int64_t)v.desc.mask + 1;
-    r->desc.tile_len = (int32_t)std::min<int64_t>(s->tile_len, N);
+    /* the tile length qqmc_eval_order takes by default, so that served
+     * results equal the plain evaluation bit for bit */
+    r->desc.tile_len = default_tile_len(r->desc, N);
     r->desc.tiles_per_shift = (int32_t)(N / r->desc.tile_len);
     r->desc.n_tiles = (int64_t)r->desc.tiles_per_shift * r->desc.n_shifts;
     r->key = TableKey(dot->eps_d, dot->gamma, dot->beta, dot->bias_v, dot->t_half, dot->n_grid,

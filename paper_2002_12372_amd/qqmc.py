@@ -21,7 +21,6 @@ MODE_CHARGE, MODE_MODEL, MODE_CONSTANT, MODE_CURRENT = 0, 1, 2, 3
 OBS_CHARGE, OBS_CURRENT = 0, 1
 METHOD_TREE, METHOD_DIRECT = 0, 1
 MAX_ORDER = 14
-SERVER_TILE_LEN = 256   # QQMC_SERVER_TILE_LEN
 
 
 class QQMCError(RuntimeError):

@@ -203,7 +203,7 @@ def test_alpha_server_bitwise(q):
     assert len(out) == 2
     gt = q.make_tables(TINY_DOT)
     for t, job in zip(tickets, jobs):
-        assert np.array_equal(out[t]["q_shift"], _solo(q, gt, job, q.SERVER_TILE_LEN))
+        assert np.array_equal(out[t]["q_shift"], _solo(q, gt, job, 0))
     assert not np.array_equal(out[tickets[0]]["q_shift"], out[tickets[1]]["q_shift"])
     srv.close()
 

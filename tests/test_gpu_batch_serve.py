@@ -96,7 +96,7 @@ def test_server_results_equal_solo_runs(q):
     assert len(out) == len(tickets)
     for t, r in zip(tickets, trace):
         tb = q.make_tables(r.dot)
-        ref = _solo(q, tb, r.job, q.SERVER_TILE_LEN)
+        ref = _solo(q, tb, r.job, 0)
         assert np.array_equal(out[t]["q_shift"], ref)
         assert out[t]["t_done"] >= out[t]["t_submit"]
     with pytest.raises(q.QQMCError):
@@ -129,4 +129,69 @@ def test_server_admission_and_alone_vs_mix(q):
         tiny.poll(12345)
     assert e.value.status == q.ENOTICKET
     tiny.close()
+    srv.close()
+
+
+def _c4_draws():
+    """16 requests from the serving ranges (eps_d in [-3, 3], Gamma in
+    [0.5, 2], V in [0, 1], beta = 20), orders 2..12, the corners of slow
+    decay (Gamma = 0.5, |eps_d| = 3, where n_sigma is near 0.05 or 0.95)
+    first; lattices of 2^10..2^12 points."""
+    rng = np.random.default_rng(404)
+    fixed = [(3.0, 0.5, 0.0), (-3.0, 0.5, 1.0), (2.9, 0.5, 0.6), (3.0, 2.0, 1.0)]
+    out = []
+    for i in range(16):
+        if i < len(fixed):
+            e, g, v = fixed[i]
+        else:
+            e, g, v = rng.uniform(-3, 3), rng.uniform(0.5, 2.0), rng.uniform(0, 1)
+        n = 2 + (i * 7) % 11
+        log2_n = 12 if n <= 6 else (11 if n <= 9 else 10)
+        K = 4 if n <= 9 else 2
+        out.append((Dot(float(e), float(g), 20.0, float(v)), order_job(900 + i, n, log2_n, K)))
+    return out
+
+
+def test_server_against_oracle_over_serving_ranges(q, oracle_mod):
+    """Every per-shift Q of 16 served requests drawn from the serving ranges.
+    The served results equal, bit for bit, the plain evaluation on the
+    library's tables; the plain evaluation on the oracle's own tables (the
+    same inputs) matches the oracle to 1e-9 relative, plus one tenth of the
+    FP64 unit roundoff of the per-point term mass M (1e-17 M): some draws
+    cancel by up to eleven orders of magnitude (|Q| / M = 1e-11 at order 11
+    with eps_d = -2.8), where the oracle's own sum of 2^n pivoted-LU terms
+    carries rounding of about 3e-19 M (2e-8 of Q against a long-double
+    evaluation of the same sum, the tree 20 times closer), while a wrong or
+    missing term would move Q by a sizeable fraction of M.  This covers the
+    elimination tree without pivoting over the whole parameter range.  The
+    served results against the oracle on its own tables (the two table
+    builders agree to about 1e-13, not bit for bit) are printed."""
+    draws = _c4_draws()
+    srv = q.Server(hbm_budget_bytes=1 << 30, max_slots=6)
+    tickets = [srv.submit(d, job, T_MEAS) for d, job in draws]
+    srv.drain()
+    worst_tree, worst_served, floor_used, cmp = 0.0, 0.0, 0, 0
+    for t, (d, job) in zip(tickets, draws):
+        served = srv.poll(t)["q_shift"]
+        n, l2 = job.order, job.log2_n
+        tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+        qo, _, _ = oracle_mod.eval_order(tb, T_MEAS, n, l2, job.lattice_a, job.shifts, 1.0)
+        mass = oracle_mod.eval_mass(tb, T_MEAS, n, l2, job.lattice_a, job.shifts, 1.0)
+        up = q.tables_from_host(tb.gl, tb.gg, tb.n_grid, tb.t_half, tb.n_sigma)
+        plain_or = _solo(q, up, job, 0)
+        plain_lib = _solo(q, q.make_tables(d), job, 0)
+        assert np.array_equal(served, plain_lib), (d, n)
+        for s in range(len(qo)):
+            m = mass[s] / (1 << l2)
+            e_tree = abs(plain_or[s] - qo[s])
+            worst_tree = max(worst_tree, e_tree / abs(qo[s]))
+            worst_served = max(worst_served, abs(served[s] - qo[s]) / abs(qo[s]))
+            cmp += 1
+            floor_used += e_tree > 1e-9 * abs(qo[s]) + 1e-15
+            assert e_tree <= 1e-9 * abs(qo[s]) + 1e-17 * m + 1e-15, \
+                ("tree", d, n, s, plain_or[s], qo[s], m)
+    print("serving ranges: tree on the oracle's tables worst relative error %.2e (%d of %d "
+          "comparisons beyond 1e-9 relative, within 1e-17 of the term mass); served against "
+          "the oracle on its own tables worst relative difference %.2e"
+          % (worst_tree, floor_used, cmp, worst_served))
     srv.close()

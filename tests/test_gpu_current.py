@@ -308,7 +308,7 @@ def test_current_server_equals_solo_runs(q):
         key = (d.eps_d, d.beta, d.lead)
         if key not in cache:
             cache[key] = q.make_tables(d)
-        assert np.array_equal(out[t]["q_shift"], _solo(q, cache[key], job, q.SERVER_TILE_LEN))
+        assert np.array_equal(out[t]["q_shift"], _solo(q, cache[key], job, 0))
     with pytest.raises(q.QQMCError):           # the current needs a dot with a lead
         srv.submit(Dot(0.3, 1.0, 2.0, 0.8, T, 4001, T, 4.0, 0),
                    order_job(99, 3, 10, 2, mode=q.MODE_CURRENT), T)

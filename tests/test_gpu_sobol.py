@@ -181,7 +181,7 @@ def test_sobol_server_equals_solo_runs(q):
     assert len(out) == len(tickets)
     tabs = [q.make_tables(d) for d in dots]
     for i, (t, (d, job)) in enumerate(zip(tickets, reqs)):
-        assert np.array_equal(out[t]["q_shift"], _solo(q, tabs[i % 2], job, q.SERVER_TILE_LEN))
+        assert np.array_equal(out[t]["q_shift"], _solo(q, tabs[i % 2], job, 0))
     srv.close()
 
 

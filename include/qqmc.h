@@ -226,6 +226,23 @@ qqmc_status qqmc_eval_order_async(qqmc_tables t, const qqmc_order *ord,
                                   double *tile_sums, double *shift_sums,
                                   int64_t *n_tiles_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): the estimate of
+ * qqmc_eval_order_async without per-tile output and without any device
+ * allocation.  The per-call device data (shifts, Sobol' numbers, the
+ * per-tile partial sums, 16 bytes per tile, and the reduction's descriptor)
+ * lives in a static device array of QQMC_NOALLOC_SCRATCH_BYTES that each
+ * device holds from its first call until the process ends.  EINVAL if a call
+ * needs more (pass a longer tile_len); otherwise as qqmc_eval_order_async,
+ * whose per-shift sums it reproduces bit for bit for the same tile_len.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other threads) race and must be serialised by
+ * the caller.  shift_sums: device, 2*n_shifts doubles, as above. */
+#define QQMC_NOALLOC_SCRATCH_BYTES (4u << 20)
+qqmc_status qqmc_eval_order_noalloc(qqmc_tables t, const qqmc_order *ord,
+                                    int32_t tile_len, void *stream,
+                                    double *shift_sums, int64_t *n_tiles_out);
+
 /* Per-point integrand f_n(u) = -2 i^{n+1} S(u) of Eq. (integral_gf) (the
  * integrand of Q_n over the ordered simplex, without warping weight).
  *   alpha   interaction shift, as in qqmc_order (finite)

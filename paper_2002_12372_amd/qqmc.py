@@ -77,6 +77,7 @@ SIGNATURES = [
     ("qqmc_free_tables", None, [_vp]),
     ("qqmc_eval_order", _i32, [_vp, _P(qqmc_order), _vp, _PD, _PD, _PD]),
     ("qqmc_eval_order_async", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _vp, _P(_i64)]),
+    ("qqmc_eval_order_noalloc", _i32, [_vp, _P(qqmc_order), _i32, _vp, _vp, _P(_i64)]),
     ("qqmc_eval_points", _i32, [_vp, _i32, _d, _d, _i32, _vp, _i64, _i32, _vp, _vp, _vp]),
     ("qqmc_lead_tables_compute_host", _i32, [_P(qqmc_dot), _PD, _PD]),
     ("qqmc_tables_lead_from_host", _i32, [_vp, _PD, _PD]),
@@ -301,6 +302,18 @@ def eval_order_async(tables, job, t_meas, shift_sums, tile_sums=None, tile_len=0
     _check(lib().qqmc_eval_order_async(
         tables.handle, ctypes.byref(o), int(tile_len), _stream(stream),
         ctypes.c_void_p(tile_sums.data_ptr() if tile_sums is not None else 0),
+        ctypes.c_void_p(shift_sums.data_ptr()), ctypes.byref(nt)))
+    return nt.value
+
+
+def eval_order_noalloc(tables, job, t_meas, shift_sums, tile_len=0, stream=None, model=None):
+    """qqmc_eval_order_noalloc: the per-shift sums of eval_order_async into
+    shift_sums (float64 CUDA tensor, 2*K), with no device allocation (the
+    library's static per-device scratch).  Returns the number of tiles."""
+    o = make_order(job, t_meas, model)
+    nt = ctypes.c_int64()
+    _check(lib().qqmc_eval_order_noalloc(
+        tables.handle, ctypes.byref(o), int(tile_len), _stream(stream),
         ctypes.c_void_p(shift_sums.data_ptr()), ctypes.byref(nt)))
     return nt.value
 

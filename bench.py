@@ -64,6 +64,28 @@ def inside_fraction(n, t_over_tau):
     return float(gammainc(n, t_over_tau))
 
 
+def counted_inside_fraction(job, t_meas, tau):
+    """Fraction of the job's lattice points inside the domain (u_n > 0),
+    counted on the host with the kernel's arithmetic: m = i a^j mod N,
+    y = m / N + shift (minus 1 past 1), v = -tau log1p(-y), u_j = u_{j-1} - v
+    in sequence.  (The host's log1p may differ from the device's in the last
+    place, which can move only points within about 1e-15 of the boundary.)"""
+    import numpy as np
+    n, N = job.order, 1 << job.log2_n
+    z = [pow(int(job.lattice_a), j, N) for j in range(n)]
+    idx = np.arange(N, dtype=np.uint64)
+    inside = 0
+    for s in range(job.shifts.shape[0]):
+        u = np.full(N, float(t_meas))
+        for j in range(n):
+            m = (idx * np.uint64(z[j])) & np.uint64(N - 1)
+            y = m.astype(np.float64) / N + job.shifts[s, j]
+            y[y >= 1.0] -= 1.0
+            u -= -tau * np.log1p(-y)
+        inside += int(np.count_nonzero(u > 0.0))
+    return inside / (N * job.shifts.shape[0])
+
+
 def cpu_baseline(order, log2_n, lattice_a, shifts, count):
     import oracle
     from qqmc_inputs import TINY_DOT as d
@@ -161,7 +183,8 @@ def run_plain(args):
     wall, launch_ms = timed_steps(step, args.steps, args.warmup, stream)
     ms_per_step = wall * 1e3 / args.steps
     value = points * args.steps / wall
-    frac_in = inside_fraction(n, d.t_meas / job.model_tau)
+    frac_model = inside_fraction(n, d.t_meas / job.model_tau)
+    frac_in = frac_model if args.sobol else counted_inside_fraction(job, d.t_meas, job.model_tau)
     alg_flops = points * (frac_in * tflops + warp_flops(n))
     avg_launch_s = sum(launch_ms) / len(launch_ms) * 1e-3
     achieved = alg_flops / avg_launch_s / 1e12
@@ -192,6 +215,9 @@ def run_plain(args):
                                   else "Korobov lattice", args.log2n, args.shifts, tau),
                    "order": n, "lattice_points": N, "shifts": args.shifts,
                    "inside_fraction": frac_in,
+                   "inside_fraction_source": "model P(n, t/tau)" if args.sobol
+                                             else "counted over the lattice",
+                   "inside_fraction_model": frac_model,
                    "inside_points_per_s": value * frac_in},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,

@@ -342,6 +342,9 @@ typedef struct qqmc_plan_s *qqmc_plan;
  * model and constant modes, and the current (whose tables must hold lead
  * functions), on the lattice or on Sobol' points, with or without a learned
  * warp (not for the current). */
+/* stream: the plan's own work (uploads, autotuning probes) is ordered after
+ * everything queued on it so far, e.g. the tables' construction; replays and
+ * result reads must come on streams ordered after the tables too. */
 qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items,
                              int32_t tile_len, int32_t grid_blocks,
                              void *stream, qqmc_plan *out);

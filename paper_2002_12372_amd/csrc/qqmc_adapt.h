@@ -49,9 +49,10 @@
 
 namespace qqmc {
 
-/* A pair step of the register tree whose growth bound exceeds this is
- * redone by the adaptive path. */
-constexpr double kGrowthFlag = 16.0;
+/* A point of the register tree whose pair steps' growth bound exceeds this
+ * is evaluated again with the shifted grouping, and if that grows beyond it
+ * too, by the adaptive path. */
+constexpr double kGrowthFlag = 64.0;
 /* The adaptive path takes a single-vertex step when its growth bound stays
  * below this at every node of the level. */
 constexpr double kGrowthSingle = 4.0;

@@ -41,6 +41,12 @@ namespace qqmc {
 namespace {
 
 constexpr int WAVE = 64;
+/* Workgroup size of every kernel that exchanges data through local memory
+ * with wave_sync (the tree kernels and the adaptive path): one wavefront,
+ * so that its local-memory operations execute in program order.  Their
+ * __launch_bounds__ and their launches both take it from here. */
+constexpr int WG_TREE = WAVE;
+static_assert(WG_TREE == WAVE, "the tree kernels run one wavefront per workgroup");
 
 template <int N, bool PAIR = false, bool CUR = false, bool SOB = false> struct Lds {
     using Gm = Geo<N, PAIR>;
@@ -372,6 +378,39 @@ __device__ __attribute__((noinline)) cplx adapt_point(const pairv *pr, const pai
     return adapt_eval<CUR, MB>(x, a, S, m, k, w0);
 }
 
+__device__ __forceinline__ cplx shfl_cplx(cplx v, int src)
+{
+    return cmk(__shfl(v.x, src, WAVE), __shfl(v.y, src, WAVE));
+}
+
+struct ShiftOut {
+    cplx v;
+    double grow;
+};
+
+/* One lane's share (8 lanes per point or item) of the shifted grouping
+ * (lane_sum_shift): from the whole matrix for orders up to 8 (pair, then
+ * single vertex), from an item's cooperative block c0 above (single vertex,
+ * then pair), with the item's top product and index parity.  Not inlined:
+ * it runs for the few flagged points, and as a function its registers stay
+ * out of the main tree's allocation. */
+template <int N, bool CUR>
+__device__ __attribute__((noinline)) ShiftOut shift_lane(const pairv *pr, const pairv *mc,
+                                                         const cplx *c0, int pre, int top,
+                                                         cplx g0, cplx prod)
+{
+    BlockSrc<N, true> src;
+    src.c = c0;
+    ShiftOut o;
+    o.grow = 0.0;
+    if constexpr (Geo<N, true>::OFF == 0)
+        o.v = lane_sum_shift<N, CUR, 2, 1>(pr, mc, src, pre, prod, 0, g0, o.grow);
+    else
+        o.v = lane_sum_shift<N, CUR, 1, 2>(pr, mc, src, pre, prod, __popc((unsigned)top) & 1, g0,
+                                           o.grow);
+    return o;
+}
+
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
 template <int N, bool PAIR = false, bool CUR = false>
@@ -472,37 +511,94 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         else s = lane_sum<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
         if constexpr (PAIR) {
             /* Points (n <= 8) or items (n > 8) whose pair steps grew beyond
-             * kGrowthFlag are evaluated again by the adaptive path; a point
-             * whose cooperative top levels grew is redone whole after its
-             * last round.  Flags, groups and results are wave-uniform. */
+             * kGrowthFlag are evaluated again with the shifted grouping
+             * (lane_sum_shift, 8 lanes each, up to 8 at a time), and those it
+             * flags too by the adaptive path; a point whose cooperative top
+             * levels grew is redone whole after its last round.  Flags,
+             * groups and results are wave-uniform. */
             constexpr double F2 = kGrowthFlag * kGrowthFlag / 4.0;
             constexpr uint64_t GM = Gm::G >= 64 ? ~0ull : ((1ull << Gm::G) - 1);
+            constexpr bool SHIFT = Gm::K >= 5 && (Gm::OFF > 0 || N >= 4);
             const uint64_t ft = __ballot(active && gtop > F2);
-            uint64_t rem = __ballot(active && (gbot > F2 || gtop > F2));
+            uint64_t fl = __ballot(active && (gbot > F2 || gtop > F2));
             if constexpr (Gm::OFF > 0) {
                 static_assert(Gm::IPP >= Gm::PPW, "a round of the paired top holds one point");
                 point_top_flag = point_top_flag || ft != 0;
-                if (point_top_flag) rem = 0;
+                if (point_top_flag) fl = 0;
             }
-            while (rem) {
-                const int g = __builtin_ctzll(rem) / Gm::G;
-                rem &= ~(GM << (g * Gm::G));
-                cplx r;
-                if constexpr (Gm::OFF == 0) {
-                    const pairv *tg = s_pairs + g * NPS;
-                    r = adapt_point<N, CUR, L::MB>(tg, tg + (CUR ? Gm::NP : pidx(0, N)), env.g0, lds + L::adapt,
-                                                    nullptr, N + 1, 0, cmk(1.0, 0.0));
-                } else {
-                    const int tg = (base + g) % Gm::IPP;
-                    cplx pg;
-                    pg.x = __shfl(prod.x, g * Gm::G, WAVE);
-                    pg.y = __shfl(prod.y, g * Gm::G, WAVE);
-                    cplx w0 = cmul(pg, pg);
-                    if (__popc((unsigned)tg) & 1) w0 = cmk(-w0.x, -w0.y);
-                    const cplx *c0g = reinterpret_cast<const cplx *>(lds + L::c0) + g * Gm::K * Gm::K;
-                    r = adapt_point<N, CUR, L::MB>(prg, mc, env.g0, lds + L::adapt, c0g, Gm::K, Gm::OFF, w0);
+            uint64_t groups = 0; /* flagged groups of the round */
+            for (int g = 0; g < Gm::PPW; ++g)
+                if ((fl >> (g * Gm::G)) & GM) groups |= 1ull << g;
+            while (groups) {
+                /* up to 8 flagged groups, one per 8-lane slot */
+                int nf = 0, mine = -1;
+                uint64_t taken = 0;
+                for (int k = 0; k < 8 && groups; ++k) {
+                    const int g = __builtin_ctzll(groups);
+                    groups &= groups - 1;
+                    taken |= 1ull << g;
+                    if ((lane >> 3) == k) mine = g;
+                    ++nf;
                 }
-                if (grp == g) s = sub == 0 ? r : cmk(0.0, 0.0);
+                (void)nf;
+                cplx r = cmk(0.0, 0.0);
+                double g2 = 0.0;
+                if constexpr (SHIFT) {
+                    /* every lane takes part in the shuffle (its source may
+                     * sit in an idle slot) */
+                    const cplx pm = shfl_cplx(prod, (mine >= 0 ? mine : 0) * Gm::G);
+                    if (mine >= 0) {
+                        const pairv *tg = Gm::OFF == 0 ? s_pairs + mine * NPS : prg;
+                        const pairv *mg = Gm::OFF == 0 ? tg + (CUR ? Gm::NP : pidx(0, N)) : mc;
+                        const cplx *c0g =
+                            Gm::OFF == 0 ? nullptr
+                                         : reinterpret_cast<const cplx *>(lds + L::c0) + mine * Gm::K * Gm::K;
+                        const ShiftOut o = shift_lane<N, CUR>(
+                            tg, mg, c0g, lane & 7, Gm::OFF == 0 ? 0 : (int)((base + mine) % Gm::IPP),
+                            env.g0, Gm::OFF == 0 ? cmk(1.0, 0.0) : pm);
+                        r = o.v;
+                        g2 = o.grow;
+                    }
+                    /* the slot's sum over its 8 lanes */
+#pragma unroll
+                    for (int m = 1; m < 8; m <<= 1) {
+                        r.x += shfl_xor_d(r.x, m);
+                        r.y += shfl_xor_d(r.y, m);
+                    }
+                } else {
+                    g2 = INFINITY;
+                }
+                const uint64_t again = __ballot(mine >= 0 && g2 > F2);
+                /* every taken group in turn: its result, from the shifted
+                 * tree or, flagged again, from the adaptive path */
+                uint64_t t = taken;
+                int k = 0;
+                while (t) {
+                    const int g = __builtin_ctzll(t);
+                    t &= t - 1;
+                    cplx rk;
+                    rk.x = __shfl(r.x, k * 8, WAVE);
+                    rk.y = __shfl(r.y, k * 8, WAVE);
+                    if ((again >> (k * 8)) & 0xffull) {
+                        if constexpr (Gm::OFF == 0) {
+                            const pairv *tg = s_pairs + g * NPS;
+                            rk = adapt_point<N, CUR, L::MB>(tg, tg + (CUR ? Gm::NP : pidx(0, N)),
+                                                             env.g0, lds + L::adapt, nullptr, N + 1,
+                                                             0, cmk(1.0, 0.0));
+                        } else {
+                            const int tg = (base + g) % Gm::IPP;
+                            const cplx pg = shfl_cplx(prod, g * Gm::G);
+                            cplx w0 = cmul(pg, pg);
+                            if (__popc((unsigned)tg) & 1) w0 = cmk(-w0.x, -w0.y);
+                            const cplx *c0g =
+                                reinterpret_cast<const cplx *>(lds + L::c0) + g * Gm::K * Gm::K;
+                            rk = adapt_point<N, CUR, L::MB>(prg, mc, env.g0, lds + L::adapt, c0g,
+                                                             Gm::K, Gm::OFF, w0);
+                        }
+                    }
+                    if (grp == g) s = sub == 0 ? rk : cmk(0.0, 0.0);
+                    ++k;
+                }
             }
         }
         /* sum over the lanes of a group, then over the groups of the round
@@ -752,7 +848,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 }
 
 template <int N, bool MODEL, bool PAIR, bool CUR = false, bool SOB = false>
-__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
+__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x) {
@@ -768,7 +864,7 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) order_kernel(ItemDesc
  * lattice (or Sobol') index of the item's tiles into it.sample_out
  * (exponential warp only, charge mode). */
 template <int N, bool PAIR, bool SOB = false>
-__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDesc it)
+__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDesc it)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t tile = blockIdx.x; tile < it.n_tiles; tile += gridDim.x)
@@ -777,7 +873,7 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) sample_kernel(ItemDes
 
 /* Production-kernel evaluation at caller-given vertex times (tree method). */
 template <int N, bool PAIR, bool CUR>
-__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(Env env, const double *u,
+__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) points_tree_kernel(Env env, const double *u,
                                                               int64_t n_points, double *f)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -830,7 +926,7 @@ __global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) points_tree_kernel(En
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
 template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
-__global__ void __launch_bounds__(64, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
+__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
                                                             const TileRef *__restrict__ tiles,
                                                             int64_t n_tiles)
 {
@@ -875,7 +971,7 @@ template <int N, bool MODEL, bool PAIR, bool CUR, bool SOB>
 hipError_t go_order(const ItemDesc &it, hipStream_t s)
 {
     const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-    hipLaunchKernelGGL((order_kernel<N, MODEL, PAIR, CUR, SOB>), dim3((unsigned)blocks), dim3(64),
+    hipLaunchKernelGGL((order_kernel<N, MODEL, PAIR, CUR, SOB>), dim3((unsigned)blocks), dim3(WG_TREE),
                        (Lds<N, PAIR, CUR, SOB>::bytes), s, it);
     return hipGetLastError();
 }
@@ -884,7 +980,7 @@ template <int N, bool PAIR, bool SOB = false>
 hipError_t go_sample(const ItemDesc &it, hipStream_t s)
 {
     const int64_t blocks = it.n_tiles < 1048576 ? it.n_tiles : 1048576;
-    hipLaunchKernelGGL((sample_kernel<N, PAIR, SOB>), dim3((unsigned)blocks), dim3(64),
+    hipLaunchKernelGGL((sample_kernel<N, PAIR, SOB>), dim3((unsigned)blocks), dim3(WG_TREE),
                        (Lds<N, PAIR, false, SOB>::bytes), s, it);
     return hipGetLastError();
 }
@@ -895,7 +991,7 @@ hipError_t go_points_tree(Env env, const double *u, int64_t n_points, double *f,
     int64_t blocks = (n_points + WAVE - 1) / WAVE;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((points_tree_kernel<N, PAIR, CUR>), dim3((unsigned)blocks), dim3(64),
+    hipLaunchKernelGGL((points_tree_kernel<N, PAIR, CUR>), dim3((unsigned)blocks), dim3(WG_TREE),
                        (Lds<N, PAIR, CUR>::bytes), s, env, u, n_points, f);
     return hipGetLastError();
 }
@@ -905,7 +1001,7 @@ hipError_t go_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t
                     int32_t grid_blocks, hipStream_t s)
 {
     const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
-    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB, MODEL>), dim3((unsigned)g), dim3(64),
+    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB, MODEL>), dim3((unsigned)g), dim3(WG_TREE),
                        (Lds<N, PAIR, CUR, SOB>::bytes), s, items_dev, tiles_dev, n_tiles);
     return hipGetLastError();
 }

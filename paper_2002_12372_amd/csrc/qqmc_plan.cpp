@@ -338,7 +338,6 @@ extern "C" {
 qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int32_t tile_len,
                              int32_t grid_blocks, void *stream, qqmc_plan *out)
 {
-    (void)stream;
     if (!items || n_items < 1 || !out) return set_error(QQMC_EINVAL, "no items");
     if (tile_len != 0 && (tile_len < 64 || (tile_len & (tile_len - 1)) != 0))
         return set_error(QQMC_EINVAL, "tile_len must be 0 or a power of two >= 64");
@@ -380,6 +379,11 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[b], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    /* the items' tables may still be being built on the caller's stream: the
+     * plan's own stream (uploads, autotuning probes, capture) waits for
+     * everything queued there so far */
+    if (e == hipSuccess) e = hipEventRecord(p->fork, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->cap, p->fork, 0);
     if (e != hipSuccess) {
         delete p;
         return hip_error(e, "plan streams");

@@ -525,6 +525,104 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
     return sgn ? cmk(-v.x, -v.y) : v;
 }
 
+/* The shifted grouping of the paired tree.  The lane's 3-bit index prefix
+ * covers two left-looking steps of sizes S0 and S1 (a pair and a single
+ * vertex: 2 then 1 from the whole matrix, 1 then 2 from a cooperative top's
+ * block), then the paired walk continues from block vertex 3.  Against the
+ * even grouping (0,1), (2,3), ... every later pair boundary moves by one
+ * vertex, so a long time gap that falls inside an even pair (the case that
+ * makes its pivot block nearly singular) falls between two pairs here.  With
+ * C the correction after a step, the trailing entries are (Wick) - C; a
+ * single step adds c row with c = col / p, a pair step U x + V y.  Returns
+ * the lane's signed sum and accumulates the squared growth bounds as the
+ * paired tree does. */
+template <int N, bool CUR, int S0, int S1>
+QQMC_HD cplx lane_sum_shift(const pairv *pr, const pairv *mc, BlockSrc<N, true> C0, int pre,
+                            cplx prod, int sgn, cplx g0, double &grow)
+{
+    static_assert(S0 + S1 == 3 && (S0 == 1 || S0 == 2), "a pair and a single vertex");
+    constexpr int K = Geo<N, true>::K, OFF = Geo<N, true>::OFF;
+    static_assert(K >= 5, "the walk needs the measurement and one vertex");
+    constexpr int SP = S0 == 2 ? 0 : 1;   /* block index of the pair's first vertex */
+    constexpr int SS = S0 == 2 ? 2 : 0;   /* block index of the single vertex        */
+    const LeafK lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
+    const int bits[3] = {(pre >> 2) & 1, (pre >> 1) & 1, pre & 1};
+    sgn ^= bits[0] ^ bits[1] ^ bits[2];
+    const int bp = bits[SP], bq = bits[SP + 1], bs = bits[SS];
+    /* table halves by address: row entries -conj(b ? g^> : g^<) (the lead's
+     * for the current's measurement column), column entries b ? g^< : g^> */
+    auto rowp = [&](int k, int j) -> const cplx * {
+        return (CUR && j == K - 1) ? &mc[OFF + k].gl : &pr[pidx(OFF + k, OFF + j)].gl;
+    };
+    auto colp = [&](int k, int i) -> const cplx * { return &pr[pidx(OFF + k, OFF + i)].gl; };
+    cplx U[K], V[K], X[K], Y[K], Cc[K], Rr[K];
+    /* correction of block entry (i, j) after the steps taken so far */
+    bool pair_done = false, single_done = false;
+    auto corr = [&](int i, int j) -> cplx {
+        cplx c = C0.at(i, j);
+        if (pair_done) c = cfma(V[i], Y[j], cfma(U[i], X[j], c));
+        if (single_done) c = cfma(Cc[i], Rr[j], c);
+        return c;
+    };
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+        const bool is_pair = (step == 0) == (S0 == 2);
+        if (is_pair) {
+            constexpr int k = SP;
+            const cplx a = csub(g0, corr(k, k)), d = csub(g0, corr(k + 1, k + 1));
+            const cplx be = csub(cnc(colp(k, k + 1)[bp]), corr(k, k + 1));
+            const cplx ga = csub(colp(k, k + 1)[bp ^ 1], corr(k + 1, k));
+            const cplx det = cfms(be, ga, cmul(a, d));
+            const cplx r = crecip_nr(det);
+            const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
+            double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
+#pragma unroll
+            for (int i = k + 2; i < K; ++i) {
+                const cplx x = csub(cnc(rowp(k, i)[bp]), corr(k, i));
+                const cplx u = csub(colp(k, i)[bp ^ 1], corr(i, k));
+                const cplx y = csub(cnc(rowp(k + 1, i)[bq]), corr(k + 1, i));
+                const cplx z = csub(colp(k + 1, i)[bq ^ 1], corr(i, k + 1));
+                X[i] = x;
+                Y[i] = y;
+                U[i] = cfms(z, gg, cmul(u, dd));
+                V[i] = cfms(u, bb, cmul(z, aa));
+                mx = fmax(mx, cabs2(x));
+                my = fmax(my, cabs2(y));
+                mu = fmax(mu, cabs2(U[i]));
+                mv = fmax(mv, cabs2(V[i]));
+            }
+            grow = fmax(grow, fmax(mu * mx, mv * my));
+            prod = cmul(prod, det);
+            pair_done = true;
+        } else {
+            constexpr int k = SS;
+            const cplx p = csub(g0, corr(k, k));
+            const cplx rp = crecip_nr(p);
+            double mc2 = 0.0, mr2 = 0.0;
+#pragma unroll
+            for (int i = k + 1; i < K; ++i) {
+                const cplx col = csub(colp(k, i)[bs ^ 1], corr(i, k));
+                const cplx row = csub(cnc(rowp(k, i)[bs]), corr(k, i));
+                Cc[i] = cmul(col, rp);
+                Rr[i] = row;
+                mc2 = fmax(mc2, cabs2(Cc[i]));
+                mr2 = fmax(mr2, cabs2(row));
+            }
+            grow = fmax(grow, mc2 * mr2);
+            prod = cmul(prod, p);
+            single_done = true;
+        }
+    }
+    Blk<K - 3> C;
+#pragma unroll
+    for (int i = 3; i < K; ++i)
+#pragma unroll
+        for (int j = 3; j < K; ++j) C.v[i - 3][j - 3] = corr(i, j);
+    cplx v = pair_walk<N, 3, CUR>(C, pr, mc, g0, lk, grow);
+    v = cmul(cmul(prod, prod), v);
+    return sgn ? cmk(-v.x, -v.y) : v;
+}
+
 /* Wick entry (i, j), i != j, of global elimination indices for index b of
  * the earlier point min(i, j); the index picks the table half by address
  * (upper entries -conj(b ? g^> : g^<), lower entries b ? g^< : g^>). */

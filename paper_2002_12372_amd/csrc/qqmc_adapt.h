@@ -13,11 +13,10 @@
  * point (where its gaps are) and on the Green's functions (how fast they
  * decay), so no fixed grouping works for every point.
  *
- * The register tree therefore measures, at every pair step, the bound
- *     |C' - C| <= max|U| max|x| + max|V| max|y|
- * on the growth of the correction block (C' = C + U x + V y, qqmc_tree.h),
- * and a point whose bound exceeds kGrowthFlag is evaluated again here.  This
- * path keeps the time order (so that the Schur corrections of a node depend
+ * The register tree therefore tracks the largest elimination multiplier of
+ * its pair steps (C' = C + U x + V y, qqmc_tree.h); a point with a large one
+ * is evaluated again, first by the shifted grouping of the register tree
+ * (lane_sum_shift), and where that grows too, here.  This path keeps the time order (so that the Schur corrections of a node depend
  * only on the indices fixed above it, the property the tree rests on) but
  * chooses the size of every elimination block from the data:
  *   - a single vertex (pivot p = g0 - C_kk, children b = 0, 1) when its
@@ -49,10 +48,18 @@
 
 namespace qqmc {
 
-/* A point of the register tree whose pair steps' growth bound exceeds this
- * is evaluated again with the shifted grouping, and if that grows beyond it
- * too, by the adaptive path. */
+/* A point of the paired register tree one of whose elimination multipliers
+ * (U, V of a pair step; largest component) exceeds kGrowthFlag is evaluated
+ * again with the shifted grouping, and if one of that tree's multipliers
+ * exceeds kShiftFlag, by the adaptive path.  Set from CPU scans against a
+ * quad-precision Keldysh sum (alpha = n_sigma, orders 7-8, two dots, 6000
+ * points): 4-8% of points are evaluated again, 0-0.13% reach the adaptive
+ * path, and every point ends within 2.5e-14 of its term mass.  (Tracking the
+ * multipliers alone costs two maximum instructions per value; a bound on the
+ * correction's growth, |U| |x| + |V| |y|, flagged slightly fewer points but
+ * made the register tree 12-25% slower.) */
 constexpr double kGrowthFlag = 64.0;
+constexpr double kShiftFlag = 256.0;
 /* The adaptive path takes a single-vertex step when its growth bound stays
  * below this at every node of the level. */
 constexpr double kGrowthSingle = 4.0;

@@ -305,14 +305,8 @@ __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int su
         const cplx det = cfms(be, ga, cmul(a, d));
         const cplx rdet = crecip_nr(det);
         const cplx dd = cmul(d, rdet), aa = cmul(a, rdet), bb = cmul(be, rdet), gg = cmul(ga, rdet);
-        /* growth bound of the step: the broadcast rows are the same in
-         * every lane, the columns U, V are spread over the lanes' rows */
-        double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
-#pragma unroll
-        for (int j = k + 2; j <= N; ++j) {
-            mx = fmax(mx, cabs2(s_r0[j]));
-            my = fmax(my, cabs2(s_r1[j]));
-        }
+        /* the step's elimination multipliers U, V, spread over the lanes'
+         * rows, enter the lane's largest multiplier */
 #pragma unroll
         for (int m = 0; m < RPL; ++m) {
             const int r = sub + m * G;
@@ -321,14 +315,12 @@ __device__ cplx top_block_pair(const pairv *pr, const pairv *mc, int top, int su
                 const cplx z = csub(wick_entry(pr, r, k + 1, bq), crow[m][k + 1]);
                 const cplx Ui = cfms(z, gg, cmul(u, dd));
                 const cplx Vi = cfms(u, bb, cmul(z, aa));
-                mu = fmax(mu, cabs2(Ui));
-                mv = fmax(mv, cabs2(Vi));
+                grow = cmaxabs(cmaxabs(grow, Ui), Vi);
 #pragma unroll
                 for (int j = k + 2; j <= N; ++j)
                     crow[m][j] = cfma(Vi, s_r1[j], cfma(Ui, s_r0[j], crow[m][j]));
             }
         }
-        grow = fmax(grow, fmax(mu * mx, mv * my));
         prod = cmul(prod, det);
         wave_sync();
     }
@@ -411,6 +403,26 @@ __device__ __attribute__((noinline)) ShiftOut shift_lane(const pairv *pr, const 
     return o;
 }
 
+/* Entry q of a point's pair table (times tm, elimination order): the pair
+ * (i, j) with q = j (j - 1) / 2 + i, or for the current beyond the NP pairs
+ * the lead values of vertex q - NP, held as -conj. */
+template <int N, bool CUR>
+__device__ __forceinline__ pairv pair_entry(int q, const double *tm, const Env &env)
+{
+    constexpr int NP = N * (N + 1) / 2;
+    pairv v;
+    if (!CUR || q < NP) {
+        const int j = pair_hi(q), i = q - j * (j - 1) / 2;
+        const double tj = j == N ? env.t_meas : tm[j];
+        v = interp_pair(env.tab, env.n_grid, env.t_half, env.inv_h, tj - tm[i]);
+    } else {
+        const pairv c = interp_pair(env.col, env.n_grid, env.t_half, env.inv_h, tm[q - NP] - env.t_meas);
+        v.gl = cnc(c.gl);
+        v.gg = cnc(c.gg);
+    }
+    return v;
+}
+
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
 template <int N, bool PAIR = false, bool CUR = false>
@@ -427,6 +439,8 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
     const int n_items = cnt * Gm::IPP;
     bool point_top_flag = false; /* paired top levels of the current point grew */
     (void)point_top_flag;
+    uint64_t deferred = 0;       /* flagged points (orders <= 8), bit per point */
+    (void)deferred;
     for (int base = 0; base < n_items; base += Gm::PPW) {
         const int item = base + grp;
         const bool active = item < n_items;
@@ -496,7 +510,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         int sgn = 0;
         BlockSrc<N, PAIR> src;
         src.c = nullptr;
-        double gtop = 0.0, gbot = 0.0; /* squared growth bounds (paired tree) */
+        double gtop = 0.0, gbot = 0.0; /* largest elimination multipliers (paired tree) */
         if constexpr (Gm::OFF > 0) {
             cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
@@ -516,7 +530,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
              * flags too by the adaptive path; a point whose cooperative top
              * levels grew is redone whole after its last round.  Flags,
              * groups and results are wave-uniform. */
-            constexpr double F2 = kGrowthFlag * kGrowthFlag / 4.0;
+            constexpr double F2 = kGrowthFlag;
             constexpr uint64_t GM = Gm::G >= 64 ? ~0ull : ((1ull << Gm::G) - 1);
             constexpr bool SHIFT = Gm::K >= 5 && (Gm::OFF > 0 || N >= 4);
             const uint64_t ft = __ballot(active && gtop > F2);
@@ -529,6 +543,12 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             uint64_t groups = 0; /* flagged groups of the round */
             for (int g = 0; g < Gm::PPW; ++g)
                 if ((fl >> (g * Gm::G)) & GM) groups |= 1ull << g;
+            if constexpr (Gm::OFF == 0) {
+                /* whole points: evaluated again after the batch's rounds,
+                 * eight at a time (one group per point, item = point) */
+                deferred |= groups << base;
+                groups = 0;
+            }
             while (groups) {
                 /* up to 8 flagged groups, one per 8-lane slot */
                 int nf = 0, mine = -1;
@@ -568,7 +588,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                 } else {
                     g2 = INFINITY;
                 }
-                const uint64_t again = __ballot(mine >= 0 && g2 > F2);
+                const uint64_t again = __ballot(mine >= 0 && g2 > kShiftFlag);
                 /* every taken group in turn: its result, from the shifted
                  * tree or, flagged again, from the adaptive path */
                 uint64_t t = taken;
@@ -626,6 +646,79 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
                 wave_sync();
             }
             if ((base + Gm::PPW) % Gm::IPP == 0) point_top_flag = false;
+        }
+    }
+    if constexpr (PAIR && Gm::OFF == 0) {
+        /* The flagged points of the batch: their tables rebuilt in the
+         * adaptive path's workspace, eight points at a time, each on eight
+         * lanes with the shifted grouping; a point flagged again is
+         * evaluated by the adaptive path (its table rebuilt in the first
+         * table slot).  Wave-uniform throughout. */
+        constexpr double F2 = kGrowthFlag;
+        constexpr bool SHIFT = N >= 4;
+        pairv *tabs = reinterpret_cast<pairv *>(lds + L::adapt);
+        static_assert(8 * NPS * (int)sizeof(pairv) <= AdaptWs<N, L::MB>::bytes,
+                      "eight pair tables fit in the adaptive workspace");
+        while (deferred) {
+            int pts[8];
+            int nf = 0;
+            for (int k = 0; k < 8; ++k) {
+                pts[k] = -1;
+                if (deferred) {
+                    pts[k] = __builtin_ctzll(deferred);
+                    deferred &= deferred - 1;
+                    ++nf;
+                }
+            }
+            int mine = -1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if ((lane >> 3) == k) mine = pts[k];
+            uint64_t again = 0;
+            cplx r = cmk(0.0, 0.0);
+            if constexpr (SHIFT) {
+                for (int e = lane; e < nf * NPS; e += WAVE) {
+                    const int slot = e / NPS, q = e - slot * NPS;
+                    int p = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k == slot) p = pts[k];
+                    tabs[e] = pair_entry<N, CUR>(q, s_times + p * N, env);
+                }
+                wave_sync();
+                double g2 = 0.0;
+                if (mine >= 0) {
+                    const pairv *tg = tabs + (lane >> 3) * NPS;
+                    const ShiftOut o = shift_lane<N, CUR>(tg, tg + (CUR ? Gm::NP : pidx(0, N)),
+                                                          nullptr, lane & 7, 0, env.g0,
+                                                          cmk(1.0, 0.0));
+                    r = o.v;
+                    g2 = o.grow;
+                }
+#pragma unroll
+                for (int m = 1; m < 8; m <<= 1) {
+                    r.x += shfl_xor_d(r.x, m);
+                    r.y += shfl_xor_d(r.y, m);
+                }
+                again = __ballot(mine >= 0 && g2 > kShiftFlag);
+                if (mine >= 0 && (lane & 7) == 0 && !((again >> lane) & 0xffull)) s_S[mine] = r;
+                wave_sync();
+            } else {
+                again = __ballot(mine >= 0);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k >= nf || !((again >> (8 * k)) & 0xffull)) continue;
+                const int p = pts[k];
+                for (int q = lane; q < NPS; q += WAVE)
+                    s_pairs[q] = pair_entry<N, CUR>(q, s_times + p * N, env);
+                wave_sync();
+                const cplx ra = adapt_point<N, CUR, L::MB>(
+                    s_pairs, s_pairs + (CUR ? Gm::NP : pidx(0, N)), env.g0, lds + L::adapt,
+                    nullptr, N + 1, 0, cmk(1.0, 0.0));
+                if (lane == 0) s_S[p] = ra;
+                wave_sync();
+            }
         }
     }
 }

@@ -84,6 +84,9 @@ QQMC_HD cplx crecip(cplx a)
 }
 QQMC_HD cplx csel(int b, cplx one, cplx zero) { return b ? one : zero; }
 QQMC_HD double cabs2(cplx a) { return fma(a.x, a.x, a.y * a.y); }
+/* max(m, |Re a|, |Im a|): the largest component, within a factor sqrt(2) of
+ * |a|, for two maximum instructions with absolute-value operands */
+QQMC_HD double cmaxabs(double m, cplx a) { return fmax(m, fmax(fabs(a.x), fabs(a.y))); }
 
 /* 1/a from the hardware reciprocal estimate refined by two Newton steps
  * (e = 1 - a r, r <- r + r e; each step squares the relative error), about
@@ -397,40 +400,34 @@ QQMC_HD cplx pair_walk(const Blk<Geo<N, true>::K - L> &C, const pairv *pr, const
             const cplx r = crecip_nr(det);
             const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
             cplx x[M - 2], u[M - 2];
-            double mx = 0.0;
 #pragma unroll
             for (int j = 2; j < M; ++j) {
                 const cplx *P = &pr[pidx(V0, V0 + j)].gl;
                 const cplx *R = (CUR && j == M - 1) ? &mc[V0].gl : P;
                 x[j - 2] = csub(cnc(R[b]), C.v[0][j]);
                 u[j - 2] = csub(P[b ^ 1], C.v[j][0]);
-                mx = fmax(mx, cabs2(x[j - 2]));
             }
             cplx sub = cmk(0.0, 0.0);
 #pragma unroll
             for (int bq = 0; bq < 2; ++bq) {
                 cplx y[M - 2], z[M - 2];
-                double my = 0.0, mu = 0.0, mv = 0.0;
 #pragma unroll
                 for (int j = 2; j < M; ++j) {
                     const cplx *Q = &pr[pidx(V0 + 1, V0 + j)].gl;
                     const cplx *R = (CUR && j == M - 1) ? &mc[V0 + 1].gl : Q;
                     y[j - 2] = csub(cnc(R[bq]), C.v[1][j]);
                     z[j - 2] = csub(Q[bq ^ 1], C.v[j][1]);
-                    my = fmax(my, cabs2(y[j - 2]));
                 }
                 Blk<M - 2> D;
 #pragma unroll
                 for (int i = 2; i < M; ++i) {
                     const cplx Ui = cfms(z[i - 2], gg, cmul(u[i - 2], dd));
                     const cplx Vi = cfms(u[i - 2], bb, cmul(z[i - 2], aa));
-                    mu = fmax(mu, cabs2(Ui));
-                    mv = fmax(mv, cabs2(Vi));
+                    grow = cmaxabs(cmaxabs(grow, Ui), Vi);
 #pragma unroll
                     for (int j = 2; j < M; ++j)
                         D.v[i - 2][j - 2] = cfma(Vi, y[j - 2], cfma(Ui, x[j - 2], C.v[i][j]));
                 }
-                grow = fmax(grow, fmax(mu * mx, mv * my));
                 const cplx w = pair_walk<N, L + 2, CUR>(D, pr, mc, g0, lk, grow);
                 sub = bq ? csub(sub, w) : cadd(sub, w);
             }
@@ -481,7 +478,6 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
             const cplx det = cfms(be, ga, cmul(a, d));
             const cplx r = crecip_nr(det);
             const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
-            double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
 #pragma unroll
             for (int i = k + 2; i < K; ++i) {
                 const cplx *P = &pr[pidx(OFF + k, OFF + i)].gl;
@@ -501,12 +497,8 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
                 yr[s][i] = y;
                 Uc[s][i] = cfms(z, gg, cmul(u, dd));
                 Vc[s][i] = cfms(u, bb, cmul(z, aa));
-                mx = fmax(mx, cabs2(x));
-                my = fmax(my, cabs2(y));
-                mu = fmax(mu, cabs2(Uc[s][i]));
-                mv = fmax(mv, cabs2(Vc[s][i]));
+                grow = cmaxabs(cmaxabs(grow, Uc[s][i]), Vc[s][i]);
             }
-            grow = fmax(grow, fmax(mu * mx, mv * my));
             prod = cmul(prod, det);
         }
         Blk<K - T> C;
@@ -534,8 +526,8 @@ QQMC_HD cplx lane_sum_pair(const pairv *pr, const pairv *mc, BlockSrc<N, true> C
  * makes its pivot block nearly singular) falls between two pairs here.  With
  * C the correction after a step, the trailing entries are (Wick) - C; a
  * single step adds c row with c = col / p, a pair step U x + V y.  Returns
- * the lane's signed sum and accumulates the squared growth bounds as the
- * paired tree does. */
+ * the lane's signed sum and accumulates the largest elimination multiplier
+ * as the paired tree does. */
 template <int N, bool CUR, int S0, int S1>
 QQMC_HD cplx lane_sum_shift(const pairv *pr, const pairv *mc, BlockSrc<N, true> C0, int pre,
                             cplx prod, int sgn, cplx g0, double &grow)
@@ -575,7 +567,6 @@ QQMC_HD cplx lane_sum_shift(const pairv *pr, const pairv *mc, BlockSrc<N, true> 
             const cplx det = cfms(be, ga, cmul(a, d));
             const cplx r = crecip_nr(det);
             const cplx dd = cmul(d, r), aa = cmul(a, r), bb = cmul(be, r), gg = cmul(ga, r);
-            double mx = 0.0, my = 0.0, mu = 0.0, mv = 0.0;
 #pragma unroll
             for (int i = k + 2; i < K; ++i) {
                 const cplx x = csub(cnc(rowp(k, i)[bp]), corr(k, i));
@@ -586,29 +577,22 @@ QQMC_HD cplx lane_sum_shift(const pairv *pr, const pairv *mc, BlockSrc<N, true> 
                 Y[i] = y;
                 U[i] = cfms(z, gg, cmul(u, dd));
                 V[i] = cfms(u, bb, cmul(z, aa));
-                mx = fmax(mx, cabs2(x));
-                my = fmax(my, cabs2(y));
-                mu = fmax(mu, cabs2(U[i]));
-                mv = fmax(mv, cabs2(V[i]));
+                grow = cmaxabs(cmaxabs(grow, U[i]), V[i]);
             }
-            grow = fmax(grow, fmax(mu * mx, mv * my));
             prod = cmul(prod, det);
             pair_done = true;
         } else {
             constexpr int k = SS;
             const cplx p = csub(g0, corr(k, k));
             const cplx rp = crecip_nr(p);
-            double mc2 = 0.0, mr2 = 0.0;
 #pragma unroll
             for (int i = k + 1; i < K; ++i) {
                 const cplx col = csub(colp(k, i)[bs ^ 1], corr(i, k));
                 const cplx row = csub(cnc(rowp(k, i)[bs]), corr(k, i));
                 Cc[i] = cmul(col, rp);
                 Rr[i] = row;
-                mc2 = fmax(mc2, cabs2(Cc[i]));
-                mr2 = fmax(mr2, cabs2(row));
+                grow = cmaxabs(grow, Cc[i]);
             }
-            grow = fmax(grow, mc2 * mr2);
             prod = cmul(prod, p);
             single_done = true;
         }

@@ -145,8 +145,9 @@ typedef struct {
  * `stream`; the handle is usable by later work on the same stream) and
  * n_sigma = -i g^<(0) on the host (digamma closed form).  At T = 0
  * (beta = +INFINITY) the grid is computed on the host from the Fourier
- * integral along a path deformed into the lower half plane (App. E,
- * "Precision calculation") and uploaded, n_sigma from the arctan closed
+ * integral turned off the real axis into the lower half plane (App. E,
+ * "Precision calculation"): along a ray from each Fermi level plus the
+ * residue of the pole it encloses; uploaded, n_sigma from the arctan closed
  * form.  With a finite half_bandwidth D (any beta) the grid is computed on
  * the host by a graded Gauss-Legendre rule over the band (theta in [0, pi],
  * omega = -D cos theta, panels refined at the Fermi levels and at eps_d),

@@ -654,7 +654,6 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
          * lanes with the shifted grouping; a point flagged again is
          * evaluated by the adaptive path (its table rebuilt in the first
          * table slot).  Wave-uniform throughout. */
-        constexpr double F2 = kGrowthFlag;
         constexpr bool SHIFT = N >= 4;
         pairv *tabs = reinterpret_cast<pairv *>(lds + L::adapt);
         static_assert(8 * NPS * (int)sizeof(pairv) <= AdaptWs<N, L::MB>::bytes,

@@ -1,6 +1,7 @@
 """CPU-side checks of the product: the C ABI exports, the host table
 builder against the oracle, the seeded input recipes, the flop model."""
 import ctypes
+import math
 import os
 import re
 
@@ -38,8 +39,15 @@ def test_library_exports_every_declared_symbol(libq):
 
 
 @pytest.mark.parametrize("d", [Dot(0.0, 1.0, 20.0, 0.0), Dot(-0.5, 1.0, 20.0, 0.2),
-                               Dot(2.7, 0.6, 20.0, 0.9), Dot(-1.3, 1.7, 35.0, 0.3)])
+                               Dot(2.7, 0.6, 20.0, 0.9), Dot(-1.3, 1.7, 35.0, 0.3),
+                               Dot(0.0, 1.0, math.inf, 0.0), Dot(0.15, 1.0, math.inf, 0.3),
+                               Dot(-1.2, 0.1, math.inf, 0.3), Dot(2.5, 2.0, math.inf, 0.5)])
 def test_host_tables_match_oracle(libq, oracle_mod, d):
+    """Finite temperature: both sides sum the residue series.  Zero
+    temperature: the library turns the Fourier integral onto a ray from each
+    Fermi level and adds the enclosed pole, the oracle keeps a real segment
+    and a vertical half-line left of both; Gauss nodes from the Jacobi matrix
+    against Newton on P_m."""
     gl, gg, ns = libq.tables_compute_host(d)
     tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
     assert abs(ns - tb.n_sigma) < 1e-14

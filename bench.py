@@ -225,14 +225,52 @@ def run_plain(args):
                      "flops_per_inside_point": tflops,
                      "avg_launch_ms": avg_launch_s * 1e3},
     }
+    if not args.no_serving and alpha == 0.0 and not args.sobol and n == 8:
+        # the metric's second half: p99 sweep latency of the serving trace,
+        # served by continuous batching and by plain launches (before the
+        # CPU leg, whose worker threads would share the host with the
+        # server's scheduling thread)
+        out["serving"] = serving_measure(args)[0]
     if not args.no_cpu and alpha == 0.0 and not args.sobol:
         out["cpu_baseline"] = cpu_baseline(n, args.log2n, job.lattice_a, job.shifts,
                                            args.cpu_sample)
-    if not args.no_serving and alpha == 0.0 and not args.sobol and n == 8:
-        # the metric's second half: p99 sweep latency of the serving trace,
-        # served by continuous batching and by plain launches
-        out["serving"] = serving_measure(args)[0]
     print(json.dumps(out), flush=True)
+
+
+def run_geometry(args):
+    """Both lane mappings of the scalar-tree charge kernel, order by order:
+    one plan per order (Gamma=1, eps_d=0, beta=20, V=0, t=10; 32 shifts;
+    N = 2^(16+floor(2(n-1)/3)) up to order 10, 2^(30-n) above), forced to
+    each mapping in turn, timed over the same steps.  One JSON line per
+    order; a mapping is (lanes per item, cooperative top levels)."""
+    import torch
+    from paper_2002_12372_amd import qqmc
+    from paper_2002_12372_amd.flops import tree_flops
+    from qqmc_inputs import Dot, batched_log2_n, order_job
+
+    stream = torch.cuda.current_stream()
+    tb = qqmc.make_tables(Dot(0.0, 1.0, 20.0, 0.0))
+    for n in range(5, 15):
+        log2_n = batched_log2_n(n) if n <= 10 else 20 - (n - 10)
+        job = order_job(900 + n, n, log2_n, 32)
+        plan = qqmc.plan_create([(tb, job)], 10.0)
+        info = qqmc.plan_info(plan)
+        auto = info["geometry"][n]
+        pts = (1 << log2_n) * 32
+        flops = pts * inside_fraction(n, 10.0) * tree_flops(n)
+        default = (1 << (n - 5), 0) if n <= 10 else (8, n - 8)
+        other = (8, n - 8) if n in (9, 10) else \
+            ((1 << (n - 4), 0) if n <= 8 else (16, n - 8))
+        row = {"order": n, "lattice_points": 1 << log2_n, "shifts": 32,
+               "tile_len": info["tile_len"], "autotuned": list(auto)}
+        for name, g in (("default", default), ("alternative", other)):
+            qqmc.plan_set_geometry(plan, n, *g)
+            _, ms = timed_steps(lambda: qqmc.plan_run(plan, stream), args.steps, args.warmup, stream)
+            t = sum(ms) / len(ms) * 1e-3
+            row[name] = {"lanes_per_item": g[0], "top_levels": g[1], "ms_per_step": t * 1e3,
+                         "points_per_s": pts / t,
+                         "frac_fp64_peak": flops / t / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+        print(json.dumps(row), flush=True)
 
 
 def run_batched(args):
@@ -268,8 +306,10 @@ def run_batched(args):
                                   tile_len=min(info["tile_len"], 1 << job.log2_n), stream=stream)
 
     wall_p, ms_p = timed_steps(per_item, args.steps, args.warmup, stream)
-    same = all(np.array_equal(rb, (lambda h: (h[0::2] + 1j * h[1::2]) / (1 << job.log2_n))(
-        buf.cpu().numpy())) for rb, buf, (_, job) in zip(res_b, sums, entries))
+    solo = [(lambda h: (h[0::2] + 1j * h[1::2]) / (1 << job.log2_n))(buf.cpu().numpy())
+            for buf, (_, job) in zip(sums, entries)]
+    same = all(np.array_equal(rb, rs) for rb, rs in zip(res_b, solo))
+    agree = max(float(np.max(np.abs(rb - rs) / np.abs(rs))) for rb, rs in zip(res_b, solo))
     flops = 0.0
     for _, job in entries:
         flops += (1 << job.log2_n) * job.shifts.shape[0] * inside_fraction(job.order, 10.0) * \
@@ -285,11 +325,13 @@ def run_batched(args):
                                "beta=20) x orders 1..10 x 16 shifts, N_n = 2^(16+floor(2(n-1)/3)-%d)"
                                % args.shrink,
                    "items": len(entries), "points": points, "tile_len": info["tile_len"],
-                   "grid_blocks": info["grid_blocks"], "plan_create_s": t_plan},
+                   "grid_blocks": info["grid_blocks"], "plan_create_s": t_plan,
+                   "lane_mappings": {n: list(g) for n, g in info["geometry"].items()}},
         "per_order_launches": {"value": points / tp_s, "unit": "points/s",
                                "ms_per_step": tp_s * 1e3},
         "speedup_vs_per_order": tp_s / tb_s,
         "bitwise_equal_to_per_order": bool(same),
+        "max_rel_diff_vs_per_order": agree,
         "roofline": {"bound": "alu", "achieved": flops / tb_s / 1e12,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": flops / tb_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
@@ -324,7 +366,9 @@ def serving_measure(args):
                 r = srv.poll(tk)
                 if r is not None:
                     done[pending.pop(tk)] = r
-            time.sleep(0.0005)
+            # completion times are the server's own clock: polling only
+            # collects them, so it need not be frequent
+            time.sleep(0.002)
         lat = np.array([done[i]["t_done"] - (t0 + trace[i].arrival_s / rate_scale)
                         for i in range(len(trace))])
         span = max(done[i]["t_done"] for i in done) - t0
@@ -548,7 +592,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
-                    choices=["plain", "batched", "serving", "stress", "learned", "bethe"],
+                    choices=["plain", "batched", "serving", "stress", "learned", "bethe", "geometry"],
                     default="plain")
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--sobol", action="store_true",
@@ -593,7 +637,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     {"plain": run_plain, "batched": run_batched, "serving": run_serving,
-     "stress": run_stress, "learned": run_learned, "bethe": run_bethe}[args.workload](args)
+     "stress": run_stress, "learned": run_learned, "bethe": run_bethe,
+     "geometry": run_geometry}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -327,8 +327,9 @@ void qqmc_free_model(qqmc_model m);
  * Many (parameter point, order) integrals in one persistent launch.  Each
  * item is estimated exactly as qqmc_eval_order_async estimates it at the
  * plan's tile_len (the same tile decomposition, hence the same per-shift
- * sums bit for bit).  The plan owns device buffers and a captured HIP graph;
- * qqmc_plan_run replays it. */
+ * sums bit for bit, as long as every order keeps its default lane mapping:
+ * see qqmc_plan_set_geometry).  The plan owns device buffers and a captured
+ * HIP graph; qqmc_plan_run replays it. */
 typedef struct {
     qqmc_tables tables;
     qqmc_order order;      /* shifts are copied at plan creation */
@@ -336,7 +337,8 @@ typedef struct {
 
 typedef struct qqmc_plan_s *qqmc_plan;
 
-/* tile_len: lattice indices per tile (0 = autotuned); grid_blocks:
+/* tile_len: lattice indices per tile (0 = autotuned, together with each
+ * order's lane mapping where there is a choice); grid_blocks:
  * persistent workgroups per order-8 launch, scaled by residency for other
  * orders (0 = autotuned, which may also choose one workgroup per tile; then
  * qqmc_plan_info reports grid_blocks 0).  Items may mix the charge, the
@@ -354,9 +356,31 @@ qqmc_status qqmc_plan_run(qqmc_plan p, void *stream);
 /* Synchronises `stream` and copies results: q_shift host, concatenated
  * 2*n_shifts(item) doubles per item in item order (divided by N). */
 qqmc_status qqmc_plan_results(qqmc_plan p, void *stream, double *q_shift);
-/* Number of tiles and of lattice points (all items, all shifts). */
+/* Number of tiles and of lattice points (all items, all shifts), the tile
+ * length and the workgroup count, and the lane mapping of each order n at
+ * index n - 1 of two arrays of QQMC_MAX_ORDER entries (either may be NULL):
+ * lanes_per_item, the lanes of one wavefront that evaluate one item
+ * together (64 / lanes items share a wavefront), and top_levels, the
+ * levels of the elimination tree that those lanes take cooperatively before
+ * each walks its own path (an item is one of the 2^top_levels top-level
+ * index prefixes of a point).  Reported for the plan's scalar-tree charge
+ * group of that order if it has one, else its first group of that order;
+ * 0 and 0 for orders the plan does not hold. */
 qqmc_status qqmc_plan_info(qqmc_plan p, int64_t *n_tiles, int64_t *n_points,
-                           int32_t *tile_len, int32_t *grid_blocks);
+                           int32_t *tile_len, int32_t *grid_blocks, int32_t *lanes_per_item,
+                           int32_t *top_levels);
+/* Lane mapping of the plan's scalar-tree charge group (lattice points, no
+ * learned warp) of order `order` >= 5, which has two: the default, the one
+ * qqmc_eval_order uses (a depth-5 register tree: 2^(n-5) lanes per point
+ * up to order 10 with no top levels, 8 lanes per item and n - 8 top levels
+ * above), and a second one -- at orders 5-8 and 11-14 a depth-4 register
+ * tree (twice the lanes per item, compiled for two waves per SIMD), at
+ * orders 9 and 10 n - 8 cooperative top levels with 8 lanes per item.  The
+ * mapping is named by its (lanes_per_item, top_levels) as qqmc_plan_info
+ * reports them; the graph is captured again.  The two agree to rounding.
+ * EINVAL if the plan has no such group or the order has no such mapping. */
+qqmc_status qqmc_plan_set_geometry(qqmc_plan p, int32_t order, int32_t lanes_per_item,
+                                   int32_t top_levels);
 void qqmc_plan_destroy(qqmc_plan p);
 
 /* ---- Serving ------------------------------------------------------------

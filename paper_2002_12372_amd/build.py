@@ -11,7 +11,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["qqmc_kernels.hip", "qqmc_kernels_pair.hip", "qqmc_kernels_cur.hip",
            "qqmc_kernels_sob.hip", "qqmc_kernels_sob_model.hip", "qqmc_kernels_sob_batch.hip",
-           "qqmc_kernels_model.hip", "qqmc_noalloc.hip",
+           "qqmc_kernels_model.hip", "qqmc_kernels_geo.hip", "qqmc_noalloc.hip",
            "qqmc_api.cpp",
            "qqmc_tables.cpp", "qqmc_plan.cpp",
            "qqmc_model.cpp", "qqmc_server.cpp"]

@@ -101,6 +101,24 @@ hipError_t launch_tables(double *tab, int32_t n_grid, double t_half, double eps_
                          double gamma, double beta, double bias_v, double n_sigma,
                          hipStream_t s);
 int32_t batch_blocks_per_cu(int32_t key);
+/* Lane mappings (qqmc_kernels_geo.hip): the batched scalar-tree charge
+ * kernel on the lattice has a second mapping from order 5 (a depth-4
+ * register tree at orders 5-8 and 11-14, cooperative top levels at 9 and
+ * 10); every other key has one.  Both mappings run the same eliminations
+ * per index vector, only split differently between a lane's path and its
+ * subtree, so tile sums agree to rounding. */
+inline bool key_plain_scalar(int32_t key)
+{
+    return !key_pair(key) && !key_current(key) && !key_sobol(key) && !key_model(key);
+}
+inline bool key_has_alt(int32_t key) { return key_order(key) >= 5 && key_plain_scalar(key); }
+hipError_t launch_batch_alt(int32_t order, const ItemDesc *items_dev, const TileRef *tiles_dev,
+                            int64_t n_tiles, int32_t grid_blocks, hipStream_t s);
+int32_t batch_blocks_per_cu_alt(int32_t order);
+/* lanes that evaluate one item together and cooperative top levels (an
+ * item is one point, or one top-level index prefix of 2^top_levels per
+ * point) of this key's default or alternative mapping */
+void mapping_shape(int32_t key, bool alt, int32_t *lanes_per_item, int32_t *top_levels);
 /* Relative cost of one tile of an item (qqmc_plan.cpp). */
 double tile_cost(const ItemDesc &d);
 int32_t default_tile_len(const ItemDesc &d, int64_t N);

@@ -48,22 +48,25 @@ constexpr int WAVE = 64;
 constexpr int WG_TREE = WAVE;
 static_assert(WG_TREE == WAVE, "the tree kernels run one wavefront per workgroup");
 
-template <int N, bool PAIR = false, bool CUR = false, bool SOB = false> struct Lds {
-    using Gm = Geo<N, PAIR>;
+template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP = kMapDefault> struct Lds {
+    using Gm = Geo<N, PAIR, MAP>;
     /* pair-table stride: the NP pairs, then for the current the n lead
      * values of the measurement column */
     static constexpr int NPS = Gm::NP + (CUR ? N : 0);
     /* queued in-domain points of a tile: up to 63 carried over plus the 64
      * of one step.  The queue runs where it measured faster: one-wave
-     * kernels with several lanes per point and no cooperative top levels
-     * (scalar tree orders 6-8, paired tree orders 6 and 8).  Elsewhere it
-     * was as fast or slower: the two-wave orders 1-4 are limited by local
-     * memory, with one lane per point (order 5) the rounds are nearly full
-     * anyway, above order 8 the default tiles are one step long, and the
-     * paired order-7 kernel sits at 256 registers, which the queue's extra
-     * live values overflow into accumulation registers (10% slower). */
+     * kernels with several lanes per point (scalar tree orders 6-10, paired
+     * tree orders 6 and 8).  Elsewhere it was as fast or slower: the
+     * two-wave orders 1-4 are limited by local memory, with one lane per
+     * point (order 5) the rounds are nearly full anyway, above order 10
+     * (three or more cooperative top levels) it measured 1% slower at order
+     * 11 and even at 12-14, and the paired order-7 kernel sits at 256
+     * registers, which the queue's extra live values overflow into
+     * accumulation registers (10% slower).  The paired tree above order 8
+     * keeps the per-step loop: its local memory goes to the adaptive path's
+     * workspace. */
     static constexpr bool QUEUE =
-        Gm::WPS == 1 && Gm::OFF == 0 && Gm::G > 1 && (!PAIR || N != 7);
+        Gm::WPS == 1 && Gm::G > 1 && Gm::OFF <= 2 && (!PAIR || (Gm::OFF == 0 && N != 7));
     static constexpr int QCAP = QUEUE ? 128 : 64;
     static constexpr int times = 0;                                    /* QCAP*N doubles */
     static constexpr int w = times + QCAP * N * 8;                     /* QCAP doubles   */
@@ -195,11 +198,11 @@ struct Env {
  * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
  * 9 x 9 trailing correction block in s_c0 and returns the product of the
  * OFF pivots. */
-template <int N, bool CUR = false>
+template <int N, bool CUR = false, int MAP = kMapDefault>
 __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
                           cplx *s_row, cplx *s_c0)
 {
-    using Gm = Geo<N>;
+    using Gm = Geo<N, false, MAP>;
     constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
     constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
     cplx crow[RPL][N + 1];
@@ -425,11 +428,11 @@ __device__ __forceinline__ pairv pair_entry(int q, const double *tm, const Env &
 
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
-template <int N, bool PAIR = false, bool CUR = false>
+template <int N, bool PAIR = false, bool CUR = false, int MAP = kMapDefault>
 __device__ void keldysh_points(int cnt, const Env &env, char *lds)
 {
-    using Gm = Geo<N, PAIR>;
-    using L = Lds<N, PAIR, CUR>;
+    using Gm = Geo<N, PAIR, MAP>;
+    using L = Lds<N, PAIR, CUR, false, MAP>;
     constexpr int NPS = L::NPS;
     const double *s_times = reinterpret_cast<const double *>(lds + L::times);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
@@ -508,7 +511,7 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         const pairv *mc = prg + (CUR ? Gm::NP : pidx(0, N));
         cplx prod = cmk(1.0, 0.0);
         int sgn = 0;
-        BlockSrc<N, PAIR> src;
+        BlockSrc<N, PAIR, MAP> src;
         src.c = nullptr;
         double gtop = 0.0, gbot = 0.0; /* largest elimination multipliers (paired tree) */
         if constexpr (Gm::OFF > 0) {
@@ -516,13 +519,13 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
             if constexpr (PAIR)
                 prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0, gtop);
-            else prod = top_block<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0);
+            else prod = top_block<N, CUR, MAP>(prg, mc, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;
         }
         cplx s;
         if constexpr (PAIR) s = lane_sum_pair<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0, gbot);
-        else s = lane_sum<N, CUR>(prg, mc, src, sub, prod, sgn, env.g0);
+        else s = lane_sum<N, CUR, MAP>(prg, mc, src, sub, prod, sgn, env.g0);
         if constexpr (PAIR) {
             /* Points (n <= 8) or items (n > 8) whose pair steps grew beyond
              * kGrowthFlag are evaluated again with the shifted grouping
@@ -792,10 +795,10 @@ __device__ __forceinline__ bool warped_point(const ItemDesc &it, uint32_t idx, c
  * learning pass): also writes Re fbar of every lattice index of the tile to
  * it.sample_out. */
 template <int N, bool MODEL, bool SAMPLE = false, bool PAIR = false, bool CUR = false,
-          bool SOB = false>
+          bool SOB = false, int MAP = kMapDefault>
 __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
 {
-    using L = Lds<N, PAIR, CUR, SOB>;
+    using L = Lds<N, PAIR, CUR, SOB, MAP>;
     double *s_times = reinterpret_cast<double *>(lds + L::times);
     double *s_w = reinterpret_cast<double *>(lds + L::w);
     cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
@@ -880,7 +883,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             /* a batch of 64 queued points, or on the tile's last step the
              * rest (up to 64; what is left then goes in the next pass) */
             const int m = queued < WAVE ? queued : WAVE;
-            keldysh_points<N, PAIR, CUR>(m, env, lds);
+            keldysh_points<N, PAIR, CUR, MAP>(m, env, lds);
             if (lane < m) {
                 const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
                 const double w = s_w[lane];
@@ -926,7 +929,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
                 it.sample_out[idx] = 0.0;
             }
             wave_sync();
-            keldysh_points<N, PAIR, CUR>(cnt, env, lds);
+            keldysh_points<N, PAIR, CUR, MAP>(cnt, env, lds);
             if (lane < cnt) {
                 const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
                 const double w = s_w[lane];
@@ -1017,8 +1020,8 @@ __global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) points_tree_kern
  * (A work queue fed by a lane-0 atomic was tried first: the compiler
  * threaded the lane-0 branches at the top and bottom of the loop into an
  * inner cycle for lanes 1..63 that never reached the next atomic.) */
-template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
-__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false, int MAP = kMapDefault>
+__global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR, MAP>::WPS)) batch_kernel(const ItemDesc *__restrict__ items,
                                                             const TileRef *__restrict__ tiles,
                                                             int64_t n_tiles)
 {
@@ -1028,7 +1031,7 @@ __global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR>::WPS)) batch_kernel(con
         const TileRef ref = tiles[t];
         /* by value: the descriptor lives in registers for the whole tile */
         const ItemDesc it = items[ref.item];
-        const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB>(it, ref.tile, lds);
+        const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB, MAP>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;
             it.tile_sums[2 * ref.tile + 1] = v.y;
@@ -1088,22 +1091,23 @@ hipError_t go_points_tree(Env env, const double *u, int64_t n_points, double *f,
     return hipGetLastError();
 }
 
-template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false, int MAP = kMapDefault>
 hipError_t go_batch(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,
                     int32_t grid_blocks, hipStream_t s)
 {
     const int64_t g = grid_blocks < n_tiles ? grid_blocks : n_tiles;
-    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB, MODEL>), dim3((unsigned)g), dim3(WG_TREE),
-                       (Lds<N, PAIR, CUR, SOB>::bytes), s, items_dev, tiles_dev, n_tiles);
+    hipLaunchKernelGGL((batch_kernel<N, PAIR, CUR, SOB, MODEL, MAP>), dim3((unsigned)g), dim3(WG_TREE),
+                       (Lds<N, PAIR, CUR, SOB, MAP>::bytes), s, items_dev, tiles_dev, n_tiles);
     return hipGetLastError();
 }
 
-template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false>
+template <int N, bool PAIR, bool CUR = false, bool SOB = false, bool MODEL = false, int MAP = kMapDefault>
 int32_t occ_batch()
 {
     int blocks = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &blocks, batch_kernel<N, PAIR, CUR, SOB, MODEL>, 64, (size_t)Lds<N, PAIR, CUR, SOB>::bytes);
+        &blocks, batch_kernel<N, PAIR, CUR, SOB, MODEL, MAP>, 64,
+        (size_t)Lds<N, PAIR, CUR, SOB, MAP>::bytes);
     return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 

@@ -18,7 +18,15 @@
  *
  * The tile length and the share of resident workgroups are chosen by a small
  * autotuner when the caller passes 0: each candidate is timed on a subsample
- * of every group (every k-th tile) and the fastest per point is kept.
+ * of every group (every k-th tile) and the fastest per point is kept.  With
+ * tile_len 0 it also picks each group's lane mapping where the kernel has
+ * two (the scalar-tree charge on the lattice from order 5: the default, or
+ * a depth-4 register tree at orders 5-8 and 11-14, cooperative top levels
+ * at 9 and 10), timing the group alone under each.  The two mappings split
+ * the eliminations differently between a lane's path and its subtree, so
+ * their sums agree to rounding, not bit for bit; with the default mapping
+ * kept (a fixed tile_len, or the default chosen) every tile sum is the
+ * single-order launch's.
  */
 #include <algorithm>
 #include <cmath>
@@ -70,9 +78,23 @@ struct Buffers {
 
 struct Group {
     int32_t key = 0, branch = 0, grid = 0; /* kernel key: order, paired tree */
+    bool alt = false;                      /* the kernel's second lane mapping */
     int64_t offset = 0, count = 0;
     double cost = 0.0;
 };
+
+int32_t group_blocks_per_cu(const Group &g)
+{
+    return g.alt ? batch_blocks_per_cu_alt(key_order(g.key)) : batch_blocks_per_cu(g.key);
+}
+
+hipError_t launch_group(const Group &g, const ItemDesc *items, const TileRef *tiles, int32_t grid,
+                        hipStream_t s)
+{
+    if (g.count <= 0) return hipSuccess;
+    return g.alt ? launch_batch_alt(key_order(g.key), items, tiles, g.count, grid, s)
+                 : launch_batch(g.key, items, tiles, g.count, grid, s);
+}
 
 } // namespace
 
@@ -256,9 +278,9 @@ hipError_t enqueue(qqmc_plan_s *p, const std::vector<Group> &groups, const TileR
          * walking a strided share of the tiles; share 0: one workgroup per
          * tile, handed out by the hardware dispatcher */
         const int32_t grid =
-            share > 0.0 ? (int32_t)std::max(1.0, share * p->n_cu * batch_blocks_per_cu(g.key))
+            share > 0.0 ? (int32_t)std::max(1.0, share * p->n_cu * group_blocks_per_cu(g))
                         : (int32_t)std::min<int64_t>(g.count, INT32_MAX);
-        if (e == hipSuccess) e = launch_batch(g.key, p->buf.items, d_tiles + g.offset, g.count, grid, b);
+        if (e == hipSuccess) e = launch_group(g, p->buf.items, d_tiles + g.offset, grid, b);
     }
     for (int b = 0; b < kBranches && e == hipSuccess; ++b) {
         if (!used[b]) continue;
@@ -289,13 +311,13 @@ qqmc_status capture(qqmc_plan_s *p)
  * given workgroup share; seconds per lattice point.  The subsample is the
  * same fraction of the work for every tile length (a quarter, less for
  * very large plans), so launch overheads weigh alike in every probe. */
-double probe(qqmc_plan_s *p, double share)
+double probe(qqmc_plan_s *p, double share, const std::vector<Group> &which)
 {
     const int64_t step = std::max<int64_t>(4, p->n_points / ((int64_t)1 << 26));
     std::vector<TileRef> sub;
     std::vector<Group> groups;
     double pts = 0.0;
-    for (const Group &g : p->groups) {
+    for (const Group &g : which) {
         Group h = g;
         h.offset = (int64_t)sub.size();
         for (int64_t t = 0; t < g.count; t += step) {
@@ -408,7 +430,7 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
                 return st;
             }
             for (double sh : shares) {
-                const double v = probe(p, sh);
+                const double v = probe(p, sh, p->groups);
                 if (v < best) {
                     best = v;
                     best_tl = tl;
@@ -424,6 +446,17 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
     if (qqmc_status st = layout(p, best_tl)) {
         delete p;
         return st;
+    }
+    if (tile_len == 0) {
+        /* lane mapping per group: each candidate timed on the group alone */
+        for (Group &g : p->groups) {
+            if (!key_has_alt(g.key)) continue;
+            Group a = g, b = g;
+            a.alt = false;
+            b.alt = true;
+            const double t0 = probe(p, best_share, {a}), t1 = probe(p, best_share, {b});
+            g.alt = t1 < t0;
+        }
     }
     if (qqmc_status st = capture(p)) {
         delete p;
@@ -460,14 +493,55 @@ qqmc_status qqmc_plan_results(qqmc_plan p, void *stream, double *q_shift)
 }
 
 qqmc_status qqmc_plan_info(qqmc_plan p, int64_t *n_tiles, int64_t *n_points, int32_t *tile_len,
-                           int32_t *grid_blocks)
+                           int32_t *grid_blocks, int32_t *lanes_per_item, int32_t *top_levels)
 {
     if (!p) return set_error(QQMC_EINVAL, "plan is NULL");
     if (n_tiles) *n_tiles = p->n_tiles;
     if (n_points) *n_points = p->n_points;
     if (tile_len) *tile_len = p->tile_len;
     if (grid_blocks) *grid_blocks = p->grid_blocks;
+    int32_t lanes[QQMC_MAX_ORDER] = {}, top[QQMC_MAX_ORDER] = {};
+    /* the scalar-tree charge group of an order first, else any group */
+    for (int pass = 0; pass < 2; ++pass)
+        for (const Group &g : p->groups) {
+            const int n = key_order(g.key) - 1;
+            if (lanes[n] == 0 && (pass == 1 || key_plain_scalar(g.key)))
+                mapping_shape(g.key, g.alt, &lanes[n], &top[n]);
+        }
+    for (int n = 0; n < QQMC_MAX_ORDER; ++n) {
+        if (lanes_per_item) lanes_per_item[n] = lanes[n];
+        if (top_levels) top_levels[n] = top[n];
+    }
     return QQMC_OK;
+}
+
+qqmc_status qqmc_plan_set_geometry(qqmc_plan p, int32_t order, int32_t lanes_per_item,
+                                   int32_t top_levels)
+{
+    if (!p) return set_error(QQMC_EINVAL, "plan is NULL");
+    for (Group &g : p->groups) {
+        if (key_order(g.key) != order || !key_has_alt(g.key)) continue;
+        bool alt = false;
+        int32_t l0, t0, l1, t1;
+        mapping_shape(g.key, false, &l0, &t0);
+        mapping_shape(g.key, true, &l1, &t1);
+        if (lanes_per_item == l0 && top_levels == t0) alt = false;
+        else if (lanes_per_item == l1 && top_levels == t1) alt = true;
+        else
+            return set_error(QQMC_EINVAL, "order " + std::to_string(order) + " has no mapping with " +
+                                              std::to_string(lanes_per_item) + " lanes per item and " +
+                                              std::to_string(top_levels) + " top levels");
+        if (alt == g.alt) return QQMC_OK;
+        g.alt = alt;
+        if (qqmc_status st = capture(p)) {
+            g.alt = !alt;
+            capture(p);
+            return st;
+        }
+        return QQMC_OK;
+    }
+    return set_error(QQMC_EINVAL, "the plan has no scalar-tree charge group of order " +
+                                      std::to_string(order) + " with a second lane mapping");
 }
 
 void qqmc_plan_destroy(qqmc_plan p) { delete p; }

@@ -27,8 +27,10 @@
  * latest point, so its own indices (0 as a row, 1 as a column) never enter.
  *
  * Work split across the lanes of one work item (G = 2^T lanes):
- *   block  K x K trailing block the lanes start from (K = min(n, 8) + 1,
- *          with the first n + 1 - K eliminations done cooperatively before);
+ *   block  K x K trailing block the lanes start from (K = n + 1 up to order
+ *          10 -- the flat mapping -- and 9 above, with the first n - 8
+ *          eliminations done cooperatively before; see Geo for the
+ *          alternatives);
  *   path   T levels eliminated per lane, left-looking, for the lane's own
  *          index prefix (lane number within the item);
  *   tree   the remaining K - 1 - T <= 5 levels walked depth first with
@@ -121,12 +123,23 @@ QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
 
 /* Work split of one item.  PAIR selects the paired tree (vertices
  * eliminated two at a time with 2x2 block pivots, for vertex diagonals that
- * may vanish): its cooperative levels and per-lane path cover whole pairs. */
-template <int N, bool PAIR = false> struct Geo {
-    /* cooperative levels: n - 8, rounded up to even for the paired tree */
-    static constexpr int OFF = N > 8 ? (PAIR ? ((N - 7) & ~1) : N - 8) : 0;
+ * may vanish): its cooperative levels and per-lane path cover whole pairs.
+ * MAP selects the lane mapping of the scalar tree: 0 the default; 1 a
+ * depth-4 register tree (twice the lanes per item, two waves per SIMD);
+ * 2 at orders 9 and 10 the first n - 8 levels eliminated cooperatively by
+ * the lanes of each top-level index prefix (the default there is the flat
+ * mapping, every lane walking its path from the full matrix). */
+constexpr int kMapDefault = 0, kMapDepth4 = 1, kMapTop = 2;
+template <int N, bool PAIR = false, int MAP = kMapDefault> struct Geo {
+    static_assert(MAP == kMapDefault || (!PAIR && (MAP == kMapDepth4 || (N == 9 || N == 10))),
+                  "the scalar tree's second mappings: depth 4, or cooperative top levels at 9, 10");
+    /* cooperative levels: the paired tree n - 8 rounded up to even above
+     * order 8, the scalar tree n - 8 above order 10 (or above 8 with
+     * kMapTop) */
+    static constexpr int OFF = PAIR ? (N > 8 ? ((N - 7) & ~1) : 0)
+                                    : (N > (MAP == kMapTop ? 8 : 10) ? N - 8 : 0);
     static constexpr int K = N + 1 - OFF;              /* block size          */
-    static constexpr int B = 5;                        /* register-tree depth */
+    static constexpr int B = MAP == kMapDepth4 ? 4 : 5; /* register-tree depth */
     /* per-lane path: scalar tree, down to a 6 x 6 block; paired tree, whole
      * pairs down to a block of at most 5 x 5 (a pair node keeps its parent
      * block live under its four children) */
@@ -239,11 +252,11 @@ QQMC_HD cplx node3_value(const Blk<3> &C, const pairv *pr, const pairv *mc, int 
  * node builds the correction blocks of BOTH children (indices 0 and 1 of the
  * level's point) before descending, so while the first child's subtree runs
  * only the second child's (m-1) x (m-1) block is held, not the m x m parent. */
-template <int N, int L, bool CUR = false>
-QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, const pairv *mc, cplx g0,
-                     const LeafK &lk)
+template <int N, int L, bool CUR = false, int MAP = kMapDefault>
+QQMC_HD cplx subtree(const Blk<Geo<N, false, MAP>::K - L> &C, const pairv *pr, const pairv *mc,
+                     cplx g0, const LeafK &lk)
 {
-    constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, M = K - L;
+    constexpr int K = Geo<N, false, MAP>::K, OFF = Geo<N, false, MAP>::OFF, M = K - L;
     if constexpr (M == 2) {
         (void)pr;
         (void)mc;
@@ -277,23 +290,23 @@ QQMC_HD cplx subtree(const Blk<Geo<N>::K - L> &C, const pairv *pr, const pairv *
                 }
             }
         }
-        const cplx v0 = subtree<N, L + 1, CUR>(D0, pr, mc, g0, lk);
-        const cplx v1 = subtree<N, L + 1, CUR>(D1, pr, mc, g0, lk);
+        const cplx v0 = subtree<N, L + 1, CUR, MAP>(D0, pr, mc, g0, lk);
+        const cplx v1 = subtree<N, L + 1, CUR, MAP>(D1, pr, mc, g0, lk);
         return cmul(cmul(p, p), csub(v0, v1));
     }
 }
 
 /* Block correction accessor: zero when the lanes start from the full matrix
  * (n <= 8), otherwise the cooperative block in local memory. */
-template <int N, bool PAIR = false> struct BlockSrc {
+template <int N, bool PAIR = false, int MAP = kMapDefault> struct BlockSrc {
     const cplx *c; /* K*K row-major, or unused */
     QQMC_HD cplx at(int i, int j) const
     {
-        if constexpr (Geo<N, PAIR>::OFF == 0) {
+        if constexpr (Geo<N, PAIR, MAP>::OFF == 0) {
             (void)i; (void)j;
             return cmk(0.0, 0.0);
         } else {
-            return c[i * Geo<N, PAIR>::K + j];
+            return c[i * Geo<N, PAIR, MAP>::K + j];
         }
     }
 };
@@ -302,11 +315,12 @@ template <int N, bool PAIR = false> struct BlockSrc {
  * bit = earliest block level), starting block correction C0, product of the
  * pivots eliminated before the block, parity of the indices fixed before.
  * Returns the signed sum over the lane's 2^B index vectors. */
-template <int N, bool CUR = false>
-QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N> C0, int pre, cplx prod,
-                      int sgn, cplx g0)
+template <int N, bool CUR = false, int MAP = kMapDefault>
+QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N, false, MAP> C0, int pre,
+                      cplx prod, int sgn, cplx g0)
 {
-    constexpr int K = Geo<N>::K, OFF = Geo<N>::OFF, T = Geo<N>::T;
+    using Gm = Geo<N, false, MAP>;
+    constexpr int K = Gm::K, OFF = Gm::OFF, T = Gm::T;
     const LeafK lk = leaf_constants<CUR>(pr[pidx(N - 1, N)], mc[N - 1]);
     cplx v;
     if constexpr (T == 0) {
@@ -316,7 +330,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N> C0, int pre,
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) C.v[i][j] = C0.at(i, j);
-        v = subtree<N, 0, CUR>(C, pr, mc, g0, lk);
+        v = subtree<N, 0, CUR, MAP>(C, pr, mc, g0, lk);
     } else {
         cplx chat[T][K], rowv[T][K];
 #pragma unroll
@@ -355,7 +369,7 @@ QQMC_HD cplx lane_sum(const pairv *pr, const pairv *mc, BlockSrc<N> C0, int pre,
                 for (int l = 0; l < T; ++l) c = cfma(chat[l][i], rowv[l][j], c);
                 C.v[i - T][j - T] = c;
             }
-        v = subtree<N, T, CUR>(C, pr, mc, g0, lk);
+        v = subtree<N, T, CUR, MAP>(C, pr, mc, g0, lk);
     }
     v = cmul(cmul(prod, prod), v);
     return sgn ? cmk(-v.x, -v.y) : v;

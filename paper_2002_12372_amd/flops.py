@@ -76,18 +76,23 @@ def warp_flops(n):
     return 8 * n + 2
 
 
-def geometry(n):
-    """Block size K, cooperative top levels, per-lane path levels T (each
-    lane walks a register tree of depth at most 5)."""
-    K = min(n, 8) + 1
+def geometry(n, alt=False):
+    """Block size K, cooperative top levels, per-lane path levels T of the
+    scalar tree's default lane mapping (a register tree of depth 5, the
+    full matrix up to order 10, cooperative top levels above) or of its
+    alternative (depth 4 at orders 5-8 and 11-14, cooperative top levels at
+    9 and 10)."""
+    depth = 4 if alt and n not in (9, 10) else 5
+    top_from = 8 if alt and n in (9, 10) else 10
+    K = n + 1 if n <= top_from else 9
     off = n + 1 - K
-    T = K - 6 if K - 1 > 5 else 0
+    T = K - 1 - depth if K - 1 > depth else 0
     return K, off, T
 
 
-def lane_flops(n):
+def lane_flops(n, alt=False):
     """Operations the kernel issues per point inside the domain."""
-    K, off, T = geometry(n)
+    K, off, T = geometry(n, alt)
     path = 0
     for k in range(T):
         path += 2 + 8 * k + 6 + (K - 1 - k) * (10 + 16 * k) + 6

@@ -84,7 +84,8 @@ SIGNATURES = [
     ("qqmc_plan_create", _i32, [_P(qqmc_batch_item), _i32, _i32, _i32, _vp, _P(_vp)]),
     ("qqmc_plan_run", _i32, [_vp, _vp]),
     ("qqmc_plan_results", _i32, [_vp, _vp, _PD]),
-    ("qqmc_plan_info", _i32, [_vp, _P(_i64), _P(_i64), _P(_i32), _P(_i32)]),
+    ("qqmc_plan_info", _i32, [_vp, _P(_i64), _P(_i64), _P(_i32), _P(_i32), _P(_i32), _P(_i32)]),
+    ("qqmc_plan_set_geometry", _i32, [_vp, _i32, _i32, _i32]),
     ("qqmc_plan_destroy", None, [_vp]),
     ("qqmc_server_create", _i32, [ctypes.c_size_t, _i32, _i32, _P(_vp)]),
     ("qqmc_submit", _i32, [_vp, _P(qqmc_dot), _P(qqmc_order), _P(_u64)]),
@@ -384,10 +385,22 @@ def plan_results(plan, stream=None):
 
 
 def plan_info(plan):
+    """Tile count, points, tile length, workgroups and, per order n present,
+    the lane mapping geometry[n] = (lanes per item, cooperative top levels)."""
     nt, npnt, tl, gb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    lanes = (ctypes.c_int32 * MAX_ORDER)()
+    top = (ctypes.c_int32 * MAX_ORDER)()
     _check(lib().qqmc_plan_info(plan.handle, ctypes.byref(nt), ctypes.byref(npnt),
-                                ctypes.byref(tl), ctypes.byref(gb)))
-    return dict(n_tiles=nt.value, n_points=npnt.value, tile_len=tl.value, grid_blocks=gb.value)
+                                ctypes.byref(tl), ctypes.byref(gb), lanes, top))
+    return dict(n_tiles=nt.value, n_points=npnt.value, tile_len=tl.value, grid_blocks=gb.value,
+                geometry={n + 1: (lanes[n], top[n]) for n in range(MAX_ORDER) if lanes[n]})
+
+
+def plan_set_geometry(plan, order, lanes_per_item, top_levels):
+    """Selects the lane mapping (lanes per item, cooperative top levels) of
+    the plan's scalar-tree charge group of this order."""
+    _check(lib().qqmc_plan_set_geometry(plan.handle, int(order), int(lanes_per_item),
+                                        int(top_levels)))
 
 
 class Server:

@@ -79,12 +79,13 @@ def _check_values(f_gpu, ref, label, mass_rel=1e-13):
     assert ok.all(), "%s: %d/%d values off" % (label, int((~ok).sum()), ok.size)
 
 
-@pytest.mark.parametrize("dot", ["alpha", "stress"])
+# the stress dot at the orders with cooperative top levels only
+_TREE_CASES = [(n, "alpha") for n in range(1, 15)] + [(n, "stress") for n in range(9, 15)]
+
+
 @pytest.mark.parametrize("alpha", [0.5, -0.35, "ns"])
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("n,dot", _TREE_CASES)
 def test_points_tree_alpha(q, oracle_mod, n, alpha, dot):
-    if dot == "stress" and n <= 8:
-        pytest.skip("the stress dot is checked at orders 9-14")
     d = STRESS_DOT if dot == "stress" else ALPHA_DOT
     tb = _tables(oracle_mod, d)
     gt = _upload(q, tb)
@@ -116,14 +117,15 @@ def _compare_q(q_gpu, q_or, label, rel=1e-9):
             "%s shift %d: %r vs %r" % (label, s, q_gpu[s], q_or[s])
 
 
-@pytest.mark.parametrize("dot", ["alpha", "stress"])
+_ORDER_SIZES = [(1, 14, 8), (2, 12, 4), (3, 12, 4), (4, 11, 3), (5, 11, 3), (6, 11, 3),
+                (7, 11, 3), (8, 11, 3), (9, 9, 2), (10, 9, 2), (11, 8, 1), (12, 8, 1)]
+_ORDER_CASES = [c + ("alpha",) for c in _ORDER_SIZES] + \
+    [c + ("stress",) for c in _ORDER_SIZES if c[0] >= 9]
+
+
 @pytest.mark.parametrize("alpha", [0.5, "ns"])
-@pytest.mark.parametrize("n,log2_n,K", [(1, 14, 8), (2, 12, 4), (3, 12, 4), (4, 11, 3),
-                                        (5, 11, 3), (6, 11, 3), (7, 11, 3), (8, 11, 3),
-                                        (9, 9, 2), (10, 9, 2), (11, 8, 1), (12, 8, 1)])
+@pytest.mark.parametrize("n,log2_n,K,dot", _ORDER_CASES)
 def test_eval_order_alpha(q, oracle_mod, n, log2_n, K, alpha, dot):
-    if dot == "stress" and n <= 8:
-        pytest.skip("the stress dot is checked at orders 9-12")
     d = STRESS_DOT if dot == "stress" else ALPHA_DOT
     tb = _tables(oracle_mod, d)
     gt = _upload(q, tb)

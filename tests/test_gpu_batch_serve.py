@@ -68,16 +68,77 @@ def test_plan_matches_single_launches_bitwise(q, oracle_mod):
     assert np.max(np.abs(res[8] - qo) / np.abs(qo)) < 1e-9
 
 
+def _geometry(n, alt):
+    """(lanes per item, cooperative top levels) of the scalar-tree charge
+    kernel's default mapping (a depth-5 register tree: 2^(n-5) lanes per
+    point up to order 10, 8 lanes per top-level prefix above) or its
+    alternative (a depth-4 tree at orders 5-8 and 11-14, cooperative top
+    levels at 9 and 10)."""
+    if n < 5:
+        return (1, 0)
+    if not alt:
+        return (1 << (n - 5), 0) if n <= 10 else (8, n - 8)
+    if n in (9, 10):
+        return (8, n - 8)
+    return (1 << (n - 4), 0) if n <= 8 else (16, n - 8)
+
+
 def test_plan_autotuned(q):
     dots, tabs, entries = _entries(q)
     plan = q.plan_create(entries, T_MEAS)
     info = q.plan_info(plan)
     assert info["tile_len"] in (64, 128, 256, 512, 1024, 2048) and info["grid_blocks"] >= 0
+    geo = info["geometry"]
+    assert sorted(geo) == [1, 3, 5, 8, 9]
+    for n, g in geo.items():
+        assert g in (_geometry(n, False), _geometry(n, True)), (n, g)
+    print("autotuned lane mappings:", geo)
     q.plan_run(plan)
     res = q.plan_results(plan)
     for (tb, job), got in zip(entries, res):
         ref = _solo(q, tb, job, info["tile_len"])
-        assert np.array_equal(got, ref)
+        if geo[job.order] == _geometry(job.order, False):
+            assert np.array_equal(got, ref)
+        else:
+            # the other lane mapping: the same estimate to rounding (the
+            # per-shift sums cancel, so the relative difference grows with
+            # the order; 1e-10 is ten times tighter than the parity bar)
+            assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10, job.order
+
+
+@pytest.mark.parametrize("n", [5, 6, 7, 8, 9, 10, 11, 12])
+def test_plan_lane_mappings_match_each_other_and_oracle(q, oracle_mod, n):
+    """Both lane mappings of the scalar-tree charge kernel against each
+    other (rounding) and the alternative against the oracle (parity bar)."""
+    d = Dot(-0.4, 1.0, 20.0, 0.3)
+    tb = q.make_tables(d)
+    log2_n, K = (11, 3) if n <= 8 else (9, 2) if n <= 10 else (8, 1)
+    job = order_job(700 + n, n, log2_n, K)
+    plan = q.plan_create([(tb, job)], T_MEAS, tile_len=64)
+    assert q.plan_info(plan)["geometry"] == {n: _geometry(n, False)}
+    q.plan_run(plan)
+    r0 = q.plan_results(plan)[0]
+    assert np.array_equal(r0, _solo(q, tb, job, 64))
+    q.plan_set_geometry(plan, n, *_geometry(n, True))
+    assert q.plan_info(plan)["geometry"] == {n: _geometry(n, True)}
+    with pytest.raises(q.QQMCError):
+        q.plan_set_geometry(plan, n, 3, 0)
+    q.plan_run(plan)
+    r1 = q.plan_results(plan)[0]
+    rel = np.max(np.abs(r1 - r0) / np.abs(r0))
+    to = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)
+    qo = oracle_mod.eval_sums(to, T_MEAS, n, job.log2_n, job.lattice_a, job.shifts,
+                              1.0) / (1 << job.log2_n)
+    worst = np.max(np.abs(r1 - qo) / np.abs(qo))
+    print("n=%d alternative vs default mapping: %.2e, vs oracle: %.2e" % (n, rel, worst))
+    # rounding only: the per-shift sums cancel (to 1e-12 relative at n = 11),
+    # so the mappings are held ten times tighter than the parity bar
+    assert rel < 1e-10
+    assert worst < 1e-9
+    # and back to the default: the single-order launch's bits again
+    q.plan_set_geometry(plan, n, *_geometry(n, False))
+    q.plan_run(plan)
+    assert np.array_equal(q.plan_results(plan)[0], r0)
 
 
 def test_server_results_equal_solo_runs(q):

@@ -311,9 +311,10 @@ qqmc_status capture(qqmc_plan_s *p)
  * given workgroup share; seconds per lattice point.  The subsample is the
  * same fraction of the work for every tile length (a quarter, less for
  * very large plans), so launch overheads weigh alike in every probe. */
-double probe(qqmc_plan_s *p, double share, const std::vector<Group> &which)
+double probe(qqmc_plan_s *p, double share, const std::vector<Group> &which, int64_t step = 0,
+             int reps = 2)
 {
-    const int64_t step = std::max<int64_t>(4, p->n_points / ((int64_t)1 << 26));
+    if (step <= 0) step = std::max<int64_t>(4, p->n_points / ((int64_t)1 << 26));
     std::vector<TileRef> sub;
     std::vector<Group> groups;
     double pts = 0.0;
@@ -335,7 +336,7 @@ double probe(qqmc_plan_s *p, double share, const std::vector<Group> &which)
     hipEventCreate(&a);
     hipEventCreate(&b);
     double best = 1e30;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < reps; ++rep) {
         hipEventRecord(a, p->cap);
         hipError_t e = enqueue(p, groups, d_sub, share, p->cap);
         hipEventRecord(b, p->cap);
@@ -454,7 +455,14 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
             Group a = g, b = g;
             a.alt = false;
             b.alt = true;
-            const double t0 = probe(p, best_share, {a}), t1 = probe(p, best_share, {b});
+            /* a group of up to 2^25 points is timed whole (a quarter of a
+             * small group is mostly launch overhead), larger ones on every
+             * k-th tile; best of three after a warm-up */
+            int64_t pts = 0;
+            for (int64_t t = 0; t < g.count; ++t) pts += p->items[p->tiles[g.offset + t].item].tile_len;
+            const int64_t step = pts <= ((int64_t)1 << 25) ? 1 : 0;
+            const double t0 = probe(p, best_share, {a}, step, 4);
+            const double t1 = probe(p, best_share, {b}, step, 4);
             g.alt = t1 < t0;
         }
     }

@@ -193,11 +193,15 @@ struct Env {
     int n_grid;
 };
 
-/* The first OFF = n - 8 eliminations of a work item (n > 8), done by the G
+/* The first OFF = n - 8 eliminations of a work item (n > 10), done by the G
  * lanes of the item's group with whole matrix rows per lane (row r on lane
  * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
  * 9 x 9 trailing correction block in s_c0 and returns the product of the
- * OFF pivots. */
+ * OFF pivots.  The Wick-table entries a level needs (the pivot row's, read
+ * by every lane of the group and used by the row's owner, and the pivot
+ * column's of the lane's own rows) depend only on the prefix, so they are
+ * read one level ahead: a level waits on local memory only for the pivot
+ * row its owner broadcasts. */
 template <int N, bool CUR = false, int MAP = kMapDefault>
 __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
                           cplx *s_row, cplx *s_c0)
@@ -211,22 +215,29 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
 #pragma unroll
         for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
     cplx prod = cmk(1.0, 0.0);
+    /* table entries of level k: wrow[j] = W(k, j), j > k; wcol[m] = W(r_m, k) */
+    cplx wrow[N + 1], wcol[RPL];
+    auto read_level = [&](int k, cplx *row, cplx *col) {
+        const int b = (top >> (OFF - 1 - k)) & 1;
+#pragma unroll
+        for (int j = k + 1; j <= N; ++j) row[j] = wick_entry_m<CUR>(pr, mc, k, j, N, b);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int r = sub + m * G;
+            col[m] = (r > k && r <= N) ? wick_entry(pr, r, k, b) : cmk(0.0, 0.0);
+        }
+    };
+    read_level(0, wrow, wcol);
 #pragma unroll
     for (int k = 0; k < OFF; ++k) {
-        const int b = (top >> (OFF - 1 - k)) & 1;
+        cplx nrow[N + 1], ncol[RPL];
+        if (k + 1 < OFF) read_level(k + 1, nrow, ncol);
 #pragma unroll
         for (int m = 0; m < RPL; ++m) {
             if (sub + m * G == k) {
-                /* every table read before the first store, so the reads
-                 * are issued together rather than each behind a store it
-                 * might alias */
-                cplx v[N + 1];
-#pragma unroll
-                for (int j = k + 1; j <= N; ++j)
-                    v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
                 s_row[k] = csub(g0, crow[m][k]);
 #pragma unroll
-                for (int j = k + 1; j <= N; ++j) s_row[j] = v[j];
+                for (int j = k + 1; j <= N; ++j) s_row[j] = csub(wrow[j], crow[m][j]);
             }
         }
         wave_sync();
@@ -236,13 +247,19 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
         for (int m = 0; m < RPL; ++m) {
             const int r = sub + m * G;
             if (r > k && r <= N) {
-                const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[m][k]), rp);
+                const cplx ch = cmul(csub(wcol[m], crow[m][k]), rp);
 #pragma unroll
                 for (int j = k + 1; j <= N; ++j) crow[m][j] = cfma(ch, s_row[j], crow[m][j]);
             }
         }
         prod = cmul(prod, p);
         wave_sync();
+        if (k + 1 < OFF) {
+#pragma unroll
+            for (int j = k + 2; j <= N; ++j) wrow[j] = nrow[j];
+#pragma unroll
+            for (int m = 0; m < RPL; ++m) wcol[m] = ncol[m];
+        }
     }
 #pragma unroll
     for (int m = 0; m < RPL; ++m) {

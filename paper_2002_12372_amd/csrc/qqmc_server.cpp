@@ -20,8 +20,14 @@
  *               one launch overlaps the next and the host prepares launches
  *               while the GPU runs;
  *   completion  when every tile of a request is done, its per-shift sums are
- *               reduced on a completion stream, copied to pinned host memory
- *               and its device buffers are returned to the pool.
+ *               reduced on the admission stream, copied to pinned host memory
+ *               and its device buffers are returned to the pool.  The
+ *               reduction is only queued when the launch retires: the
+ *               scheduler issues the next launch first and collects the
+ *               results once their event has fired (the reduction kernel
+ *               waits for compute units behind the launch in flight, and
+ *               waiting for it at once would leave that launch's tail
+ *               alone on the GPU).
  * Green's-function tables stay on the device, shared by requests with the
  * same dot parameters (reference counted; unused ones are evicted first when
  * memory runs short).  A request is cut into the tiles qqmc_eval_order
@@ -90,13 +96,19 @@ struct Launch {
     uint64_t seq = 0;
 };
 
-/* Per-shift reduction of finished requests. */
+/* Per-shift reduction of finished requests: at most one in flight (its
+ * buffers are reused by the next). */
 struct Completion {
     hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
     ItemDesc *h_items = nullptr, *d_items = nullptr;
     int64_t *h_base = nullptr, *d_base = nullptr;
     double *h_sums = nullptr, *d_sums = nullptr;
     size_t cap_items = 0, cap_base = 0, cap_sums = 0;
+    bool pending = false;
+    hipError_t error = hipSuccess;
+    std::vector<std::shared_ptr<Request>> fin;
+    std::vector<int64_t> base;
 };
 
 /* Grows a pinned host / device buffer pair to at least `need` elements. */
@@ -364,47 +376,26 @@ bool issue(qqmc_server_s *s, Launch &L)
     return true;
 }
 
-/* Reduces the per-shift sums of finished requests on the completion stream,
- * copies them back and releases their device buffers (lock held). */
-void complete(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin)
+/* Finishes the completion in flight, if any: waits for its event (lock
+ * released meanwhile), then hands the per-shift results to the requests and
+ * returns their budget.  Called by the scheduler thread only. */
+void complete_end(qqmc_server_s *s, std::unique_lock<std::mutex> &lk)
 {
-    if (fin.empty()) return;
     Completion &C = s->comp;
-    std::vector<int64_t> base(fin.size());
-    int64_t sums = 0;
-    int32_t kmax = 1;
-    for (size_t c = 0; c < fin.size(); ++c) {
-        base[c] = sums;
-        sums += fin[c]->desc.n_shifts;
-        kmax = std::max(kmax, fin[c]->desc.n_shifts);
-    }
-    hipError_t e = grow_pair(&C.h_items, &C.d_items, &C.cap_items, fin.size());
-    if (e == hipSuccess) e = grow_pair(&C.h_base, &C.d_base, &C.cap_base, fin.size());
-    if (e == hipSuccess) e = grow_pair(&C.h_sums, &C.d_sums, &C.cap_sums, 2 * (size_t)sums);
-    if (e == hipSuccess) {
-        for (size_t c = 0; c < fin.size(); ++c) {
-            C.h_items[c] = fin[c]->desc;
-            C.h_base[c] = base[c];
-        }
-        e = hipMemcpyAsync(C.d_items, C.h_items, sizeof(ItemDesc) * fin.size(), hipMemcpyHostToDevice,
-                           C.stream);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(C.d_base, C.h_base, sizeof(int64_t) * fin.size(), hipMemcpyHostToDevice, C.stream);
-    if (e == hipSuccess)
-        e = launch_shift_reduce(C.d_items, (int32_t)fin.size(), C.d_base, C.d_sums, kmax, C.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(C.h_sums, C.d_sums, sizeof(double) * 2 * sums, hipMemcpyDeviceToHost, C.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(C.stream);
+    if (!C.pending) return;
+    lk.unlock();
+    hipError_t e = hipEventSynchronize(C.done);
+    lk.lock();
+    if (C.error != hipSuccess) e = C.error;
     const qqmc_status st = e == hipSuccess ? QQMC_OK : hip_error(e, "server completion");
     const double now = s->now();
-    for (size_t c = 0; c < fin.size(); ++c) {
-        auto &r = fin[c];
+    for (size_t c = 0; c < C.fin.size(); ++c) {
+        auto &r = C.fin[c];
         if (r->status == QQMC_OK && st != QQMC_OK) r->status = st;
         if (r->status == QQMC_OK) {
             const int K = r->desc.n_shifts;
             const double N = (double)r->desc.mask + 1.0;
-            const double *v = C.h_sums + 2 * base[c];
+            const double *v = C.h_sums + 2 * C.base[c];
             r->q_shift.resize(2 * (size_t)K);
             double mr = 0.0, mi = 0.0;
             for (int k = 0; k < K; ++k) {
@@ -421,17 +412,14 @@ void complete(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin)
             for (int k = 0; k < K; ++k) ss += (r->q_shift[2 * k] - mr) * (r->q_shift[2 * k] - mr);
             r->q_stderr = K > 1 ? std::sqrt(ss / (K - 1)) / std::sqrt((double)K) : std::nan("");
         }
-        hipFreeAsync(r->d_shifts, C.stream);
-        hipFreeAsync(r->d_tiles, C.stream);
-        if (r->d_sobol) hipFreeAsync(r->d_sobol, C.stream);
-        r->d_shifts = r->d_tiles = nullptr;
-        r->d_sobol = nullptr;
         s->used -= request_bytes(*r, false);
         auto it = s->tables.find(r->key);
         if (it != s->tables.end()) it->second.refs -= 1;
         r->t_done = now;
         r->finished = true;
     }
+    C.fin.clear();
+    C.pending = false;
     std::vector<std::shared_ptr<Request>> still;
     for (auto &r : s->active)
         if (!r->finished) still.push_back(r);
@@ -439,8 +427,56 @@ void complete(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin)
     s->cv_done.notify_all();
 }
 
-/* Waits for launch L (lock released meanwhile) and completes the requests
- * whose last tiles it ran. */
+/* Queues the per-shift reduction of finished requests on the completion
+ * stream, the copy of the sums to pinned host memory and the release of the
+ * requests' device buffers, then records the completion's event; the
+ * results are taken by complete_end.  Lock held. */
+void complete_begin(qqmc_server_s *s, std::vector<std::shared_ptr<Request>> &fin,
+                    std::unique_lock<std::mutex> &lk)
+{
+    if (fin.empty()) return;
+    complete_end(s, lk);
+    Completion &C = s->comp;
+    C.base.assign(fin.size(), 0);
+    int64_t sums = 0;
+    int32_t kmax = 1;
+    for (size_t c = 0; c < fin.size(); ++c) {
+        C.base[c] = sums;
+        sums += fin[c]->desc.n_shifts;
+        kmax = std::max(kmax, fin[c]->desc.n_shifts);
+    }
+    hipError_t e = grow_pair(&C.h_items, &C.d_items, &C.cap_items, fin.size());
+    if (e == hipSuccess) e = grow_pair(&C.h_base, &C.d_base, &C.cap_base, fin.size());
+    if (e == hipSuccess) e = grow_pair(&C.h_sums, &C.d_sums, &C.cap_sums, 2 * (size_t)sums);
+    if (e == hipSuccess) {
+        for (size_t c = 0; c < fin.size(); ++c) {
+            C.h_items[c] = fin[c]->desc;
+            C.h_base[c] = C.base[c];
+        }
+        e = hipMemcpyAsync(C.d_items, C.h_items, sizeof(ItemDesc) * fin.size(), hipMemcpyHostToDevice,
+                           C.stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(C.d_base, C.h_base, sizeof(int64_t) * fin.size(), hipMemcpyHostToDevice, C.stream);
+    if (e == hipSuccess)
+        e = launch_shift_reduce(C.d_items, (int32_t)fin.size(), C.d_base, C.d_sums, kmax, C.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(C.h_sums, C.d_sums, sizeof(double) * 2 * sums, hipMemcpyDeviceToHost, C.stream);
+    for (auto &r : fin) {
+        hipFreeAsync(r->d_shifts, C.stream);
+        hipFreeAsync(r->d_tiles, C.stream);
+        if (r->d_sobol) hipFreeAsync(r->d_sobol, C.stream);
+        r->d_shifts = r->d_tiles = nullptr;
+        r->d_sobol = nullptr;
+    }
+    const hipError_t er = hipEventRecord(C.done, C.stream);
+    C.error = e != hipSuccess ? e : er;
+    C.fin.swap(fin);
+    C.pending = true;
+}
+
+/* Waits for launch L (lock released meanwhile) and starts the completion
+ * of the requests whose last tiles it ran. */
 void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
 {
     lk.unlock();
@@ -453,7 +489,7 @@ void retire(qqmc_server_s *s, Launch &L, std::unique_lock<std::mutex> &lk)
         if (pr.first->done_tiles == pr.first->desc.n_tiles) fin.push_back(pr.first);
     }
     L.issued.clear();
-    complete(s, fin);
+    complete_begin(s, fin, lk);
 }
 
 void worker_loop(qqmc_server_s *s)
@@ -462,6 +498,11 @@ void worker_loop(qqmc_server_s *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         admit(s);
+        /* results whose reduction has finished, without waiting */
+        if (s->comp.pending && hipEventQuery(s->comp.done) != hipErrorNotReady) {
+            complete_end(s, lk);
+            continue;
+        }
         int slot = -1;
         for (int i = 0; i < kSlots; ++i)
             if (!s->launches[i].busy) {
@@ -476,6 +517,10 @@ void worker_loop(qqmc_server_s *s)
                 oldest = i;
         if (oldest >= 0) {
             retire(s, s->launches[oldest], lk);
+            continue;
+        }
+        if (s->comp.pending) {
+            complete_end(s, lk);
             continue;
         }
         if (s->stop && s->waiting.empty() && s->active.empty()) break;
@@ -507,14 +552,23 @@ qqmc_status qqmc_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     hipGetDevice(&s->device);
-    hipError_t e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->comp.stream, hipStreamNonBlocking);
+    /* Three streams: the two launch slots, created first, and one for
+     * admission and completion.  HIP maps a process's streams onto a few
+     * hardware queues (four by default) and streams past that share one;
+     * two launch streams on one queue run one after the other, which takes
+     * the overlap of launch tails away (measured: one kernel in flight 97%
+     * of the time instead of two, 7% longer makespan, when a fourth server
+     * stream shared a queue after the caller's default stream). */
+    hipError_t e = hipSuccess;
     for (int i = 0; i < kSlots && e == hipSuccess; ++i) {
         Launch &L = s->launches[i];
         e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted, hipEventDisableTiming);
+    s->comp.stream = s->admit_stream;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->comp.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete s;
         return hip_error(e, "server streams");
@@ -643,7 +697,7 @@ void qqmc_server_destroy(qqmc_server s)
         if (r->d_sobol) hipFree(r->d_sobol);
     }
     for (auto &kv : s->tables) qqmc_free_tables(kv.second.t);
-    if (C.stream) hipStreamDestroy(C.stream);
+    if (C.done) hipEventDestroy(C.done);
     if (s->admitted) hipEventDestroy(s->admitted);
     if (s->admit_stream) hipStreamDestroy(s->admit_stream);
     delete s;

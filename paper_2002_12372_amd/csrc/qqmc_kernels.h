@@ -77,8 +77,9 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
     static constexpr int pairs = ids + QCAP * 4;                       /* tables*NP pairv */
-    /* one broadcast row per group (two for the paired tree) */
-    static constexpr int rows = PAIR ? 2 : 1;
+    /* broadcast rows per group: two for the paired tree and for the scalar
+     * tree's two-level top steps */
+    static constexpr int rows = (PAIR || Gm::OFF >= 2) ? 2 : 1;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
     static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
     static constexpr int c0_end = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
@@ -197,11 +198,17 @@ struct Env {
  * lanes of the item's group with whole matrix rows per lane (row r on lane
  * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
  * 9 x 9 trailing correction block in s_c0 and returns the product of the
- * OFF pivots.  The Wick-table entries a level needs (the pivot row's, read
- * by every lane of the group and used by the row's owner, and the pivot
- * column's of the lane's own rows) depend only on the prefix, so they are
- * read one level ahead: a level waits on local memory only for the pivot
- * row its owner broadcasts. */
+ * OFF pivots.
+ *
+ * Levels go two at a time: with T = (Wick entries) - C the trailing matrix,
+ * vertices k and k+1 are eliminated together through their 2x2 block
+ * P = [[T_kk, T_k,k+1], [T_k+1,k, T_k+1,k+1]] (entries of vertex k on b_k,
+ * the later row of k+1 on b_k+1),
+ *     C_rj += [T_rk T_r,k+1] P^{-1} [T_kj; T_k+1,j],   j, r > k + 1,
+ * which is the two single steps' Schur complement, and det P is the product
+ * of their two pivots.  Both owners broadcast their rows through s_row at
+ * once, so a pair of levels waits on local memory once instead of twice;
+ * an odd last level is a single step. */
 template <int N, bool CUR = false, int MAP = kMapDefault>
 __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cplx g0,
                           cplx *s_row, cplx *s_c0)
@@ -209,56 +216,93 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
     using Gm = Geo<N, false, MAP>;
     constexpr int OFF = Gm::OFF, K = Gm::K, G = Gm::G;
     constexpr int RPL = (N + G) / G; /* rows per lane: ceil((N + 1) / G) */
+    cplx *s_r0 = s_row, *s_r1 = s_row + (N + 1);
     cplx crow[RPL][N + 1];
 #pragma unroll
     for (int m = 0; m < RPL; ++m)
 #pragma unroll
         for (int j = 0; j <= N; ++j) crow[m][j] = cmk(0.0, 0.0);
     cplx prod = cmk(1.0, 0.0);
-    /* table entries of level k: wrow[j] = W(k, j), j > k; wcol[m] = W(r_m, k) */
-    cplx wrow[N + 1], wcol[RPL];
-    auto read_level = [&](int k, cplx *row, cplx *col) {
+#pragma unroll
+    for (int k = 0; k < OFF; k += 2) {
         const int b = (top >> (OFF - 1 - k)) & 1;
-#pragma unroll
-        for (int j = k + 1; j <= N; ++j) row[j] = wick_entry_m<CUR>(pr, mc, k, j, N, b);
-#pragma unroll
-        for (int m = 0; m < RPL; ++m) {
-            const int r = sub + m * G;
-            col[m] = (r > k && r <= N) ? wick_entry(pr, r, k, b) : cmk(0.0, 0.0);
-        }
-    };
-    read_level(0, wrow, wcol);
-#pragma unroll
-    for (int k = 0; k < OFF; ++k) {
-        cplx nrow[N + 1], ncol[RPL];
-        if (k + 1 < OFF) read_level(k + 1, nrow, ncol);
-#pragma unroll
-        for (int m = 0; m < RPL; ++m) {
-            if (sub + m * G == k) {
-                s_row[k] = csub(g0, crow[m][k]);
-#pragma unroll
-                for (int j = k + 1; j <= N; ++j) s_row[j] = csub(wrow[j], crow[m][j]);
-            }
-        }
-        wave_sync();
-        const cplx p = s_row[k];
-        const cplx rp = crecip_nr(p);
-#pragma unroll
-        for (int m = 0; m < RPL; ++m) {
-            const int r = sub + m * G;
-            if (r > k && r <= N) {
-                const cplx ch = cmul(csub(wcol[m], crow[m][k]), rp);
-#pragma unroll
-                for (int j = k + 1; j <= N; ++j) crow[m][j] = cfma(ch, s_row[j], crow[m][j]);
-            }
-        }
-        prod = cmul(prod, p);
-        wave_sync();
         if (k + 1 < OFF) {
+            const int bq = (top >> (OFF - 2 - k)) & 1;
 #pragma unroll
-            for (int j = k + 2; j <= N; ++j) wrow[j] = nrow[j];
+            for (int m = 0; m < RPL; ++m) {
+                const int r = sub + m * G;
+                /* every table read before the first store, so the reads
+                 * are issued together rather than each behind a store it
+                 * might alias */
+                if (r == k) {
+                    cplx v[N + 1];
 #pragma unroll
-            for (int m = 0; m < RPL; ++m) wcol[m] = ncol[m];
+                    for (int j = k + 1; j <= N; ++j)
+                        v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
+                    s_r0[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                    for (int j = k + 1; j <= N; ++j) s_r0[j] = v[j];
+                } else if (r == k + 1) {
+                    cplx v[N + 1];
+                    /* (k+1, k): the earlier point is k, so index b */
+                    v[k] = csub(wick_entry(pr, k + 1, k, b), crow[m][k]);
+#pragma unroll
+                    for (int j = k + 2; j <= N; ++j)
+                        v[j] = csub(wick_entry_m<CUR>(pr, mc, k + 1, j, N, bq), crow[m][j]);
+                    s_r1[k] = v[k];
+                    s_r1[k + 1] = csub(g0, crow[m][k + 1]);
+#pragma unroll
+                    for (int j = k + 2; j <= N; ++j) s_r1[j] = v[j];
+                }
+            }
+            wave_sync();
+            const cplx a = s_r0[k], bb = s_r0[k + 1], c = s_r1[k], d = s_r1[k + 1];
+            const cplx det = cfms(bb, c, cmul(a, d)); /* a d - bb c */
+            const cplx rd = crecip_nr(det);
+            const cplx ia = cmul(a, rd), ib = cmul(bb, rd), ic = cmul(c, rd), id = cmul(d, rd);
+#pragma unroll
+            for (int m = 0; m < RPL; ++m) {
+                const int r = sub + m * G;
+                if (r > k + 1 && r <= N) {
+                    const cplx u = csub(wick_entry(pr, r, k, b), crow[m][k]);
+                    const cplx v = csub(wick_entry(pr, r, k + 1, bq), crow[m][k + 1]);
+                    /* [x y] = [u v] P^{-1} */
+                    const cplx x = cfms(v, ic, cmul(u, id));
+                    const cplx y = cfms(u, ib, cmul(v, ia));
+#pragma unroll
+                    for (int j = k + 2; j <= N; ++j)
+                        crow[m][j] = cfma(y, s_r1[j], cfma(x, s_r0[j], crow[m][j]));
+                }
+            }
+            prod = cmul(prod, det);
+            wave_sync();
+        } else {
+#pragma unroll
+            for (int m = 0; m < RPL; ++m) {
+                if (sub + m * G == k) {
+                    cplx v[N + 1];
+#pragma unroll
+                    for (int j = k + 1; j <= N; ++j)
+                        v[j] = csub(wick_entry_m<CUR>(pr, mc, k, j, N, b), crow[m][j]);
+                    s_r0[k] = csub(g0, crow[m][k]);
+#pragma unroll
+                    for (int j = k + 1; j <= N; ++j) s_r0[j] = v[j];
+                }
+            }
+            wave_sync();
+            const cplx p = s_r0[k];
+            const cplx rp = crecip_nr(p);
+#pragma unroll
+            for (int m = 0; m < RPL; ++m) {
+                const int r = sub + m * G;
+                if (r > k && r <= N) {
+                    const cplx ch = cmul(csub(wick_entry(pr, r, k, b), crow[m][k]), rp);
+#pragma unroll
+                    for (int j = k + 1; j <= N; ++j) crow[m][j] = cfma(ch, s_r0[j], crow[m][j]);
+                }
+            }
+            prod = cmul(prod, p);
+            wave_sync();
         }
     }
 #pragma unroll

@@ -52,13 +52,15 @@ namespace qqmc {
  * (U, V of a pair step; largest component) exceeds kGrowthFlag is evaluated
  * again with the shifted grouping, and if one of that tree's multipliers
  * exceeds kShiftFlag, by the adaptive path.  Set from CPU scans against a
- * quad-precision Keldysh sum (alpha = n_sigma, orders 7-8, two dots, 6000
- * points): 4-8% of points are evaluated again, 0-0.13% reach the adaptive
- * path, and every point ends within 2.5e-14 of its term mass.  (Tracking the
- * multipliers alone costs two maximum instructions per value; a bound on the
- * correction's growth, |U| |x| + |V| |y|, flagged slightly fewer points but
- * made the register tree 12-25% slower.) */
-constexpr double kGrowthFlag = 64.0;
+ * quad-precision Keldysh sum (alpha = n_sigma; orders 6-8 on five dots,
+ * among them the paper's finite-bandwidth dot at t = 100, 1500 points each):
+ * with 128, 2-8% of points are evaluated again and every point the register
+ * tree keeps is within 3.5e-14 of its term mass (64: 5-14% evaluated again,
+ * 2.4e-14; 256: up to 1.5e-13); 0-0.13% reach the adaptive path.  (Tracking
+ * the multipliers alone costs two maximum instructions per value; a bound on
+ * the correction's growth, |U| |x| + |V| |y|, flagged slightly fewer points
+ * but made the register tree 12-25% slower.) */
+constexpr double kGrowthFlag = 128.0;
 constexpr double kShiftFlag = 256.0;
 /* The adaptive path takes a single-vertex step when its growth bound stays
  * below this at every node of the level. */

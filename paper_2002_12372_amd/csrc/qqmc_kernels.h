@@ -89,7 +89,17 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
      * keeps a workgroup (Sobol' numbers included) within 40 KiB, the share
      * of each of the four one-wave workgroups a compute unit holds in its
      * 160 KiB of local memory */
-    static constexpr int adapt = (c0_end + 15) & ~15;
+    /* the paired tree's flagged points carried from one batch of a tile to
+     * the next (orders <= 8): up to eight points' times and weights, their
+     * count, the results of a pass and the sum of their contributions */
+    static constexpr bool CARRY = PAIR && Gm::OFF == 0;
+    static constexpr int dq = (c0_end + 15) & ~15;                     /* 8*N doubles */
+    static constexpr int dq_w = dq + (CARRY ? 8 * N * 8 : 0);          /* 8 doubles   */
+    static constexpr int dq_res = dq_w + (CARRY ? 8 * 8 : 0);          /* 8 cplx      */
+    static constexpr int dq_sum = dq_res + (CARRY ? 8 * 16 : 0);       /* cplx        */
+    static constexpr int dq_n = dq_sum + (CARRY ? 16 : 0);             /* int         */
+    static constexpr int dq_end = dq_n + (CARRY ? 16 : 0);
+    static constexpr int adapt = (dq_end + 15) & ~15;
     static constexpr int sob_bytes = N * 32 * 4;
     static constexpr int kShare = 40960;
     static constexpr int MB = !PAIR ? 8
@@ -489,7 +499,10 @@ __device__ __forceinline__ pairv pair_entry(int q, const double *tm, const Env &
 
 /* Evaluates S(u) for the `cnt` points whose vertex times (elimination order,
  * earliest first) sit in s_times; writes S to s_S[0..cnt). */
-template <int N, bool PAIR = false, bool CUR = false, int MAP = kMapDefault>
+template <int N, bool CUR, bool CARRY>
+__device__ void resolve_flagged(uint64_t deferred, bool flush, const Env &env, char *lds);
+
+template <int N, bool PAIR = false, bool CUR = false, int MAP = kMapDefault, bool CARRY = false>
 __device__ void keldysh_points(int cnt, const Env &env, char *lds)
 {
     using Gm = Geo<N, PAIR, MAP>;
@@ -712,77 +725,151 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             if ((base + Gm::PPW) % Gm::IPP == 0) point_top_flag = false;
         }
     }
-    if constexpr (PAIR && Gm::OFF == 0) {
-        /* The flagged points of the batch: their tables rebuilt in the
-         * adaptive path's workspace, eight points at a time, each on eight
-         * lanes with the shifted grouping; a point flagged again is
-         * evaluated by the adaptive path (its table rebuilt in the first
-         * table slot).  Wave-uniform throughout. */
-        constexpr bool SHIFT = N >= 4;
-        pairv *tabs = reinterpret_cast<pairv *>(lds + L::adapt);
-        static_assert(8 * NPS * (int)sizeof(pairv) <= AdaptWs<N, L::MB>::bytes,
-                      "eight pair tables fit in the adaptive workspace");
-        while (deferred) {
-            int pts[8];
-            int nf = 0;
-            for (int k = 0; k < 8; ++k) {
-                pts[k] = -1;
-                if (deferred) {
-                    pts[k] = __builtin_ctzll(deferred);
-                    deferred &= deferred - 1;
-                    ++nf;
-                }
+    if constexpr (PAIR && Gm::OFF == 0) resolve_flagged<N, CUR, CARRY>(deferred, false, env, lds);
+}
+
+/* The paired tree's flagged points (orders <= 8): re-evaluated eight at a
+ * time, each on eight lanes with the shifted grouping, their tables rebuilt
+ * in the adaptive path's workspace; a point flagged again is evaluated by
+ * the adaptive path (its table rebuilt in the first table slot).  `deferred`
+ * holds the batch's flagged points (bit per point of s_times).
+ *
+ * With CARRY (the tile function, not the learning pass) a pass runs only
+ * when eight points are at hand: the batch's leftover flagged points move to
+ * a queue in local memory (times and weights; their batch sums become zero)
+ * and fill the next batch's first pass, and `flush` (the tile's end) runs
+ * whatever is queued.  A queued point's result, prefactor times weight, is
+ * added to the queue's sum by lane 0 in slot order; the tile adds that sum
+ * once, so tile sums stay reproducible.  Without CARRY every flagged point
+ * is resolved into s_S before returning.  Wave-uniform throughout. */
+template <int N, bool CUR, bool CARRY>
+__device__ void resolve_flagged(uint64_t deferred, bool flush, const Env &env, char *lds)
+{
+    using Gm = Geo<N, true>;
+    using L = Lds<N, true, CUR>;
+    constexpr int NPS = L::NPS;
+    constexpr bool SHIFT = N >= 4;
+    const int lane = threadIdx.x;
+    const double *s_times = reinterpret_cast<const double *>(lds + L::times);
+    const double *s_w = reinterpret_cast<const double *>(lds + L::w);
+    cplx *s_S = reinterpret_cast<cplx *>(lds + L::S);
+    pairv *s_pairs = reinterpret_cast<pairv *>(lds + L::pairs);
+    pairv *tabs = reinterpret_cast<pairv *>(lds + L::adapt);
+    double *q_times = reinterpret_cast<double *>(lds + L::dq);
+    double *q_w = reinterpret_cast<double *>(lds + L::dq_w);
+    cplx *q_res = reinterpret_cast<cplx *>(lds + L::dq_res);
+    cplx *q_sum = reinterpret_cast<cplx *>(lds + L::dq_sum);
+    int *q_n = reinterpret_cast<int *>(lds + L::dq_n);
+    static_assert(8 * NPS * (int)sizeof(pairv) <= AdaptWs<N, L::MB>::bytes,
+                  "eight pair tables fit in the adaptive workspace");
+    int carried = CARRY ? *q_n : 0;
+    for (;;) {
+        const int nb = __popcll(deferred);
+        if (carried + nb == 0) break;
+        if (CARRY && !flush && carried + nb < 8) break;
+        /* slots: the queued points first (all of them: fewer than eight),
+         * then points of the batch */
+        int pts[8];
+        int nf = 0;
+        for (int k = 0; k < 8; ++k) {
+            pts[k] = -1;
+            if (k < carried) {
+                pts[k] = k;
+                ++nf;
+            } else if (deferred) {
+                pts[k] = __builtin_ctzll(deferred);
+                deferred &= deferred - 1;
+                ++nf;
             }
-            int mine = -1;
+        }
+        const int slot = lane >> 3;
+        int mine = -1;
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if ((lane >> 3) == k) mine = pts[k];
-            uint64_t again = 0;
-            cplx r = cmk(0.0, 0.0);
-            if constexpr (SHIFT) {
-                for (int e = lane; e < nf * NPS; e += WAVE) {
-                    const int slot = e / NPS, q = e - slot * NPS;
-                    int p = 0;
+        for (int k = 0; k < 8; ++k)
+            if (slot == k) mine = pts[k];
+        auto times_of = [&](int k, int p) -> const double * {
+            return k < carried ? q_times + p * N : s_times + p * N;
+        };
+        uint64_t again = 0;
+        cplx r = cmk(0.0, 0.0);
+        if constexpr (SHIFT) {
+            for (int e = lane; e < nf * NPS; e += WAVE) {
+                const int sl = e / NPS, q = e - sl * NPS;
+                int p = 0;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (k == slot) p = pts[k];
-                    tabs[e] = pair_entry<N, CUR>(q, s_times + p * N, env);
-                }
-                wave_sync();
-                double g2 = 0.0;
-                if (mine >= 0) {
-                    const pairv *tg = tabs + (lane >> 3) * NPS;
-                    const ShiftOut o = shift_lane<N, CUR>(tg, tg + (CUR ? Gm::NP : pidx(0, N)),
-                                                          nullptr, lane & 7, 0, env.g0,
-                                                          cmk(1.0, 0.0));
-                    r = o.v;
-                    g2 = o.grow;
-                }
-#pragma unroll
-                for (int m = 1; m < 8; m <<= 1) {
-                    r.x += shfl_xor_d(r.x, m);
-                    r.y += shfl_xor_d(r.y, m);
-                }
-                again = __ballot(mine >= 0 && g2 > kShiftFlag);
-                if (mine >= 0 && (lane & 7) == 0 && !((again >> lane) & 0xffull)) s_S[mine] = r;
-                wave_sync();
-            } else {
-                again = __ballot(mine >= 0);
+                for (int k = 0; k < 8; ++k)
+                    if (k == sl) p = pts[k];
+                tabs[e] = pair_entry<N, CUR>(q, times_of(sl, p), env);
+            }
+            wave_sync();
+            double g2 = 0.0;
+            if (mine >= 0) {
+                const pairv *tg = tabs + slot * NPS;
+                const ShiftOut o = shift_lane<N, CUR>(tg, tg + (CUR ? Gm::NP : pidx(0, N)), nullptr,
+                                                      lane & 7, 0, env.g0, cmk(1.0, 0.0));
+                r = o.v;
+                g2 = o.grow;
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k >= nf || !((again >> (8 * k)) & 0xffull)) continue;
-                const int p = pts[k];
-                for (int q = lane; q < NPS; q += WAVE)
-                    s_pairs[q] = pair_entry<N, CUR>(q, s_times + p * N, env);
-                wave_sync();
-                const cplx ra = adapt_point<N, CUR, L::MB>(
-                    s_pairs, s_pairs + (CUR ? Gm::NP : pidx(0, N)), env.g0, lds + L::adapt,
-                    nullptr, N + 1, 0, cmk(1.0, 0.0));
-                if (lane == 0) s_S[p] = ra;
+            for (int m = 1; m < 8; m <<= 1) {
+                r.x += shfl_xor_d(r.x, m);
+                r.y += shfl_xor_d(r.y, m);
+            }
+            again = __ballot(mine >= 0 && g2 > kShiftFlag);
+            if (mine >= 0 && (lane & 7) == 0 && !((again >> lane) & 0xffull)) {
+                if (slot < carried) q_res[slot] = r;
+                else s_S[mine] = r;
+            }
+            wave_sync();
+        } else {
+            again = __ballot(mine >= 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= nf || !((again >> (8 * k)) & 0xffull)) continue;
+            const int p = pts[k];
+            const double *tm = times_of(k, p);
+            for (int q = lane; q < NPS; q += WAVE) s_pairs[q] = pair_entry<N, CUR>(q, tm, env);
+            wave_sync();
+            const cplx ra = adapt_point<N, CUR, L::MB>(
+                s_pairs, s_pairs + (CUR ? Gm::NP : pidx(0, N)), env.g0, lds + L::adapt, nullptr, N + 1,
+                0, cmk(1.0, 0.0));
+            if (lane == 0) {
+                if (k < carried) q_res[k] = ra;
+                else s_S[p] = ra;
+            }
+            wave_sync();
+        }
+        if constexpr (CARRY) {
+            if (carried > 0) {
+                if (lane == 0) {
+                    cplx acc = *q_sum;
+                    for (int k = 0; k < carried; ++k) {
+                        const cplx f = observable_prefactor<N, CUR>(q_res[k]);
+                        acc = cadd(acc, cmk(f.x * q_w[k], f.y * q_w[k]));
+                    }
+                    *q_sum = acc;
+                }
                 wave_sync();
             }
         }
+        carried = 0;
+    }
+    if constexpr (CARRY) {
+        /* the batch's leftover flagged points join the queue */
+        int k = carried;
+        while (deferred) {
+            const int p = __builtin_ctzll(deferred);
+            deferred &= deferred - 1;
+            for (int j = lane; j < N; j += WAVE) q_times[k * N + j] = s_times[p * N + j];
+            if (lane == 0) {
+                q_w[k] = s_w[p];
+                s_S[p] = cmk(0.0, 0.0);
+            }
+            ++k;
+        }
+        if (lane == 0) *q_n = k;
+        wave_sync();
     }
 }
 
@@ -903,6 +990,16 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
                 for (int j = 0; j < N; ++j) word[j] ^= s_v[j * 32 + k];
             }
     }
+    /* the paired tree's queue of flagged points, carried across the
+     * tile's batches (not in the learning pass) */
+    constexpr bool CARRY = L::CARRY && !SAMPLE;
+    if constexpr (CARRY) {
+        if (lane == 0) {
+            *reinterpret_cast<int *>(lds + L::dq_n) = 0;
+            *reinterpret_cast<cplx *>(lds + L::dq_sum) = cmk(0.0, 0.0);
+        }
+        wave_sync();
+    }
     Kahan acc;
     if constexpr (L::QUEUE) {
         /* In-domain points queue in local memory across steps and the trees
@@ -944,7 +1041,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             /* a batch of 64 queued points, or on the tile's last step the
              * rest (up to 64; what is left then goes in the next pass) */
             const int m = queued < WAVE ? queued : WAVE;
-            keldysh_points<N, PAIR, CUR, MAP>(m, env, lds);
+            keldysh_points<N, PAIR, CUR, MAP, CARRY>(m, env, lds);
             if (lane < m) {
                 const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
                 const double w = s_w[lane];
@@ -990,7 +1087,7 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
                 it.sample_out[idx] = 0.0;
             }
             wave_sync();
-            keldysh_points<N, PAIR, CUR, MAP>(cnt, env, lds);
+            keldysh_points<N, PAIR, CUR, MAP, CARRY>(cnt, env, lds);
             if (lane < cnt) {
                 const cplx f = observable_prefactor<N, CUR>(s_S[lane]);
                 const double w = s_w[lane];
@@ -999,6 +1096,12 @@ __device__ cplx order_tile(const ItemDesc &it, int64_t tile, char *lds)
             }
             wave_sync();
         }
+    }
+    if constexpr (CARRY) {
+        /* the queued flagged points: their last pass, and their sum */
+        resolve_flagged<N, CUR, true>(0, true, env, lds);
+        const cplx q = *reinterpret_cast<const cplx *>(lds + L::dq_sum);
+        if (lane == 0 && (q.x != 0.0 || q.y != 0.0)) acc.add(q);
     }
     return wave_sum(acc.value());
 }

@@ -326,9 +326,9 @@ void qqmc_free_model(qqmc_model m);
 /* ---- Batched form -------------------------------------------------------
  * Many (parameter point, order) integrals in one persistent launch.  Each
  * item is estimated exactly as qqmc_eval_order_async estimates it at the
- * plan's tile_len (the same tile decomposition, hence the same per-shift
- * sums bit for bit, as long as every order keeps its default lane mapping:
- * see qqmc_plan_set_geometry).  The plan owns device buffers and a captured
+ * plan's tile_len (0: at each item's default; the same tile decomposition,
+ * hence the same per-shift sums bit for bit, as long as every order keeps
+ * its default lane mapping: see qqmc_plan_set_geometry).  The plan owns device buffers and a captured
  * HIP graph; qqmc_plan_run replays it. */
 typedef struct {
     qqmc_tables tables;
@@ -357,7 +357,9 @@ qqmc_status qqmc_plan_run(qqmc_plan p, void *stream);
  * 2*n_shifts(item) doubles per item in item order (divided by N). */
 qqmc_status qqmc_plan_results(qqmc_plan p, void *stream, double *q_shift);
 /* Number of tiles and of lattice points (all items, all shifts), the tile
- * length and the workgroup count, and the lane mapping of each order n at
+ * length (0: each item at its own default tile length, the one
+ * qqmc_eval_order takes when given 0) and the workgroup count, and the lane
+ * mapping of each order n at
  * index n - 1 of two arrays of QQMC_MAX_ORDER entries (either may be NULL):
  * lanes_per_item, the lanes of one wavefront that evaluate one item
  * together (64 / lanes items share a wavefront), and top_levels, the

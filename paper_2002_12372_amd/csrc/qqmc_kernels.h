@@ -19,11 +19,13 @@
  *   3. for every compacted point builds the pair table of interpolated
  *      g^<(tau), g^>(tau) in LDS (lanes of the point's group share the work),
  *   4. evaluates the Keldysh sum with the elimination tree of qqmc_tree.h,
- *      G = 2^T lanes per point (or per top-level prefix for n > 8),
+ *      G = 2^T lanes per point (or per top-level prefix above order 10),
  *   5. folds -2 i^{n+1} S(u) W into a per-lane compensated accumulator.
- * The tree kernels are compiled for two waves per SIMD (256 registers per
- * lane; the few values that do not fit go to scratch), which measured
- * faster than one wave per SIMD with no spills.
+ * The tree kernels whose lanes start from a 6 x 6 block (scalar orders 5
+ * and up, every paired order from 4) are compiled for one wave per SIMD:
+ * the register tree needs the whole register file (architectural and
+ * accumulation registers) and spills nothing; the smaller orders run two
+ * waves per SIMD (Geo::WPS).
  * The tile's sum goes to one slot of a partials array; a second kernel sums
  * the slots of each shift in a fixed order.  No floating-point atomics are
  * used anywhere, so results are bitwise reproducible.

@@ -4,22 +4,8 @@
  * reduction, the direct method, the table build, and the routing of every
  * launch to its variant unit (device templates in qqmc_kernels.h).
  *
- * Work decomposition.  One workgroup is one 64-lane wavefront.  A work tile
- * is (shift s, 64*c consecutive lattice indices).  For every 64 indices the
- * wave
- *   1. generates the shifted Korobov lattice point and warps it through the
- *      inverse CDF of the product model h(v) = exp(-v/tau) (one lane per
- *      index: Eqs. (warper1d), (x_of_v_simple), (hi_expo)),
- *   2. compacts the points inside the domain 0 < u_n (App. I: points outside
- *      contribute exactly zero) with a ballot,
- *   3. for every compacted point builds the pair table of interpolated
- *      g^<(tau), g^>(tau) in LDS (lanes of the point's group share the work),
- *   4. evaluates the Keldysh sum with the elimination tree of qqmc_tree.h,
- *      G = 2^T lanes per point (or per top-level prefix for n > 8),
- *   5. folds -2 i^{n+1} S(u) W into a per-lane compensated accumulator.
- * The tree kernels are compiled for two waves per SIMD (256 registers per
- * lane; the few values that do not fit go to scratch), which measured
- * faster than one wave per SIMD with no spills.
+ * Work decomposition: qqmc_kernels.h (the five steps per 64 lattice
+ * indices, the lane mapping, the register budget).
  * The tile's sum goes to one slot of a partials array; a second kernel sums
  * the slots of each shift in a fixed order.  No floating-point atomics are
  * used anywhere, so results are bitwise reproducible.

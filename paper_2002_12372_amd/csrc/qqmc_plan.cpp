@@ -18,7 +18,10 @@
  *
  * The tile length and the share of resident workgroups are chosen by a small
  * autotuner when the caller passes 0: each candidate is timed on a subsample
- * of every group (every k-th tile) and the fastest per point is kept.  With
+ * of every group (every k-th tile) and the fastest per point is kept.  The
+ * tile-length candidates are one length for every item (64 .. 2048) and each
+ * item at its own default length (the one qqmc_eval_order takes when given
+ * 0).  With
  * tile_len 0 it also picks each group's lane mapping where the kernel has
  * two (the scalar-tree charge on the lattice from order 5: the default, or
  * a depth-4 register tree at orders 5-8 and 11-14, cooperative top levels
@@ -191,7 +194,11 @@ void make_groups(qqmc_plan_s *p, const std::vector<std::pair<double, TileRef>> &
     }
 }
 
-/* Lays out tiles for tile length `tl` and (re)allocates the device buffers. */
+/* Lays out tiles for tile length `tl` (kPerItemTiles: each item at the
+ * tile length qqmc_eval_order takes by default) and (re)allocates the
+ * device buffers. */
+constexpr int32_t kPerItemTiles = 0;
+
 qqmc_status layout(qqmc_plan_s *p, int32_t tl)
 {
     p->buf.release();
@@ -201,7 +208,7 @@ qqmc_status layout(qqmc_plan_s *p, int32_t tl)
     for (size_t i = 0; i < p->items.size(); ++i) {
         ItemDesc &d = p->items[i];
         const int64_t N = (int64_t)d.mask + 1;
-        d.tile_len = tl < N ? tl : (int32_t)N;
+        d.tile_len = tl == kPerItemTiles ? default_tile_len(d, N) : (tl < N ? tl : (int32_t)N);
         d.tiles_per_shift = (int32_t)(N / d.tile_len);
         d.n_tiles = (int64_t)d.tiles_per_shift * d.n_shifts;
         const double c = tile_cost(d);
@@ -417,8 +424,12 @@ qqmc_status qqmc_plan_create(const qqmc_batch_item *items, int32_t n_items, int3
 
     /* grid_blocks given: it caps the workgroups of every order's launch,
      * expressed as a share of that order's full residency */
+    /* candidates: every item at its own default length first (ties keep
+     * it: its sums are then the default single launch's), then one length
+     * for all */
     std::vector<int32_t> tls = tile_len ? std::vector<int32_t>{tile_len}
-                                        : std::vector<int32_t>{64, 128, 256, 512, 1024, 2048};
+                                        : std::vector<int32_t>{kPerItemTiles, 64, 128, 256, 512,
+                                                               1024, 2048};
     std::vector<double> shares = {1.0, 0.5, 0.0};
     if (grid_blocks) shares = {std::min(1.0, (double)grid_blocks / (p->n_cu * batch_blocks_per_cu(8)))};
     int32_t best_tl = tls[0];

@@ -1195,8 +1195,9 @@ __global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR, MAP>::WPS)) batch_kerne
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
-        /* by value: the descriptor lives in registers for the whole tile */
-        const ItemDesc it = items[ref.item];
+        /* by reference: fields are loaded where they are used (scalar loads), which keeps
+           the descriptor out of the registers the tree needs */
+        const ItemDesc &it = items[ref.item];
         const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB, MAP>(it, ref.tile, lds);
         if (threadIdx.x == 0) {
             it.tile_sums[2 * ref.tile] = v.x;

@@ -43,6 +43,8 @@ namespace qqmc {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int ilog2(int v) { return v > 1 ? 1 + ilog2(v / 2) : 0; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
 /* Workgroup size of every kernel that exchanges data through local memory
  * with wave_sync (the tree kernels and the adaptive path): one wavefront,
  * so that its local-memory operations execute in program order.  Their
@@ -83,7 +85,16 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
      * tree's two-level top steps */
     static constexpr int rows = (PAIR || Gm::OFF >= 2) ? 2 : 1;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
-    static constexpr int c0 = row + (Gm::OFF > 0 ? rows * Gm::PPW * (N + 1) * 16 : 0);
+    /* the round-shared top (scalar tree above order 10, default mapping):
+     * instead of the rows, a block buffer (the levels whose children do not
+     * go to the c0 blocks), the rank-1 vectors of one level and the pivots */
+    static constexpr bool RTOP = !PAIR && MAP == kMapDefault && Gm::OFF > 0;
+    static constexpr int TL = RTOP ? ilog2(Gm::PPW) : 0;       /* tree levels */
+    static constexpr int ybuf = RTOP ? cmax(N * N, (Gm::PPW / 2) * (Gm::K + 1) * (Gm::K + 1)) : 0;
+    static constexpr int vecn = RTOP ? cmax(2 * N, 2 * Gm::PPW * Gm::K) : 0;
+    static constexpr int pivn = 16;
+    static constexpr int row_bytes = RTOP ? (ybuf + vecn + pivn) * 16 : rows * Gm::PPW * (N + 1) * 16;
+    static constexpr int c0 = row + (Gm::OFF > 0 ? row_bytes : 0);
     static constexpr int c0_end = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
     /* the paired tree's adaptive re-evaluation (qqmc_adapt.h), placed
      * before the Sobol' numbers so that its offset and size are the same with
@@ -326,6 +337,143 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
         }
     }
     wave_sync();
+    return prod;
+}
+
+/* One level of the round-shared top: NPAR parent correction blocks of
+ * size M x M at src (zero when ZERO), each eliminated at its first index
+ * (global index gk) for NB index values (both, or the fixed bfix), giving
+ * NPAR * NB child blocks of size (M-1) x (M-1) at dst, child (P, b) at
+ * position P * NB + b, and the parents' pivots at s_piv[0..NPAR).  Phase
+ * one computes every parent's pivot and its rank-1 vectors
+ *     c_b[i] = (W_b(i, 0) - C[i][0]) / p,   row_b[j] = W_b(0, j) - C[0][j],
+ * phase two every child entry C[i][j] + c_b[i] row_b[j], both spread over
+ * the 64 lanes; each phase issues all its local-memory reads before it
+ * computes, so a level waits on local memory twice. */
+template <int N, bool CUR, int NPAR, int NB, int M, bool ZERO>
+__device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int gk, int bfix,
+                                           cplx g0, const cplx *src, cplx *dst, cplx *s_vec,
+                                           cplx *s_piv)
+{
+    constexpr int S = M - 1;
+    constexpr int NVEC = NPAR * NB * 2 * S, NV = NVEC + NPAR;
+    constexpr int IV = (NV + WAVE - 1) / WAVE;
+    const int lane = threadIdx.x;
+    cplx val[IV];
+#pragma unroll
+    for (int t = 0; t < IV; ++t) {
+        const int q = lane + t * WAVE;
+        val[t] = cmk(0.0, 0.0);
+        if (q < NVEC) {
+            const int idx = q % S + 1, kind = (q / S) & 1;
+            const int b = NB == 2 ? (q / (2 * S)) & 1 : bfix;
+            const cplx *C = src + (q / (NB * 2 * S)) * M * M;
+            if (kind == 0) {
+                const cplx w = wick_entry(pr, gk + idx, gk, b);
+                const cplx p = ZERO ? g0 : csub(g0, C[0]);
+                val[t] = cmul(ZERO ? w : csub(w, C[idx * M]), crecip_nr(p));
+            } else {
+                const cplx w = wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b);
+                val[t] = ZERO ? w : csub(w, C[idx]);
+            }
+        } else if (q < NV) {
+            val[t] = ZERO ? g0 : csub(g0, src[(q - NVEC) * M * M]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < IV; ++t) {
+        const int q = lane + t * WAVE;
+        if (q < NVEC) s_vec[q] = val[t];
+        else if (q < NV) s_piv[q - NVEC] = val[t];
+    }
+    wave_sync();
+    constexpr int NE = NPAR * S * S;
+    constexpr int IE = (NE + WAVE - 1) / WAVE;
+    cplx cc[IE], cv[IE][NB], rv[IE][NB];
+#pragma unroll
+    for (int t = 0; t < IE; ++t) {
+        const int q = lane + t * WAVE < NE ? lane + t * WAVE : NE - 1;
+        const int P = q / (S * S), rem = q % (S * S), i = rem / S, j = rem % S;
+        cc[t] = ZERO ? cmk(0.0, 0.0) : src[P * M * M + (i + 1) * M + (j + 1)];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            cv[t][b] = s_vec[((P * NB + b) * 2 + 0) * S + i];
+            rv[t][b] = s_vec[((P * NB + b) * 2 + 1) * S + j];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < IE; ++t) {
+        const int q = lane + t * WAVE;
+        if (q < NE) {
+            const int P = q / (S * S), rem = q % (S * S);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                dst[(P * NB + b) * S * S + rem] = cfma(cv[t][b], rv[t][b], cc[t]);
+        }
+    }
+    wave_sync();
+}
+
+/* Levels LAM.. of the round-shared top: the first CH = OFF - TL are the
+ * chain of index bits that the round's items share (one parent, one child),
+ * the last TL the tree over the bits in which they differ.  The children of
+ * the last level land in the c0 blocks (s_x); earlier levels alternate
+ * between s_y and s_x so that no level reads the buffer it writes. */
+template <int N, bool CUR, int LAM, int OFF, int TL>
+__device__ __forceinline__ void rtop_levels(const pairv *pr, const pairv *mc, int rpre, cplx g0,
+                                            cplx *s_x, cplx *s_y, cplx *s_vec, cplx *s_piv)
+{
+    if constexpr (LAM < OFF) {
+        constexpr int CH = OFF - TL;
+        constexpr bool TREE = LAM >= CH;
+        constexpr int NPAR = TREE ? (1 << (LAM - CH)) : 1, NB = TREE ? 2 : 1;
+        constexpr bool TO_X = ((OFF - 1 - LAM) & 1) == 0;
+        constexpr int M = N + 1 - LAM, SH = TREE ? 0 : CH - 1 - LAM;
+        using L = Lds<N, false, CUR, false, kMapDefault>;
+        static_assert(NPAR * NB * (M - 1) * (M - 1) <=
+                          (TO_X ? Geo<N>::PPW * Geo<N>::K * Geo<N>::K : L::ybuf),
+                      "the level's children fit their buffer");
+        static_assert(NPAR * NB * 2 * (M - 1) <= L::vecn, "the level's vectors fit");
+        const int bfix = TREE ? 0 : (rpre >> SH) & 1;
+        rtop_level<N, CUR, NPAR, NB, M, LAM == 0>(
+            pr, mc, LAM, bfix, g0, TO_X ? s_y : s_x, TO_X ? s_x : s_y, s_vec,
+            s_piv + (TREE ? CH + NPAR - 1 : LAM));
+        rtop_levels<N, CUR, LAM + 1, OFF, TL>(pr, mc, rpre, g0, s_x, s_y, s_vec, s_piv);
+    }
+}
+
+/* The first OFF = n - 8 eliminations of the scalar tree above order 10,
+ * shared by the PPW items of a round (one point; items differ in the last
+ * TL = log2(PPW) bits of their index prefix, and share the CH = OFF - TL
+ * bits before, the round's prefix rpre).  The whole wave eliminates the CH
+ * shared levels once and the TL levels as a tree (1, 2, 4, ... parents),
+ * one level at a time, instead of every item repeating the OFF levels
+ * of its own prefix.  Leaves item g's 9 x 9 trailing correction block at
+ * c0 + g K K and returns, for the calling lane's item grp, the product of
+ * its OFF pivots. */
+template <int N, bool CUR>
+__device__ cplx round_top(const pairv *pr, const pairv *mc, int rpre, int grp, cplx g0, char *lds)
+{
+    using L = Lds<N, false, CUR, false, kMapDefault>;
+    using Gm = Geo<N, false, kMapDefault>;
+    constexpr int OFF = Gm::OFF, TL = L::TL, CH = OFF - TL;
+    static_assert(L::RTOP && Gm::IPP >= Gm::PPW && (1 << TL) == Gm::PPW, "one point per round");
+    static_assert(N + 1 - OFF == Gm::K, "the last level leaves K x K blocks");
+    static_assert(CH + (1 << TL) - 1 <= L::pivn, "pivots of every level");
+    static_assert(Gm::PPW * Gm::K * Gm::K >= N * N && L::ybuf >= N * N, "chain children fit");
+    static_assert(L::vecn >= 2 * N && L::vecn >= 2 * Gm::PPW * Gm::K, "vectors of every level");
+    cplx *s_x = reinterpret_cast<cplx *>(lds + L::c0);
+    cplx *s_y = reinterpret_cast<cplx *>(lds + L::row);
+    cplx *s_vec = s_y + L::ybuf;
+    cplx *s_piv = s_vec + L::vecn;
+    /* the previous round's lanes have read their blocks */
+    wave_sync();
+    rtop_levels<N, CUR, 0, OFF, TL>(pr, mc, rpre, g0, s_x, s_y, s_vec, s_piv);
+    cplx prod = cmk(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) prod = cmul(prod, s_piv[k]);
+#pragma unroll
+    for (int l = 0; l < TL; ++l) prod = cmul(prod, s_piv[CH + (1 << l) - 1 + (grp >> (TL - l))]);
     return prod;
 }
 
@@ -595,6 +743,8 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
             if constexpr (PAIR)
                 prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0, gtop);
+            else if constexpr (L::RTOP)
+                prod = round_top<N, CUR>(prg, mc, (base % Gm::IPP) / Gm::PPW, grp, env.g0, lds);
             else prod = top_block<N, CUR, MAP>(prg, mc, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;

@@ -356,36 +356,37 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
                                            cplx *s_piv)
 {
     constexpr int S = M - 1;
-    constexpr int NVEC = NPAR * NB * 2 * S, NV = NVEC + NPAR;
-    constexpr int IV = (NV + WAVE - 1) / WAVE;
+    /* column and row tasks in separate loops (one vector entry of each per
+     * task q = (P NB + b) S + idx - 1), so that no iteration branches on
+     * the kind */
+    constexpr int NC = NPAR * NB * S;
+    constexpr int IC = (NC + WAVE - 1) / WAVE;
+    static_assert(NPAR <= WAVE, "one pivot per lane");
     const int lane = threadIdx.x;
-    cplx val[IV];
+    cplx vc[IC], vr[IC];
 #pragma unroll
-    for (int t = 0; t < IV; ++t) {
+    for (int t = 0; t < IC; ++t) {
+        const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
+        const int idx = q % S + 1;
+        const int b = NB == 2 ? (q / S) & 1 : bfix;
+        const cplx *C = src + (q / (NB * S)) * M * M;
+        const cplx p = ZERO ? g0 : csub(g0, C[0]);
+        const cplx wc = wick_entry(pr, gk + idx, gk, b);
+        const cplx wr = wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b);
+        vc[t] = cmul(ZERO ? wc : csub(wc, C[idx * M]), crecip_nr(p));
+        vr[t] = ZERO ? wr : csub(wr, C[idx]);
+    }
+    const cplx vp = ZERO ? g0 : csub(g0, src[(lane < NPAR ? lane : 0) * M * M]);
+#pragma unroll
+    for (int t = 0; t < IC; ++t) {
         const int q = lane + t * WAVE;
-        val[t] = cmk(0.0, 0.0);
-        if (q < NVEC) {
-            const int idx = q % S + 1, kind = (q / S) & 1;
-            const int b = NB == 2 ? (q / (2 * S)) & 1 : bfix;
-            const cplx *C = src + (q / (NB * 2 * S)) * M * M;
-            if (kind == 0) {
-                const cplx w = wick_entry(pr, gk + idx, gk, b);
-                const cplx p = ZERO ? g0 : csub(g0, C[0]);
-                val[t] = cmul(ZERO ? w : csub(w, C[idx * M]), crecip_nr(p));
-            } else {
-                const cplx w = wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b);
-                val[t] = ZERO ? w : csub(w, C[idx]);
-            }
-        } else if (q < NV) {
-            val[t] = ZERO ? g0 : csub(g0, src[(q - NVEC) * M * M]);
+        if (q < NC) {
+            const int o = (q / S) * 2 * S + q % S;
+            s_vec[o] = vc[t];
+            s_vec[o + S] = vr[t];
         }
     }
-#pragma unroll
-    for (int t = 0; t < IV; ++t) {
-        const int q = lane + t * WAVE;
-        if (q < NVEC) s_vec[q] = val[t];
-        else if (q < NV) s_piv[q - NVEC] = val[t];
-    }
+    if (lane < NPAR) s_piv[lane] = vp;
     wave_sync();
     constexpr int NE = NPAR * S * S;
     constexpr int IE = (NE + WAVE - 1) / WAVE;

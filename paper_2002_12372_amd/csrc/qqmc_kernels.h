@@ -376,17 +376,18 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
         vc[t] = cmul(ZERO ? wc : csub(wc, C[idx * M]), crecip_nr(p));
         vr[t] = ZERO ? wr : csub(wr, C[idx]);
     }
-    const cplx vp = ZERO ? g0 : csub(g0, src[(lane < NPAR ? lane : 0) * M * M]);
+    /* lanes past the end repeat the last task (or parent 0) and store the
+     * same value to the same address, so no store needs a branch */
+    const int pl = lane < NPAR ? lane : 0;
+    const cplx vp = ZERO ? g0 : csub(g0, src[pl * M * M]);
 #pragma unroll
     for (int t = 0; t < IC; ++t) {
-        const int q = lane + t * WAVE;
-        if (q < NC) {
-            const int o = (q / S) * 2 * S + q % S;
-            s_vec[o] = vc[t];
-            s_vec[o + S] = vr[t];
-        }
+        const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
+        const int o = (q / S) * 2 * S + q % S;
+        s_vec[o] = vc[t];
+        s_vec[o + S] = vr[t];
     }
-    if (lane < NPAR) s_piv[lane] = vp;
+    s_piv[pl] = vp;
     wave_sync();
     constexpr int NE = NPAR * S * S;
     constexpr int IE = (NE + WAVE - 1) / WAVE;
@@ -404,13 +405,11 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
     }
 #pragma unroll
     for (int t = 0; t < IE; ++t) {
-        const int q = lane + t * WAVE;
-        if (q < NE) {
-            const int P = q / (S * S), rem = q % (S * S);
+        const int q = lane + t * WAVE < NE ? lane + t * WAVE : NE - 1;
+        const int P = q / (S * S), rem = q % (S * S);
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                dst[(P * NB + b) * S * S + rem] = cfma(cv[t][b], rv[t][b], cc[t]);
-        }
+        for (int b = 0; b < NB; ++b)
+            dst[(P * NB + b) * S * S + rem] = cfma(cv[t][b], rv[t][b], cc[t]);
     }
     wave_sync();
 }

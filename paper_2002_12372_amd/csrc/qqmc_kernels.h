@@ -349,48 +349,56 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
  *     c_b[i] = (W_b(i, 0) - C[i][0]) / p,   row_b[j] = W_b(0, j) - C[0][j],
  * phase two every child entry C[i][j] + c_b[i] row_b[j], both spread over
  * the 64 lanes; each phase issues all its local-memory reads before it
- * computes, so a level waits on local memory twice. */
+ * computes, so a level waits on local memory twice (the first level, whose
+ * parent is zero, once). */
 template <int N, bool CUR, int NPAR, int NB, int M, bool ZERO>
 __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int gk, int bfix,
                                            cplx g0, const cplx *src, cplx *dst, cplx *s_vec,
                                            cplx *s_piv)
 {
     constexpr int S = M - 1;
-    /* column and row tasks in separate loops (one vector entry of each per
-     * task q = (P NB + b) S + idx - 1), so that no iteration branches on
-     * the kind */
-    constexpr int NC = NPAR * NB * S;
-    constexpr int IC = (NC + WAVE - 1) / WAVE;
-    static_assert(NPAR <= WAVE, "one pivot per lane");
     const int lane = threadIdx.x;
-    cplx vc[IC], vr[IC];
+    if constexpr (!ZERO) {
+        /* column and row tasks in separate loops (one vector entry of each
+         * per task q = (P NB + b) S + idx - 1), so that no iteration branches
+         * on the kind */
+        constexpr int NC = NPAR * NB * S;
+        constexpr int IC = (NC + WAVE - 1) / WAVE;
+        static_assert(NPAR <= WAVE, "one pivot per lane");
+        cplx vc[IC], vr[IC];
 #pragma unroll
-    for (int t = 0; t < IC; ++t) {
-        const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
-        const int idx = q % S + 1;
-        const int b = NB == 2 ? (q / S) & 1 : bfix;
-        const cplx *C = src + (q / (NB * S)) * M * M;
-        const cplx p = ZERO ? g0 : csub(g0, C[0]);
-        const cplx wc = wick_entry(pr, gk + idx, gk, b);
-        const cplx wr = wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b);
-        vc[t] = cmul(ZERO ? wc : csub(wc, C[idx * M]), crecip_nr(p));
-        vr[t] = ZERO ? wr : csub(wr, C[idx]);
-    }
-    /* lanes past the end repeat the last task (or parent 0) and store the
-     * same value to the same address, so no store needs a branch */
-    const int pl = lane < NPAR ? lane : 0;
-    const cplx vp = ZERO ? g0 : csub(g0, src[pl * M * M]);
+        for (int t = 0; t < IC; ++t) {
+            const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
+            const int idx = q % S + 1;
+            const int b = NB == 2 ? (q / S) & 1 : bfix;
+            const cplx *C = src + (q / (NB * S)) * M * M;
+            const cplx p = csub(g0, C[0]);
+            vc[t] = cmul(csub(wick_entry(pr, gk + idx, gk, b), C[idx * M]), crecip_nr(p));
+            vr[t] = csub(wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b), C[idx]);
+        }
+        /* lanes past the end repeat the last task (or parent 0) and store
+         * the same value to the same address, so no store needs a branch */
+        const int pl = lane < NPAR ? lane : 0;
+        const cplx vp = csub(g0, src[pl * M * M]);
 #pragma unroll
-    for (int t = 0; t < IC; ++t) {
-        const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
-        const int o = (q / S) * 2 * S + q % S;
-        s_vec[o] = vc[t];
-        s_vec[o + S] = vr[t];
+        for (int t = 0; t < IC; ++t) {
+            const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
+            const int o = (q / S) * 2 * S + q % S;
+            s_vec[o] = vc[t];
+            s_vec[o + S] = vr[t];
+        }
+        s_piv[pl] = vp;
+        wave_sync();
+    } else {
+        /* the first level: a zero parent, so the vectors are Wick entries
+         * (the columns over the vertex diagonal g0), read where they are
+         * used below; no vector phase */
+        static_assert(NPAR == 1, "one parent at the first level");
+        s_piv[0] = g0;
     }
-    s_piv[pl] = vp;
-    wave_sync();
     constexpr int NE = NPAR * S * S;
     constexpr int IE = (NE + WAVE - 1) / WAVE;
+    const cplx r0 = ZERO ? crecip_nr(g0) : cmk(0.0, 0.0);
     cplx cc[IE], cv[IE][NB], rv[IE][NB];
 #pragma unroll
     for (int t = 0; t < IE; ++t) {
@@ -399,8 +407,14 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
         cc[t] = ZERO ? cmk(0.0, 0.0) : src[P * M * M + (i + 1) * M + (j + 1)];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            cv[t][b] = s_vec[((P * NB + b) * 2 + 0) * S + i];
-            rv[t][b] = s_vec[((P * NB + b) * 2 + 1) * S + j];
+            if constexpr (ZERO) {
+                const int bb = NB == 2 ? b : bfix;
+                cv[t][b] = cmul(wick_entry(pr, gk + i + 1, gk, bb), r0);
+                rv[t][b] = wick_entry_m<CUR>(pr, mc, gk, gk + j + 1, N, bb);
+            } else {
+                cv[t][b] = s_vec[((P * NB + b) * 2 + 0) * S + i];
+                rv[t][b] = s_vec[((P * NB + b) * 2 + 1) * S + j];
+            }
         }
     }
 #pragma unroll

@@ -81,15 +81,19 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
     static constexpr int tables =
         Gm::IPP == 1 ? Gm::PPW : (Gm::PPW >= Gm::IPP ? Gm::PPW / Gm::IPP : 1);
     static constexpr int pairs = ids + QCAP * 4;                       /* tables*NP pairv */
-    /* broadcast rows per group: two for the paired tree and for the scalar
-     * tree's two-level top steps */
-    static constexpr int rows = (PAIR || Gm::OFF >= 2) ? 2 : 1;
+    /* broadcast rows per group of the paired tree's pair steps and of the
+     * per-item top's two-level steps */
+    static constexpr int rows = 2;
     static constexpr int row = pairs + tables * NPS * 32;      /* rows*PPW*(N+1) cplx */
-    /* the round-shared top (scalar tree above order 10, default mapping):
-     * instead of the rows, a block buffer (the levels whose children do not
-     * go to the c0 blocks), the rank-1 vectors of one level and the pivots */
-    static constexpr bool RTOP = !PAIR && MAP == kMapDefault && Gm::OFF > 0;
-    static constexpr int TL = RTOP ? ilog2(Gm::PPW) : 0;       /* tree levels */
+    /* the round-shared top of the scalar tree (the default mapping above
+     * order 10 and the cooperative-top mapping at orders 9 and 10; the
+     * depth-4 mapping, two waves per SIMD, keeps per-item tops, whose fewer
+     * live values it measured 1.5-2.2x faster with): instead of the rows, a
+     * block buffer (the levels whose children do not go to the c0 blocks),
+     * the rank-1 vectors of one level and the pivots */
+    static constexpr bool RTOP = !PAIR && Gm::OFF > 0 && MAP != kMapDepth4;
+    /* tree levels per point (the round holds `tables` points) */
+    static constexpr int TL = RTOP ? ilog2(Gm::PPW / tables) : 0;
     static constexpr int ybuf = RTOP ? cmax(N * N, (Gm::PPW / 2) * (Gm::K + 1) * (Gm::K + 1)) : 0;
     static constexpr int vecn = RTOP ? cmax(2 * N, 2 * Gm::PPW * Gm::K) : 0;
     static constexpr int pivn = 16;
@@ -217,8 +221,8 @@ struct Env {
     int n_grid;
 };
 
-/* The first OFF = n - 8 eliminations of a work item (n > 10), done by the G
- * lanes of the item's group with whole matrix rows per lane (row r on lane
+/* The first OFF = n - 8 eliminations of a work item in the depth-4 mapping
+ * (n > 10), done by the G lanes of the item's group with whole matrix rows per lane (row r on lane
  * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
  * 9 x 9 trailing correction block in s_c0 and returns the product of the
  * OFF pivots.
@@ -351,12 +355,15 @@ __device__ cplx top_block(const pairv *pr, const pairv *mc, int top, int sub, cp
  * the 64 lanes; each phase issues all its local-memory reads before it
  * computes, so a level waits on local memory twice (the first level, whose
  * parent is zero, once). */
-template <int N, bool CUR, int NPAR, int NB, int M, bool ZERO>
-__device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int gk, int bfix,
-                                           cplx g0, const cplx *src, cplx *dst, cplx *s_vec,
-                                           cplx *s_piv)
+template <int N, bool CUR, int NPAR, int NB, int M, bool ZERO, int PPP, int NPS>
+__device__ __forceinline__ void rtop_level(const pairv *pr0, int gk, int bfix, cplx g0,
+                                           const cplx *src, cplx *dst, cplx *s_vec, cplx *s_piv)
 {
     constexpr int S = M - 1;
+    /* parent P belongs to point P / PPP of the round, whose pair table is
+     * pr0 + (P / PPP) NPS; the measurement column of the current follows
+     * the NP pairs, the charge's is the pairs (k, n) */
+    constexpr int MC = CUR ? N * (N + 1) / 2 : pidx(0, N);
     const int lane = threadIdx.x;
     if constexpr (!ZERO) {
         /* column and row tasks in separate loops (one vector entry of each
@@ -371,10 +378,12 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
             const int q = lane + t * WAVE < NC ? lane + t * WAVE : NC - 1;
             const int idx = q % S + 1;
             const int b = NB == 2 ? (q / S) & 1 : bfix;
-            const cplx *C = src + (q / (NB * S)) * M * M;
+            const int P = q / (NB * S);
+            const pairv *pr = pr0 + (P / PPP) * NPS;
+            const cplx *C = src + P * M * M;
             const cplx p = csub(g0, C[0]);
             vc[t] = cmul(csub(wick_entry(pr, gk + idx, gk, b), C[idx * M]), crecip_nr(p));
-            vr[t] = csub(wick_entry_m<CUR>(pr, mc, gk, gk + idx, N, b), C[idx]);
+            vr[t] = csub(wick_entry_m<CUR>(pr, pr + MC, gk, gk + idx, N, b), C[idx]);
         }
         /* lanes past the end repeat the last task (or parent 0) and store
          * the same value to the same address, so no store needs a branch */
@@ -390,11 +399,11 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
         s_piv[pl] = vp;
         wave_sync();
     } else {
-        /* the first level: a zero parent, so the vectors are Wick entries
+        /* the first level: zero parents, so the vectors are Wick entries
          * (the columns over the vertex diagonal g0), read where they are
          * used below; no vector phase */
-        static_assert(NPAR == 1, "one parent at the first level");
-        s_piv[0] = g0;
+        static_assert(NPAR <= WAVE && PPP == 1, "one parent per point at the first level");
+        s_piv[lane < NPAR ? lane : 0] = g0;
     }
     constexpr int NE = NPAR * S * S;
     constexpr int IE = (NE + WAVE - 1) / WAVE;
@@ -409,8 +418,9 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
         for (int b = 0; b < NB; ++b) {
             if constexpr (ZERO) {
                 const int bb = NB == 2 ? b : bfix;
+                const pairv *pr = pr0 + P * NPS;
                 cv[t][b] = cmul(wick_entry(pr, gk + i + 1, gk, bb), r0);
-                rv[t][b] = wick_entry_m<CUR>(pr, mc, gk, gk + j + 1, N, bb);
+                rv[t][b] = wick_entry_m<CUR>(pr, pr + MC, gk, gk + j + 1, N, bb);
             } else {
                 cv[t][b] = s_vec[((P * NB + b) * 2 + 0) * S + i];
                 rv[t][b] = s_vec[((P * NB + b) * 2 + 1) * S + j];
@@ -430,50 +440,57 @@ __device__ __forceinline__ void rtop_level(const pairv *pr, const pairv *mc, int
 
 /* Levels LAM.. of the round-shared top: the first CH = OFF - TL are the
  * chain of index bits that the round's items share (one parent, one child),
- * the last TL the tree over the bits in which they differ.  The children of
- * the last level land in the c0 blocks (s_x); earlier levels alternate
- * between s_y and s_x so that no level reads the buffer it writes. */
-template <int N, bool CUR, int LAM, int OFF, int TL>
-__device__ __forceinline__ void rtop_levels(const pairv *pr, const pairv *mc, int rpre, cplx g0,
-                                            cplx *s_x, cplx *s_y, cplx *s_vec, cplx *s_piv)
+ * the last TL the tree over the bits in which they differ, for each of the
+ * round's PTS points (PTS 2^l parents at tree level l; a chain only with one
+ * point per round).  The children of the last level land in the c0 blocks
+ * (s_x); earlier levels alternate between s_y and s_x so that no level reads
+ * the buffer it writes. */
+template <int N, bool CUR, int MAP, int LAM, int OFF, int TL, int PTS>
+__device__ __forceinline__ void rtop_levels(const pairv *pr0, int rpre, cplx g0, cplx *s_x,
+                                            cplx *s_y, cplx *s_vec, cplx *s_piv)
 {
     if constexpr (LAM < OFF) {
+        using L = Lds<N, false, CUR, false, MAP>;
+        using Gm = Geo<N, false, MAP>;
         constexpr int CH = OFF - TL;
         constexpr bool TREE = LAM >= CH;
-        constexpr int NPAR = TREE ? (1 << (LAM - CH)) : 1, NB = TREE ? 2 : 1;
+        constexpr int PPP = TREE ? (1 << (LAM - CH)) : 1;
+        constexpr int NPAR = TREE ? PTS * PPP : 1, NB = TREE ? 2 : 1;
         constexpr bool TO_X = ((OFF - 1 - LAM) & 1) == 0;
         constexpr int M = N + 1 - LAM, SH = TREE ? 0 : CH - 1 - LAM;
-        using L = Lds<N, false, CUR, false, kMapDefault>;
-        static_assert(NPAR * NB * (M - 1) * (M - 1) <=
-                          (TO_X ? Geo<N>::PPW * Geo<N>::K * Geo<N>::K : L::ybuf),
+        static_assert(NPAR * NB * (M - 1) * (M - 1) <= (TO_X ? Gm::PPW * Gm::K * Gm::K : L::ybuf),
                       "the level's children fit their buffer");
         static_assert(NPAR * NB * 2 * (M - 1) <= L::vecn, "the level's vectors fit");
         const int bfix = TREE ? 0 : (rpre >> SH) & 1;
-        rtop_level<N, CUR, NPAR, NB, M, LAM == 0>(
-            pr, mc, LAM, bfix, g0, TO_X ? s_y : s_x, TO_X ? s_x : s_y, s_vec,
-            s_piv + (TREE ? CH + NPAR - 1 : LAM));
-        rtop_levels<N, CUR, LAM + 1, OFF, TL>(pr, mc, rpre, g0, s_x, s_y, s_vec, s_piv);
+        rtop_level<N, CUR, NPAR, NB, M, LAM == 0, PPP, L::NPS>(
+            pr0, LAM, bfix, g0, TO_X ? s_y : s_x, TO_X ? s_x : s_y, s_vec,
+            s_piv + (TREE ? CH + PTS * (PPP - 1) : LAM));
+        rtop_levels<N, CUR, MAP, LAM + 1, OFF, TL, PTS>(pr0, rpre, g0, s_x, s_y, s_vec, s_piv);
     }
 }
 
-/* The first OFF = n - 8 eliminations of the scalar tree above order 10,
- * shared by the PPW items of a round (one point; items differ in the last
- * TL = log2(PPW) bits of their index prefix, and share the CH = OFF - TL
- * bits before, the round's prefix rpre).  The whole wave eliminates the CH
- * shared levels once and the TL levels as a tree (1, 2, 4, ... parents),
- * one level at a time, instead of every item repeating the OFF levels
- * of its own prefix.  Leaves item g's 9 x 9 trailing correction block at
- * c0 + g K K and returns, for the calling lane's item grp, the product of
- * its OFF pivots. */
-template <int N, bool CUR>
-__device__ cplx round_top(const pairv *pr, const pairv *mc, int rpre, int grp, cplx g0, char *lds)
+/* The first OFF = n - 8 eliminations of the scalar tree (above order 10,
+ * and at orders 9 and 10 in the cooperative-top mapping; 8 lanes per
+ * item), shared by the PPW items of a round.  The round holds PTS points (their pair tables from
+ * pr0 on, NPS pairs apart) of PPW / PTS items each; items of a point differ
+ * in the last TL = log2(PPW / PTS) bits of their index prefix and, with one
+ * point per round, share the CH = OFF - TL bits before (the round's prefix
+ * rpre).  The whole wave eliminates the CH shared levels once and the TL
+ * levels as a tree per point (1, 2, 4, ... parents), one level at a time,
+ * instead of every item repeating the OFF levels of its own prefix.  Leaves
+ * item g's 9 x 9 trailing correction block at c0 + g K K and returns, for
+ * the calling lane's item grp, the product of its OFF pivots. */
+template <int N, bool CUR, int MAP>
+__device__ cplx round_top(const pairv *pr0, int rpre, int grp, cplx g0, char *lds)
 {
-    using L = Lds<N, false, CUR, false, kMapDefault>;
-    using Gm = Geo<N, false, kMapDefault>;
-    constexpr int OFF = Gm::OFF, TL = L::TL, CH = OFF - TL;
-    static_assert(L::RTOP && Gm::IPP >= Gm::PPW && (1 << TL) == Gm::PPW, "one point per round");
+    using L = Lds<N, false, CUR, false, MAP>;
+    using Gm = Geo<N, false, MAP>;
+    constexpr int OFF = Gm::OFF, TL = L::TL, CH = OFF - TL, PTS = L::tables;
+    static_assert(L::RTOP && PTS * (1 << TL) == Gm::PPW && (PTS == 1 || CH == 0),
+                  "whole points per round, a chain only with one point");
+    static_assert(PTS == 1 || Gm::IPP == (1 << TL), "every item of a point in the round");
     static_assert(N + 1 - OFF == Gm::K, "the last level leaves K x K blocks");
-    static_assert(CH + (1 << TL) - 1 <= L::pivn, "pivots of every level");
+    static_assert(CH + PTS * ((1 << TL) - 1) <= L::pivn, "pivots of every level");
     static_assert(Gm::PPW * Gm::K * Gm::K >= N * N && L::ybuf >= N * N, "chain children fit");
     static_assert(L::vecn >= 2 * N && L::vecn >= 2 * Gm::PPW * Gm::K, "vectors of every level");
     cplx *s_x = reinterpret_cast<cplx *>(lds + L::c0);
@@ -482,12 +499,13 @@ __device__ cplx round_top(const pairv *pr, const pairv *mc, int rpre, int grp, c
     cplx *s_piv = s_vec + L::vecn;
     /* the previous round's lanes have read their blocks */
     wave_sync();
-    rtop_levels<N, CUR, 0, OFF, TL>(pr, mc, rpre, g0, s_x, s_y, s_vec, s_piv);
+    rtop_levels<N, CUR, MAP, 0, OFF, TL, PTS>(pr0, rpre, g0, s_x, s_y, s_vec, s_piv);
     cplx prod = cmk(1.0, 0.0);
 #pragma unroll
     for (int k = 0; k < CH; ++k) prod = cmul(prod, s_piv[k]);
 #pragma unroll
-    for (int l = 0; l < TL; ++l) prod = cmul(prod, s_piv[CH + (1 << l) - 1 + (grp >> (TL - l))]);
+    for (int l = 0; l < TL; ++l)
+        prod = cmul(prod, s_piv[CH + PTS * ((1 << l) - 1) + (grp >> (TL - l))]);
     return prod;
 }
 
@@ -753,12 +771,12 @@ __device__ void keldysh_points(int cnt, const Env &env, char *lds)
         src.c = nullptr;
         double gtop = 0.0, gbot = 0.0; /* largest elimination multipliers (paired tree) */
         if constexpr (Gm::OFF > 0) {
-            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             cplx *s_c0 = reinterpret_cast<cplx *>(lds + L::c0) + grp * Gm::K * Gm::K;
+            cplx *s_row = reinterpret_cast<cplx *>(lds + L::row) + grp * L::rows * (N + 1);
             if constexpr (PAIR)
                 prod = top_block_pair<N, CUR>(prg, mc, top, sub, env.g0, s_row, s_c0, gtop);
             else if constexpr (L::RTOP)
-                prod = round_top<N, CUR>(prg, mc, (base % Gm::IPP) / Gm::PPW, grp, env.g0, lds);
+                prod = round_top<N, CUR, MAP>(s_pairs, (base % Gm::IPP) / Gm::PPW, grp, env.g0, lds);
             else prod = top_block<N, CUR, MAP>(prg, mc, top, sub, env.g0, s_row, s_c0);
             sgn = __popc((unsigned)top) & 1;
             src.c = s_c0;

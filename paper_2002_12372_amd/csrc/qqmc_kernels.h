@@ -45,6 +45,9 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int ilog2(int v) { return v > 1 ? 1 + ilog2(v / 2) : 0; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+/* offset of chain level k's output among the kept chain blocks of order n:
+ * the sum of (n - j)^2 over the levels j < k */
+constexpr int chain_off(int n, int k) { return k <= 0 ? 0 : chain_off(n, k - 1) + (n - k + 1) * (n - k + 1); }
 /* Workgroup size of every kernel that exchanges data through local memory
  * with wave_sync (the tree kernels and the adaptive path): one wavefront,
  * so that its local-memory operations execute in program order.  Their
@@ -97,7 +100,12 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
     static constexpr int ybuf = RTOP ? cmax(N * N, (Gm::PPW / 2) * (Gm::K + 1) * (Gm::K + 1)) : 0;
     static constexpr int vecn = RTOP ? cmax(2 * N, 2 * Gm::PPW * Gm::K) : 0;
     static constexpr int pivn = 16;
-    static constexpr int row_bytes = RTOP ? (ybuf + vecn + pivn) * 16 : rows * Gm::PPW * (N + 1) * 16;
+    /* the shared chain levels' outputs but the last, kept from one round of
+     * a point to the next (levels 0 .. CH-2, blocks of (n-k)^2) */
+    static constexpr int CH = RTOP ? Gm::OFF - TL : 0;
+    static constexpr int cbufn = CH >= 2 ? chain_off(N, CH - 1) : 0;
+    static constexpr int row_bytes =
+        RTOP ? (ybuf + vecn + pivn + cbufn) * 16 : rows * Gm::PPW * (N + 1) * 16;
     static constexpr int c0 = row + (Gm::OFF > 0 ? row_bytes : 0);
     static constexpr int c0_end = c0 + (Gm::OFF > 0 ? Gm::PPW * Gm::K * Gm::K * 16 : 0);
     /* the paired tree's adaptive re-evaluation (qqmc_adapt.h), placed
@@ -222,10 +230,10 @@ struct Env {
 };
 
 /* The first OFF = n - 8 eliminations of a work item in the depth-4 mapping
- * (n > 10), done by the G lanes of the item's group with whole matrix rows per lane (row r on lane
- * r mod G; right-looking, no pivoting, index prefix `top`).  Leaves the
- * 9 x 9 trailing correction block in s_c0 and returns the product of the
- * OFF pivots.
+ * (n > 10), done by the G lanes of the item's group with whole matrix rows
+ * per lane (row r on lane r mod G; right-looking, no pivoting, index prefix
+ * `top`).  Leaves the 9 x 9 trailing correction block in s_c0 and returns
+ * the product of the OFF pivots.
  *
  * Levels go two at a time: with T = (Wick entries) - C the trailing matrix,
  * vertices k and k+1 are eliminated together through their 2x2 block
@@ -442,12 +450,16 @@ __device__ __forceinline__ void rtop_level(const pairv *pr0, int gk, int bfix, c
  * chain of index bits that the round's items share (one parent, one child),
  * the last TL the tree over the bits in which they differ, for each of the
  * round's PTS points (PTS 2^l parents at tree level l; a chain only with one
- * point per round).  The children of the last level land in the c0 blocks
- * (s_x); earlier levels alternate between s_y and s_x so that no level reads
- * the buffer it writes. */
+ * point per round).  Chain levels before k0 are skipped: their outputs,
+ * kept in s_c (all chain levels but the last), are those of the previous
+ * round of the same point.  The last chain level writes the buffer that the
+ * first tree level does not, and the tree levels alternate between s_x and
+ * s_y so that no level reads the buffer it writes; the children of the last
+ * level land in the c0 blocks (s_x). */
 template <int N, bool CUR, int MAP, int LAM, int OFF, int TL, int PTS>
-__device__ __forceinline__ void rtop_levels(const pairv *pr0, int rpre, cplx g0, cplx *s_x,
-                                            cplx *s_y, cplx *s_vec, cplx *s_piv)
+__device__ __forceinline__ void rtop_levels(const pairv *pr0, int rpre, int k0, cplx g0,
+                                            cplx *s_x, cplx *s_y, cplx *s_c, cplx *s_vec,
+                                            cplx *s_piv)
 {
     if constexpr (LAM < OFF) {
         using L = Lds<N, false, CUR, false, MAP>;
@@ -456,26 +468,37 @@ __device__ __forceinline__ void rtop_levels(const pairv *pr0, int rpre, cplx g0,
         constexpr bool TREE = LAM >= CH;
         constexpr int PPP = TREE ? (1 << (LAM - CH)) : 1;
         constexpr int NPAR = TREE ? PTS * PPP : 1, NB = TREE ? 2 : 1;
-        constexpr bool TO_X = ((OFF - 1 - LAM) & 1) == 0;
         constexpr int M = N + 1 - LAM, SH = TREE ? 0 : CH - 1 - LAM;
-        static_assert(NPAR * NB * (M - 1) * (M - 1) <= (TO_X ? Gm::PPW * Gm::K * Gm::K : L::ybuf),
+        /* tree level l writes s_x when TL - 1 - l is even */
+        constexpr bool T0_X = ((TL - 1) & 1) == 0;
+        constexpr bool TO_X = TREE ? ((OFF - 1 - LAM) & 1) == 0 : (LAM == CH - 1 ? !T0_X : false);
+        constexpr bool TO_C = !TREE && LAM < CH - 1;
+        static_assert(TO_C || NPAR * NB * (M - 1) * (M - 1) <=
+                                  (TO_X ? Gm::PPW * Gm::K * Gm::K : L::ybuf),
                       "the level's children fit their buffer");
+        static_assert(!TO_C || chain_off(N, LAM + 1) <= L::cbufn, "the chain level fits its slot");
         static_assert(NPAR * NB * 2 * (M - 1) <= L::vecn, "the level's vectors fit");
+        cplx *dst = TO_C ? s_c + chain_off(N, LAM) : (TO_X ? s_x : s_y);
+        const cplx *src = LAM == 0          ? nullptr
+                          : LAM <= CH - 1   ? s_c + chain_off(N, LAM - 1)
+                          : LAM == CH       ? (T0_X ? s_y : s_x)
+                                            : (TO_X ? s_y : s_x);
         const int bfix = TREE ? 0 : (rpre >> SH) & 1;
-        rtop_level<N, CUR, NPAR, NB, M, LAM == 0, PPP, L::NPS>(
-            pr0, LAM, bfix, g0, TO_X ? s_y : s_x, TO_X ? s_x : s_y, s_vec,
-            s_piv + (TREE ? CH + PTS * (PPP - 1) : LAM));
-        rtop_levels<N, CUR, MAP, LAM + 1, OFF, TL, PTS>(pr0, rpre, g0, s_x, s_y, s_vec, s_piv);
+        if (TREE || LAM >= k0)
+            rtop_level<N, CUR, NPAR, NB, M, LAM == 0, PPP, L::NPS>(
+                pr0, LAM, bfix, g0, src, dst, s_vec, s_piv + (TREE ? CH + PTS * (PPP - 1) : LAM));
+        rtop_levels<N, CUR, MAP, LAM + 1, OFF, TL, PTS>(pr0, rpre, k0, g0, s_x, s_y, s_c, s_vec,
+                                                        s_piv);
     }
 }
 
 /* The first OFF = n - 8 eliminations of the scalar tree (above order 10,
  * and at orders 9 and 10 in the cooperative-top mapping; 8 lanes per
- * item), shared by the PPW items of a round.  The round holds PTS points (their pair tables from
- * pr0 on, NPS pairs apart) of PPW / PTS items each; items of a point differ
- * in the last TL = log2(PPW / PTS) bits of their index prefix and, with one
- * point per round, share the CH = OFF - TL bits before (the round's prefix
- * rpre).  The whole wave eliminates the CH shared levels once and the TL
+ * item), shared by the PPW items of a round.  The round holds PTS points
+ * (their pair tables from pr0 on, NPS pairs apart) of PPW / PTS items each;
+ * items of a point differ in the last TL = log2(PPW / PTS) bits of their
+ * index prefix and, with one point per round, share the CH = OFF - TL bits
+ * before (the round's prefix rpre).  The whole wave eliminates the CH shared levels once and the TL
  * levels as a tree per point (1, 2, 4, ... parents), one level at a time,
  * instead of every item repeating the OFF levels of its own prefix.  Leaves
  * item g's 9 x 9 trailing correction block at c0 + g K K and returns, for
@@ -493,13 +516,19 @@ __device__ cplx round_top(const pairv *pr0, int rpre, int grp, cplx g0, char *ld
     static_assert(CH + PTS * ((1 << TL) - 1) <= L::pivn, "pivots of every level");
     static_assert(Gm::PPW * Gm::K * Gm::K >= N * N && L::ybuf >= N * N, "chain children fit");
     static_assert(L::vecn >= 2 * N && L::vecn >= 2 * Gm::PPW * Gm::K, "vectors of every level");
+    static_assert(CH == L::CH, "one chain length");
     cplx *s_x = reinterpret_cast<cplx *>(lds + L::c0);
     cplx *s_y = reinterpret_cast<cplx *>(lds + L::row);
     cplx *s_vec = s_y + L::ybuf;
     cplx *s_piv = s_vec + L::vecn;
+    cplx *s_c = s_piv + L::pivn;
+    /* rounds of a point come in order of rpre, from 0: chain level k (bit
+     * CH-1-k of rpre) changed from the previous round iff that bit flipped,
+     * i.e. from level CH-1-ctz(rpre) on; a new point (rpre 0) redoes all */
+    const int k0 = rpre == 0 ? 0 : CH - 1 - __builtin_ctz((unsigned)rpre);
     /* the previous round's lanes have read their blocks */
     wave_sync();
-    rtop_levels<N, CUR, MAP, 0, OFF, TL, PTS>(pr0, rpre, g0, s_x, s_y, s_vec, s_piv);
+    rtop_levels<N, CUR, MAP, 0, OFF, TL, PTS>(pr0, rpre, k0, g0, s_x, s_y, s_c, s_vec, s_piv);
     cplx prod = cmk(1.0, 0.0);
 #pragma unroll
     for (int k = 0; k < CH; ++k) prod = cmul(prod, s_piv[k]);
@@ -1377,8 +1406,9 @@ __global__ void __launch_bounds__(WG_TREE, (Geo<N, PAIR, MAP>::WPS)) batch_kerne
     extern __shared__ __attribute__((aligned(16))) char lds[];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef ref = tiles[t];
-        /* by reference: fields are loaded where they are used (scalar loads), which keeps
-           the descriptor out of the registers the tree needs */
+        /* by reference: fields are loaded where they are used (scalar
+         * loads), which keeps the descriptor out of the registers the tree
+         * needs */
         const ItemDesc &it = items[ref.item];
         const cplx v = order_tile<N, MODEL, false, PAIR, CUR, SOB, MAP>(it, ref.tile, lds);
         if (threadIdx.x == 0) {

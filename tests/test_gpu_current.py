@@ -129,7 +129,8 @@ def _compare(qs, qo, floor, label):
 
 @pytest.mark.parametrize("alpha", [0.0, "ns"])
 @pytest.mark.parametrize("n,log2_n,K", [(1, 13, 4), (2, 12, 4), (3, 11, 3), (5, 10, 3),
-                                        (8, 9, 2), (10, 8, 2), (12, 7, 1)])
+                                        (8, 9, 2), (10, 8, 2), (11, 7, 1), (12, 7, 1),
+                                        (14, 6, 1)])
 def test_eval_order_current(q, oracle_mod, otab, n, log2_n, K, alpha):
     tb = otab[1]
     a = tb.n_sigma if alpha == "ns" else alpha

@@ -36,7 +36,7 @@ def _compare(qs, qo, label, floor=None):
 
 
 @pytest.mark.parametrize("n,log2_n,K", [(1, 14, 8), (2, 12, 4), (4, 11, 3), (6, 11, 2),
-                                        (8, 10, 2), (10, 8, 2), (12, 7, 1)])
+                                        (8, 10, 2), (10, 8, 2), (12, 7, 1), (14, 6, 1)])
 def test_sobol_estimates_match_oracle(q, oracle_mod, n, log2_n, K):
     d = STRESS_DOT if n > 8 else TINY_DOT
     tb = oracle_mod.Tables(d.eps_d, d.gamma, d.beta, d.bias_v, d.n_grid, d.t_half)

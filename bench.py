@@ -245,8 +245,12 @@ def run_geometry(args):
     order; a mapping is (lanes per item, cooperative top levels)."""
     import torch
     from paper_2002_12372_amd import qqmc
-    from paper_2002_12372_amd.flops import tree_flops
+    from paper_2002_12372_amd.flops import geometry, tree_flops
     from qqmc_inputs import Dot, batched_log2_n, order_job
+
+    def shape(n, alt):
+        _, off, t = geometry(n, alt)
+        return (1 << t, off)
 
     stream = torch.cuda.current_stream()
     tb = qqmc.make_tables(Dot(0.0, 1.0, 20.0, 0.0))
@@ -258,9 +262,7 @@ def run_geometry(args):
         auto = info["geometry"][n]
         pts = (1 << log2_n) * 32
         flops = pts * inside_fraction(n, 10.0) * tree_flops(n)
-        default = (1 << (n - 5), 0) if n <= 10 else (8, n - 8)
-        other = (8, n - 8) if n in (9, 10) else \
-            ((1 << (n - 4), 0) if n <= 8 else (16, n - 8))
+        default, other = shape(n, False), shape(n, True)
         row = {"order": n, "lattice_points": 1 << log2_n, "shifts": 32,
                "tile_len": info["tile_len"], "autotuned": list(auto)}
         for name, g in (("default", default), ("alternative", other)):

@@ -375,9 +375,11 @@ qqmc_status qqmc_plan_info(qqmc_plan p, int64_t *n_tiles, int64_t *n_points,
  * learned warp) of order `order` >= 5, which has two: the default, the one
  * qqmc_eval_order uses (a depth-5 register tree: 2^(n-5) lanes per point
  * up to order 10 with no top levels, 8 lanes per item and n - 8 top levels
- * above), and a second one -- at orders 5-8 and 11-14 a depth-4 register
- * tree (twice the lanes per item, compiled for two waves per SIMD), at
- * orders 9 and 10 n - 8 cooperative top levels with 8 lanes per item.  The
+ * above; at orders 5 and 6 a depth-4 tree, 2^(n-4) lanes per point, two
+ * waves per SIMD), and a second one -- at orders 5 and 6 the depth-5 tree,
+ * at orders 7, 8 and 11-14 a depth-4 register tree (twice the lanes per
+ * item, compiled for two waves per SIMD), at orders 9 and 10 n - 8
+ * cooperative top levels with 8 lanes per item.  The
  * mapping is named by its (lanes_per_item, top_levels) as qqmc_plan_info
  * reports them; the graph is captured again.  The two agree to rounding.
  * EINVAL if the plan has no such group or the order has no such mapping. */

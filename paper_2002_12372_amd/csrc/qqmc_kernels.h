@@ -134,11 +134,8 @@ template <int N, bool PAIR = false, bool CUR = false, bool SOB = false, int MAP 
     static constexpr int sobv = adapt + (PAIR ? AdaptWs<N, MB>::bytes : 0);
     static constexpr int bytes = sobv + (SOB ? sob_bytes : 0);
     /* one-wave-per-SIMD kernels: four workgroups share a compute unit's
-     * 160 KiB of local memory.  The exception is the current at order 5
-     * (one lane per point, 64 pair tables of 20 entries: 45 KB), which runs
-     * three workgroups per compute unit */
-    static_assert(Gm::WPS != 1 || bytes <= kShare || (CUR && Gm::G == 1),
-                  "a one-wave workgroup within a quarter of LDS");
+     * 160 KiB of local memory */
+    static_assert(Gm::WPS != 1 || bytes <= kShare, "a one-wave workgroup within a quarter of LDS");
 };
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m)

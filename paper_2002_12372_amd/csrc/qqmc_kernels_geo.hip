@@ -1,14 +1,16 @@
 /*
  * qqmc_kernels_geo.hip -- the second lane mapping of the scalar-tree charge
- * kernels on the lattice, for the batched plan's autotuner.  Orders 5-8 and
+ * kernels on the lattice, for the batched plan's autotuner.  Orders 7, 8 and
  * 11-14: a depth-4 register tree (each lane starts from a 5 x 5 trailing
  * block, so twice the lanes share an item: 16 per point at order 8 instead
- * of 8), compiled for two waves per SIMD.  Orders 9 and 10: the first n - 8
- * levels eliminated cooperatively by the 8 lanes of each top-level index
- * prefix, each lane then starting from the prefix's 9 x 9 block (the default
- * there is the flat mapping, 2^(n-5) lanes per point each walking its path
- * from the full matrix).  Orders 1-4 have a single mapping (one lane walks
- * the whole tree either way).
+ * of 8), compiled for two waves per SIMD.  Orders 5 and 6, whose default is
+ * the depth-4 tree: the depth-5 tree (half the lanes per point, one wave per
+ * SIMD).  Orders 9 and 10: the first n - 8 levels eliminated cooperatively
+ * by the 8 lanes of each top-level index prefix, each lane then starting
+ * from the prefix's 9 x 9 block (the default there is the flat mapping,
+ * 2^(n-5) lanes per point each walking its path from the full matrix).
+ * Orders 1-4 have a single mapping (one lane walks the whole tree either
+ * way).
  */
 #include "qqmc_kernels.h"
 
@@ -16,7 +18,10 @@ namespace qqmc {
 
 namespace {
 
-template <int N> constexpr int alt_map() { return (N == 9 || N == 10) ? kMapTop : kMapDepth4; }
+template <int N> constexpr int alt_map()
+{
+    return (N == 9 || N == 10) ? kMapTop : (N == 5 || N == 6) ? kMapDepth5 : kMapDepth4;
+}
 
 template <int N> struct BatchAlt {
     static hipError_t run(const ItemDesc *items_dev, const TileRef *tiles_dev, int64_t n_tiles,

@@ -24,8 +24,9 @@
  * 0).  With
  * tile_len 0 it also picks each group's lane mapping where the kernel has
  * two (the scalar-tree charge on the lattice from order 5: the default, or
- * a depth-4 register tree at orders 5-8 and 11-14, cooperative top levels
- * at 9 and 10), timing the group alone under each.  The two mappings split
+ * a depth-5 register tree at orders 5 and 6, a depth-4 one at orders 7, 8
+ * and 11-14, cooperative top levels at 9 and 10), timing the group alone
+ * under each.  The two mappings split
  * the eliminations differently between a lane's path and its subtree, so
  * their sums agree to rounding, not bit for bit; with the default mapping
  * kept (a fixed tile_len, or the default chosen) every tile sum is the

@@ -124,22 +124,27 @@ QQMC_HD constexpr int pidx(int i, int j) { return j * (j - 1) / 2 + i; }
 /* Work split of one item.  PAIR selects the paired tree (vertices
  * eliminated two at a time with 2x2 block pivots, for vertex diagonals that
  * may vanish): its cooperative levels and per-lane path cover whole pairs.
- * MAP selects the lane mapping of the scalar tree: 0 the default; 1 a
- * depth-4 register tree (twice the lanes per item, two waves per SIMD);
- * 2 at orders 9 and 10 the first n - 8 levels eliminated cooperatively by
- * the lanes of each top-level index prefix (the default there is the flat
- * mapping, every lane walking its path from the full matrix). */
-constexpr int kMapDefault = 0, kMapDepth4 = 1, kMapTop = 2;
+ * MAP selects the lane mapping of the scalar tree: 0 the default (a
+ * depth-5 register tree, depth 4 at orders 5 and 6, where it measured
+ * faster); 1 a depth-4 register tree (twice the lanes per item, two waves
+ * per SIMD); 3 a depth-5 register tree (the second mapping at orders 5 and
+ * 6); 2 at orders 9 and 10 the first n - 8 levels eliminated cooperatively
+ * by the lanes of each top-level index prefix (the default there is the
+ * flat mapping, every lane walking its path from the full matrix). */
+constexpr int kMapDefault = 0, kMapDepth4 = 1, kMapTop = 2, kMapDepth5 = 3;
 template <int N, bool PAIR = false, int MAP = kMapDefault> struct Geo {
-    static_assert(MAP == kMapDefault || (!PAIR && (MAP == kMapDepth4 || (N == 9 || N == 10))),
-                  "the scalar tree's second mappings: depth 4, or cooperative top levels at 9, 10");
+    static_assert(MAP == kMapDefault ||
+                      (!PAIR && (MAP == kMapDepth4 || MAP == kMapDepth5 || (N == 9 || N == 10))),
+                  "the scalar tree's second mappings: depth 4 or 5, or cooperative top levels at 9, 10");
     /* cooperative levels: the paired tree n - 8 rounded up to even above
      * order 8, the scalar tree n - 8 above order 10 (or above 8 with
      * kMapTop) */
     static constexpr int OFF = PAIR ? (N > 8 ? ((N - 7) & ~1) : 0)
                                     : (N > (MAP == kMapTop ? 8 : 10) ? N - 8 : 0);
     static constexpr int K = N + 1 - OFF;              /* block size          */
-    static constexpr int B = MAP == kMapDepth4 ? 4 : 5; /* register-tree depth */
+    /* register-tree depth */
+    static constexpr int B =
+        (MAP == kMapDepth4 || (MAP == kMapDefault && !PAIR && (N == 5 || N == 6))) ? 4 : 5;
     /* per-lane path: scalar tree, down to a 6 x 6 block; paired tree, whole
      * pairs down to a block of at most 5 x 5 (a pair node keeps its parent
      * block live under its four children) */

@@ -78,11 +78,14 @@ def warp_flops(n):
 
 def geometry(n, alt=False):
     """Block size K, cooperative top levels, per-lane path levels T of the
-    scalar tree's default lane mapping (a register tree of depth 5, the
-    full matrix up to order 10, cooperative top levels above) or of its
-    alternative (depth 4 at orders 5-8 and 11-14, cooperative top levels at
-    9 and 10)."""
-    depth = 4 if alt and n not in (9, 10) else 5
+    scalar tree's default lane mapping (a register tree of depth 5, depth 4
+    at orders 5 and 6; the full matrix up to order 10, cooperative top
+    levels above) or of its alternative (depth 5 at orders 5 and 6, depth 4
+    at orders 7, 8 and 11-14, cooperative top levels at 9 and 10)."""
+    if n in (5, 6):
+        depth = 5 if alt else 4
+    else:
+        depth = 4 if alt and n not in (9, 10) else 5
     top_from = 8 if alt and n in (9, 10) else 10
     K = n + 1 if n <= top_from else 9
     off = n + 1 - K

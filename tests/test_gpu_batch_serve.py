@@ -71,11 +71,14 @@ def test_plan_matches_single_launches_bitwise(q, oracle_mod):
 def _geometry(n, alt):
     """(lanes per item, cooperative top levels) of the scalar-tree charge
     kernel's default mapping (a depth-5 register tree: 2^(n-5) lanes per
-    point up to order 10, 8 lanes per top-level prefix above) or its
-    alternative (a depth-4 tree at orders 5-8 and 11-14, cooperative top
-    levels at 9 and 10)."""
+    point up to order 10, 8 lanes per top-level prefix above; at orders 5
+    and 6 a depth-4 tree, 2^(n-4) lanes) or its alternative (a depth-5 tree
+    at orders 5 and 6, a depth-4 tree at orders 7, 8 and 11-14, cooperative
+    top levels at 9 and 10)."""
     if n < 5:
         return (1, 0)
+    if n in (5, 6):
+        return (1 << (n - 5), 0) if alt else (1 << (n - 4), 0)
     if not alt:
         return (1 << (n - 5), 0) if n <= 10 else (8, n - 8)
     if n in (9, 10):
